@@ -1,0 +1,201 @@
+/*
+ * mppi.h -- C ABI of the MI355X (gfx950) hot path of reference-free
+ * sampling-based MPC (Schramm, Fabre, Perrin-Gilbert, Carpentier,
+ * arXiv 2511.19204).
+ *
+ * One call to mppi_step runs the inner loop of the paper's Algorithm 1
+ * ("Reference-Free MPPI") for one robot state: I planning iterations of
+ *   sample perturbed spline knots  (Alg. 1 sampling step, Sec. III-B noise
+ *                                   schedule, eq. vel-clamp),
+ *   roll every sample out          (Alg. 1 simulate step: PD tracking of the
+ *                                   cubic Hermite reference, eq. hermite_segment
+ *                                   and eq. pd-controller; floating-base rigid
+ *                                   bodies with soft contact),
+ *   score it                       (Sec. IV-A running and terminal costs),
+ *   weight and update              (eq. softmax_minmax / eq. omega-weights and
+ *                                   eq. update-nominal applied to the knots),
+ *   track the best sample          (Sec. III-D).
+ * All compute runs in hand-written HIP kernels on the device; the host only
+ * validates arguments and enqueues work.
+ *
+ * Conventions
+ *   - Spatial vectors are (angular; linear).
+ *   - A floating-base model has body 0 = free base; its state is
+ *     q = [p(3), quaternion w,x,y,z (4), joints(n_u)],
+ *     v = [base angular velocity (3), base linear velocity (3), joints(n_u)],
+ *     the base twist in base coordinates.  A fixed-base model has q = v = joints.
+ *   - Every other body carries one revolute joint (joint j of body j + 1, or
+ *     body j for a fixed base).  Parents precede children (parent[i] < i).
+ *   - Knot arrays are [2][n_knots][n_u] float: positions, then velocities.
+ *   - Device pointers are plain hipMalloc'd (or torch) device memory on the
+ *     current device; host pointers are read only during the call.
+ *   - Calls are asynchronous on the given stream (hipStream_t passed as void*,
+ *     NULL = the null stream); outputs are valid once the stream completes.
+ *   - Results are a pure function of (model, params, seed, tick, state,
+ *     knots_in): independent of batching, launch shape, stream and other work.
+ *
+ * Errors: every entry point returns an mppi_status.  Argument and shape errors
+ * are detected on the host (MPPI_EINVAL); HIP runtime failures give
+ * MPPI_EDEVICE; mppi_last_error() returns a thread-local message for the last
+ * non-OK status.  Device data is never inspected on the host: non-finite
+ * rollouts are counted and given zero weight on the device.
+ */
+#ifndef MPPI_H
+#define MPPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MPPI_OK = 0,
+  MPPI_EINVAL = -1,
+  MPPI_ENOMEM = -2,
+  MPPI_EDEVICE = -3,
+  MPPI_EBUSY = -4,
+  MPPI_ENOSLOT = -5
+} mppi_status;
+
+/* Kinematic tree, inertias, actuators and soft contact (host memory, float).
+ * The tree is the robot the rollouts simulate (the paper simulates its robots
+ * in the Simple simulator; this library integrates them itself, see below). */
+typedef struct {
+  int32_t n_bodies;          /* 1..64                                          */
+  int32_t floating_base;     /* 1: body 0 is a 6-DoF free base; 0: fixed base  */
+  const int32_t* parent;     /* [n_bodies], parent[i] < i, -1 = world          */
+  const float* axis;         /* [n_bodies][3] unit joint axis in the joint frame */
+  const float* R_tree;       /* [n_bodies][9] row-major, joint frame in parent  */
+  const float* p_tree;       /* [n_bodies][3] joint frame origin in parent      */
+  const float* mass;         /* [n_bodies]                                      */
+  const float* com;          /* [n_bodies][3] centre of mass in the body frame  */
+  const float* inertia;      /* [n_bodies][6] xx yy zz xy xz yz about the com   */
+  const float* q_min;        /* [n_u] joint position bounds                    */
+  const float* q_max;        /* [n_u]                                           */
+  const float* tau_max;      /* [n_u] actuator torque limits                    */
+  const float* kp;           /* [n_u] PD gains                                  */
+  const float* kd;           /* [n_u]                                           */
+  int32_t n_contacts;        /* 0..32                                           */
+  const int32_t* contact_body; /* [n_contacts]                                  */
+  const float* contact_pos;  /* [n_contacts][3] point in the body frame         */
+  float k_contact;           /* normal spring  N/m  (ground plane z = 0)        */
+  float d_contact;           /* normal damper  N s/m                            */
+  float mu;                  /* Coulomb friction coefficient                    */
+  float eps_fric;            /* friction smoothing velocity  m/s                */
+  float gravity;             /* m/s^2, along -z                                 */
+  int32_t ee_body;           /* end-effector body for the reaching cost, or -1  */
+  float ee_pos[3];           /* end-effector point in that body's frame         */
+  int32_t n_substeps;        /* physics steps per control step, >= 1            */
+  const float* armature;     /* [n_u] reflected rotor inertia per joint, or NULL (zero) */
+} mppi_model_desc;
+
+/* Controller parameters of one MPC instance (the Require line of Alg. 1 plus
+ * the cost weights of Sec. IV-A). */
+typedef struct {
+  int32_t n_samples;         /* N: sampled trajectories per iteration, 1..65536 */
+  int32_t horizon;           /* H: control steps per rollout, 1..4096           */
+  int32_t n_knots;           /* K: spline knots per joint, 2..64                */
+  int32_t n_iters;           /* I: planning iterations per call, 1..64          */
+  float dt;                  /* control step, s                                 */
+  float lambda;              /* softmax temperature > 0                         */
+  int32_t weight_mode;       /* 0: min-max normalised costs, 1: raw costs       */
+  int32_t noise_mode;        /* 0: exponential annealing kernel, 1: linear      */
+  float scale_q, beta1, beta2; /* mode 0: std = scale_q exp(-(I-i)/(beta1 I) - (K-k)/(beta2 K)) */
+  float sigma_lo, sigma_hi;  /* mode 1: std = lo + (hi - lo) k / (K - 1)        */
+  int32_t cost_kind;         /* 0: end-effector height, 1: locomotion           */
+  float w_h, w_or, w_q, w_cv, w_cf, w_eff, w_H; /* locomotion weights           */
+  float w_ee, w_tau;         /* end-effector weights                           */
+  float z_des;               /* desired base (or end-effector) height           */
+  float v_des[3];            /* commanded base velocity (terminal target)       */
+  const float* f0z;          /* [n_contacts] reference normal force per point   */
+  const float* q0_cost;      /* [n_u] reference joint configuration             */
+} mppi_params;
+
+/* Per-call results besides the knots (device memory). */
+typedef struct {
+  float S_best;              /* lowest cost simulated in this call (+inf if none) */
+  int32_t best_iter;         /* iteration that found it, -1 if none             */
+  int32_t n_nonfinite;       /* rollouts with a non-finite cost, all iterations */
+  int32_t all_nonfinite_iters; /* iterations whose rollouts were all non-finite  */
+} mppi_step_info;
+
+typedef struct mppi_model mppi_model;   /* device-resident tree (opaque)       */
+typedef struct mppi_ctx mppi_ctx;       /* one MPC instance (opaque)           */
+
+/* Upload a tree.  Validates shapes (parent order, unit axes within 1e-4,
+ * positive masses, contact bodies in range).  The model owns its device copy;
+ * the caller keeps ownership of desc.  Errors: MPPI_EINVAL, MPPI_EDEVICE. */
+mppi_status mppi_model_create(const mppi_model_desc* desc, mppi_model** out);
+mppi_status mppi_model_destroy(mppi_model* m);
+
+/* Create an MPC instance on the current device.  Precomputes the noise
+ * schedule (Sec. III-B, "precomputed and cached once") in FP64 and stores it as
+ * float; allocates the per-sample knot and cost buffers.  The counter-based
+ * noise is keyed by seed; the tick counter starts at 0 and advances by one per
+ * mppi_step.  The model must outlive the context. */
+mppi_status mppi_create(const mppi_model* m, const mppi_params* p, uint64_t seed, mppi_ctx** out);
+mppi_status mppi_destroy(mppi_ctx* c);
+mppi_status mppi_set_tick(mppi_ctx* c, uint32_t tick);
+mppi_status mppi_get_tick(const mppi_ctx* c, uint32_t* tick);
+
+/* Launch shape: lanes per rollout (a power of two 4..64 holding every body, or
+ * 0 = automatic).  Any valid value gives identical results. */
+mppi_status mppi_set_lanes_per_rollout(mppi_ctx* c, int32_t lanes);
+mppi_status mppi_get_lanes_per_rollout(const mppi_ctx* c, int32_t* lanes);
+
+/* One MPC step (Alg. 1 inner loop, I iterations) from d_state.
+ *   d_state      [n_q + n_v] device float, the (predicted) robot state
+ *   d_knots_in   [2][K][n_u] device float, warm-start nominal knots
+ *   d_knots_out  [2][K][n_u] device float, nominal after I iterations (may alias d_knots_in)
+ *   d_best_knots [2][K][n_u] device float or NULL, the best simulated sample
+ *   d_info       device mppi_step_info or NULL
+ *   d_costs      [I][N] device float or NULL, every rollout cost
+ * Uses the context's tick, then advances it.  If every rollout of an
+ * iteration is non-finite the nominal is left unchanged for that iteration. */
+mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float* d_knots_in, float* d_knots_out,
+                      float* d_best_knots, mppi_step_info* d_info, float* d_costs, void* stream);
+
+/* The same for n instances in fused launches (each array has n entries;
+ * d_best_knots / d_info entries may be NULL).  Instances may differ in model,
+ * N, H, K and I.  Each result equals that instance's own mppi_step. */
+mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const float* const* d_states,
+                            const float* const* d_knots_in, float* const* d_knots_out,
+                            float* const* d_best_knots, mppi_step_info* const* d_infos, void* stream);
+
+/* ---- Verification entry points (same device code as mppi_step) ---------- */
+
+/* Philox4x32-10 block function: d_ctr [n][4], d_key [n][2] -> d_out [n][4]. */
+mppi_status mppi_debug_philox(const uint32_t* d_ctr, const uint32_t* d_key, uint32_t* d_out, int32_t n,
+                              void* stream);
+
+/* The perturbed, clipped and clamped knots of every sample of iteration iter
+ * at tick `tick` around d_knots_in: d_samples [N][2][K][n_u]. */
+mppi_status mppi_debug_samples(mppi_ctx* c, const float* d_knots_in, int32_t iter, uint32_t tick,
+                               float* d_samples, void* stream);
+
+/* Accelerations of one physics step of step size dt for n states: PD tracking
+ * of (d_qref, d_vref) [n][n_u], soft contact and the linearly implicit terms.
+ * d_q [n][n_q], d_v [n][n_v] -> d_qdd [n][n_v]. */
+mppi_status mppi_debug_dynamics(const mppi_model* m, int32_t n, const float* d_q, const float* d_v,
+                                const float* d_qref, const float* d_vref, float dt, float* d_qdd,
+                                void* stream);
+
+/* Roll out given sample knots d_samples [N][2][K][n_u] from d_state:
+ * d_costs [N]; d_masks [N][H] (nullable) = contact bitmask at each control step. */
+mppi_status mppi_debug_rollouts(mppi_ctx* c, const float* d_state, const float* d_samples, float* d_costs,
+                                uint32_t* d_masks, void* stream);
+
+/* Weights and update from given costs d_costs [N] and samples d_samples
+ * [N][2][K][n_u]: d_knots_out = sum_n w_n sample_n (unchanged d_knots_in if no
+ * cost is finite), d_weights [N] (nullable). */
+mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, const float* d_samples,
+                              const float* d_knots_in, float* d_knots_out, float* d_weights, void* stream);
+
+const char* mppi_last_error(void);
+const char* mppi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPPI_H */

@@ -41,7 +41,7 @@ class OrcModel(C.Structure):
         ("kd", _dp), ("n_contacts", C.c_int32), ("contact_body", _ip), ("contact_pos", _dp),
         ("k_contact", C.c_double), ("d_contact", C.c_double), ("mu", C.c_double),
         ("eps_fric", C.c_double), ("gravity", C.c_double), ("ee_body", C.c_int32),
-        ("ee_pos", C.c_double * 3), ("n_substeps", C.c_int32),
+        ("ee_pos", C.c_double * 3), ("n_substeps", C.c_int32), ("armature", _dp),
     ]
 
 
@@ -73,6 +73,7 @@ def lib():
                                       C.c_int, C.c_int, C.c_int, _dp, _dp, C.c_int]
         _lib.orc_step.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, C.c_uint64, C.c_uint32, _dp,
                                   _dp, _dp, _ip, _dp, _ip, _ip, C.c_int]
+        _lib.orc_step_f32.argtypes = _lib.orc_step.argtypes
         _lib.orc_hermite.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                      _dp, _dp]
         _lib.orc_weights.argtypes = [C.c_int, _dp, C.c_double, C.c_int, _dp, _ip]
@@ -121,6 +122,9 @@ class _Model:
         for k in range(3):
             s.ee_pos[k] = float(m["ee_pos"][k])
         s.n_substeps = int(m.get("n_substeps", 1))
+        arm = np.asarray(m.get("armature", np.zeros(self_nu := nb - (1 if m["floating_base"] else 0))),
+                         dtype=np.float64)
+        a, s.armature = _d(arm); self.keep.append(a)
         self.s = s
         self.nu = nb - (1 if m["floating_base"] else 0)
         self.nq = self.nu + (7 if m["floating_base"] else 0)
@@ -220,6 +224,20 @@ def forward_dynamics_f32(model, q, v, tau, with_contacts=True):
     _check(lib().orc_forward_dynamics_f32(C.c_void_p(M.ptr), qa.ctypes.data_as(_fp),
                                           va.ctypes.data_as(_fp), ta.ctypes.data_as(_fp),
                                           int(with_contacts), qdd.ctypes.data_as(_fp)), "fd32")
+    return qdd
+
+
+def step_dynamics_f32(model, q, v, qr, vr, dt):
+    """step_dynamics in float arithmetic (FP32-vs-FP64 diagnosis only)."""
+    M = _Model(model)
+    f = lambda a: np.ascontiguousarray(a, np.float32)  # noqa: E731
+    qa, va, ra, sa = f(q), f(v), f(qr), f(vr)
+    qdd = np.zeros(M.nv, np.float32)
+    L = lib()
+    L.orc_step_dynamics_f32.argtypes = [C.c_void_p, _fp, _fp, _fp, _fp, C.c_float, _fp]
+    _check(L.orc_step_dynamics_f32(M.ptr, qa.ctypes.data_as(_fp), va.ctypes.data_as(_fp),
+                                   ra.ctypes.data_as(_fp), sa.ctypes.data_as(_fp), dt,
+                                   qdd.ctypes.data_as(_fp)), "step_dynamics_f32")
     return qdd
 
 
@@ -381,8 +399,9 @@ def dense_route_update(w, samples, nk, nu, H, dt):
     return out
 
 
-def step(model, params, x0, knots_in, seed, tick, threads=None):
-    """Full MPC step; returns a dict with knots, best_knots, S_best, best_iter, costs, ..."""
+def step(model, params, x0, knots_in, seed, tick, threads=None, f32=False):
+    """Full MPC step; returns a dict with knots, best_knots, S_best, best_iter, costs, ...
+    f32=True runs sampling and rollouts in float (FP32 divergence diagnosis only)."""
     M = _Model(model); P = _Params(params, M.nu)
     xa, xp = _d(x0); ka, kp = _d(knots_in)
     E = 2 * params["n_knots"] * M.nu
@@ -390,7 +409,8 @@ def step(model, params, x0, knots_in, seed, tick, threads=None):
     costs = np.zeros((params["n_iters"], params["n_samples"]))
     nnf = C.c_int32(); anf = C.c_int32()
     th = threads or os.cpu_count() or 1
-    _check(lib().orc_step(M.ptr, P.ptr, xp, kp, seed, tick, out.ctypes.data_as(_dp),
+    fn = lib().orc_step_f32 if f32 else lib().orc_step
+    _check(fn(M.ptr, P.ptr, xp, kp, seed, tick, out.ctypes.data_as(_dp),
                           best.ctypes.data_as(_dp), C.byref(sb), C.byref(bi),
                           costs.ctypes.data_as(_dp), C.byref(nnf), C.byref(anf), th), "step")
     return {"knots": out, "best_knots": best, "S_best": sb.value, "best_iter": bi.value,

@@ -57,6 +57,7 @@ typedef struct {
   int32_t ee_body;
   double ee_pos[3];
   int32_t n_substeps;          // physics steps per control step (>= 1)
+  const double* armature;      // [n_u] reflected rotor inertia of each joint, or null (zero)
 } orc_model;
 
 typedef struct {
@@ -295,7 +296,7 @@ template <class T> struct Model {
   std::vector<V3<T>> axis, p_tree, com, cpos;
   std::vector<M3<T>> R_tree;
   std::vector<M6<T>> Ibody;  // spatial inertia in body coordinates
-  std::vector<T> mass, qmin, qmax, taumax, kp, kd;
+  std::vector<T> mass, qmin, qmax, taumax, kp, kd, arm;
   std::vector<int> cbody;
   T k = 0, d = 0, mu = 0, eps = 0, g = 0;
   int ee_body = -1;
@@ -340,6 +341,7 @@ template <class T> static Model<T> load_model(const orc_model* m) {
     M.taumax.push_back((T)m->tau_max[j]);
     M.kp.push_back((T)m->kp[j]);
     M.kd.push_back((T)m->kd[j]);
+    M.arm.push_back(m->armature ? (T)m->armature[j] : T(0));
   }
   for (int c = 0; c < M.nc; ++c) {
     M.cbody.push_back(m->contact_body[c]);
@@ -576,7 +578,7 @@ static std::vector<T> aba(const Model<T>& M, const Kin<T>& K, const T* tau, cons
       Dv += S[k] * U[i][k];
       sp += S[k] * pA[i][k];
     }
-    D[i] = Dv + (g ? g[M.joint[i]] : T(0));
+    D[i] = Dv + M.arm[M.joint[i]] + (g ? g[M.joint[i]] : T(0));
     u[i] = tau[M.joint[i]] - sp;
     int lam = M.parent[i];
     if (lam >= 0) {
@@ -636,7 +638,7 @@ template <class T> static std::vector<T> crba(const Model<T>& M, const Kin<T>& K
     V6<T> F = m6_v(IC[i], S);
     T hii = 0;
     for (int k = 0; k < 6; ++k) hii += S[k] * F[k];
-    H[di * nv + di] = hii;
+    H[di * nv + di] = hii + M.arm[M.joint[i]];
     int j = i;
     while (M.parent[j] >= 0) {
       F = m6T_v(K.Xup[j], F);
@@ -691,7 +693,7 @@ static std::vector<T> rnea(const Model<T>& M, const Kin<T>& K, const T* qdd, con
     V6<T> S = joint_S(M, i);
     T t = 0;
     for (int k = 0; k < 6; ++k) t += S[k] * f[i][k];
-    tau[vo + M.joint[i]] = t;
+    tau[vo + M.joint[i]] = t + M.arm[M.joint[i]] * qdd[vo + M.joint[i]];
     int lam = M.parent[i];
     if (lam >= 0) {
       V6<T> fp = m6T_v(K.Xup[i], f[i]);
@@ -1113,6 +1115,21 @@ int orc_body_poses(const orc_model* m, const double* q, double* R, double* p) {
   return 0;
 }
 
+// The same in float arithmetic (diagnosis of FP32-vs-FP64 divergence only).
+int orc_step_dynamics_f32(const orc_model* m, const float* q, const float* v, const float* qr, const float* vr,
+                          float dt, float* qdd) {
+  if (!model_ok(m) || !(dt >= 0)) return -1;
+  Model<float> M = load_model<float>(m);
+  PDOut<float> pd = pd_law(M, q, v, qr, vr, dt);
+  Kin<float> K = kinematics(M, q, v);
+  std::vector<V6<float>> fext;
+  std::vector<M6<float>> Iadd;
+  contacts(M, K, fext, dt, &Iadd);
+  std::vector<float> a = aba(M, K, pd.tau.data(), fext, &Iadd, pd.g.data());
+  std::copy(a.begin(), a.end(), qdd);
+  return 0;
+}
+
 // One physics step of the rollout integrator from (q, v) tracking the
 // reference (qr, vr): accelerations as in orc_step_dynamics, then
 // v += dt qdd, q += dt v (base: position by R v_lin, quaternion by the
@@ -1311,19 +1328,21 @@ int orc_dense_route_update(int n, int nk, int nu, int H, double dt, const double
 // The full MPC step (Alg. 1 inner loop): I iterations of sample -> simulate ->
 // weight -> update, with best-sample tracking (Sec. III-D: strict
 // improvement, lowest index among equal minima, S_best starts at +inf).
-int orc_step(const orc_model* m, const orc_params* p, const double* x0, const double* knots_in, uint64_t seed,
-             uint32_t tick, double* knots_out, double* best_knots, double* S_best, int* best_iter,
-             double* costs, int* n_nonfinite, int* all_nonfinite_iters, int threads) {
-  if (!model_ok(m) || !params_ok(m, p)) return -1;
-  Model<double> M = load_model<double>(m);
+// Sampling and rollouts run in T; weights and the update in double.
+}  // extern "C"
+template <class T>
+static int step_impl(const orc_model* m, const orc_params* p, const double* x0, const double* knots_in,
+                     uint64_t seed, uint32_t tick, double* knots_out, double* best_knots, double* S_best,
+                     int* best_iter, double* costs, int* n_nonfinite, int* all_nonfinite_iters, int threads) {
+  Model<T> M = load_model<T>(m);
   const int N = p->n_samples, E = 2 * p->n_knots * M.nu;
   std::vector<double> nominal(knots_in, knots_in + E), S(N), w(N), samples((size_t)N * E);
   std::vector<double> best(nominal);
   double sbest = std::numeric_limits<double>::infinity();
   int bit = -1, nnf = 0, allnf = 0;
   for (int it = 0; it < p->n_iters; ++it) {
-    run_rollouts<double>(M, p, x0, nominal.data(), seed, tick, it, 0, N, S.data(), samples.data(),
-                         threads < 1 ? 1 : threads);
+    run_rollouts<T>(M, p, x0, nominal.data(), seed, tick, it, 0, N, S.data(), samples.data(),
+                    threads < 1 ? 1 : threads);
     int nstar = -1;
     int nf = weights(N, S.data(), p->lambda, p->weight_mode, w.data(), &nstar);
     nnf += N - nf;
@@ -1349,6 +1368,24 @@ int orc_step(const orc_model* m, const orc_params* p, const double* x0, const do
   if (n_nonfinite) *n_nonfinite = nnf;
   if (all_nonfinite_iters) *all_nonfinite_iters = allnf;
   return 0;
+}
+extern "C" {
+
+int orc_step(const orc_model* m, const orc_params* p, const double* x0, const double* knots_in, uint64_t seed,
+             uint32_t tick, double* knots_out, double* best_knots, double* S_best, int* best_iter,
+             double* costs, int* n_nonfinite, int* all_nonfinite_iters, int threads) {
+  if (!model_ok(m) || !params_ok(m, p)) return -1;
+  return step_impl<double>(m, p, x0, knots_in, seed, tick, knots_out, best_knots, S_best, best_iter, costs,
+                           n_nonfinite, all_nonfinite_iters, threads);
+}
+
+// The same with sampling and rollouts in float (diagnosis of FP32 divergence only).
+int orc_step_f32(const orc_model* m, const orc_params* p, const double* x0, const double* knots_in, uint64_t seed,
+                 uint32_t tick, double* knots_out, double* best_knots, double* S_best, int* best_iter,
+                 double* costs, int* n_nonfinite, int* all_nonfinite_iters, int threads) {
+  if (!model_ok(m) || !params_ok(m, p)) return -1;
+  return step_impl<float>(m, p, x0, knots_in, seed, tick, knots_out, best_knots, S_best, best_iter, costs,
+                          n_nonfinite, all_nonfinite_iters, threads);
 }
 
 }  // extern "C"

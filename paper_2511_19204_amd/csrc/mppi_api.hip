@@ -1,0 +1,751 @@
+// mppi_api.hip -- host side of the C ABI in include/mppi.h: argument checks,
+// model upload, per-instance device buffers, launch planning for single and
+// batched steps.  Every arithmetic step of the controller runs in the kernels
+// of mppi_kernels.hip; this file only validates, allocates and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mppi.h"
+#include "mppi_dev.hpp"
+
+namespace mppi {
+// kernels (mppi_kernels.hip)
+template <int G> __global__ void rollout_kernel(const DevInst*, const int2*, int);
+template <int G> __global__ void sample_kernel(const DevInst*, int);
+template <int G>
+__global__ void dynamics_kernel(const DevModel*, int, const float*, const float*, const float*, const float*, float,
+                                float*, int);
+struct UpdateOut {
+  float* knots_out;
+  float* best_out;
+  void* info_out;
+};
+__global__ void update_kernel(const DevUpdate*, const UpdateOut*, UpdateOut);
+struct StageItem {
+  const float* src;
+  float* dst;
+  int32_t count;
+};
+__global__ void stage_kernel(const StageItem*);
+__global__ void philox_kernel(const uint32_t*, const uint32_t*, uint32_t*, int);
+constexpr int kSlot = 28;
+inline int group_floats(int G, int E) { return G * kSlot + 16 + ((E + 3) & ~3) + G; }
+}  // namespace mppi
+
+using namespace mppi;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static mppi_status fail(mppi_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t _e = (expr);                                                                   \
+    if (_e != hipSuccess) return fail(MPPI_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// objects
+// ---------------------------------------------------------------------------
+struct mppi_model {
+  DevModel host;
+  DevModel* dev = nullptr;
+  int device = 0;
+  int nq = 0, nv = 0;
+};
+
+struct mppi_ctx {
+  const mppi_model* m = nullptr;
+  mppi_params p{};
+  uint64_t seed = 0;
+  int N = 0, H = 0, K = 0, I = 0, nu = 0, E = 0, nq = 0, nv = 0, nc = 0;
+  int lanes = 0;
+  int device = 0;
+  float delta = 0.f;
+  // device buffers
+  float *sigma = nullptr, *x0 = nullptr, *nom = nullptr, *samples = nullptr, *costs = nullptr;
+  float *best_state = nullptr, *f0z = nullptr, *q0 = nullptr;
+  uint32_t* tick = nullptr;
+  DevInst* d_insts = nullptr;   // [I]
+  DevUpdate* d_ups = nullptr;   // [I]
+  std::vector<DevInst> h_insts;
+  std::vector<DevUpdate> h_ups;
+};
+
+static int next_pow2(int x) {
+  int g = 4;
+  while (g < x) g <<= 1;
+  return g;
+}
+
+static bool valid_lanes(int G, const DevModel& M) { return (G == 4 || G == 8 || G == 16 || G == 32 || G == 64) && G >= M.nb; }
+
+static int lds_bytes(int G, int E) { return (64 / G) * group_floats(G, E) * (int)sizeof(float); }
+
+// ---------------------------------------------------------------------------
+// model
+// ---------------------------------------------------------------------------
+extern "C" mppi_status mppi_model_create(const mppi_model_desc* d, mppi_model** out) {
+  if (!d || !out) return fail(MPPI_EINVAL, "null argument");
+  const int nb = d->n_bodies;
+  if (nb < 1 || nb > kMaxBodies) return fail(MPPI_EINVAL, "n_bodies must be in 1..64");
+  if (d->n_contacts < 0 || d->n_contacts > kMaxContacts) return fail(MPPI_EINVAL, "n_contacts must be in 0..32");
+  if (d->n_substeps < 1) return fail(MPPI_EINVAL, "n_substeps must be >= 1");
+  if (!d->parent || !d->axis || !d->R_tree || !d->p_tree || !d->mass || !d->com || !d->inertia)
+    return fail(MPPI_EINVAL, "null tree array");
+  const int fb = d->floating_base ? 1 : 0;
+  const int nu = nb - fb;
+  if (nu < 1) return fail(MPPI_EINVAL, "model has no actuated joint");
+  if (!d->q_min || !d->q_max || !d->tau_max || !d->kp || !d->kd) return fail(MPPI_EINVAL, "null joint array");
+  if (d->n_contacts > 0 && (!d->contact_body || !d->contact_pos)) return fail(MPPI_EINVAL, "null contact array");
+  if (fb && d->parent[0] != -1) return fail(MPPI_EINVAL, "floating base must be body 0 with parent -1");
+  auto* m = new mppi_model();
+  DevModel& M = m->host;
+  std::memset(&M, 0, sizeof(M));
+  M.nb = nb; M.fb = fb; M.nu = nu; M.nc = d->n_contacts; M.nsub = d->n_substeps;
+  M.k = d->k_contact; M.d = d->d_contact; M.mu = d->mu; M.eps = d->eps_fric; M.g = d->gravity;
+  M.ee_body = d->ee_body;
+  if (d->ee_body >= nb || d->ee_body < -1) { delete m; return fail(MPPI_EINVAL, "ee_body out of range"); }
+  for (int k = 0; k < 3; ++k) M.ee_pos[k] = d->ee_pos[k];
+  int maxd = 0;
+  for (int i = 0; i < nb; ++i) {
+    const int lam = d->parent[i];
+    if (lam >= i) { delete m; return fail(MPPI_EINVAL, "parent[i] must be < i"); }
+    if (fb && i > 0 && lam < 0) { delete m; return fail(MPPI_EINVAL, "only the base may have parent -1"); }
+    if (!(d->mass[i] > 0.f)) { delete m; return fail(MPPI_EINVAL, "masses must be positive"); }
+    M.parent[i] = lam;
+    M.depth[i] = lam < 0 ? (fb ? 0 : 1) : M.depth[lam] + 1;
+    maxd = std::max(maxd, M.depth[i]);
+    if (lam >= 0) {
+      if (M.n_child[lam] >= kMaxChildren) { delete m; return fail(MPPI_EINVAL, "more than 8 children on a body"); }
+      M.child[lam][M.n_child[lam]++] = i;
+    }
+    M.mass[i] = d->mass[i];
+    M.mtot += d->mass[i];
+    for (int k = 0; k < 3; ++k) { M.com[i][k] = d->com[3 * i + k]; M.p_tree[i][k] = d->p_tree[3 * i + k]; }
+    for (int k = 0; k < 6; ++k) M.Ic[i][k] = d->inertia[6 * i + k];
+    if (fb && i == 0) continue;
+    // joint rotation C(q) = R_tree Rot(a, q) = R_tree a a^T + cos q (-R_tree K^2) + sin q (R_tree K)
+    const double a[3] = {d->axis[3 * i], d->axis[3 * i + 1], d->axis[3 * i + 2]};
+    const double an = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    if (std::fabs(an - 1.0) > 1e-4) { delete m; return fail(MPPI_EINVAL, "joint axes must be unit vectors"); }
+    double Rt[9];
+    for (int k = 0; k < 9; ++k) Rt[k] = d->R_tree[9 * i + k];
+    const double K[9] = {0, -a[2], a[1], a[2], 0, -a[0], -a[1], a[0], 0};
+    double K2[9], aa[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double s = 0;
+        for (int k = 0; k < 3; ++k) s += K[r * 3 + k] * K[k * 3 + c];
+        K2[r * 3 + c] = s;
+        aa[r * 3 + c] = a[r] * a[c];
+      }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double p0 = 0, p1 = 0, p2 = 0;
+        for (int k = 0; k < 3; ++k) {
+          p0 += Rt[r * 3 + k] * aa[k * 3 + c];
+          p1 -= Rt[r * 3 + k] * K2[k * 3 + c];
+          p2 += Rt[r * 3 + k] * K[k * 3 + c];
+        }
+        M.P[i][r * 3 + c] = (float)p0;
+        M.P[i][9 + r * 3 + c] = (float)p1;
+        M.P[i][18 + r * 3 + c] = (float)p2;
+      }
+    for (int r = 0; r < 3; ++r)
+      M.axis_p[i][r] = (float)(Rt[r * 3] * a[0] + Rt[r * 3 + 1] * a[1] + Rt[r * 3 + 2] * a[2]);
+    const int j = i - fb;
+    M.qmin[j] = d->q_min[j]; M.qmax[j] = d->q_max[j]; M.taumax[j] = d->tau_max[j];
+    M.kp[j] = d->kp[j]; M.kd[j] = d->kd[j];
+    M.arm[j] = d->armature ? d->armature[j] : 0.f;
+    if (!(M.arm[j] >= 0.f)) { delete m; return fail(MPPI_EINVAL, "armature must be >= 0"); }
+    if (!(M.qmin[j] < M.qmax[j])) { delete m; return fail(MPPI_EINVAL, "q_min must be < q_max"); }
+  }
+  M.max_depth = maxd;
+  M.n_levels = maxd + 1;
+  // contacts grouped by body (stable within a body)
+  int ci = 0;
+  for (int b = 0; b < nb; ++b) {
+    M.c_begin[b] = ci;
+    for (int c = 0; c < d->n_contacts; ++c) {
+      if (d->contact_body[c] < 0 || d->contact_body[c] >= nb) { delete m; return fail(MPPI_EINVAL, "contact_body out of range"); }
+      if (d->contact_body[c] != b) continue;
+      for (int k = 0; k < 3; ++k) M.cpos[ci][k] = d->contact_pos[3 * c + k];
+      M.corig[ci] = c;
+      ++ci;
+    }
+    M.c_count[b] = ci - M.c_begin[b];
+  }
+  // base spatial inertia about its own origin (packed symmetric 6x6)
+  if (fb) {
+    const double mm = d->mass[0];
+    const double c[3] = {d->com[0], d->com[1], d->com[2]};
+    const float* in = d->inertia;
+    const double Ic[9] = {in[0], in[3], in[4], in[3], in[1], in[5], in[4], in[5], in[2]};
+    const double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+    double full[6][6] = {};
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) full[r][q] = Ic[r * 3 + q] + mm * ((r == q ? c2 : 0) - c[r] * c[q]);
+    const double cx[9] = {0, -c[2], c[1], c[2], 0, -c[0], -c[1], c[0], 0};
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) { full[r][q + 3] = mm * cx[r * 3 + q]; full[q + 3][r] = full[r][q + 3]; }
+    for (int r = 0; r < 3; ++r) full[r + 3][r + 3] = mm;
+    int e = 0;
+    for (int r = 0; r < 6; ++r)
+      for (int q = r; q < 6; ++q) M.base_I[e++] = (float)full[r][q];
+  }
+  m->nq = fb ? 7 + nu : nu;
+  m->nv = fb ? 6 + nu : nu;
+  hipError_t e1 = hipGetDevice(&m->device);
+  hipError_t e2 = e1 == hipSuccess ? hipMalloc(&m->dev, sizeof(DevModel)) : e1;
+  hipError_t e3 = e2 == hipSuccess ? hipMemcpy(m->dev, &M, sizeof(DevModel), hipMemcpyHostToDevice) : e2;
+  if (e3 != hipSuccess) {
+    if (m->dev) (void)hipFree(m->dev);
+    delete m;
+    return fail(MPPI_EDEVICE, std::string("model upload: ") + hipGetErrorString(e3));
+  }
+  *out = m;
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_model_destroy(mppi_model* m) {
+  if (!m) return fail(MPPI_EINVAL, "null model");
+  if (m->dev) (void)hipFree(m->dev);
+  delete m;
+  return MPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+static void free_ctx_buffers(mppi_ctx* c) {
+  void* ptrs[] = {c->sigma, c->x0, c->nom, c->samples, c->costs, c->best_state, c->f0z, c->q0,
+                  c->tick, c->d_insts, c->d_ups};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+static void build_tables(mppi_ctx* c) {
+  const DevModel& M = c->m->host;
+  c->h_insts.assign(c->I, DevInst{});
+  c->h_ups.assign(c->I, DevUpdate{});
+  for (int it = 0; it < c->I; ++it) {
+    DevInst& d = c->h_insts[it];
+    d.model = c->m->dev;
+    d.sigma = c->sigma;
+    d.x0 = c->x0;
+    d.nominal = c->nom + (size_t)(it == 0 ? 0 : 1 + (it % 2)) * c->E;
+    d.samples = c->samples;
+    d.costs = c->costs + (size_t)it * c->N;
+    d.masks = nullptr;
+    d.f0z = c->f0z;
+    d.q0 = c->q0;
+    d.N = c->N; d.H = c->H; d.K = c->K; d.nu = c->nu; d.E = c->E; d.iter = it; d.n_iters = c->I;
+    d.cost_kind = c->p.cost_kind; d.lanes = c->lanes; d.weight_mode = c->p.weight_mode;
+    d.tick_ptr = c->tick; d.tick_value = 0; d.use_tick_value = 0;
+    d.seed_lo = (uint32_t)(c->seed & 0xffffffffu); d.seed_hi = (uint32_t)(c->seed >> 32);
+    d.dt = c->p.dt; d.delta = c->delta; d.lambda = c->p.lambda;
+    d.w_h = c->p.w_h; d.w_or = c->p.w_or; d.w_q = c->p.w_q; d.w_cv = c->p.w_cv; d.w_cf = c->p.w_cf;
+    d.w_eff = c->p.w_eff; d.w_H = c->p.w_H; d.w_ee = c->p.w_ee; d.w_tau = c->p.w_tau; d.z_des = c->p.z_des;
+    for (int k = 0; k < 3; ++k) d.v_des[k] = c->p.v_des[k];
+    d.generate = 1;
+    (void)M;
+    DevUpdate& u = c->h_ups[it];
+    u.costs = d.costs;
+    u.samples = c->samples;
+    u.nominal_in = d.nominal;
+    u.nominal_out = c->nom + (size_t)(1 + ((it + 1) % 2)) * c->E;
+    u.weights = nullptr;
+    u.best_knots = nullptr;
+    u.info = nullptr;
+    u.best_state = c->best_state;
+    u.tick = c->tick;
+    u.N = c->N; u.E = c->E; u.iter = it; u.weight_mode = c->p.weight_mode;
+    u.first_iter = it == 0; u.last_iter = it == c->I - 1;
+    u.lambda = c->p.lambda;
+  }
+}
+
+extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, uint64_t seed, mppi_ctx** out) {
+  if (!m || !p || !out) return fail(MPPI_EINVAL, "null argument");
+  if (p->n_samples < 1 || p->n_samples > 65536) return fail(MPPI_EINVAL, "n_samples must be in 1..65536");
+  if (p->horizon < 1 || p->horizon > 4096) return fail(MPPI_EINVAL, "horizon must be in 1..4096");
+  if (p->n_knots < 2 || p->n_knots > kMaxKnots) return fail(MPPI_EINVAL, "n_knots must be in 2..64");
+  if (p->n_iters < 1 || p->n_iters > 64) return fail(MPPI_EINVAL, "n_iters must be in 1..64");
+  if (!(p->dt > 0.f) || !(p->lambda > 0.f)) return fail(MPPI_EINVAL, "dt and lambda must be positive");
+  if (p->weight_mode != 0 && p->weight_mode != 1) return fail(MPPI_EINVAL, "weight_mode must be 0 or 1");
+  if (p->noise_mode != 0 && p->noise_mode != 1) return fail(MPPI_EINVAL, "noise_mode must be 0 or 1");
+  if (p->noise_mode == 0 && !(p->beta1 > 0.f && p->beta2 > 0.f)) return fail(MPPI_EINVAL, "beta1, beta2 must be positive");
+  const DevModel& M = m->host;
+  if (p->cost_kind == 0 && M.ee_body < 0) return fail(MPPI_EINVAL, "end-effector cost needs ee_body");
+  if (p->cost_kind == 1 && !M.fb) return fail(MPPI_EINVAL, "locomotion cost needs a floating base");
+  if (p->cost_kind != 0 && p->cost_kind != 1) return fail(MPPI_EINVAL, "cost_kind must be 0 or 1");
+  if (p->cost_kind == 1 && (!p->q0_cost || (M.nc > 0 && !p->f0z))) return fail(MPPI_EINVAL, "null q0_cost / f0z");
+  if ((long)p->horizon * M.nsub * (p->n_knots - 1) >= (1L << 30)) return fail(MPPI_EINVAL, "horizon too long");
+  auto* c = new mppi_ctx();
+  c->m = m; c->p = *p; c->seed = seed;
+  c->N = p->n_samples; c->H = p->horizon; c->K = p->n_knots; c->I = p->n_iters;
+  c->nu = M.nu; c->E = 2 * c->K * c->nu; c->nq = m->nq; c->nv = m->nv; c->nc = M.nc;
+  c->delta = (float)((double)p->horizon * (double)p->dt / (double)(p->n_knots - 1));
+  c->lanes = next_pow2(M.nb);
+  c->p.f0z = nullptr; c->p.q0_cost = nullptr;
+  auto bail = [&](hipError_t e, const char* what) {
+    free_ctx_buffers(c);
+    delete c;
+    return fail(MPPI_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&c->device)) != hipSuccess) return bail(e, "hipGetDevice");
+  // noise schedule in FP64, stored as float (Sec. III-B: precomputed once)
+  std::vector<float> sig((size_t)c->I * c->K);
+  for (int it = 0; it < c->I; ++it)
+    for (int k = 0; k < c->K; ++k) {
+      double s;
+      if (p->noise_mode == 0)
+        s = (double)p->scale_q * std::exp(-(double)it / ((double)p->beta1 * c->I) - (double)(c->K - k) / ((double)p->beta2 * c->K));
+      else
+        s = (double)p->sigma_lo + ((double)p->sigma_hi - (double)p->sigma_lo) * (double)k / (double)(c->K - 1);
+      sig[(size_t)it * c->K + k] = (float)s;
+    }
+  const size_t E = c->E;
+  if ((e = hipMalloc(&c->sigma, sig.size() * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc sigma");
+  if ((e = hipMalloc(&c->x0, (c->nq + c->nv) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc x0");
+  if ((e = hipMalloc(&c->nom, 3 * E * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc nominal");
+  if ((e = hipMalloc(&c->samples, (size_t)c->N * E * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc samples");
+  if ((e = hipMalloc(&c->costs, (size_t)c->I * c->N * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc costs");
+  if ((e = hipMalloc(&c->best_state, (E + 4) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc best");
+  if ((e = hipMalloc(&c->f0z, std::max(M.nc, 1) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc f0z");
+  if ((e = hipMalloc(&c->q0, c->nu * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc q0");
+  if ((e = hipMalloc(&c->tick, sizeof(uint32_t))) != hipSuccess) return bail(e, "hipMalloc tick");
+  if ((e = hipMalloc(&c->d_insts, c->I * sizeof(DevInst))) != hipSuccess) return bail(e, "hipMalloc insts");
+  if ((e = hipMalloc(&c->d_ups, c->I * sizeof(DevUpdate))) != hipSuccess) return bail(e, "hipMalloc ups");
+  std::vector<float> f0(std::max(M.nc, 1), 0.f), q0(c->nu, 0.f);
+  if (p->f0z)
+    for (int i = 0; i < M.nc; ++i) f0[i] = p->f0z[i];
+  if (p->q0_cost)
+    for (int i = 0; i < c->nu; ++i) q0[i] = p->q0_cost[i];
+  const uint32_t zero = 0;
+  if ((e = hipMemcpy(c->sigma, sig.data(), sig.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload sigma");
+  if ((e = hipMemcpy(c->f0z, f0.data(), f0.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload f0z");
+  if ((e = hipMemcpy(c->q0, q0.data(), q0.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload q0");
+  if ((e = hipMemcpy(c->tick, &zero, sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload tick");
+  build_tables(c);
+  if ((e = hipMemcpy(c->d_insts, c->h_insts.data(), c->I * sizeof(DevInst), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload insts");
+  if ((e = hipMemcpy(c->d_ups, c->h_ups.data(), c->I * sizeof(DevUpdate), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload ups");
+  *out = c;
+  return MPPI_OK;
+}
+
+static void purge_plans(const mppi_ctx* c);
+
+extern "C" mppi_status mppi_destroy(mppi_ctx* c) {
+  if (!c) return fail(MPPI_EINVAL, "null context");
+  purge_plans(c);
+  free_ctx_buffers(c);
+  delete c;
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_set_tick(mppi_ctx* c, uint32_t tick) {
+  if (!c) return fail(MPPI_EINVAL, "null context");
+  HIP_TRY(hipMemcpy(c->tick, &tick, sizeof(uint32_t), hipMemcpyHostToDevice));
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_get_tick(const mppi_ctx* c, uint32_t* tick) {
+  if (!c || !tick) return fail(MPPI_EINVAL, "null argument");
+  HIP_TRY(hipMemcpy(tick, c->tick, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_set_lanes_per_rollout(mppi_ctx* c, int32_t lanes) {
+  if (!c) return fail(MPPI_EINVAL, "null context");
+  const int G = lanes == 0 ? next_pow2(c->m->host.nb) : lanes;
+  if (!valid_lanes(G, c->m->host)) return fail(MPPI_EINVAL, "lanes must be a power of two in 4..64 holding every body");
+  c->lanes = G;
+  for (auto& d : c->h_insts) d.lanes = G;
+  HIP_TRY(hipMemcpy(c->d_insts, c->h_insts.data(), c->I * sizeof(DevInst), hipMemcpyHostToDevice));
+  purge_plans(c);
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_get_lanes_per_rollout(const mppi_ctx* c, int32_t* lanes) {
+  if (!c || !lanes) return fail(MPPI_EINVAL, "null argument");
+  *lanes = c->lanes;
+  return MPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+template <int G>
+static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2* work, int E_max, hipStream_t s) {
+  const int stride = group_floats(G, E_max);
+  hipLaunchKernelGGL(rollout_kernel<G>, dim3(blocks), dim3(64), lds_bytes(G, E_max), s, insts, work, stride);
+  return hipGetLastError();
+}
+
+static hipError_t launch_rollout(int G, int blocks, const DevInst* insts, const int2* work, int E_max, hipStream_t s) {
+  switch (G) {
+    case 4: return launch_rollout_G<4>(blocks, insts, work, E_max, s);
+    case 8: return launch_rollout_G<8>(blocks, insts, work, E_max, s);
+    case 16: return launch_rollout_G<16>(blocks, insts, work, E_max, s);
+    case 32: return launch_rollout_G<32>(blocks, insts, work, E_max, s);
+    default: return launch_rollout_G<64>(blocks, insts, work, E_max, s);
+  }
+}
+
+extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float* d_knots_in, float* d_knots_out,
+                                 float* d_best_knots, mppi_step_info* d_info, float* d_costs, void* stream) {
+  if (!c || !d_state || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(c->x0, d_state, (c->nq + c->nv) * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->nom, d_knots_in, c->E * sizeof(float), hipMemcpyDeviceToDevice, s));
+  const int R = 64 / c->lanes;
+  const int blocks = (c->N + R - 1) / R;
+  for (int it = 0; it < c->I; ++it) {
+    HIP_TRY(launch_rollout(c->lanes, blocks, c->d_insts + it, nullptr, c->E, s));
+    UpdateOut o{nullptr, nullptr, nullptr};
+    const UpdateOut* op = nullptr;
+    if (it == c->I - 1) {
+      o = UpdateOut{d_knots_out, d_best_knots, d_info};
+      op = nullptr;
+    }
+    hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, s, c->d_ups + it, op, o);
+    HIP_TRY(hipGetLastError());
+  }
+  if (d_costs) HIP_TRY(hipMemcpyAsync(d_costs, c->costs, (size_t)c->I * c->N * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return MPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched steps: cached launch plans keyed by the instance list
+// ---------------------------------------------------------------------------
+namespace {
+struct GroupLaunch {
+  int G = 0, blocks = 0, E_max = 0;
+  int2* work = nullptr;  // device [blocks]
+};
+struct IterPlan {
+  DevInst* insts = nullptr;     // device, indexed by work.x
+  DevUpdate* ups = nullptr;     // device [n_active]
+  std::vector<int> active;      // instance indices (into the batch) active in this iteration
+  std::vector<GroupLaunch> groups;
+};
+struct Plan {
+  std::vector<const mppi_ctx*> ctxs;
+  int device = 0;
+  std::vector<IterPlan> iters;
+  ~Plan() {
+    for (auto& it : iters) {
+      if (it.insts) (void)hipFree(it.insts);
+      if (it.ups) (void)hipFree(it.ups);
+      for (auto& g : it.groups)
+        if (g.work) (void)hipFree(g.work);
+    }
+  }
+};
+// per-call argument block uploaded through a pinned ring
+struct RingSlot {
+  void* host = nullptr;
+  void* dev = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+std::mutex g_mu;
+std::vector<std::unique_ptr<Plan>> g_plans;
+std::vector<RingSlot> g_ring;
+int g_ring_next = 0;
+}  // namespace
+
+static void purge_plans(const mppi_ctx* c) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_plans.erase(std::remove_if(g_plans.begin(), g_plans.end(),
+                               [&](const std::unique_ptr<Plan>& p) {
+                                 return std::find(p->ctxs.begin(), p->ctxs.end(), c) != p->ctxs.end();
+                               }),
+                g_plans.end());
+}
+
+static mppi_status build_plan(const std::vector<const mppi_ctx*>& ctxs, Plan** out) {
+  auto plan = std::make_unique<Plan>();
+  plan->ctxs = ctxs;
+  HIP_TRY(hipGetDevice(&plan->device));
+  int Imax = 0;
+  for (auto* c : ctxs) Imax = std::max(Imax, c->I);
+  plan->iters.resize(Imax);
+  for (int it = 0; it < Imax; ++it) {
+    IterPlan& ip = plan->iters[it];
+    std::vector<DevInst> hi;
+    std::vector<DevUpdate> hu;
+    for (int i = 0; i < (int)ctxs.size(); ++i) {
+      if (ctxs[i]->I <= it) continue;
+      ip.active.push_back(i);
+      hi.push_back(ctxs[i]->h_insts[it]);
+      hu.push_back(ctxs[i]->h_ups[it]);
+    }
+    HIP_TRY(hipMalloc(&ip.insts, hi.size() * sizeof(DevInst)));
+    HIP_TRY(hipMemcpy(ip.insts, hi.data(), hi.size() * sizeof(DevInst), hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&ip.ups, hu.size() * sizeof(DevUpdate)));
+    HIP_TRY(hipMemcpy(ip.ups, hu.data(), hu.size() * sizeof(DevUpdate), hipMemcpyHostToDevice));
+    // one launch per lane count; inside it the longest rollouts first
+    std::map<int, std::vector<int>> byG;
+    for (int a = 0; a < (int)ip.active.size(); ++a) byG[ctxs[ip.active[a]]->lanes].push_back(a);
+    for (auto& kv : byG) {
+      GroupLaunch gl;
+      gl.G = kv.first;
+      const int R = 64 / gl.G;
+      std::vector<int> order = kv.second;
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const mppi_ctx* cx = ctxs[ip.active[x]];
+        const mppi_ctx* cy = ctxs[ip.active[y]];
+        return (long)cx->H * cx->m->host.nsub * cx->m->host.nb > (long)cy->H * cy->m->host.nsub * cy->m->host.nb;
+      });
+      std::vector<int2> work;
+      for (int a : order) {
+        const mppi_ctx* c = ctxs[ip.active[a]];
+        gl.E_max = std::max(gl.E_max, c->E);
+        for (int n0 = 0; n0 < c->N; n0 += R) work.push_back(make_int2(a, n0));
+      }
+      gl.blocks = (int)work.size();
+      HIP_TRY(hipMalloc(&gl.work, work.size() * sizeof(int2)));
+      HIP_TRY(hipMemcpy(gl.work, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice));
+      ip.groups.push_back(gl);
+    }
+  }
+  *out = plan.get();
+  g_plans.push_back(std::move(plan));
+  if (g_plans.size() > 32) g_plans.erase(g_plans.begin());
+  return MPPI_OK;
+}
+
+static mppi_status ring_slot(size_t bytes, RingSlot** out) {
+  if (g_ring.empty()) g_ring.resize(8);
+  RingSlot& r = g_ring[g_ring_next];
+  g_ring_next = (g_ring_next + 1) % (int)g_ring.size();
+  if (r.pending) {
+    HIP_TRY(hipEventSynchronize(r.ev));
+    r.pending = false;
+  }
+  if (r.cap < bytes) {
+    if (r.host) (void)hipHostFree(r.host);
+    if (r.dev) (void)hipFree(r.dev);
+    r.host = r.dev = nullptr;
+    size_t cap = std::max<size_t>(bytes, 4096);
+    HIP_TRY(hipHostMalloc(&r.host, cap));
+    HIP_TRY(hipMalloc(&r.dev, cap));
+    r.cap = cap;
+  }
+  if (!r.ev) HIP_TRY(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
+  *out = &r;
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const float* const* d_states,
+                                       const float* const* d_knots_in, float* const* d_knots_out,
+                                       float* const* d_best_knots, mppi_step_info* const* d_infos, void* stream) {
+  if (n < 1 || !ctxs || !d_states || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
+  std::vector<const mppi_ctx*> list(n);
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !d_states[i] || !d_knots_in[i] || !d_knots_out[i]) return fail(MPPI_EINVAL, "null entry");
+    list[i] = ctxs[i];
+    for (int k = 0; k < i; ++k)
+      if (list[k] == list[i]) return fail(MPPI_EINVAL, "an instance appears twice in one batch");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Plan* plan = nullptr;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  for (auto& p : g_plans)
+    if (p->ctxs == list && p->device == dev) { plan = p.get(); break; }
+  if (!plan) {
+    mppi_status st = build_plan(list, &plan);
+    if (st != MPPI_OK) return st;
+  }
+  // per-call block: stage items [2n], then per-iteration output tables
+  const int Imax = (int)plan->iters.size();
+  size_t n_out = 0;
+  for (auto& ip : plan->iters) n_out += ip.active.size();
+  const size_t bytes = 2 * n * sizeof(StageItem) + n_out * sizeof(UpdateOut);
+  RingSlot* r = nullptr;
+  mppi_status st = ring_slot(bytes, &r);
+  if (st != MPPI_OK) return st;
+  auto* items = reinterpret_cast<StageItem*>(r->host);
+  for (int i = 0; i < n; ++i) {
+    items[2 * i] = StageItem{d_states[i], list[i]->x0, list[i]->nq + list[i]->nv};
+    items[2 * i + 1] = StageItem{d_knots_in[i], list[i]->nom, list[i]->E};
+  }
+  auto* outs = reinterpret_cast<UpdateOut*>(items + 2 * n);
+  std::vector<size_t> out_off(Imax);
+  size_t off = 0;
+  for (int it = 0; it < Imax; ++it) {
+    out_off[it] = off;
+    for (int a : plan->iters[it].active) {
+      const bool last = list[a]->I - 1 == it;
+      outs[off++] = last ? UpdateOut{d_knots_out[a], d_best_knots ? d_best_knots[a] : nullptr,
+                                     d_infos ? (void*)d_infos[a] : nullptr}
+                         : UpdateOut{nullptr, nullptr, nullptr};
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(r->dev, r->host, bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(r->ev, s));
+  r->pending = true;
+  auto* d_items = reinterpret_cast<StageItem*>(r->dev);
+  auto* d_outs = reinterpret_cast<UpdateOut*>(d_items + 2 * n);
+  hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(256), 0, s, d_items);
+  HIP_TRY(hipGetLastError());
+  for (int it = 0; it < Imax; ++it) {
+    IterPlan& ip = plan->iters[it];
+    for (auto& g : ip.groups) HIP_TRY(launch_rollout(g.G, g.blocks, ip.insts, g.work, g.E_max, s));
+    hipLaunchKernelGGL(update_kernel, dim3((unsigned)ip.active.size()), dim3(256), 0, s, ip.ups, d_outs + out_off[it],
+                       UpdateOut{nullptr, nullptr, nullptr});
+    HIP_TRY(hipGetLastError());
+  }
+  return MPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// verification entry points
+// ---------------------------------------------------------------------------
+extern "C" mppi_status mppi_debug_philox(const uint32_t* d_ctr, const uint32_t* d_key, uint32_t* d_out, int32_t n,
+                                         void* stream) {
+  if (n < 0 || (n > 0 && (!d_ctr || !d_key || !d_out))) return fail(MPPI_EINVAL, "bad arguments");
+  if (n == 0) return MPPI_OK;
+  hipLaunchKernelGGL(philox_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, d_ctr, d_key, d_out, n);
+  HIP_TRY(hipGetLastError());
+  return MPPI_OK;
+}
+
+template <int G>
+static hipError_t launch_samples_G(const DevInst* inst, int N, int E, hipStream_t s) {
+  const int R = 64 / G;
+  hipLaunchKernelGGL(sample_kernel<G>, dim3((N + R - 1) / R), dim3(64), lds_bytes(G, E), s, inst, group_floats(G, E));
+  return hipGetLastError();
+}
+
+// A scratch DevInst (device) for verification launches, released after the stream drains.
+static mppi_status debug_inst(const DevInst& h, hipStream_t s, DevInst** out) {
+  DevInst* d = nullptr;
+  HIP_TRY(hipMalloc(&d, sizeof(DevInst)));
+  HIP_TRY(hipMemcpyAsync(d, &h, sizeof(DevInst), hipMemcpyHostToDevice, s));
+  *out = d;
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_debug_samples(mppi_ctx* c, const float* d_knots_in, int32_t iter, uint32_t tick,
+                                          float* d_samples, void* stream) {
+  if (!c || !d_knots_in || !d_samples || iter < 0 || iter >= c->I) return fail(MPPI_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  DevInst h = c->h_insts[iter];
+  h.nominal = d_knots_in;
+  h.samples = d_samples;
+  h.use_tick_value = 1;
+  h.tick_value = tick;
+  DevInst* d = nullptr;
+  mppi_status st = debug_inst(h, s, &d);
+  if (st != MPPI_OK) return st;
+  hipError_t e;
+  switch (c->lanes) {
+    case 4: e = launch_samples_G<4>(d, c->N, c->E, s); break;
+    case 8: e = launch_samples_G<8>(d, c->N, c->E, s); break;
+    case 16: e = launch_samples_G<16>(d, c->N, c->E, s); break;
+    case 32: e = launch_samples_G<32>(d, c->N, c->E, s); break;
+    default: e = launch_samples_G<64>(d, c->N, c->E, s); break;
+  }
+  HIP_TRY(e);
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipFree(d));
+  return MPPI_OK;
+}
+
+template <int G>
+static hipError_t launch_dyn_G(const mppi_model* m, int n, const float* q, const float* v, const float* qr,
+                               const float* vr, float dt, float* qdd, hipStream_t s) {
+  const int R = 64 / G;
+  hipLaunchKernelGGL(dynamics_kernel<G>, dim3((n + R - 1) / R), dim3(64), lds_bytes(G, 0), s, m->dev, n, q, v, qr, vr,
+                     dt, qdd, group_floats(G, 0));
+  return hipGetLastError();
+}
+
+extern "C" mppi_status mppi_debug_dynamics(const mppi_model* m, int32_t n, const float* d_q, const float* d_v,
+                                           const float* d_qref, const float* d_vref, float dt, float* d_qdd,
+                                           void* stream) {
+  if (!m || n < 0 || !(dt >= 0.f)) return fail(MPPI_EINVAL, "bad arguments");
+  if (n == 0) return MPPI_OK;
+  if (!d_q || !d_v || !d_qref || !d_vref || !d_qdd) return fail(MPPI_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const int G = next_pow2(m->host.nb);
+  hipError_t e;
+  switch (G) {
+    case 4: e = launch_dyn_G<4>(m, n, d_q, d_v, d_qref, d_vref, dt, d_qdd, s); break;
+    case 8: e = launch_dyn_G<8>(m, n, d_q, d_v, d_qref, d_vref, dt, d_qdd, s); break;
+    case 16: e = launch_dyn_G<16>(m, n, d_q, d_v, d_qref, d_vref, dt, d_qdd, s); break;
+    case 32: e = launch_dyn_G<32>(m, n, d_q, d_v, d_qref, d_vref, dt, d_qdd, s); break;
+    default: e = launch_dyn_G<64>(m, n, d_q, d_v, d_qref, d_vref, dt, d_qdd, s); break;
+  }
+  HIP_TRY(e);
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_debug_rollouts(mppi_ctx* c, const float* d_state, const float* d_samples, float* d_costs,
+                                           uint32_t* d_masks, void* stream) {
+  if (!c || !d_state || !d_samples || !d_costs) return fail(MPPI_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  DevInst h = c->h_insts[0];
+  h.x0 = d_state;
+  h.samples = const_cast<float*>(d_samples);
+  h.costs = d_costs;
+  h.masks = d_masks;
+  h.generate = 0;
+  DevInst* d = nullptr;
+  mppi_status st = debug_inst(h, s, &d);
+  if (st != MPPI_OK) return st;
+  const int R = 64 / c->lanes;
+  HIP_TRY(launch_rollout(c->lanes, (c->N + R - 1) / R, d, nullptr, c->E, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipFree(d));
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, const float* d_samples,
+                                         const float* d_knots_in, float* d_knots_out, float* d_weights, void* stream) {
+  if (!c || !d_costs || !d_samples || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  DevUpdate h = c->h_ups[0];
+  h.costs = d_costs;
+  h.samples = d_samples;
+  h.nominal_in = d_knots_in;
+  h.nominal_out = d_knots_out;
+  h.weights = d_weights;
+  h.first_iter = 1;
+  h.last_iter = 0;
+  h.tick = nullptr;
+  DevUpdate* d = nullptr;
+  HIP_TRY(hipMalloc(&d, sizeof(DevUpdate)));
+  HIP_TRY(hipMemcpyAsync(d, &h, sizeof(DevUpdate), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, s, d, nullptr, UpdateOut{nullptr, nullptr, nullptr});
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipFree(d));
+  return MPPI_OK;
+}
+
+extern "C" const char* mppi_last_error(void) { return g_err.c_str(); }
+extern "C" const char* mppi_version(void) { return "mppi-gfx950 0.1"; }

@@ -1,0 +1,282 @@
+"""ctypes binding of libmppi.so (the C ABI declared in include/mppi.h).
+
+Argument marshalling only: every step of the controller runs in the HIP
+kernels of the library.  Device buffers are torch CUDA (HIP) tensors; streams
+are torch streams.  The library is loaded on first use and a missing or
+unloadable library raises -- there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmppi.so")
+_lib = None
+
+MPPI_OK = 0
+
+
+class MppiError(RuntimeError):
+    pass
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [
+        ("n_bodies", C.c_int32), ("floating_base", C.c_int32), ("parent", C.POINTER(C.c_int32)),
+        ("axis", C.POINTER(C.c_float)), ("R_tree", C.POINTER(C.c_float)),
+        ("p_tree", C.POINTER(C.c_float)), ("mass", C.POINTER(C.c_float)),
+        ("com", C.POINTER(C.c_float)), ("inertia", C.POINTER(C.c_float)),
+        ("q_min", C.POINTER(C.c_float)), ("q_max", C.POINTER(C.c_float)),
+        ("tau_max", C.POINTER(C.c_float)), ("kp", C.POINTER(C.c_float)),
+        ("kd", C.POINTER(C.c_float)), ("n_contacts", C.c_int32),
+        ("contact_body", C.POINTER(C.c_int32)), ("contact_pos", C.POINTER(C.c_float)),
+        ("k_contact", C.c_float), ("d_contact", C.c_float), ("mu", C.c_float),
+        ("eps_fric", C.c_float), ("gravity", C.c_float), ("ee_body", C.c_int32),
+        ("ee_pos", C.c_float * 3), ("n_substeps", C.c_int32),
+        ("armature", C.POINTER(C.c_float)),
+    ]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_samples", C.c_int32), ("horizon", C.c_int32), ("n_knots", C.c_int32),
+        ("n_iters", C.c_int32), ("dt", C.c_float), ("lam", C.c_float),
+        ("weight_mode", C.c_int32), ("noise_mode", C.c_int32), ("scale_q", C.c_float),
+        ("beta1", C.c_float), ("beta2", C.c_float), ("sigma_lo", C.c_float),
+        ("sigma_hi", C.c_float), ("cost_kind", C.c_int32), ("w_h", C.c_float),
+        ("w_or", C.c_float), ("w_q", C.c_float), ("w_cv", C.c_float), ("w_cf", C.c_float),
+        ("w_eff", C.c_float), ("w_H", C.c_float), ("w_ee", C.c_float), ("w_tau", C.c_float),
+        ("z_des", C.c_float), ("v_des", C.c_float * 3), ("f0z", C.POINTER(C.c_float)),
+        ("q0_cost", C.POINTER(C.c_float)),
+    ]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("S_best", C.c_float), ("best_iter", C.c_int32), ("n_nonfinite", C.c_int32),
+                ("all_nonfinite_iters", C.c_int32)]
+
+
+EXPORTS = [
+    "mppi_model_create", "mppi_model_destroy", "mppi_create", "mppi_destroy", "mppi_set_tick",
+    "mppi_get_tick", "mppi_set_lanes_per_rollout", "mppi_get_lanes_per_rollout", "mppi_step",
+    "mppi_step_batch", "mppi_debug_philox", "mppi_debug_samples", "mppi_debug_dynamics",
+    "mppi_debug_rollouts", "mppi_debug_update", "mppi_last_error", "mppi_version",
+]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MppiError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u32, u64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64
+        L.mppi_model_create.argtypes = [C.POINTER(ModelDesc), C.POINTER(vp)]
+        L.mppi_model_destroy.argtypes = [vp]
+        L.mppi_create.argtypes = [vp, C.POINTER(Params), u64, C.POINTER(vp)]
+        L.mppi_destroy.argtypes = [vp]
+        L.mppi_set_tick.argtypes = [vp, u32]
+        L.mppi_get_tick.argtypes = [vp, C.POINTER(u32)]
+        L.mppi_set_lanes_per_rollout.argtypes = [vp, i32]
+        L.mppi_get_lanes_per_rollout.argtypes = [vp, C.POINTER(i32)]
+        L.mppi_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.mppi_step_batch.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp]
+        L.mppi_debug_philox.argtypes = [vp, vp, vp, i32, vp]
+        L.mppi_debug_samples.argtypes = [vp, vp, i32, u32, vp, vp]
+        L.mppi_debug_dynamics.argtypes = [vp, i32, vp, vp, vp, vp, C.c_float, vp, vp]
+        L.mppi_debug_rollouts.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mppi_debug_update.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.mppi_last_error.restype = C.c_char_p
+        L.mppi_version.restype = C.c_char_p
+        for name in EXPORTS[:-2]:
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != MPPI_OK:
+        raise MppiError(f"{what} failed ({rc}): {lib().mppi_last_error().decode()}")
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the library must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _farr(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1))
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _iarr(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class Model:
+    """Device-resident kinematic tree built from a synth model dict."""
+
+    def __init__(self, m):
+        keep = []
+        d = ModelDesc()
+        nb = len(m["parent"])
+        d.n_bodies = nb
+        d.floating_base = 1 if m["floating_base"] else 0
+        a, d.parent = _iarr(m["parent"]); keep.append(a)
+        for name in ("axis", "R_tree", "p_tree", "mass", "com", "inertia", "q_min", "q_max",
+                     "tau_max", "kp", "kd"):
+            a, p = _farr(m[name]); keep.append(a); setattr(d, name, p)
+        nc = len(m["contact_body"])
+        d.n_contacts = nc
+        a, d.contact_body = _iarr(m["contact_body"] if nc else [0]); keep.append(a)
+        a, d.contact_pos = _farr(m["contact_pos"] if nc else [0, 0, 0]); keep.append(a)
+        d.k_contact, d.d_contact = m["k_contact"], m["d_contact"]
+        d.mu, d.eps_fric, d.gravity = m["mu"], m["eps_fric"], m["gravity"]
+        d.ee_body = int(m["ee_body"])
+        for k in range(3):
+            d.ee_pos[k] = float(m["ee_pos"][k])
+        d.n_substeps = int(m.get("n_substeps", 1))
+        a, d.armature = _farr(m.get("armature", np.zeros(m["n_u"]))); keep.append(a)
+        h = C.c_void_p()
+        _check(lib().mppi_model_create(C.byref(d), C.byref(h)), "mppi_model_create")
+        self.h = h
+        self.nb = nb
+        self.nu = m["n_u"]
+        self.nq = m["n_q"]
+        self.nv = m["n_v"]
+        self.nc = nc
+
+    def close(self):
+        if self.h:
+            _check(lib().mppi_model_destroy(self.h), "mppi_model_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dynamics(self, q, v, qref, vref, dt, out, stream=None):
+        """Accelerations of one physics step for a batch of states (device tensors)."""
+        n = q.shape[0]
+        _check(lib().mppi_debug_dynamics(self.h, n, _ptr(q), _ptr(v), _ptr(qref), _ptr(vref),
+                                         float(dt), _ptr(out), _stream(stream)),
+               "mppi_debug_dynamics")
+
+
+def make_params(p):
+    s = Params()
+    for name in ("n_samples", "horizon", "n_knots", "n_iters", "weight_mode", "noise_mode",
+                 "cost_kind"):
+        setattr(s, name, int(p[name]))
+    for name in ("dt", "scale_q", "beta1", "beta2", "sigma_lo", "sigma_hi", "w_h", "w_or",
+                 "w_q", "w_cv", "w_cf", "w_eff", "w_H", "w_ee", "w_tau", "z_des"):
+        setattr(s, name, float(p[name]))
+    s.lam = float(p["lambda"])
+    for k in range(3):
+        s.v_des[k] = float(p["v_des"][k])
+    f0, s.f0z = _farr(p["f0z"] if len(p["f0z"]) else [0.0])
+    q0, s.q0_cost = _farr(p["q0_cost"])
+    return s, (f0, q0)
+
+
+class Controller:
+    """One MPC instance (mppi_ctx)."""
+
+    def __init__(self, model, params, seed, lanes=0):
+        self.model = model
+        self.params = dict(params)
+        s, self._keep = make_params(params)
+        h = C.c_void_p()
+        _check(lib().mppi_create(model.h, C.byref(s), C.c_uint64(seed), C.byref(h)), "mppi_create")
+        self.h = h
+        self.N, self.H, self.K, self.I = (params["n_samples"], params["horizon"],
+                                          params["n_knots"], params["n_iters"])
+        self.E = 2 * self.K * model.nu
+        if lanes:
+            self.set_lanes(lanes)
+
+    def close(self):
+        if self.h:
+            _check(lib().mppi_destroy(self.h), "mppi_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def tick(self):
+        t = C.c_uint32()
+        _check(lib().mppi_get_tick(self.h, C.byref(t)), "mppi_get_tick")
+        return t.value
+
+    @tick.setter
+    def tick(self, value):
+        _check(lib().mppi_set_tick(self.h, C.c_uint32(value)), "mppi_set_tick")
+
+    @property
+    def lanes(self):
+        g = C.c_int32()
+        _check(lib().mppi_get_lanes_per_rollout(self.h, C.byref(g)), "mppi_get_lanes_per_rollout")
+        return g.value
+
+    def set_lanes(self, lanes):
+        _check(lib().mppi_set_lanes_per_rollout(self.h, int(lanes)), "mppi_set_lanes_per_rollout")
+
+    def step(self, state, knots_in, knots_out, best_knots=None, info=None, costs=None, stream=None):
+        _check(lib().mppi_step(self.h, _ptr(state), _ptr(knots_in), _ptr(knots_out),
+                               _ptr(best_knots), _ptr(info), _ptr(costs), _stream(stream)),
+               "mppi_step")
+
+    def samples(self, knots_in, iteration, tick, out, stream=None):
+        _check(lib().mppi_debug_samples(self.h, _ptr(knots_in), int(iteration), C.c_uint32(tick),
+                                        _ptr(out), _stream(stream)), "mppi_debug_samples")
+
+    def rollouts(self, state, samples, costs, masks=None, stream=None):
+        _check(lib().mppi_debug_rollouts(self.h, _ptr(state), _ptr(samples), _ptr(costs),
+                                         _ptr(masks), _stream(stream)), "mppi_debug_rollouts")
+
+    def update(self, costs, samples, knots_in, knots_out, weights=None, stream=None):
+        _check(lib().mppi_debug_update(self.h, _ptr(costs), _ptr(samples), _ptr(knots_in),
+                                       _ptr(knots_out), _ptr(weights), _stream(stream)),
+               "mppi_debug_update")
+
+
+def step_batch(ctrls, states, knots_in, knots_out, best_knots=None, infos=None, stream=None):
+    """Fused step of several controllers (lists of equal length)."""
+    n = len(ctrls)
+    arr = lambda xs: (C.c_void_p * n)(*[x.h if isinstance(x, Controller) else (x.data_ptr() if x is not None else None) for x in xs])  # noqa: E731
+    hs = arr(ctrls)
+    st = arr(states)
+    ki = arr(knots_in)
+    ko = arr(knots_out)
+    bk = arr(best_knots) if best_knots is not None else None
+    inf = arr(infos) if infos is not None else None
+    _check(lib().mppi_step_batch(n, hs, st, ki, ko, bk, inf, _stream(stream)), "mppi_step_batch")
+
+
+def philox(ctr, key, out, stream=None):
+    n = ctr.shape[0]
+    _check(lib().mppi_debug_philox(_ptr(ctr), _ptr(key), _ptr(out), n, _stream(stream)),
+           "mppi_debug_philox")
+
+
+def version():
+    return lib().mppi_version().decode()

@@ -19,7 +19,8 @@ device path and the FP64 oracle start from identical numbers.
 Model dict keys: floating_base, parent[nb], axis[nb,3], R_tree[nb,3,3],
 p_tree[nb,3], mass[nb], com[nb,3], inertia[nb,6] (xx yy zz xy xz yz about the
 com), q_min/q_max/tau_max/kp/kd/q0[n_u], contact_body[nc], contact_pos[nc,3],
-k_contact, d_contact, mu, eps_fric, gravity, ee_body, ee_pos[3], x0[nq+nv].
+k_contact, d_contact, mu, eps_fric, gravity, ee_body, ee_pos[3], n_substeps,
+armature[n_u] (reflected rotor inertia per joint), x0[nq+nv].
 """
 import numpy as np
 
@@ -113,6 +114,7 @@ def chain_model(seed=0):
                       joint=(-2.5, 2.5, 30.0, 30.0, 0.3, 0.0))
     m = t.finish("chain3", False, [], np.zeros((0, 3)), ee_body=2, ee_pos=(L[2], 0, 0))
     m["n_substeps"] = 1
+    m["armature"] = f32(np.zeros(3))
     m["x0"] = f32(np.zeros(6))
     return m
 
@@ -145,6 +147,7 @@ def quadruped_model(seed=0):
     cpos = [(0.0, 0.0, -L)] * 4
     m = t.finish("quadruped18", True, feet, cpos)
     m["n_substeps"] = 1
+    m["armature"] = f32(np.full(m["n_u"], 0.01))
     m_tot = float(np.sum(m["mass"]))
     sink = m_tot * GRAVITY / (4 * m["k_contact"])
     z0 = 2 * L * np.cos(hip0) - sink
@@ -210,6 +213,7 @@ def humanoid_model(seed=0):
     cpos = cpos + [(0.0, 0.0, -Lf)] * 2
     m = t.finish("humanoid27", True, cbody, cpos)
     m["n_substeps"] = 1
+    m["armature"] = f32(np.full(m["n_u"], 0.02))
     m_tot = float(np.sum(m["mass"]))
     sink = m_tot * GRAVITY / (8 * m["k_contact"])
     depth = 0.06 + 0.05 + 0.05 + 2 * Lt * np.cos(bend) + 0.04 + hf

@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+entry point include/mppi.h declares, and rejects malformed arguments on the host
+before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2511_19204_amd import mppi, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mppi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mppi_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mppi.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(mppi.EXPORTS)
+    assert mppi.version().startswith("mppi")
+
+
+def _desc(m, **over):
+    d = mppi.ModelDesc()
+    keep = []
+    a, d.parent = mppi._iarr(over.get("parent", m["parent"])); keep.append(a)
+    for name in ("axis", "R_tree", "p_tree", "mass", "com", "inertia", "q_min", "q_max", "tau_max", "kp", "kd"):
+        a, p = mppi._farr(over.get(name, m[name])); keep.append(a); setattr(d, name, p)
+    d.n_bodies = over.get("n_bodies", len(m["parent"]))
+    d.floating_base = 1 if m["floating_base"] else 0
+    d.n_contacts = len(m["contact_body"])
+    a, d.contact_body = mppi._iarr(m["contact_body"] if d.n_contacts else [0]); keep.append(a)
+    a, d.contact_pos = mppi._farr(m["contact_pos"] if d.n_contacts else [0, 0, 0]); keep.append(a)
+    d.ee_body = over.get("ee_body", m["ee_body"])
+    d.n_substeps = over.get("n_substeps", 1)
+    d.gravity = 9.81
+    return d, keep
+
+
+@pytest.mark.parametrize("bad", [
+    {"n_bodies": 0}, {"n_bodies": 65}, {"n_substeps": 0}, {"ee_body": 7},
+    {"parent": [-1, 1, 1]}, {"mass": [1.0, -1.0, 1.0]},
+    {"axis": [[0, 2, 0]] * 3}, {"q_min": [1, 1, 1], "q_max": [0, 0, 0]},
+])
+def test_model_create_rejects_bad_descriptions(bad):
+    m = synth.chain_model(0)
+    d, keep = _desc(m, **bad)
+    h = C.c_void_p()
+    rc = mppi.lib().mppi_model_create(C.byref(d), C.byref(h))
+    assert rc == -1
+    assert len(mppi.lib().mppi_last_error()) > 0
+
+
+def test_null_arguments_are_rejected():
+    L = mppi.lib()
+    assert L.mppi_model_create(None, None) == -1
+    assert L.mppi_create(None, None, 0, None) == -1
+    assert L.mppi_step(None, None, None, None, None, None, None, None) == -1
+    assert L.mppi_step_batch(0, None, None, None, None, None, None, None) == -1
+    assert L.mppi_destroy(None) == -1
+    assert L.mppi_debug_philox(None, None, None, -1, None) == -1
+    assert L.mppi_debug_philox(None, None, None, 0, None) == 0

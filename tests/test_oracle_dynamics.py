@@ -132,6 +132,9 @@ def test_mass_matrix_equals_kinetic_energy_hessian(name):
         ref[i, i] = 2 * T1[i]
         for j in range(i):
             ref[i, j] = ref[j, i] = _kinetic_energy(m, q, E[i] + E[j]) - T1[i] - T1[j]
+    # rotor (armature) kinetic energy 1/2 I_a qd_j^2 adds to the joint diagonal
+    off = 6 if m["floating_base"] else 0
+    ref[off:, off:] += np.diag(np.asarray(m.get("armature", np.zeros(m["n_u"]))))
     assert np.allclose(Hm, Hm.T, atol=1e-14)
     assert np.max(np.abs(Hm - ref)) < 1e-7 * np.max(np.abs(ref))
 
