@@ -1,0 +1,270 @@
+#!/usr/bin/env python3
+"""Throughput and latency of the MPPI hot path on one MI355X.
+
+Primary workload (the throughput configuration): the 18-DoF quadruped tree,
+K = 4096 sampled knot sets, H = 200 control steps at dt = 5 ms, 8 knots per
+joint, one planning iteration per MPC step.  A step = one mppi_step call (knot
+sampling, all rollouts, weights, update, best tracking), inputs resident in HBM.
+value = rollout steps (K * H * I) per second over the timed steps.
+
+Also reported:
+  latency_ms       p50 / p99 of the primary step (HIP events on its stream);
+  batched_vs_plain 64 robots drawn from the serving mix (chain / quadruped /
+                   humanoid, K in 32..1024, H in 50..200, 3 iterations): one
+                   plain mppi_step per robot in sequence vs one fused
+                   mppi_step_batch, rollout-steps/s and per-robot tick latency;
+  roofline         the rollout kernel: algorithmic FP32 operations per launch
+                   (flops.flops_per_rollout_step x K x H) / its mean duration,
+                   against the FP32 vector peak (ALU-bound path);
+  cpu_baseline     the CPU oracle (FP64, OpenMP over samples) on a bounded sample
+                   of the same workload.
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rollout-steps/sec (K·H/s) + p50/p99 MPC-tick latency, batched vs plain, 1 GPU"
+FP32_PEAK_TFLOPS = 157.3        # MI355X FP32 vector (packed) peak
+FP32_PEAK_NONPACKED = 78.6      # one FP32 op per lane per cycle
+HBM_PEAK_GBS = 8000.0
+
+
+def _pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("mppi_kernels.hip", "mppi_dev.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2511_19204_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(digest):
+    """HBM bytes per rollout launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "rollout_quadruped_k4096_h200.pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_digest") != digest:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def primary(args, torch, mppi, synth, flops):
+    m, p, seed = synth.config("quadruped_tp", n_samples=args.samples)
+    model = mppi.Model(m)
+    ctrl = mppi.Controller(model, p, seed, lanes=args.lanes)
+    st = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
+    k0 = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
+    ka, kb = k0.clone(), torch.zeros_like(k0)
+    for _ in range(args.warmup):
+        ctrl.step(st, ka, kb)
+        ka, kb = kb, ka
+    torch.cuda.synchronize()
+    ctrl.profile(True)
+    ctrl.profile_read()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record(stream)
+        ctrl.step(st, ka, kb)
+        evs[i][1].record(stream)
+        ka, kb = kb, ka
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    roll_ms, n_roll, upd_ms, n_upd = ctrl.profile_read()
+    ctrl.profile(False)
+    lat = [a.elapsed_time(b) for a, b in evs]
+    N, H, I = p["n_samples"], p["horizon"], p["n_iters"]
+    steps_rollout = N * H * I
+    fl = flops.flops_per_rollout_step(m)
+    avg_roll_s = roll_ms / max(n_roll, 1) / 1e3
+    achieved = fl * N * H / avg_roll_s / 1e12
+    res = {
+        "model": m, "params": p, "ctrl": ctrl, "model_h": model,
+        "wall": wall, "value": steps_rollout * args.steps / wall, "lat": lat,
+        "kernel_ms": roll_ms / max(n_roll, 1), "update_ms": upd_ms / max(n_upd, 1),
+        "achieved_tflops": achieved, "flops_per_rollout_step": fl, "lanes": ctrl.lanes,
+    }
+    return res
+
+
+def batched_vs_plain(args, torch, mppi, synth):
+    robots = synth.serving_mix(args.robots, seed=0)
+    made = []
+    for (m, p, seed) in robots:
+        model = mppi.Model(m)
+        c = mppi.Controller(model, p, seed)
+        st = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
+        ki = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
+        ko = torch.zeros_like(ki)
+        made.append((model, c, st, ki, ko, p))
+    work = sum(p["n_samples"] * p["horizon"] * p["n_iters"] for (_, _, _, _, _, p) in made)
+    stream = torch.cuda.current_stream()
+    rounds = max(2, args.rounds)
+
+    def plain_round():
+        start = torch.cuda.Event(enable_timing=True)
+        ends = [torch.cuda.Event(enable_timing=True) for _ in made]
+        start.record(stream)
+        for i, (_, c, st, ki, ko, _) in enumerate(made):
+            c.step(st, ki, ko)
+            ends[i].record(stream)
+        return start, ends
+
+    ctrls = [c for (_, c, _, _, _, _) in made]
+    states = [st for (_, _, st, _, _, _) in made]
+    kins = [ki for (_, _, _, ki, _, _) in made]
+    kouts = [ko for (_, _, _, _, ko, _) in made]
+
+    def batched_round():
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        mppi.step_batch(ctrls, states, kins, kouts)
+        end.record(stream)
+        return start, [end] * len(made)
+
+    out = {}
+    for name, fn in (("plain", plain_round), ("batched", batched_round)):
+        fn()  # warm-up (builds the batched launch plan once)
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        recs = [fn() for _ in range(rounds)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for start, ends in recs:
+            lat.extend(start.elapsed_time(e) for e in ends)
+        out[name] = {"rollout_steps_per_s": work * rounds / wall, "ms_per_round": 1e3 * wall / rounds,
+                     "tick_latency_p50_ms": _pct(lat, 50), "tick_latency_p99_ms": _pct(lat, 99)}
+    out["robots"] = len(made)
+    out["rollout_steps_per_round"] = work
+    out["speedup"] = out["batched"]["rollout_steps_per_s"] / out["plain"]["rollout_steps_per_s"]
+    return out
+
+
+def cpu_baseline(args, res):
+    import oracle as O
+    from paper_2511_19204_amd import synth
+    m, p = res["model"], res["params"]
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    count = args.cpu_sample
+    kn = synth.nominal_knots(m, p["n_knots"])
+    O.rollouts(m, p, m["x0"], kn, 1000, 1, 0, 0, cores, threads=cores)  # warm-up
+    t0 = time.perf_counter()
+    O.rollouts(m, p, m["x0"], kn, 1000, 1, 0, 0, count, threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": count * p["horizon"] / dt, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{count} of the {p['n_samples']} rollouts of one step (H={p['horizon']}), FP64, "
+                      f"OpenMP over samples, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--samples", type=int, default=4096)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per rollout (0 = automatic)")
+    ap.add_argument("--robots", type=int, default=64)
+    ap.add_argument("--rounds", type=int, default=10)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design note, not a runnable path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2511_19204_amd import flops, mppi, synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    mppi.lib()
+
+    if args.calibrate_copy:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    res = primary(args, torch, mppi, synth, flops)
+    bvp = None if args.no_batch else batched_vs_plain(args, torch, mppi, synth)
+    cpu = None if args.no_cpu else cpu_baseline(args, res)
+    digest = kernel_source_digest()
+    traffic = measured_traffic(digest)
+    p = res["params"]
+    lat = res["lat"]
+    out = {
+        "metric": METRIC,
+        "value": res["value"],
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * res["wall"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "quadruped18_throughput: 18-DoF floating-base quadruped tree, "
+                        f"K={p['n_samples']} samples, H={p['horizon']} steps at dt={p['dt']:.3g} s, "
+                        f"{p['n_knots']} Hermite knots/joint, {p['n_iters']} iteration per MPC step, "
+                        "soft contact k=2e4 d=200 mu=0.8, linear noise std 0.05->0.4 rad",
+            "samples": p["n_samples"], "horizon": p["horizon"], "knots": p["n_knots"],
+            "iterations_per_step": p["n_iters"], "lanes_per_rollout": res["lanes"],
+            "parallelism": "single GPU",
+        },
+        "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)},
+        "roofline": {
+            "bound": "alu",
+            "achieved": res["achieved_tflops"],
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": res["achieved_tflops"] / FP32_PEAK_TFLOPS,
+            "frac_nonpacked_peak": res["achieved_tflops"] / FP32_PEAK_NONPACKED,
+            "traffic": traffic,
+            "kernel": f"rollout_kernel<{res['lanes']}>",
+            "kernel_ms": res["kernel_ms"],
+            "update_kernel_ms": res["update_ms"],
+            "flops_per_rollout_step": res["flops_per_rollout_step"],
+            "kernel_source_digest": digest,
+        },
+        "cpu_baseline": cpu,
+        "batched_vs_plain": bvp,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -192,6 +192,16 @@ mppi_status mppi_debug_rollouts(mppi_ctx* c, const float* d_state, const float* 
 mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, const float* d_samples,
                               const float* d_knots_in, float* d_knots_out, float* d_weights, void* stream);
 
+/* ---- Kernel timing ------------------------------------------------------- */
+
+/* When enabled, mppi_step records a HIP event pair around every rollout and
+ * update launch on its stream.  mppi_profile_read waits for the recorded events,
+ * returns the summed kernel time (ms) and launch counts since the last read, and
+ * recycles the events.  Costs a few microseconds per launch; off by default. */
+mppi_status mppi_profile_enable(mppi_ctx* c, int32_t on);
+mppi_status mppi_profile_read(mppi_ctx* c, double* rollout_ms, int32_t* n_rollout, double* update_ms,
+                              int32_t* n_update);
+
 const char* mppi_last_error(void);
 const char* mppi_version(void);
 

@@ -37,8 +37,13 @@ struct StageItem {
 };
 __global__ void stage_kernel(const StageItem*);
 __global__ void philox_kernel(const uint32_t*, const uint32_t*, uint32_t*, int);
-constexpr int kSlot = 28;
-inline int group_floats(int G, int E) { return G * kSlot + 16 + ((E + 3) & ~3) + G; }
+constexpr int kSlot = 29;
+constexpr int kUpdThreads = 1024;
+inline int group_floats(int G, int E) {
+  const int raw = G * kSlot + 16 + ((E + 3) & ~3) + G;
+  const int want = G < 32 ? G : 0;
+  return raw + ((want - raw % 32) + 64) % 32;
+}
 }  // namespace mppi
 
 using namespace mppi;
@@ -85,7 +90,21 @@ struct mppi_ctx {
   DevUpdate* d_ups = nullptr;   // [I]
   std::vector<DevInst> h_insts;
   std::vector<DevUpdate> h_ups;
+  // kernel timing (HIP events around each launch on the launch stream) when enabled
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_roll, ev_upd, ev_pool;
 };
+
+static mppi_status ev_pair(mppi_ctx* c, std::pair<hipEvent_t, hipEvent_t>* out) {
+  if (!c->ev_pool.empty()) {
+    *out = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return MPPI_OK;
+  }
+  HIP_TRY(hipEventCreate(&out->first));
+  HIP_TRY(hipEventCreate(&out->second));
+  return MPPI_OK;
+}
 
 static int next_pow2(int x) {
   int g = 4;
@@ -233,6 +252,14 @@ extern "C" mppi_status mppi_model_destroy(mppi_model* m) {
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
+static void free_ctx_events(mppi_ctx* c) {
+  for (auto* v : {&c->ev_roll, &c->ev_upd, &c->ev_pool})
+    for (auto& e : *v) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+}
+
 static void free_ctx_buffers(mppi_ctx* c) {
   void* ptrs[] = {c->sigma, c->x0, c->nom, c->samples, c->costs, c->best_state, c->f0z, c->q0,
                   c->tick, c->d_insts, c->d_ups};
@@ -356,6 +383,7 @@ static void purge_plans(const mppi_ctx* c);
 extern "C" mppi_status mppi_destroy(mppi_ctx* c) {
   if (!c) return fail(MPPI_EINVAL, "null context");
   purge_plans(c);
+  free_ctx_events(c);
   free_ctx_buffers(c);
   delete c;
   return MPPI_OK;
@@ -419,15 +447,28 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
   const int R = 64 / c->lanes;
   const int blocks = (c->N + R - 1) / R;
   for (int it = 0; it < c->I; ++it) {
-    HIP_TRY(launch_rollout(c->lanes, blocks, c->d_insts + it, nullptr, c->E, s));
-    UpdateOut o{nullptr, nullptr, nullptr};
-    const UpdateOut* op = nullptr;
-    if (it == c->I - 1) {
-      o = UpdateOut{d_knots_out, d_best_knots, d_info};
-      op = nullptr;
+    std::pair<hipEvent_t, hipEvent_t> er{}, eu{};
+    if (c->profile) {
+      mppi_status st = ev_pair(c, &er);
+      if (st != MPPI_OK) return st;
+      HIP_TRY(hipEventRecord(er.first, s));
     }
-    hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, s, c->d_ups + it, op, o);
+    HIP_TRY(launch_rollout(c->lanes, blocks, c->d_insts + it, nullptr, c->E, s));
+    if (c->profile) {
+      HIP_TRY(hipEventRecord(er.second, s));
+      c->ev_roll.push_back(er);
+      mppi_status st = ev_pair(c, &eu);
+      if (st != MPPI_OK) return st;
+      HIP_TRY(hipEventRecord(eu.first, s));
+    }
+    UpdateOut o{nullptr, nullptr, nullptr};
+    if (it == c->I - 1) o = UpdateOut{d_knots_out, d_best_knots, d_info};
+    hipLaunchKernelGGL(update_kernel, dim3(1), dim3(kUpdThreads), 0, s, c->d_ups + it, nullptr, o);
     HIP_TRY(hipGetLastError());
+    if (c->profile) {
+      HIP_TRY(hipEventRecord(eu.second, s));
+      c->ev_upd.push_back(eu);
+    }
   }
   if (d_costs) HIP_TRY(hipMemcpyAsync(d_costs, c->costs, (size_t)c->I * c->N * sizeof(float), hipMemcpyDeviceToDevice, s));
   return MPPI_OK;
@@ -614,7 +655,7 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
   for (int it = 0; it < Imax; ++it) {
     IterPlan& ip = plan->iters[it];
     for (auto& g : ip.groups) HIP_TRY(launch_rollout(g.G, g.blocks, ip.insts, g.work, g.E_max, s));
-    hipLaunchKernelGGL(update_kernel, dim3((unsigned)ip.active.size()), dim3(256), 0, s, ip.ups, d_outs + out_off[it],
+    hipLaunchKernelGGL(update_kernel, dim3((unsigned)ip.active.size()), dim3(kUpdThreads), 0, s, ip.ups, d_outs + out_off[it],
                        UpdateOut{nullptr, nullptr, nullptr});
     HIP_TRY(hipGetLastError());
   }
@@ -740,7 +781,7 @@ extern "C" mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, cons
   DevUpdate* d = nullptr;
   HIP_TRY(hipMalloc(&d, sizeof(DevUpdate)));
   HIP_TRY(hipMemcpyAsync(d, &h, sizeof(DevUpdate), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, s, d, nullptr, UpdateOut{nullptr, nullptr, nullptr});
+  hipLaunchKernelGGL(update_kernel, dim3(1), dim3(kUpdThreads), 0, s, d, nullptr, UpdateOut{nullptr, nullptr, nullptr});
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipFree(d));
@@ -749,3 +790,39 @@ extern "C" mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, cons
 
 extern "C" const char* mppi_last_error(void) { return g_err.c_str(); }
 extern "C" const char* mppi_version(void) { return "mppi-gfx950 0.1"; }
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+extern "C" mppi_status mppi_profile_enable(mppi_ctx* c, int32_t on) {
+  if (!c) return fail(MPPI_EINVAL, "null context");
+  c->profile = on != 0;
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_profile_read(mppi_ctx* c, double* rollout_ms, int32_t* n_rollout, double* update_ms,
+                                         int32_t* n_update) {
+  if (!c || !rollout_ms || !n_rollout || !update_ms || !n_update) return fail(MPPI_EINVAL, "null argument");
+  double tr = 0, tu = 0;
+  for (auto& e : c->ev_roll) {
+    HIP_TRY(hipEventSynchronize(e.second));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+    tr += ms;
+  }
+  for (auto& e : c->ev_upd) {
+    HIP_TRY(hipEventSynchronize(e.second));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+    tu += ms;
+  }
+  *rollout_ms = tr;
+  *n_rollout = (int32_t)c->ev_roll.size();
+  *update_ms = tu;
+  *n_update = (int32_t)c->ev_upd.size();
+  for (auto* v : {&c->ev_roll, &c->ev_upd}) {
+    for (auto& e : *v) c->ev_pool.push_back(e);
+    v->clear();
+  }
+  return MPPI_OK;
+}

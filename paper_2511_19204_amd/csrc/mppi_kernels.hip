@@ -47,6 +47,11 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
 
 __device__ __forceinline__ float u01(uint32_t x) { return ((float)(x >> 9) + 0.5f) * 0x1p-23f; }
 
+// 1-ulp hardware reciprocal and reciprocal square root (v_rcp_f32 / v_rsq_f32),
+// used where a correctly rounded quotient is not required
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // packed symmetric 6x6, upper triangle row by row
 __host__ __device__ constexpr int SI(int i, int j) {
   return i <= j ? i * 6 - i * (i - 1) / 2 + (j - i) : j * 6 - j * (j - 1) / 2 + (i - j);
@@ -77,14 +82,20 @@ __device__ __forceinline__ void quat_R(const float* q, float* R) {
 }
 
 // LDS layout of one rollout group (floats):
-//   slot[b][28] per body: forward kinematics R(9) p(3) v(6) beta(6);
+//   slot[b][29] per body: forward kinematics R(9) p(3) v(6) beta(6);
 //                         reused by the backward sweep for Ia(21) pa(6),
 //                         then by the forward sweep for a'(6)
 //   base[16]   : world rotation (9) and position (3) of frame B
 //   knots[E]   : this rollout's knots
 //   red[G]     : reduction scratch
-constexpr int kSlot = 28;
-__host__ __device__ inline int group_floats(int G, int E) { return G * kSlot + 16 + ((E + 3) & ~3) + G; }
+// The slot stride is odd and a group's size is padded to G (mod 32) floats, so
+// the 64 lanes of a wavefront (64/G groups) touch distinct LDS banks.
+constexpr int kSlot = 29;
+__host__ __device__ inline int group_floats(int G, int E) {
+  const int raw = G * kSlot + 16 + ((E + 3) & ~3) + G;
+  const int want = G < 32 ? G : 0;
+  return raw + ((want - raw % 32) + 64) % 32;
+}
 
 // ---------------------------------------------------------------------------
 // Per-lane physics of one step.  Lane b (< nb) owns body b and its joint.
@@ -110,6 +121,40 @@ struct StepIO {
   float cost;          // running-cost terms of this lane (when want_cost)
   uint32_t mask;       // contact activity bits of this lane's contacts
 };
+
+// Per-lane constants of the body (and joint) a lane owns, loaded once per kernel.
+struct BodyConst {
+  float P[27];        // joint rotation C(q) = P0 + cos q P1 + sin q P2
+  float p_tree[3], axis_p[3], com[3], Ic[6];
+  float mass, kp, kd, taumax, arm;
+  int parent, depth, n_child, c_begin, c_count;
+};
+
+__device__ __forceinline__ void load_body(const DevModel& M, int b, bool body_lane, BodyConst& c) {
+  const int bb = body_lane ? b : 0;
+  const int j = bb - M.fb;
+  const bool joint = body_lane && j >= 0;
+#pragma unroll
+  for (int k = 0; k < 27; ++k) c.P[k] = M.P[bb][k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    c.p_tree[k] = M.p_tree[bb][k];
+    c.axis_p[k] = M.axis_p[bb][k];
+    c.com[k] = M.com[bb][k];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) c.Ic[k] = M.Ic[bb][k];
+  c.mass = M.mass[bb];
+  c.kp = joint ? M.kp[j] : 0.f;
+  c.kd = joint ? M.kd[j] : 0.f;
+  c.taumax = joint ? M.taumax[j] : 0.f;
+  c.arm = joint ? M.arm[j] : 0.f;
+  c.parent = M.parent[bb];
+  c.depth = body_lane ? M.depth[bb] : -1;
+  c.n_child = body_lane ? M.n_child[bb] : 0;
+  c.c_begin = M.c_begin[bb];
+  c.c_count = body_lane ? M.c_count[bb] : 0;
+}
 
 // motion vector m given about point O, re-expressed about O + e: (w, v + w x e)
 __device__ __forceinline__ void shift_motion(const float* m, const float* e, float* out) {
@@ -165,8 +210,8 @@ __device__ __forceinline__ void shift_inertia_to_parent(const float* I, const fl
 // terminal = true evaluates only the kinematics and the end-effector height term
 // of the terminal cost (end-effector task) at the current state.
 template <int G>
-__device__ void physics_step(const DevModel& M, const DevInst* I, float* __restrict__ gs, int b, bool body_lane,
-                             StepIO& io, bool want_cost, bool terminal = false) {
+__device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevInst* I, float* __restrict__ gs,
+                             int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
   float* slots = gs;
   float* base = gs + G * kSlot;
   const int fb = M.fb;
@@ -177,15 +222,15 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
   // ---- PD law (linearly implicit gain on unsaturated joints)
   float tau = 0.f, gain = 0.f;
   if (is_joint) {
-    const float t = M.kp[j] * (io.qref - io.q) + M.kd[j] * (io.vref - io.v);
-    const float tm = M.taumax[j];
+    const float t = bc.kp * (io.qref - io.q) + bc.kd * (io.vref - io.v);
+    const float tm = bc.taumax;
     if (t >= tm) {
       tau = tm;
     } else if (t <= -tm) {
       tau = -tm;
     } else {
       tau = t;
-      gain = io.dt * (M.kd[j] + io.dt * M.kp[j]);
+      gain = io.dt * (bc.kd + io.dt * bc.kp);
     }
   }
   io.tau = tau;
@@ -213,7 +258,7 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
 
   // ---- forward kinematics, level by level (slot: R, p, v, beta about the body origin)
   float R[9], p[3], e[3], ax[3], v[6], c[6], beta[6];
-  const int depth = body_lane ? M.depth[b] : -1;
+  const int depth = bc.depth;
   if (is_base) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.f : 0.f;
@@ -226,7 +271,7 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
   if (is_joint) sincosf(io.q, &sq, &cq);
   for (int d = 1; d <= M.max_depth; ++d) {
     if (is_joint && depth == d) {
-      const int lam = M.parent[b];
+      const int lam = bc.parent;
       float Rl[9], pl[3], vl[6], bl[6];
       if (lam >= 0) {
         const float* s = slots + lam * kSlot;
@@ -244,7 +289,7 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
 #pragma unroll
         for (int k = 0; k < 6; ++k) { vl[k] = 0.f; bl[k] = 0.f; }
       }
-      const float* P = M.P[b];
+      const float* P = bc.P;
       float C[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) C[k] = P[k] + cq * P[9 + k] + sq * P[18 + k];
@@ -255,9 +300,9 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
           R[r * 3 + cc] = Rl[r * 3 + 0] * C[0 * 3 + cc] + Rl[r * 3 + 1] * C[1 * 3 + cc] + Rl[r * 3 + 2] * C[2 * 3 + cc];
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        e[r] = Rl[r * 3 + 0] * M.p_tree[b][0] + Rl[r * 3 + 1] * M.p_tree[b][1] + Rl[r * 3 + 2] * M.p_tree[b][2];
+        e[r] = Rl[r * 3 + 0] * bc.p_tree[0] + Rl[r * 3 + 1] * bc.p_tree[1] + Rl[r * 3 + 2] * bc.p_tree[2];
         p[r] = pl[r] + e[r];
-        ax[r] = Rl[r * 3 + 0] * M.axis_p[b][0] + Rl[r * 3 + 1] * M.axis_p[b][1] + Rl[r * 3 + 2] * M.axis_p[b][2];
+        ax[r] = Rl[r * 3 + 0] * bc.axis_p[0] + Rl[r * 3 + 1] * bc.axis_p[1] + Rl[r * 3 + 2] * bc.axis_p[2];
       }
       // v = shift(v_parent) + S qd with S = (axis, 0) about the joint origin
       shift_motion(vl, e, v);
@@ -311,12 +356,12 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
 #pragma unroll
       for (int k = 0; k < 21; ++k) IA[k] = M.base_I[k];
     } else {
-      const float m = M.mass[b];
+      const float m = bc.mass;
       float cw[3];
-      const float cb[3] = {M.com[b][0], M.com[b][1], M.com[b][2]};
+      const float cb[3] = {bc.com[0], bc.com[1], bc.com[2]};
 #pragma unroll
       for (int r = 0; r < 3; ++r) cw[r] = R[r * 3 + 0] * cb[0] + R[r * 3 + 1] * cb[1] + R[r * 3 + 2] * cb[2];
-      const float* Ic = M.Ic[b];
+      const float* Ic = bc.Ic;
       const float Ib[9] = {Ic[0], Ic[3], Ic[4], Ic[3], Ic[1], Ic[5], Ic[4], Ic[5], Ic[2]};
       float RI[9];
 #pragma unroll
@@ -349,7 +394,7 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
     pA[3] = t2[0]; pA[4] = t2[1]; pA[5] = t2[2];
 
     // contacts carried by this body (point x relative to the body origin)
-    const int c0 = M.c_begin[b], cn = M.c_count[b];
+    const int c0 = bc.c_begin, cn = bc.c_count;
     for (int ci = c0; ci < c0 + cn; ++ci) {
       const float r0 = M.cpos[ci][0], r1 = M.cpos[ci][1], r2 = M.cpos[ci][2];
       float x[3];
@@ -368,8 +413,9 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
       float fn = 0.f;
       if (pw[2] < 0.f) fn = fmaxf(0.f, -M.k * pw[2] - M.d * vw[2]);
       const float n2 = vw[0] * vw[0] + vw[1] * vw[1] + M.eps * M.eps;
-      const float nrm = sqrtf(n2);
-      const float fw[3] = {-M.mu * fn * vw[0] / nrm, -M.mu * fn * vw[1] / nrm, fn};
+      const float inv_nrm = rsq(n2), inv_n2 = inv_nrm * inv_nrm;
+      const float mfn = M.mu * fn * inv_nrm;
+      const float fw[3] = {-mfn * vw[0], -mfn * vw[1], fn};
       float fB[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) fB[r] = Rb[0 * 3 + r] * fw[0] + Rb[1 * 3 + r] * fw[1] + Rb[2 * 3 + r] * fw[2];
@@ -380,9 +426,9 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
       if (fn > 0.f) {
         mask |= 1u << M.corig[ci];
         // velocity Jacobian of the contact law (world), tangential-normal coupling dropped
-        const float aa = M.mu * fn / nrm;
-        const float Dw[9] = {aa * (1.f - vw[0] * vw[0] / n2), -aa * vw[0] * vw[1] / n2, 0.f,
-                             -aa * vw[0] * vw[1] / n2, aa * (1.f - vw[1] * vw[1] / n2), 0.f,
+        const float aa = mfn;
+        const float Dw[9] = {aa * (1.f - vw[0] * vw[0] * inv_n2), -aa * vw[0] * vw[1] * inv_n2, 0.f,
+                             -aa * vw[0] * vw[1] * inv_n2, aa * (1.f - vw[1] * vw[1] * inv_n2), 0.f,
                              0.f, 0.f, M.d};
         float T[9], D[9];
 #pragma unroll
@@ -469,7 +515,7 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
   float U[6], invD = 0.f, u = 0.f;
   for (int d = M.max_depth; d >= 0; --d) {
     if (body_lane && depth == d) {
-      const int nch = M.n_child[b];
+      const int nch = bc.n_child;
       for (int k = 0; k < nch; ++k) {
         const float* s = slots + M.child[b][k] * kSlot;
 #pragma unroll
@@ -482,8 +528,8 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
 #pragma unroll
         for (int r = 0; r < 6; ++r)
           U[r] = IA[SI(r, 0)] * ax[0] + IA[SI(r, 1)] * ax[1] + IA[SI(r, 2)] * ax[2];
-        const float Dv = (M.arm[j] + gain) + (ax[0] * U[0] + ax[1] * U[1] + ax[2] * U[2]);
-        invD = 1.f / Dv;
+        const float Dv = (bc.arm + gain) + (ax[0] * U[0] + ax[1] * U[1] + ax[2] * U[2]);
+        invD = rcp(Dv);
         u = tau - (ax[0] * pA[0] + ax[1] * pA[1] + ax[2] * pA[2]);
         float Ia[21];
 #pragma unroll
@@ -512,7 +558,7 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
 
   // ---- root: floating base solves IA0 a0' = -pA0 (Cholesky); fixed roots use -a_g
   if (is_base) {
-    float L[21];
+    float L[21], invL[6];
 #pragma unroll
     for (int q = 0; q < 21; ++q) L[q] = IA[q];
     // in-place Cholesky of the packed symmetric matrix (lower factor stored as L[SI(i,j)], j <= i)
@@ -521,9 +567,9 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
       float dsum = L[SI(jj, jj)];
 #pragma unroll
       for (int k = 0; k < jj; ++k) dsum -= L[SI(jj, k)] * L[SI(jj, k)];
-      const float ljj = sqrtf(dsum);
-      const float inv = 1.f / ljj;
-      L[SI(jj, jj)] = ljj;
+      const float inv = rsq(dsum);
+      invL[jj] = inv;
+      L[SI(jj, jj)] = dsum * inv;
 #pragma unroll
       for (int i = jj + 1; i < 6; ++i) {
         float sm = L[SI(i, jj)];
@@ -538,14 +584,14 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
       float sm = -pA[i];
 #pragma unroll
       for (int k = 0; k < i; ++k) sm -= L[SI(i, k)] * y[k];
-      y[i] = sm / L[SI(i, i)];
+      y[i] = sm * invL[i];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
       float sm = y[i];
 #pragma unroll
       for (int k = i + 1; k < 6; ++k) sm -= L[SI(k, i)] * a0[k];
-      a0[i] = sm / L[SI(i, i)];
+      a0[i] = sm * invL[i];
     }
     float* s0 = slots;
 #pragma unroll
@@ -559,7 +605,7 @@ __device__ void physics_step(const DevModel& M, const DevInst* I, float* __restr
   float qdd = 0.f;
   for (int d = 1; d <= M.max_depth; ++d) {
     if (is_joint && depth == d) {
-      const int lam = M.parent[b];
+      const int lam = bc.parent;
       float al[6];
       if (lam >= 0) {
         const float* s = slots + lam * kSlot;
@@ -633,8 +679,8 @@ __device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, 
 
 // Hermite reference of joint jj at fine step f of F (eq. hermite_segment and
 // its time derivative); segment and local time from integer arithmetic.
-__device__ __forceinline__ void hermite(const float* knots, int K, int nu, int F, float delta, int f, int jj,
-                                        float* qr, float* vr) {
+__device__ __forceinline__ void hermite(const float* knots, int K, int nu, int F, float delta, float inv_delta,
+                                        int f, int jj, float* qr, float* vr) {
   const int m = f * (K - 1);
   int seg = m / F;
   seg = seg < K - 2 ? seg : K - 2;
@@ -646,7 +692,7 @@ __device__ __forceinline__ void hermite(const float* knots, int K, int nu, int F
   const float q0 = knots[seg * nu + jj], q1 = knots[(seg + 1) * nu + jj];
   const float v0 = knots[KU + seg * nu + jj], v1 = knots[KU + (seg + 1) * nu + jj];
   *qr = h00 * q0 + h10 * delta * v0 + h01 * q1 + h11 * delta * v1;
-  *vr = (d00 * q0 + d10 * delta * v0 + d01 * q1 + d11 * delta * v1) / delta;
+  *vr = (d00 * q0 + d10 * delta * v0 + d01 * q1 + d11 * delta * v1) * inv_delta;
 }
 
 template <int G>
@@ -686,7 +732,7 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
     const float th = 0.5f * wn * dt;
     float sn, cs;
     sincosf(th, &sn, &cs);
-    const float k = sn / wn;
+    const float k = sn * rcp(wn);
     e0 = cs; e1 = k * bv[0]; e2 = k * bv[1]; e3 = k * bv[2];
   }
   const float a0 = bq[3], a1 = bq[4], a2 = bq[5], a3 = bq[6];
@@ -694,7 +740,7 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
   const float r1 = a0 * e1 + a1 * e0 + a2 * e3 - a3 * e2;
   const float r2 = a0 * e2 - a1 * e3 + a2 * e0 + a3 * e1;
   const float r3 = a0 * e3 + a1 * e2 - a2 * e1 + a3 * e0;
-  const float inv = 1.f / sqrtf(r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
+  const float inv = rsq(r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
   bq[3] = r0 * inv; bq[4] = r1 * inv; bq[5] = r2 * inv; bq[6] = r3 * inv;
 }
 
@@ -748,11 +794,14 @@ __global__ __launch_bounds__(64) void rollout_kernel(const DevInst* __restrict__
 
   const int nsub = M.nsub, H = I.H, F = H * nsub;
   io.dt = I.dt / (float)nsub;
+  const float inv_delta = 1.f / I.delta;
+  BodyConst bc;
+  load_body(M, b, body_lane, bc);
   float acc = 0.f;
   for (int f = 0; f < F; ++f) {
     const bool control = (f % nsub) == 0;
-    if (is_joint) hermite(knots, I.K, I.nu, F, I.delta, f, j, &io.qref, &io.vref);
-    physics_step<G>(M, &I, gs, b, body_lane, io, control);
+    if (is_joint) hermite(knots, I.K, I.nu, F, I.delta, inv_delta, f, j, &io.qref, &io.vref);
+    physics_step<G>(M, bc, &I, gs, b, body_lane, io, control);
     if (control) {
       acc += io.cost;
       if (I.masks) {
@@ -778,7 +827,7 @@ __global__ __launch_bounds__(64) void rollout_kernel(const DevInst* __restrict__
     }
   } else {
     // end-effector height at x_H
-    physics_step<G>(M, &I, gs, b, body_lane, io, false, true);
+    physics_step<G>(M, bc, &I, gs, b, body_lane, io, false, true);
     acc += io.cost;
   }
   float S = group_sum<G>(acc, red, l);
@@ -798,18 +847,33 @@ struct UpdateOut {
   void* info_out;     // mppi_step_info or null
 };
 
-constexpr int kUpdThreads = 256;
+constexpr int kUpdThreads = 1024;
+constexpr int kUpdWaves = kUpdThreads / 64;
+constexpr int kUpdChunk = 4096;  // samples whose weights sit in LDS at a time
 
-// outs: per-block output table (batched calls) or null, then `single` is used.
+// Block-wide reductions in a fixed order (tree over threads), deterministic.
+__device__ __forceinline__ float block_sum(float x, float* buf) {
+  const int t = threadIdx.x;
+  buf[t] = x;
+  __syncthreads();
+  for (int off = kUpdThreads / 2; off > 0; off >>= 1) {
+    if (t < off) buf[t] += buf[t + off];
+    __syncthreads();
+  }
+  const float r = buf[0];
+  __syncthreads();
+  return r;
+}
+
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __restrict__ ups,
                                                              const UpdateOut* __restrict__ outs, UpdateOut single) {
   const DevUpdate& U = ups[blockIdx.x];
   const int t = threadIdx.x, N = U.N, E = U.E;
   __shared__ float s_v[kUpdThreads];
   __shared__ int s_i[kUpdThreads];
-  __shared__ float s_w[kUpdThreads];
-  __shared__ float s_part[4][64];
-  __shared__ float s_stats[4];
+  __shared__ float s_x[kUpdThreads];
+  __shared__ float s_w[kUpdChunk];
+  __shared__ float s_part[kUpdWaves][64];
 
   // 1. finite minimum (lowest index), maximum and count
   float mn = INFINITY, mx = -INFINITY;
@@ -822,87 +886,80 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
       mx = fmaxf(mx, S);
     }
   }
-  s_v[t] = mn; s_i[t] = arg; s_w[t] = mx;
+  s_v[t] = mn; s_i[t] = arg; s_x[t] = mx;
   __syncthreads();
   for (int off = kUpdThreads / 2; off > 0; off >>= 1) {
     if (t < off) {
       const float om = s_v[t + off];
       const int oi = s_i[t + off];
       if (om < s_v[t] || (om == s_v[t] && oi < s_i[t])) { s_v[t] = om; s_i[t] = oi; }
-      s_w[t] = fmaxf(s_w[t], s_w[t + off]);
+      s_x[t] = fmaxf(s_x[t], s_x[t + off]);
     }
     __syncthreads();
   }
-  const float smin = s_v[0], smax = s_w[0];
+  const float smin = s_v[0], smax = s_x[0];
   const int nstar = s_i[0];
   __syncthreads();
-  s_i[t] = nf;
-  __syncthreads();
-  for (int off = kUpdThreads / 2; off > 0; off >>= 1) {
-    if (t < off) s_i[t] += s_i[t + off];
-    __syncthreads();
-  }
-  const int nfin = s_i[0];
-  __syncthreads();
+  const int nfin = (int)block_sum((float)nf, s_x);
 
   // 2. unnormalised weights e_n = exp(-S_hat / lambda) and their sum
   const float range = smax - smin;
   const float inv_range = (U.weight_mode == 0 && range > 0.f) ? 1.f / range : 0.f;
   const float inv_lam = 1.f / U.lambda;
+  auto weight = [&](float S) -> float {
+    if (!isfinite(S)) return 0.f;
+    const float sh = U.weight_mode == 0 ? (S - smin) * inv_range : (S - smin);
+    return expf(-sh * inv_lam);
+  };
   float zs = 0.f;
-  for (int n = t; n < N; n += kUpdThreads) {
-    const float S = U.costs[n];
-    float e = 0.f;
-    if (isfinite(S)) {
-      const float sh = U.weight_mode == 0 ? (S - smin) * inv_range : (S - smin);
-      e = expf(-sh * inv_lam);
-    }
-    zs += e;
-  }
-  s_w[t] = zs;
-  __syncthreads();
-  for (int off = kUpdThreads / 2; off > 0; off >>= 1) {
-    if (t < off) s_w[t] += s_w[t + off];
-    __syncthreads();
-  }
-  const float invZ = nfin > 0 ? 1.f / s_w[0] : 0.f;
-  __syncthreads();
+  for (int n = t; n < N; n += kUpdThreads) zs += weight(U.costs[n]);
+  const float Z = block_sum(zs, s_x);
+  const float invZ = nfin > 0 ? 1.f / Z : 0.f;
   if (U.weights)
-    for (int n = t; n < N; n += kUpdThreads) {
-      const float S = U.costs[n];
-      float e = 0.f;
-      if (isfinite(S)) {
-        const float sh = U.weight_mode == 0 ? (S - smin) * inv_range : (S - smin);
-        e = expf(-sh * inv_lam);
-      }
-      U.weights[n] = e * invZ;
-    }
+    for (int n = t; n < N; n += kUpdThreads) U.weights[n] = weight(U.costs[n]) * invZ;
 
-  // 3. weighted knot average: waves split the samples, lanes the elements
+  // 3. weighted knot average: waves split the samples, lanes the knot elements
   const UpdateOut* o = outs ? outs + blockIdx.x : &single;
   float* dst = (U.last_iter && o && o->knots_out) ? o->knots_out : U.nominal_out;
   const int wv = t / 64, ln = t % 64;
-  for (int e0 = 0; e0 < E; e0 += 64) {
-    const int e = e0 + ln;
-    float acc = 0.f;
-    if (e < E && nfin > 0) {
-      for (int n = wv; n < N; n += 4) {
-        const float S = U.costs[n];
-        if (!isfinite(S)) continue;
-        const float sh = U.weight_mode == 0 ? (S - smin) * inv_range : (S - smin);
-        const float w = expf(-sh * inv_lam) * invZ;
-        acc = fmaf(w, U.samples[(size_t)n * E + e], acc);
+  const int n_e = (E + 63) / 64;
+  // accumulate each element's sum across chunks in registers of wave 0 after the reduction
+  for (int eb = 0; eb < n_e; ++eb) {
+    const int e = eb * 64 + ln;
+    float total = 0.f;
+    for (int c0 = 0; c0 < N; c0 += kUpdChunk) {
+      const int cn = min(kUpdChunk, N - c0);
+      __syncthreads();
+      for (int n = t; n < cn; n += kUpdThreads) s_w[n] = weight(U.costs[c0 + n]) * invZ;
+      __syncthreads();
+      float acc = 0.f;
+      if (e < E && nfin > 0) {
+        const float* col = U.samples + (size_t)c0 * E + e;
+        int n = wv;
+        for (; n + 3 * kUpdWaves < cn; n += 4 * kUpdWaves) {
+          const float a0 = col[(size_t)n * E];
+          const float a1 = col[(size_t)(n + kUpdWaves) * E];
+          const float a2 = col[(size_t)(n + 2 * kUpdWaves) * E];
+          const float a3 = col[(size_t)(n + 3 * kUpdWaves) * E];
+          acc = fmaf(s_w[n], a0, acc);
+          acc = fmaf(s_w[n + kUpdWaves], a1, acc);
+          acc = fmaf(s_w[n + 2 * kUpdWaves], a2, acc);
+          acc = fmaf(s_w[n + 3 * kUpdWaves], a3, acc);
+        }
+        for (; n < cn; n += kUpdWaves) acc = fmaf(s_w[n], col[(size_t)n * E], acc);
+      }
+      s_part[wv][ln] = acc;
+      __syncthreads();
+      if (wv == 0) {
+        float sum = 0.f;
+#pragma unroll
+        for (int k = 0; k < kUpdWaves; ++k) sum += s_part[k][ln];
+        total += sum;
       }
     }
-    s_part[wv][ln] = acc;
-    __syncthreads();
-    if (wv == 0 && e < E) {
-      const float v = nfin > 0 ? ((s_part[0][ln] + s_part[1][ln]) + (s_part[2][ln] + s_part[3][ln]))
-                               : U.nominal_in[e];
-      dst[e] = v;
-    }
-    __syncthreads();
+    if (wv == 0 && e < E) dst[e] = nfin > 0 ? total : U.nominal_in[e];
   }
+  __syncthreads();
 
   // 4. best-sample tracking across the iterations of this call
   float* bs = U.best_state;  // [E] knots, then S_best, best_iter, n_nonfinite, all_nonfinite
@@ -917,6 +974,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
   }
   __syncthreads();
   const bool improve = nfin > 0 && U.costs[nstar] < bs[E];
+  __syncthreads();
   if (improve)
     for (int e = t; e < E; e += kUpdThreads) bs[e] = U.samples[(size_t)nstar * E + e];
   __syncthreads();
@@ -941,7 +999,6 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
     }
   }
   if (U.last_iter && t == 0 && U.tick) U.tick[0] += 1u;
-  (void)s_stats;
 }
 
 // Copy per-call inputs (state, warm-start knots) into instance buffers.
@@ -1005,7 +1062,9 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
 #pragma unroll
   for (int k = 0; k < 6; ++k) { io.bv[k] = fb ? v[(size_t)s * nv + k] : 0.f; io.ba[k] = 0.f; }
   io.dt = dt;
-  physics_step<G>(M, nullptr, gs, l, body_lane, io, false);
+  BodyConst bc;
+  load_body(M, l, body_lane, bc);
+  physics_step<G>(M, bc, nullptr, gs, l, body_lane, io, false);
   if (!valid) return;
   if (is_joint) qdd[(size_t)s * nv + (fb ? 6 : 0) + j] = io.qdd;
   if (fb && l == 0)

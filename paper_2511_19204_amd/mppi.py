@@ -61,7 +61,8 @@ EXPORTS = [
     "mppi_model_create", "mppi_model_destroy", "mppi_create", "mppi_destroy", "mppi_set_tick",
     "mppi_get_tick", "mppi_set_lanes_per_rollout", "mppi_get_lanes_per_rollout", "mppi_step",
     "mppi_step_batch", "mppi_debug_philox", "mppi_debug_samples", "mppi_debug_dynamics",
-    "mppi_debug_rollouts", "mppi_debug_update", "mppi_last_error", "mppi_version",
+    "mppi_debug_rollouts", "mppi_debug_update", "mppi_profile_enable", "mppi_profile_read",
+    "mppi_last_error", "mppi_version",
 ]
 
 
@@ -87,6 +88,9 @@ def lib():
         L.mppi_debug_dynamics.argtypes = [vp, i32, vp, vp, vp, vp, C.c_float, vp, vp]
         L.mppi_debug_rollouts.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mppi_debug_update.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.mppi_profile_enable.argtypes = [vp, i32]
+        L.mppi_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i32),
+                                        C.POINTER(C.c_double), C.POINTER(i32)]
         L.mppi_last_error.restype = C.c_char_p
         L.mppi_version.restype = C.c_char_p
         for name in EXPORTS[:-2]:
@@ -244,6 +248,18 @@ class Controller:
         _check(lib().mppi_step(self.h, _ptr(state), _ptr(knots_in), _ptr(knots_out),
                                _ptr(best_knots), _ptr(info), _ptr(costs), _stream(stream)),
                "mppi_step")
+
+    def profile(self, on=True):
+        """Record HIP events around this instance's kernel launches."""
+        _check(lib().mppi_profile_enable(self.h, 1 if on else 0), "mppi_profile_enable")
+
+    def profile_read(self):
+        """(rollout ms, rollout launches, update ms, update launches) since the last read."""
+        tr, tu = C.c_double(), C.c_double()
+        nr, nu = C.c_int32(), C.c_int32()
+        _check(lib().mppi_profile_read(self.h, C.byref(tr), C.byref(nr), C.byref(tu), C.byref(nu)),
+               "mppi_profile_read")
+        return tr.value, nr.value, tu.value, nu.value
 
     def samples(self, knots_in, iteration, tick, out, stream=None):
         _check(lib().mppi_debug_samples(self.h, _ptr(knots_in), int(iteration), C.c_uint32(tick),
