@@ -425,52 +425,50 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
       pA[3] -= fB[0]; pA[4] -= fB[1]; pA[5] -= fB[2];
       if (fn > 0.f) {
         mask |= 1u << M.corig[ci];
-        // velocity Jacobian of the contact law (world), tangential-normal coupling dropped
+        // Velocity Jacobian of the contact law (world), tangential-normal coupling
+        // dropped: D_w = a I + (d - a) z z^T - a w w^T with a = mu f_n / n and
+        // w = v_t / n.  In B axes z -> zb (third row of Rb) and w -> ub = Rb^T w.
         const float aa = mfn;
-        const float Dw[9] = {aa * (1.f - vw[0] * vw[0] * inv_n2), -aa * vw[0] * vw[1] * inv_n2, 0.f,
-                             -aa * vw[0] * vw[1] * inv_n2, aa * (1.f - vw[1] * vw[1] * inv_n2), 0.f,
-                             0.f, 0.f, M.d};
-        float T[9], D[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc)
-            T[r * 3 + cc] = Dw[r * 3 + 0] * Rb[0 * 3 + cc] + Dw[r * 3 + 1] * Rb[1 * 3 + cc] + Dw[r * 3 + 2] * Rb[2 * 3 + cc];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc)
-            D[r * 3 + cc] = Rb[0 * 3 + r] * T[0 * 3 + cc] + Rb[1 * 3 + r] * T[1 * 3 + cc] + Rb[2 * 3 + r] * T[2 * 3 + cc];
+        const float al = M.d - aa;
+        const float zb[3] = {Rb[6], Rb[7], Rb[8]};
+        const float wt[2] = {vw[0] * inv_nrm, vw[1] * inv_nrm};
+        const float ub[3] = {Rb[0] * wt[0] + Rb[3] * wt[1], Rb[1] * wt[0] + Rb[4] * wt[1],
+                             Rb[2] * wt[0] + Rb[5] * wt[1]};
         const float dt = io.dt;
-        // added inertia dt P^T D P with P = [-x^x, 1]: blocks (-X D X, X D; -D X, D)
-        const float X[9] = {0.f, -x[2], x[1], x[2], 0.f, -x[0], -x[1], x[0], 0.f};
-        float XD[9];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc)
-            XD[r * 3 + cc] = X[r * 3 + 0] * D[0 * 3 + cc] + X[r * 3 + 1] * D[1 * 3 + cc] + X[r * 3 + 2] * D[2 * 3 + cc];
+        // added inertia dt P^T D P with P = [-x^x, 1]; with w1 = x x zb, w2 = x x ub:
+        //   top-left  a (|x|^2 I - x x^T) + al w1 w1^T - a w2 w2^T
+        //   top-right a x^x + al w1 zb^T - a w2 ub^T,   bottom-right D
+        float w1[3], w2[3];
+        cross3(x, zb, w1);
+        cross3(x, ub, w2);
+        const float x2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        const float dta = dt * aa, dtal = dt * al;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
           for (int cc = r; cc < 3; ++cc) {
-            const float tl = -(XD[r * 3 + 0] * X[0 * 3 + cc] + XD[r * 3 + 1] * X[1 * 3 + cc] + XD[r * 3 + 2] * X[2 * 3 + cc]);
+            const float tl = aa * ((r == cc ? x2 : 0.f) - x[r] * x[cc]) + al * w1[r] * w1[cc] - aa * w2[r] * w2[cc];
             IA[SI(r, cc)] += dt * tl;
-            IA[SI(r + 3, cc + 3)] += dt * D[r * 3 + cc];
+            const float br = (r == cc ? aa : 0.f) + al * zb[r] * zb[cc] - aa * ub[r] * ub[cc];
+            IA[SI(r + 3, cc + 3)] += dt * br;
           }
+        const float Xm[9] = {0.f, -x[2], x[1], x[2], 0.f, -x[0], -x[1], x[0], 0.f};
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
-          for (int cc = 0; cc < 3; ++cc) IA[SI(r, cc + 3)] += dt * XD[r * 3 + cc];
+          for (int cc = 0; cc < 3; ++cc)
+            IA[SI(r, cc + 3)] += dta * Xm[r * 3 + cc] + dtal * w1[r] * zb[cc] - dta * w2[r] * ub[cc];
         // bias of the added inertia: dt P^T D P (a_g - beta) = dt (x x Dw', Dw'), w' = P (a_g - beta)
         const float sa[3] = {-beta[0], -beta[1], -beta[2]};
         const float sl[3] = {agl[0] - beta[3], agl[1] - beta[4], agl[2] - beta[5]};
         float sx[3];
         cross3(sa, x, sx);
         const float w3[3] = {sl[0] + sx[0], sl[1] + sx[1], sl[2] + sx[2]};
+        const float zw = zb[0] * w3[0] + zb[1] * w3[1] + zb[2] * w3[2];
+        const float uw = ub[0] * w3[0] + ub[1] * w3[1] + ub[2] * w3[2];
         float Dw3[3];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) Dw3[r] = D[r * 3 + 0] * w3[0] + D[r * 3 + 1] * w3[1] + D[r * 3 + 2] * w3[2];
+        for (int r = 0; r < 3; ++r) Dw3[r] = aa * w3[r] + al * zw * zb[r] - aa * uw * ub[r];
         float xd[3];
         cross3(x, Dw3, xd);
         pA[0] += dt * xd[0]; pA[1] += dt * xd[1]; pA[2] += dt * xd[2];
