@@ -163,6 +163,68 @@ mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const float* const
                             const float* const* d_knots_in, float* const* d_knots_out,
                             float* const* d_best_knots, mppi_step_info* const* d_infos, void* stream);
 
+/* Process-wide options of batched launches.  persistent = 1 runs each rollout
+ * launch of a batch as a persistent grid (one workgroup per resident wavefront
+ * slot) whose wavefronts take (instance, sample) work items from a device
+ * counter, longest rollouts first; 0 launches one workgroup per work item.
+ * Results do not depend on the choice. */
+typedef struct {
+  int32_t persistent;
+} mppi_batch_opts;
+mppi_status mppi_set_batch_options(const mppi_batch_opts* o);
+
+/* A fixed batch captured once into a hipGraph (inputs/outputs as in
+ * mppi_step_batch, pointers fixed at capture, buffers owned by the caller and
+ * alive while the graph is used).  Each mppi_graph_launch is one MPC step of
+ * every instance and advances their ticks; it equals mppi_step_batch on the
+ * same pointers.  The graph holds kernel nodes only. */
+typedef struct mppi_graph mppi_graph;
+mppi_status mppi_graph_create(int32_t n, mppi_ctx* const* ctxs, const float* const* d_states,
+                              const float* const* d_knots_in, float* const* d_knots_out,
+                              float* const* d_best_knots, mppi_step_info* const* d_infos, mppi_graph** out);
+mppi_status mppi_graph_launch(mppi_graph* g, void* stream);
+mppi_status mppi_graph_destroy(mppi_graph* g);
+
+/* Autotuner: times `reps` steps of the instance from (d_state, d_knots) for each
+ * valid lanes-per-rollout value and keeps the fastest; results are cached per
+ * (model, N, H, K) for the process.  The instance's tick is restored.  Blocks
+ * until the timing steps finish.  Writes the chosen value to *best_lanes
+ * (nullable). */
+mppi_status mppi_autotune(mppi_ctx* c, const float* d_state, const float* d_knots, int32_t reps, void* stream,
+                          int32_t* best_lanes);
+
+/* ---- Serving: continuous batching of MPC ticks --------------------------- */
+
+/* A server owns n_streams HIP streams and a worker thread.  Submitted ticks wait
+ * in a FIFO; whenever a stream is free the worker forms a batch of up to
+ * max_batch pending ticks whose instance is not already on the device (one
+ * outstanding tick per instance) and launches it (mode 0: one fused batched
+ * step; mode 1: plain per-instance steps, the baseline).  Ticks that arrive while
+ * others run join the next batch, so work from several batches overlaps on the
+ * device.  Each result equals the instance's own mppi_step (the instance's
+ * warm-start knots and noise tick stay on the device).  persistent selects the
+ * persistent rollout launch (mppi_batch_opts).  Buffers passed to submit must
+ * stay valid until the tick is reported done. */
+typedef struct {
+  int32_t max_pending;   /* pending ticks beyond which submit returns MPPI_ENOSLOT */
+  int32_t n_streams;     /* 1..8 batches in flight                              */
+  int32_t max_batch;     /* ticks per batch                                     */
+  int32_t mode;          /* 0 batched, 1 plain per-instance launches            */
+  int32_t persistent;    /* 1: persistent rollout launches                      */
+} mppi_server_cfg;
+typedef struct mppi_server mppi_server;
+mppi_status mppi_server_create(const mppi_server_cfg* cfg, mppi_server** out);
+/* Non-blocking; *ticket identifies the tick.  MPPI_ENOSLOT when the queue is full. */
+mppi_status mppi_server_submit(mppi_server* s, mppi_ctx* c, const float* d_state, const float* d_knots_in,
+                               float* d_knots_out, uint64_t* ticket);
+/* *done = 1 once the tick's outputs are complete on the device; then *latency_s is
+ * submit-to-completion wall time and the ticket is released. */
+mppi_status mppi_server_poll(mppi_server* s, uint64_t ticket, int32_t* done, double* latency_s);
+/* Wait (up to timeout_s) until nothing is pending or in flight; MPPI_EBUSY on timeout. */
+mppi_status mppi_server_drain(mppi_server* s, double timeout_s);
+mppi_status mppi_server_stats(mppi_server* s, int64_t* batches, int64_t* requests);
+mppi_status mppi_server_destroy(mppi_server* s);
+
 /* ---- Verification entry points (same device code as mppi_step) ---------- */
 
 /* Philox4x32-10 block function: d_ctr [n][4], d_key [n][2] -> d_out [n][4]. */

@@ -10,8 +10,14 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mppi.h"
@@ -20,6 +26,8 @@
 namespace mppi {
 // kernels (mppi_kernels.hip)
 template <int G> __global__ void rollout_kernel(const DevInst*, const int2*, int);
+template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int);
+__global__ void reset_counters(unsigned int*, int);
 template <int G> __global__ void sample_kernel(const DevInst*, int);
 template <int G>
 __global__ void dynamics_kernel(const DevModel*, int, const float*, const float*, const float*, const float*, float,
@@ -438,6 +446,40 @@ static hipError_t launch_rollout(int G, int blocks, const DevInst* insts, const 
   }
 }
 
+template <int G>
+static hipError_t launch_persistent_G(int n_items, const DevInst* insts, const int2* work, int E_max,
+                                      unsigned int* counter, hipStream_t s) {
+  const int stride = group_floats(G, E_max);
+  const int lds = lds_bytes(G, E_max);
+  int dev = 0, cus = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rollout_persistent_kernel<G>, 64, lds);
+  const int grid = std::min(n_items, std::max(1, cus) * std::max(1, per_cu));
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, counter, 1);
+  hipLaunchKernelGGL(rollout_persistent_kernel<G>, dim3(grid), dim3(64), lds, s, insts, work, n_items, counter, stride);
+  return hipGetLastError();
+}
+
+static hipError_t launch_persistent(int G, int n_items, const DevInst* insts, const int2* work, int E_max,
+                                    unsigned int* counter, hipStream_t s) {
+  switch (G) {
+    case 4: return launch_persistent_G<4>(n_items, insts, work, E_max, counter, s);
+    case 8: return launch_persistent_G<8>(n_items, insts, work, E_max, counter, s);
+    case 16: return launch_persistent_G<16>(n_items, insts, work, E_max, counter, s);
+    case 32: return launch_persistent_G<32>(n_items, insts, work, E_max, counter, s);
+    default: return launch_persistent_G<64>(n_items, insts, work, E_max, counter, s);
+  }
+}
+
+static std::atomic<int> g_persistent{0};
+
+extern "C" mppi_status mppi_set_batch_options(const mppi_batch_opts* o) {
+  if (!o) return fail(MPPI_EINVAL, "null options");
+  g_persistent = o->persistent ? 1 : 0;
+  return MPPI_OK;
+}
+
 extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float* d_knots_in, float* d_knots_out,
                                  float* d_best_knots, mppi_step_info* d_info, float* d_costs, void* stream) {
   if (!c || !d_state || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
@@ -480,7 +522,8 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
 namespace {
 struct GroupLaunch {
   int G = 0, blocks = 0, E_max = 0;
-  int2* work = nullptr;  // device [blocks]
+  int2* work = nullptr;            // device [blocks]
+  unsigned int* counter = nullptr; // device work counter of the persistent form
 };
 struct IterPlan {
   DevInst* insts = nullptr;     // device, indexed by work.x
@@ -496,8 +539,10 @@ struct Plan {
     for (auto& it : iters) {
       if (it.insts) (void)hipFree(it.insts);
       if (it.ups) (void)hipFree(it.ups);
-      for (auto& g : it.groups)
+      for (auto& g : it.groups) {
         if (g.work) (void)hipFree(g.work);
+        if (g.counter) (void)hipFree(g.counter);
+      }
     }
   }
 };
@@ -565,6 +610,7 @@ static mppi_status build_plan(const std::vector<const mppi_ctx*>& ctxs, Plan** o
         for (int n0 = 0; n0 < c->N; n0 += R) work.push_back(make_int2(a, n0));
       }
       gl.blocks = (int)work.size();
+      HIP_TRY(hipMalloc(&gl.counter, sizeof(unsigned int)));
       HIP_TRY(hipMalloc(&gl.work, work.size() * sizeof(int2)));
       HIP_TRY(hipMemcpy(gl.work, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice));
       ip.groups.push_back(gl);
@@ -654,11 +700,188 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
   HIP_TRY(hipGetLastError());
   for (int it = 0; it < Imax; ++it) {
     IterPlan& ip = plan->iters[it];
-    for (auto& g : ip.groups) HIP_TRY(launch_rollout(g.G, g.blocks, ip.insts, g.work, g.E_max, s));
+    for (auto& g : ip.groups) {
+      if (g_persistent)
+        HIP_TRY(launch_persistent(g.G, g.blocks, ip.insts, g.work, g.E_max, g.counter, s));
+      else
+        HIP_TRY(launch_rollout(g.G, g.blocks, ip.insts, g.work, g.E_max, s));
+    }
     hipLaunchKernelGGL(update_kernel, dim3((unsigned)ip.active.size()), dim3(kUpdThreads), 0, s, ip.ups, d_outs + out_off[it],
                        UpdateOut{nullptr, nullptr, nullptr});
     HIP_TRY(hipGetLastError());
   }
+  return MPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graphs: a fixed batch captured once (tables uploaded at creation; the graph
+// holds kernels only) and replayed; every replay is one MPC step of every
+// instance and advances their ticks
+// ---------------------------------------------------------------------------
+struct mppi_graph {
+  Plan* plan = nullptr;
+  std::vector<const mppi_ctx*> ctxs;
+  void* dev_block = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" mppi_status mppi_graph_create(int32_t n, mppi_ctx* const* ctxs, const float* const* d_states,
+                                         const float* const* d_knots_in, float* const* d_knots_out,
+                                         float* const* d_best_knots, mppi_step_info* const* d_infos,
+                                         mppi_graph** out) {
+  if (n < 1 || !ctxs || !d_states || !d_knots_in || !d_knots_out || !out) return fail(MPPI_EINVAL, "null argument");
+  std::vector<const mppi_ctx*> list(n);
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !d_states[i] || !d_knots_in[i] || !d_knots_out[i]) return fail(MPPI_EINVAL, "null entry");
+    list[i] = ctxs[i];
+    for (int k = 0; k < i; ++k)
+      if (list[k] == list[i]) return fail(MPPI_EINVAL, "an instance appears twice in one batch");
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  // a graph owns its own plan (not the shared cache, which may evict)
+  Plan* plan = nullptr;
+  mppi_status st = build_plan(list, &plan);
+  if (st != MPPI_OK) return st;
+  auto owned = std::move(g_plans.back());
+  g_plans.pop_back();
+  const int Imax = (int)plan->iters.size();
+  size_t n_out = 0;
+  for (auto& ip : plan->iters) n_out += ip.active.size();
+  const size_t bytes = 2 * n * sizeof(StageItem) + n_out * sizeof(UpdateOut);
+  std::vector<char> host(bytes);
+  auto* items = reinterpret_cast<StageItem*>(host.data());
+  for (int i = 0; i < n; ++i) {
+    items[2 * i] = StageItem{d_states[i], list[i]->x0, list[i]->nq + list[i]->nv};
+    items[2 * i + 1] = StageItem{d_knots_in[i], list[i]->nom, list[i]->E};
+  }
+  auto* outs = reinterpret_cast<UpdateOut*>(items + 2 * n);
+  std::vector<size_t> out_off(Imax);
+  size_t off = 0;
+  for (int it = 0; it < Imax; ++it) {
+    out_off[it] = off;
+    for (int a : plan->iters[it].active) {
+      const bool last = list[a]->I - 1 == it;
+      outs[off++] = last ? UpdateOut{d_knots_out[a], d_best_knots ? d_best_knots[a] : nullptr,
+                                     d_infos ? (void*)d_infos[a] : nullptr}
+                         : UpdateOut{nullptr, nullptr, nullptr};
+    }
+  }
+  auto g = std::make_unique<mppi_graph>();
+  HIP_TRY(hipMalloc(&g->dev_block, bytes));
+  HIP_TRY(hipMemcpy(g->dev_block, host.data(), bytes, hipMemcpyHostToDevice));
+  auto* d_items = reinterpret_cast<StageItem*>(g->dev_block);
+  auto* d_outs = reinterpret_cast<UpdateOut*>(d_items + 2 * n);
+  hipStream_t cs;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(256), 0, cs, d_items);
+    for (int it = 0; it < Imax && e == hipSuccess; ++it) {
+      IterPlan& ip = plan->iters[it];
+      for (auto& gl : ip.groups) {
+        e = g_persistent ? launch_persistent(gl.G, gl.blocks, ip.insts, gl.work, gl.E_max, gl.counter, cs)
+                         : launch_rollout(gl.G, gl.blocks, ip.insts, gl.work, gl.E_max, cs);
+        if (e != hipSuccess) break;
+      }
+      hipLaunchKernelGGL(update_kernel, dim3((unsigned)ip.active.size()), dim3(kUpdThreads), 0, cs, ip.ups,
+                         d_outs + out_off[it], UpdateOut{nullptr, nullptr, nullptr});
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e2;
+    g->graph = graph;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    (void)hipFree(g->dev_block);
+    return fail(MPPI_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  g->plan = owned.release();
+  g->ctxs = list;
+  *out = g.release();
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_graph_launch(mppi_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(MPPI_EINVAL, "null graph");
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_graph_destroy(mppi_graph* g) {
+  if (!g) return fail(MPPI_EINVAL, "null graph");
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->dev_block) (void)hipFree(g->dev_block);
+  delete g->plan;
+  delete g;
+  return MPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: lanes per rollout of one instance, by timing real steps
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<const mppi_model*, int, int, int>, int> g_tuned;
+}
+
+extern "C" mppi_status mppi_autotune(mppi_ctx* c, const float* d_state, const float* d_knots, int32_t reps,
+                                     void* stream, int32_t* best_lanes) {
+  if (!c || !d_state || !d_knots) return fail(MPPI_EINVAL, "null argument");
+  const auto key = std::make_tuple(c->m, c->N, c->H, c->K);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      mppi_status st = mppi_set_lanes_per_rollout(c, it->second);
+      if (st == MPPI_OK && best_lanes) *best_lanes = it->second;
+      return st;
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t tick0 = 0;
+  HIP_TRY(hipMemcpy(&tick0, c->tick, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  float* scratch = nullptr;
+  HIP_TRY(hipMalloc(&scratch, c->E * sizeof(float)));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = c->lanes;
+  float best_ms = 1e30f;
+  const int first = next_pow2(c->m->host.nb);
+  reps = std::max(1, reps);
+  for (int G = first; G <= 64; G *= 2) {
+    mppi_status st = mppi_set_lanes_per_rollout(c, G);
+    if (st != MPPI_OK) break;
+    st = mppi_step(c, d_state, d_knots, scratch, nullptr, nullptr, nullptr, s);  // warm-up
+    if (st != MPPI_OK) break;
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) {
+      st = mppi_step(c, d_state, d_knots, scratch, nullptr, nullptr, nullptr, s);
+      if (st != MPPI_OK) break;
+    }
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) { best_ms = ms; best = G; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(scratch);
+  HIP_TRY(hipMemcpy(c->tick, &tick0, sizeof(uint32_t), hipMemcpyHostToDevice));
+  mppi_status st = mppi_set_lanes_per_rollout(c, best);
+  if (st != MPPI_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best;
+  }
+  if (best_lanes) *best_lanes = best;
   return MPPI_OK;
 }
 
@@ -824,5 +1047,305 @@ extern "C" mppi_status mppi_profile_read(mppi_ctx* c, double* rollout_ms, int32_
     for (auto& e : *v) c->ev_pool.push_back(e);
     v->clear();
   }
+  return MPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches of arbitrary composition without device allocation: launch tables
+// built on the host and uploaded in one async copy from the pinned ring
+// ---------------------------------------------------------------------------
+struct BatchReq {
+  mppi_ctx* ctx;
+  const float* state;
+  const float* knots_in;
+  float* knots_out;
+};
+
+static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsigned int* counters, int n_counters,
+                                        bool persistent, hipStream_t s) {
+  const int n = (int)reqs.size();
+  int Imax = 0;
+  for (auto& r : reqs) Imax = std::max(Imax, r.ctx->I);
+  struct GroupDesc { int G, E_max; size_t work_off; int n_items; };
+  struct IterDesc { size_t inst_off, up_off, out_off; int n_active; std::vector<GroupDesc> groups; };
+  std::vector<IterDesc> iters(Imax);
+  // sizes
+  size_t bytes = 2 * n * sizeof(StageItem);
+  std::vector<std::vector<int>> active(Imax);
+  for (int it = 0; it < Imax; ++it)
+    for (int i = 0; i < n; ++i)
+      if (reqs[i].ctx->I > it) active[it].push_back(i);
+  auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+  bytes = align(bytes);
+  for (int it = 0; it < Imax; ++it) {
+    IterDesc& d = iters[it];
+    d.n_active = (int)active[it].size();
+    d.inst_off = bytes; bytes = align(bytes + d.n_active * sizeof(DevInst));
+    d.up_off = bytes; bytes = align(bytes + d.n_active * sizeof(DevUpdate));
+    d.out_off = bytes; bytes = align(bytes + d.n_active * sizeof(UpdateOut));
+    std::map<int, std::vector<int>> byG;
+    for (int a = 0; a < d.n_active; ++a) byG[reqs[active[it][a]].ctx->lanes].push_back(a);
+    for (auto& kv : byG) {
+      GroupDesc g{kv.first, 0, bytes, 0};
+      const int R = 64 / g.G;
+      for (int a : kv.second) {
+        g.n_items += (reqs[active[it][a]].ctx->N + R - 1) / R;
+        g.E_max = std::max(g.E_max, reqs[active[it][a]].ctx->E);
+      }
+      bytes = align(bytes + g.n_items * sizeof(int2));
+      d.groups.push_back(g);
+    }
+  }
+  RingSlot* r = nullptr;
+  mppi_status st = ring_slot(bytes, &r);
+  if (st != MPPI_OK) return st;
+  char* h = reinterpret_cast<char*>(r->host);
+  char* dv = reinterpret_cast<char*>(r->dev);
+  auto* items = reinterpret_cast<StageItem*>(h);
+  for (int i = 0; i < n; ++i) {
+    items[2 * i] = StageItem{reqs[i].state, reqs[i].ctx->x0, reqs[i].ctx->nq + reqs[i].ctx->nv};
+    items[2 * i + 1] = StageItem{reqs[i].knots_in, reqs[i].ctx->nom, reqs[i].ctx->E};
+  }
+  for (int it = 0; it < Imax; ++it) {
+    IterDesc& d = iters[it];
+    auto* hi = reinterpret_cast<DevInst*>(h + d.inst_off);
+    auto* hu = reinterpret_cast<DevUpdate*>(h + d.up_off);
+    auto* ho = reinterpret_cast<UpdateOut*>(h + d.out_off);
+    for (int a = 0; a < d.n_active; ++a) {
+      const BatchReq& q = reqs[active[it][a]];
+      hi[a] = q.ctx->h_insts[it];
+      hu[a] = q.ctx->h_ups[it];
+      ho[a] = q.ctx->I - 1 == it ? UpdateOut{q.knots_out, nullptr, nullptr} : UpdateOut{nullptr, nullptr, nullptr};
+    }
+    std::map<int, std::vector<int>> byG;
+    for (int a = 0; a < d.n_active; ++a) byG[reqs[active[it][a]].ctx->lanes].push_back(a);
+    size_t gi = 0;
+    for (auto& kv : byG) {
+      GroupDesc& g = d.groups[gi++];
+      const int R = 64 / g.G;
+      std::vector<int> order = kv.second;
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const mppi_ctx* cx = reqs[active[it][x]].ctx;
+        const mppi_ctx* cy = reqs[active[it][y]].ctx;
+        return (long)cx->H * cx->m->host.nsub * cx->m->host.nb > (long)cy->H * cy->m->host.nsub * cy->m->host.nb;
+      });
+      auto* w = reinterpret_cast<int2*>(h + g.work_off);
+      int k = 0;
+      for (int a : order)
+        for (int n0 = 0; n0 < reqs[active[it][a]].ctx->N; n0 += R) w[k++] = make_int2(a, n0);
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(r->dev, r->host, bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(r->ev, s));
+  r->pending = true;
+  hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(256), 0, s, reinterpret_cast<StageItem*>(dv));
+  HIP_TRY(hipGetLastError());
+  int ci = 0;
+  for (int it = 0; it < Imax; ++it) {
+    IterDesc& d = iters[it];
+    auto* di = reinterpret_cast<const DevInst*>(dv + d.inst_off);
+    for (auto& g : d.groups) {
+      auto* w = reinterpret_cast<const int2*>(dv + g.work_off);
+      if (persistent && counters && ci < n_counters)
+        HIP_TRY(launch_persistent(g.G, g.n_items, di, w, g.E_max, counters + ci++, s));
+      else
+        HIP_TRY(launch_rollout(g.G, g.n_items, di, w, g.E_max, s));
+    }
+    hipLaunchKernelGGL(update_kernel, dim3((unsigned)d.n_active), dim3(kUpdThreads), 0, s,
+                       reinterpret_cast<const DevUpdate*>(dv + d.up_off), reinterpret_cast<const UpdateOut*>(dv + d.out_off),
+                       UpdateOut{nullptr, nullptr, nullptr});
+    HIP_TRY(hipGetLastError());
+  }
+  return MPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// serving: continuous batching of MPC ticks from many instances
+// ---------------------------------------------------------------------------
+namespace {
+using Clock = std::chrono::steady_clock;
+struct SrvReq {
+  mppi_ctx* ctx;
+  const float* state;
+  const float* knots_in;
+  float* knots_out;
+  Clock::time_point t_submit;
+  double latency = 0;
+  int status = 0;  // 0 pending, 1 on the device, 2 done
+};
+struct SrvSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  bool busy = false;
+  std::vector<uint64_t> tickets;
+  unsigned int* counters = nullptr;
+};
+}  // namespace
+
+struct mppi_server {
+  mppi_server_cfg cfg{};
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uint64_t> pending;
+  std::unordered_map<uint64_t, SrvReq> reqs;
+  std::unordered_map<const mppi_ctx*, int> busy;
+  std::vector<SrvSlot> slots;
+  std::thread worker;
+  std::atomic<bool> stop{false};
+  uint64_t next_ticket = 1;
+  std::string error;
+  int64_t launched_batches = 0, launched_requests = 0;
+};
+
+static void server_loop(mppi_server* S) {
+  (void)hipSetDevice(S->device);
+  std::vector<BatchReq> batch;
+  while (!S->stop.load()) {
+    bool progressed = false;
+    for (auto& sl : S->slots) {
+      if (!sl.busy) continue;
+      if (hipEventQuery(sl.ev) != hipSuccess) continue;
+      const auto now = Clock::now();
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (uint64_t t : sl.tickets) {
+        auto it = S->reqs.find(t);
+        if (it == S->reqs.end()) continue;
+        it->second.status = 2;
+        it->second.latency = std::chrono::duration<double>(now - it->second.t_submit).count();
+        S->busy.erase(it->second.ctx);
+      }
+      sl.tickets.clear();
+      sl.busy = false;
+      progressed = true;
+    }
+    for (auto& sl : S->slots) {
+      if (sl.busy) continue;
+      batch.clear();
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto it = S->pending.begin(); it != S->pending.end() && (int)batch.size() < S->cfg.max_batch;) {
+          SrvReq& r = S->reqs[*it];
+          if (S->busy.count(r.ctx)) { ++it; continue; }
+          S->busy[r.ctx] = 1;
+          r.status = 1;
+          batch.push_back(BatchReq{r.ctx, r.state, r.knots_in, r.knots_out});
+          sl.tickets.push_back(*it);
+          it = S->pending.erase(it);
+        }
+      }
+      if (batch.empty()) continue;
+      mppi_status st = MPPI_OK;
+      if (S->cfg.mode == 1) {
+        for (auto& b : batch) {
+          st = mppi_step(b.ctx, b.state, b.knots_in, b.knots_out, nullptr, nullptr, nullptr, sl.stream);
+          if (st != MPPI_OK) break;
+        }
+      } else {
+        std::lock_guard<std::mutex> lk(g_mu);
+        st = launch_batch_dynamic(batch, sl.counters, 64 * 5, S->cfg.persistent != 0, sl.stream);
+      }
+      if (st == MPPI_OK && hipEventRecord(sl.ev, sl.stream) != hipSuccess) st = MPPI_EDEVICE;
+      if (st != MPPI_OK) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->error = g_err.empty() ? "launch failed" : g_err;
+        S->stop = true;
+        break;
+      }
+      sl.busy = true;
+      S->launched_batches += 1;
+      S->launched_requests += (int64_t)batch.size();
+      progressed = true;
+    }
+    if (!progressed) {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait_for(lk, std::chrono::microseconds(20));
+    }
+  }
+}
+
+extern "C" mppi_status mppi_server_create(const mppi_server_cfg* cfg, mppi_server** out) {
+  if (!cfg || !out) return fail(MPPI_EINVAL, "null argument");
+  if (cfg->n_streams < 1 || cfg->n_streams > 8) return fail(MPPI_EINVAL, "n_streams must be in 1..8");
+  if (cfg->max_batch < 1 || cfg->max_pending < 1) return fail(MPPI_EINVAL, "max_batch and max_pending must be >= 1");
+  if (cfg->mode != 0 && cfg->mode != 1) return fail(MPPI_EINVAL, "mode must be 0 (batched) or 1 (plain)");
+  auto S = std::make_unique<mppi_server>();
+  S->cfg = *cfg;
+  HIP_TRY(hipGetDevice(&S->device));
+  S->slots.resize(cfg->n_streams);
+  for (auto& sl : S->slots) {
+    HIP_TRY(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+    HIP_TRY(hipMalloc(&sl.counters, 64 * 5 * sizeof(unsigned int)));
+  }
+  S->worker = std::thread(server_loop, S.get());
+  *out = S.release();
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_server_submit(mppi_server* S, mppi_ctx* c, const float* d_state, const float* d_knots_in,
+                                          float* d_knots_out, uint64_t* ticket) {
+  if (!S || !c || !d_state || !d_knots_in || !d_knots_out || !ticket) return fail(MPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stop) return fail(MPPI_EDEVICE, "server stopped: " + S->error);
+  if ((int)S->pending.size() >= S->cfg.max_pending) return fail(MPPI_ENOSLOT, "pending queue full");
+  const uint64_t t = S->next_ticket++;
+  S->reqs[t] = SrvReq{c, d_state, d_knots_in, d_knots_out, Clock::now()};
+  S->pending.push_back(t);
+  *ticket = t;
+  S->cv.notify_one();
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_server_poll(mppi_server* S, uint64_t ticket, int32_t* done, double* latency_s) {
+  if (!S || !done) return fail(MPPI_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(MPPI_EINVAL, "unknown ticket");
+  *done = it->second.status == 2 ? 1 : 0;
+  if (*done) {
+    if (latency_s) *latency_s = it->second.latency;
+    S->reqs.erase(it);
+  }
+  if (S->stop && !S->error.empty()) return fail(MPPI_EDEVICE, "server stopped: " + S->error);
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_server_drain(mppi_server* S, double timeout_s) {
+  if (!S) return fail(MPPI_EINVAL, "null server");
+  const auto t0 = Clock::now();
+  for (;;) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (S->stop && !S->error.empty()) return fail(MPPI_EDEVICE, "server stopped: " + S->error);
+      bool idle = S->pending.empty();
+      for (auto& sl : S->slots) idle = idle && !sl.busy;
+      if (idle) return MPPI_OK;
+    }
+    if (std::chrono::duration<double>(Clock::now() - t0).count() > timeout_s) return fail(MPPI_EBUSY, "drain timed out");
+    std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
+}
+
+extern "C" mppi_status mppi_server_stats(mppi_server* S, int64_t* batches, int64_t* requests) {
+  if (!S) return fail(MPPI_EINVAL, "null server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (batches) *batches = S->launched_batches;
+  if (requests) *requests = S->launched_requests;
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_server_destroy(mppi_server* S) {
+  if (!S) return fail(MPPI_EINVAL, "null server");
+  S->stop = true;
+  S->cv.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  for (auto& sl : S->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.counters) (void)hipFree(sl.counters);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  delete S;
   return MPPI_OK;
 }

@@ -413,7 +413,7 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
       float fn = 0.f;
       if (pw[2] < 0.f) fn = fmaxf(0.f, -M.k * pw[2] - M.d * vw[2]);
       const float n2 = vw[0] * vw[0] + vw[1] * vw[1] + M.eps * M.eps;
-      const float inv_nrm = rsq(n2), inv_n2 = inv_nrm * inv_nrm;
+      const float inv_nrm = rsq(n2);
       const float mfn = M.mu * fn * inv_nrm;
       const float fw[3] = {-mfn * vw[0], -mfn * vw[1], fn};
       float fB[3];
@@ -743,20 +743,15 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
 }
 
 // ---------------------------------------------------------------------------
-// Fused rollout kernel.  Block = one wavefront; work[blockIdx] = (instance,
-// first sample) or, when work is null, instance 0 and sample blockIdx * 64/G.
+// Fused rollout of one work item: 64/G rollouts of one instance, samples
+// w.y .. w.y + 64/G - 1 (those >= N are computed but not stored).
 // ---------------------------------------------------------------------------
 template <int G>
-__global__ __launch_bounds__(64) void rollout_kernel(const DevInst* __restrict__ insts, const int2* __restrict__ work,
-                                                     int group_stride) {
-  extern __shared__ float smem[];
-  constexpr int R = 64 / G;
+__device__ void rollout_item(const DevInst& I, int first, int group_stride, float* smem) {
   const int lane = threadIdx.x;
   const int grp = lane / G, l = lane % G;
-  const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
-  const DevInst& I = insts[w.x];
   const DevModel& M = *I.model;
-  const int n = w.y + grp;
+  const int n = first + grp;
   const bool valid = n < I.N;
   float* gs = smem + grp * group_stride;
   float* knots = gs + G * kSlot + 16;
@@ -833,6 +828,41 @@ __global__ __launch_bounds__(64) void rollout_kernel(const DevInst* __restrict__
     if (!isfinite(S)) S = INFINITY;
     I.costs[n] = S;
   }
+  wave_sync();
+}
+
+// Block = one wavefront; work[blockIdx] = (instance, first sample) or, when work
+// is null, instance 0 and sample blockIdx * 64/G.
+template <int G>
+__global__ __launch_bounds__(64) void rollout_kernel(const DevInst* __restrict__ insts, const int2* __restrict__ work,
+                                                     int group_stride) {
+  extern __shared__ float smem[];
+  constexpr int R = 64 / G;
+  const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
+  rollout_item<G>(insts[w.x], w.y, group_stride, smem);
+}
+
+// Persistent form: a grid sized to the resident wavefronts; each wavefront takes
+// work items from a device counter until the table is exhausted (every wavefront
+// reaches that exit).  Which wavefront runs an item does not change its result.
+template <int G>
+__global__ __launch_bounds__(64) void rollout_persistent_kernel(const DevInst* __restrict__ insts,
+                                                                const int2* __restrict__ work, int n_items,
+                                                                unsigned int* __restrict__ counter, int group_stride) {
+  extern __shared__ float smem[];
+  for (;;) {
+    int item = 0;
+    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    item = __builtin_amdgcn_readfirstlane(item);
+    if (item >= n_items) break;
+    const int2 w = work[item];
+    rollout_item<G>(insts[w.x], w.y, group_stride, smem);
+  }
+}
+
+__global__ void reset_counters(unsigned int* __restrict__ c, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) c[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1072,6 +1102,7 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
 // explicit instantiations
 #define MPPI_INST(G)                                                                                   \
   template __global__ void rollout_kernel<G>(const DevInst*, const int2*, int);                        \
+  template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int); \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void dynamics_kernel<G>(const DevModel*, int, const float*, const float*,        \
                                               const float*, const float*, float, float*, int);

@@ -62,8 +62,20 @@ EXPORTS = [
     "mppi_get_tick", "mppi_set_lanes_per_rollout", "mppi_get_lanes_per_rollout", "mppi_step",
     "mppi_step_batch", "mppi_debug_philox", "mppi_debug_samples", "mppi_debug_dynamics",
     "mppi_debug_rollouts", "mppi_debug_update", "mppi_profile_enable", "mppi_profile_read",
+    "mppi_set_batch_options", "mppi_graph_create", "mppi_graph_launch", "mppi_graph_destroy",
+    "mppi_autotune", "mppi_server_create", "mppi_server_submit", "mppi_server_poll",
+    "mppi_server_drain", "mppi_server_stats", "mppi_server_destroy",
     "mppi_last_error", "mppi_version",
 ]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("persistent", C.c_int32)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("max_pending", C.c_int32), ("n_streams", C.c_int32), ("max_batch", C.c_int32),
+                ("mode", C.c_int32), ("persistent", C.c_int32)]
 
 
 def lib():
@@ -91,10 +103,23 @@ def lib():
         L.mppi_profile_enable.argtypes = [vp, i32]
         L.mppi_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i32),
                                         C.POINTER(C.c_double), C.POINTER(i32)]
+        L.mppi_set_batch_options.argtypes = [C.POINTER(BatchOpts)]
+        L.mppi_graph_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
+        L.mppi_graph_launch.argtypes = [vp, vp]
+        L.mppi_graph_destroy.argtypes = [vp]
+        L.mppi_autotune.argtypes = [vp, vp, vp, i32, vp, C.POINTER(i32)]
+        L.mppi_server_create.argtypes = [C.POINTER(ServerCfg), C.POINTER(vp)]
+        L.mppi_server_submit.argtypes = [vp, vp, vp, vp, vp, C.POINTER(u64)]
+        L.mppi_server_poll.argtypes = [vp, u64, C.POINTER(i32), C.POINTER(C.c_double)]
+        L.mppi_server_drain.argtypes = [vp, C.c_double]
+        L.mppi_server_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.mppi_server_destroy.argtypes = [vp]
         L.mppi_last_error.restype = C.c_char_p
         L.mppi_version.restype = C.c_char_p
         for name in EXPORTS[:-2]:
             getattr(L, name).restype = C.c_int32
+        L.mppi_last_error.restype = C.c_char_p
+        L.mppi_version.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -286,6 +311,96 @@ def step_batch(ctrls, states, knots_in, knots_out, best_knots=None, infos=None, 
     bk = arr(best_knots) if best_knots is not None else None
     inf = arr(infos) if infos is not None else None
     _check(lib().mppi_step_batch(n, hs, st, ki, ko, bk, inf, _stream(stream)), "mppi_step_batch")
+
+
+def _ptr_array(xs):
+    n = len(xs)
+    return (C.c_void_p * n)(*[(x.h if isinstance(x, Controller) else x.data_ptr()) if x is not None else None
+                              for x in xs])
+
+
+def set_batch_options(persistent):
+    o = BatchOpts(1 if persistent else 0)
+    _check(lib().mppi_set_batch_options(C.byref(o)), "mppi_set_batch_options")
+
+
+class Graph:
+    """A fixed batch captured into a hipGraph; launch() = one step of every instance."""
+
+    def __init__(self, ctrls, states, knots_in, knots_out, best_knots=None, infos=None):
+        self._keep = (ctrls, states, knots_in, knots_out, best_knots, infos)
+        h = C.c_void_p()
+        _check(lib().mppi_graph_create(len(ctrls), _ptr_array(ctrls), _ptr_array(states),
+                                       _ptr_array(knots_in), _ptr_array(knots_out),
+                                       _ptr_array(best_knots) if best_knots is not None else None,
+                                       _ptr_array(infos) if infos is not None else None, C.byref(h)),
+               "mppi_graph_create")
+        self.h = h
+
+    def launch(self, stream=None):
+        _check(lib().mppi_graph_launch(self.h, _stream(stream)), "mppi_graph_launch")
+
+    def close(self):
+        if self.h:
+            _check(lib().mppi_graph_destroy(self.h), "mppi_graph_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(ctrl, state, knots, reps=3, stream=None):
+    g = C.c_int32()
+    _check(lib().mppi_autotune(ctrl.h, _ptr(state), _ptr(knots), int(reps), _stream(stream), C.byref(g)),
+           "mppi_autotune")
+    return g.value
+
+
+class Server:
+    """Continuous-batching server of MPC ticks (mode "batched" or "plain")."""
+
+    def __init__(self, n_streams=2, max_batch=256, max_pending=100000, mode="batched", persistent=False):
+        cfg = ServerCfg(int(max_pending), int(n_streams), int(max_batch), 0 if mode == "batched" else 1,
+                        1 if persistent else 0)
+        h = C.c_void_p()
+        _check(lib().mppi_server_create(C.byref(cfg), C.byref(h)), "mppi_server_create")
+        self.h = h
+
+    def submit(self, ctrl, state, knots_in, knots_out):
+        t = C.c_uint64()
+        _check(lib().mppi_server_submit(self.h, ctrl.h, _ptr(state), _ptr(knots_in), _ptr(knots_out),
+                                        C.byref(t)), "mppi_server_submit")
+        return t.value
+
+    def poll(self, ticket):
+        """None while running, else the submit-to-completion latency in seconds."""
+        done = C.c_int32()
+        lat = C.c_double()
+        _check(lib().mppi_server_poll(self.h, C.c_uint64(ticket), C.byref(done), C.byref(lat)),
+               "mppi_server_poll")
+        return lat.value if done.value else None
+
+    def drain(self, timeout_s=60.0):
+        _check(lib().mppi_server_drain(self.h, float(timeout_s)), "mppi_server_drain")
+
+    def stats(self):
+        b, r = C.c_int64(), C.c_int64()
+        _check(lib().mppi_server_stats(self.h, C.byref(b), C.byref(r)), "mppi_server_stats")
+        return b.value, r.value
+
+    def close(self):
+        if self.h:
+            _check(lib().mppi_server_destroy(self.h), "mppi_server_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def philox(ctr, key, out, stream=None):

@@ -1,0 +1,175 @@
+"""Batching and serving on the GPU: persistent launches, graph replays, the
+autotuner and the continuous-batching server.  Every path must reproduce the
+instance's own plain mppi_step bit for bit (same kernels, fixed-order
+reductions, device-resident ticks)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2511_19204_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2511_19204_amd import mppi
+
+
+def _t(x):
+    return torch.tensor(np.asarray(x), dtype=torch.float32, device="cuda")
+
+
+def _robots(n, seed=0):
+    """A small uneven mix (chain / quadruped / humanoid, K and H vary)."""
+    out = []
+    for (m, p, s) in synth.serving_mix(n, seed=seed):
+        p = dict(p)
+        p["n_samples"] = min(p["n_samples"], 96)
+        p["horizon"] = min(p["horizon"], 80)
+        model = mppi.Model(m)
+        out.append((m, p, s, model, mppi.Controller(model, p, s)))
+    return out
+
+
+def _buffers(robots):
+    st = [_t(m["x0"]) for (m, p, s, model, c) in robots]
+    ki = [_t(synth.nominal_knots(m, p["n_knots"])) for (m, p, s, model, c) in robots]
+    ko = [torch.zeros_like(k) for k in ki]
+    return st, ki, ko
+
+
+def _plain_reference(robots, ticks):
+    """Per-instance plain steps: knots after each of `ticks` warm-started steps."""
+    refs = []
+    for (m, p, s, model, c) in robots:
+        c.tick = 0
+        st = _t(m["x0"])
+        k = _t(synth.nominal_knots(m, p["n_knots"]))
+        seq = []
+        for _ in range(ticks):
+            out = torch.zeros_like(k)
+            c.step(st, k, out)
+            torch.cuda.synchronize()
+            seq.append(out.cpu().numpy())
+            k = out
+        refs.append(seq)
+    return refs
+
+
+@pytest.fixture(scope="module")
+def mix():
+    robots = _robots(6)
+    return robots, _plain_reference(robots, 3)
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batched_steps_equal_plain_steps(mix, persistent):
+    robots, refs = mix
+    mppi.set_batch_options(persistent)
+    try:
+        for (*_, c) in robots:
+            c.tick = 0
+        st, ki, ko = _buffers(robots)
+        ctrls = [c for (*_, c) in robots]
+        for t in range(3):
+            mppi.step_batch(ctrls, st, ki, ko)
+            torch.cuda.synchronize()
+            for i in range(len(robots)):
+                assert np.array_equal(ko[i].cpu().numpy(), refs[i][t]), (persistent, t, i)
+            ki = [k.clone() for k in ko]
+    finally:
+        mppi.set_batch_options(False)
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_graph_replays_equal_eager_steps(mix, persistent):
+    """Replay the captured batch several times, with eager work and syncs between
+    replays; every replay must equal the plain step of the same tick."""
+    robots, refs = mix
+    mppi.set_batch_options(persistent)
+    try:
+        for (*_, c) in robots:
+            c.tick = 0
+        st, ki, ko = _buffers(robots)
+        ctrls = [c for (*_, c) in robots]
+        g = mppi.Graph(ctrls, st, ki, ko)
+        for t in range(3):
+            g.launch()
+            torch.cuda.synchronize()
+            _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
+            for i in range(len(robots)):
+                assert np.array_equal(ko[i].cpu().numpy(), refs[i][t]), (persistent, t, i)
+            for i in range(len(robots)):
+                ki[i].copy_(ko[i])  # warm start in place: the graph reads the same buffers
+            torch.cuda.synchronize()
+        g.close()
+    finally:
+        mppi.set_batch_options(False)
+
+
+def test_autotune_picks_a_valid_lane_count_without_changing_results():
+    m, p, s = synth.config("quadruped", n_samples=256)
+    model = mppi.Model(m)
+    c = mppi.Controller(model, p, s)
+    st, k = _t(m["x0"]), _t(synth.nominal_knots(m, p["n_knots"]))
+    c.tick = 5
+    a = torch.zeros_like(k)
+    c.step(st, k, a)
+    c.tick = 5
+    g = mppi.autotune(c, st, k, reps=2)
+    assert g in (16, 32, 64) and c.lanes == g and c.tick == 5
+    b = torch.zeros_like(k)
+    c.step(st, k, b)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_server_result_is_the_same_alone_and_in_the_mix(mix, mode):
+    """Robot 0 served alone, then in a mix where the other robots' ticks arrive in
+    between (continuous batching): its knots after every tick equal the plain
+    step's, and so do every other robot's."""
+    robots, refs = mix
+    srv = mppi.Server(n_streams=2, max_batch=64, mode=mode)
+    try:
+        # alone
+        (m0, p0, s0, model0, c0) = robots[0]
+        c0.tick = 0
+        st0 = _t(m0["x0"])
+        k0 = _t(synth.nominal_knots(m0, p0["n_knots"]))
+        for t in range(3):
+            out = torch.zeros_like(k0)
+            tk = srv.submit(c0, st0, k0, out)
+            while srv.poll(tk) is None:
+                time.sleep(1e-4)
+            assert np.array_equal(out.cpu().numpy(), refs[0][t])
+            k0 = out
+        # in the mix: every robot submits 3 ticks, staggered, at most one outstanding each
+        for (*_, c) in robots:
+            c.tick = 0
+        st, ki, _ = _buffers(robots)
+        outs = [[torch.zeros_like(ki[i]) for _ in range(3)] for i in range(len(robots))]
+        nxt = [0] * len(robots)
+        live = {}
+        rng = np.random.default_rng(0)
+        while any(n < 3 for n in nxt) or live:
+            for i in rng.permutation(len(robots)):
+                if i not in live and nxt[i] < 3:
+                    src = ki[i] if nxt[i] == 0 else outs[i][nxt[i] - 1]
+                    live[i] = srv.submit(robots[i][4], st[i], src, outs[i][nxt[i]])
+                    nxt[i] += 1
+            for i in list(live):
+                if srv.poll(live[i]) is not None:
+                    del live[i]
+            time.sleep(2e-4)
+        srv.drain()
+        for i in range(len(robots)):
+            for t in range(3):
+                assert np.array_equal(outs[i][t].cpu().numpy(), refs[i][t]), (mode, i, t)
+        batches, requests = srv.stats()
+        assert requests == 3 + 3 * len(robots)
+        if mode == "batched":
+            assert batches < requests  # ticks were batched together
+    finally:
+        srv.close()
