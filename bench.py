@@ -12,7 +12,12 @@ Also reported:
   batched_vs_plain 64 robots drawn from the serving mix (chain / quadruped /
                    humanoid, K in 32..1024, H in 50..200, 3 iterations): one
                    plain mppi_step per robot in sequence vs one fused
-                   mppi_step_batch, rollout-steps/s and per-robot tick latency;
+                   mppi_step_batch vs its captured hipGraph, rollout-steps/s and
+                   per-robot tick latency;
+  serving          the same robots ticking as Poisson processes at 50 Hz for a few
+                   seconds, served with continuous batching vs plain per-instance
+                   launches: throughput, p50/p99 latency from tick arrival, 20 ms
+                   deadline misses;
   roofline         the rollout kernel: algorithmic FP32 operations per launch
                    (flops.flops_per_rollout_step x K x H) / its mean duration,
                    against the FP32 vector peak (ALU-bound path);
@@ -145,8 +150,18 @@ def batched_vs_plain(args, torch, mppi, synth):
         end.record(stream)
         return start, [end] * len(made)
 
+    graph = mppi.Graph(ctrls, states, kins, kouts)
+
+    def graph_round():
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        graph.launch()
+        end.record(stream)
+        return start, [end] * len(made)
+
     out = {}
-    for name, fn in (("plain", plain_round), ("batched", batched_round)):
+    for name, fn in (("plain", plain_round), ("batched", batched_round), ("graph", graph_round)):
         fn()  # warm-up (builds the batched launch plan once)
         torch.cuda.synchronize()
         lat = []
@@ -158,10 +173,63 @@ def batched_vs_plain(args, torch, mppi, synth):
             lat.extend(start.elapsed_time(e) for e in ends)
         out[name] = {"rollout_steps_per_s": work * rounds / wall, "ms_per_round": 1e3 * wall / rounds,
                      "tick_latency_p50_ms": _pct(lat, 50), "tick_latency_p99_ms": _pct(lat, 99)}
+    graph.close()
     out["robots"] = len(made)
     out["rollout_steps_per_round"] = work
     out["speedup"] = out["batched"]["rollout_steps_per_s"] / out["plain"]["rollout_steps_per_s"]
     return out
+
+
+def serving(args, torch, mppi, synth, mode):
+    """Poisson MPC ticks (50 Hz per robot) from the 64-robot mix, served by the
+    continuous-batching server (mode "batched") or by plain per-instance steps
+    (mode "plain"); at most one outstanding tick per robot, so a tick that arrives
+    while the robot's previous one runs waits, and its latency counts from arrival."""
+    robots = synth.serving_mix(args.robots, seed=0)
+    ticks = synth.poisson_ticks(len(robots), args.serve_seconds, rate_hz=50.0, seed=0)
+    made = []
+    for (m, p, seed) in robots:
+        model = mppi.Model(m)
+        c = mppi.Controller(model, p, seed)
+        st = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
+        k = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
+        made.append((model, c, st, k, p["n_samples"] * p["horizon"] * p["n_iters"]))
+    srv = mppi.Server(n_streams=args.serve_streams, max_batch=len(made), mode=mode)
+    # warm-up: one tick per robot
+    tk = [srv.submit(c, st, k, k) for (_, c, st, k, _) in made]
+    srv.drain()
+    for t in tk:
+        srv.poll(t)
+    torch.cuda.synchronize()
+    nxt = [0] * len(made)
+    live = {}
+    lat, work_done = [], 0
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        for i, (_, c, st, k, w) in enumerate(made):
+            if i not in live and nxt[i] < len(ticks[i]) and ticks[i][nxt[i]] <= now:
+                arrival = ticks[i][nxt[i]]
+                live[i] = (srv.submit(c, st, k, k), arrival, time.perf_counter() - t0, w)
+                nxt[i] += 1
+        for i in list(live):
+            ticket, arrival, sub, w = live[i]
+            srv_lat = srv.poll(ticket)
+            if srv_lat is not None:
+                lat.append((sub - arrival) + srv_lat)
+                work_done += w
+                del live[i]
+        if not live and all(nxt[i] >= len(ticks[i]) for i in range(len(made))):
+            break
+        time.sleep(5e-5)
+    wall = time.perf_counter() - t0
+    batches, requests = srv.stats()
+    srv.close()
+    lat_ms = np.asarray(lat) * 1e3
+    return {"rollout_steps_per_s": work_done / wall, "ticks": len(lat), "wall_s": wall,
+            "tick_latency_p50_ms": _pct(lat_ms, 50), "tick_latency_p99_ms": _pct(lat_ms, 99),
+            "deadline_miss_frac": float(np.mean(lat_ms > 20.0)), "batches": batches,
+            "ticks_per_batch": requests / max(batches, 1)}
 
 
 def cpu_baseline(args, res):
@@ -176,12 +244,15 @@ def cpu_baseline(args, res):
     count = args.cpu_sample
     kn = synth.nominal_knots(m, p["n_knots"])
     O.rollouts(m, p, m["x0"], kn, 1000, 1, 0, 0, cores, threads=cores)  # warm-up
+    reps = max(1, args.cpu_reps)
     t0 = time.perf_counter()
-    O.rollouts(m, p, m["x0"], kn, 1000, 1, 0, 0, count, threads=cores)
+    for r in range(reps):
+        O.rollouts(m, p, m["x0"], kn, 1000, 1 + r, 0, 0, count, threads=cores)
     dt = time.perf_counter() - t0
-    return {"value": count * p["horizon"] / dt, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{count} of the {p['n_samples']} rollouts of one step (H={p['horizon']}), FP64, "
-                      f"OpenMP over samples, {dt:.1f} s wall"}
+    return {"value": reps * count * p["horizon"] / dt, "unit": "rollout-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{reps} steps x {count} of the {p['n_samples']} rollouts (H={p['horizon']}), FP64, "
+                      f"OpenMP over samples, {dt:.1f} s wall ({dt * cores:.0f} core-s)"}
 
 
 def main():
@@ -194,8 +265,12 @@ def main():
     ap.add_argument("--robots", type=int, default=64)
     ap.add_argument("--rounds", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-streams", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -218,6 +293,12 @@ def main():
         del a, b
     res = primary(args, torch, mppi, synth, flops)
     bvp = None if args.no_batch else batched_vs_plain(args, torch, mppi, synth)
+    srv = None
+    if not args.no_serve:
+        srv = {"batched": serving(args, torch, mppi, synth, "batched"),
+               "plain": serving(args, torch, mppi, synth, "plain"),
+               "robots": args.robots, "rate_hz": 50.0, "deadline_ms": 20.0,
+               "seconds": args.serve_seconds}
     cpu = None if args.no_cpu else cpu_baseline(args, res)
     digest = kernel_source_digest()
     traffic = measured_traffic(digest)
@@ -262,6 +343,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "batched_vs_plain": bvp,
+        "serving": srv,
     }
     print(json.dumps(out), flush=True)
 

@@ -536,6 +536,7 @@ struct Plan {
   int device = 0;
   std::vector<IterPlan> iters;
   ~Plan() {
+    (void)hipDeviceSynchronize();  // kernels of earlier calls may still read these tables
     for (auto& it : iters) {
       if (it.insts) (void)hipFree(it.insts);
       if (it.ups) (void)hipFree(it.ups);
@@ -627,6 +628,7 @@ static mppi_status ring_slot(size_t bytes, RingSlot** out) {
   RingSlot& r = g_ring[g_ring_next];
   g_ring_next = (g_ring_next + 1) % (int)g_ring.size();
   if (r.pending) {
+    // waits for the last kernel that read this slot's tables (any stream)
     HIP_TRY(hipEventSynchronize(r.ev));
     r.pending = false;
   }
@@ -692,7 +694,9 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
     }
   }
   HIP_TRY(hipMemcpyAsync(r->dev, r->host, bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(r->ev, s));
+  // the slot is reusable only once every kernel reading its tables has finished:
+  // its event is recorded after the last of them (below), since another call may
+  // run on another stream
   r->pending = true;
   auto* d_items = reinterpret_cast<StageItem*>(r->dev);
   auto* d_outs = reinterpret_cast<UpdateOut*>(d_items + 2 * n);
@@ -710,6 +714,7 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
                        UpdateOut{nullptr, nullptr, nullptr});
     HIP_TRY(hipGetLastError());
   }
+  HIP_TRY(hipEventRecord(r->ev, s));
   return MPPI_OK;
 }
 
@@ -1136,8 +1141,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
     }
   }
   HIP_TRY(hipMemcpyAsync(r->dev, r->host, bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(r->ev, s));
-  r->pending = true;
+  r->pending = true;  // event recorded after the last kernel reading the tables
   hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(256), 0, s, reinterpret_cast<StageItem*>(dv));
   HIP_TRY(hipGetLastError());
   int ci = 0;
@@ -1156,6 +1160,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
                        UpdateOut{nullptr, nullptr, nullptr});
     HIP_TRY(hipGetLastError());
   }
+  HIP_TRY(hipEventRecord(r->ev, s));
   return MPPI_OK;
 }
 

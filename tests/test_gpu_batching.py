@@ -173,3 +173,39 @@ def test_server_result_is_the_same_alone_and_in_the_mix(mix, mode):
             assert batches < requests  # ticks were batched together
     finally:
         srv.close()
+
+
+def test_server_three_streams_many_uneven_batches():
+    """Regression: batches of very different sizes on three streams recycle the
+    per-call launch-table buffers while earlier batches still run on other
+    streams; a buffer may only be reused after the last kernel reading it ends.
+    Every result must still equal the plain step."""
+    robots = _robots(16, seed=3)
+    ticks = 6
+    refs = _plain_reference(robots, ticks)
+    srv = mppi.Server(n_streams=3, max_batch=5, mode="batched")
+    try:
+        for (*_, c) in robots:
+            c.tick = 0
+        st, ki, _ = _buffers(robots)
+        outs = [[torch.zeros_like(ki[i]) for _ in range(ticks)] for i in range(len(robots))]
+        nxt = [0] * len(robots)
+        live = {}
+        rng = np.random.default_rng(1)
+        while any(n < ticks for n in nxt) or live:
+            for i in rng.permutation(len(robots))[: rng.integers(1, len(robots) + 1)]:
+                if i not in live and nxt[i] < ticks:
+                    src = ki[i] if nxt[i] == 0 else outs[i][nxt[i] - 1]
+                    live[i] = srv.submit(robots[i][4], st[i], src, outs[i][nxt[i]])
+                    nxt[i] += 1
+            for i in list(live):
+                if srv.poll(live[i]) is not None:
+                    del live[i]
+        srv.drain()
+        for i in range(len(robots)):
+            for t in range(ticks):
+                assert np.array_equal(outs[i][t].cpu().numpy(), refs[i][t]), (i, t)
+        batches, requests = srv.stats()
+        assert requests == ticks * len(robots) and batches > 8
+    finally:
+        srv.close()
