@@ -76,7 +76,7 @@ def measured_traffic(digest):
 def primary(args, torch, mppi, synth, flops):
     m, p, seed = synth.config("quadruped_tp", n_samples=args.samples)
     model = mppi.Model(m)
-    ctrl = mppi.Controller(model, p, seed, lanes=args.lanes)
+    ctrl = mppi.Controller(model, p, seed, lanes=args.lanes, schedule=args.schedule)
     st = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
     k0 = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
     ka, kb = k0.clone(), torch.zeros_like(k0)
@@ -110,6 +110,7 @@ def primary(args, torch, mppi, synth, flops):
         "wall": wall, "value": steps_rollout * args.steps / wall, "lat": lat,
         "kernel_ms": roll_ms / max(n_roll, 1), "update_ms": upd_ms / max(n_upd, 1),
         "achieved_tflops": achieved, "flops_per_rollout_step": fl, "lanes": ctrl.lanes,
+        "schedule": ctrl.schedule,
     }
     return res
 
@@ -119,7 +120,7 @@ def batched_vs_plain(args, torch, mppi, synth):
     made = []
     for (m, p, seed) in robots:
         model = mppi.Model(m)
-        c = mppi.Controller(model, p, seed)
+        c = mppi.Controller(model, p, seed, schedule=args.schedule)
         st = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
         ki = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
         ko = torch.zeros_like(ki)
@@ -190,7 +191,7 @@ def serving(args, torch, mppi, synth, mode):
     made = []
     for (m, p, seed) in robots:
         model = mppi.Model(m)
-        c = mppi.Controller(model, p, seed)
+        c = mppi.Controller(model, p, seed, schedule=args.schedule)
         st = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
         k = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
         made.append((model, c, st, k, p["n_samples"] * p["horizon"] * p["n_iters"]))
@@ -261,7 +262,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--samples", type=int, default=4096)
-    ap.add_argument("--lanes", type=int, default=0, help="lanes per rollout (0 = automatic)")
+    ap.add_argument("--lanes", type=int, default=0, help="body schedule with this many lanes per rollout")
+    ap.add_argument("--schedule", choices=["body", "chain"], default=None,
+                    help="rollout schedule (default: the library's choice)")
     ap.add_argument("--robots", type=int, default=64)
     ap.add_argument("--rounds", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=4096)
@@ -324,6 +327,7 @@ def main():
                         "soft contact k=2e4 d=200 mu=0.8, linear noise std 0.05->0.4 rad",
             "samples": p["n_samples"], "horizon": p["horizon"], "knots": p["n_knots"],
             "iterations_per_step": p["n_iters"], "lanes_per_rollout": res["lanes"],
+            "schedule": res["schedule"],
             "parallelism": "single GPU",
         },
         "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)},
@@ -335,7 +339,8 @@ def main():
             "frac": res["achieved_tflops"] / FP32_PEAK_TFLOPS,
             "frac_nonpacked_peak": res["achieved_tflops"] / FP32_PEAK_NONPACKED,
             "traffic": traffic,
-            "kernel": f"rollout_kernel<{res['lanes']}>",
+            "kernel": (f"chain_kernel<{res['lanes']}>" if res["schedule"] == "chain"
+                       else f"rollout_kernel<{res['lanes']}>"),
             "kernel_ms": res["kernel_ms"],
             "update_kernel_ms": res["update_ms"],
             "flops_per_rollout_step": res["flops_per_rollout_step"],

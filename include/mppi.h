@@ -139,8 +139,25 @@ mppi_status mppi_destroy(mppi_ctx* c);
 mppi_status mppi_set_tick(mppi_ctx* c, uint32_t tick);
 mppi_status mppi_get_tick(const mppi_ctx* c, uint32_t* tick);
 
-/* Launch shape: lanes per rollout (a power of two 4..64 holding every body, or
- * 0 = automatic).  Any valid value gives identical results. */
+/* Rollout schedule: how the lanes of a wavefront share the rigid-body tree of
+ * one rollout (the articulated-body sweeps of the forward dynamics).
+ *   MPPI_SCHEDULE_BODY   one lane per body; the tree is swept level by level,
+ *                        lanes per rollout = a power of two 4..64 >= n_bodies.
+ *   MPPI_SCHEDULE_CHAIN  one lane per kinematic chain of the tree's heavy-path
+ *                        decomposition (a body continues its parent's chain when
+ *                        it heads the parent's largest subtree); each lane walks
+ *                        its chain, lanes per rollout = the next power of two
+ *                        >= the number of chains.  Needs at most 8 chains and
+ *                        tree depth <= 15 (MPPI_EINVAL otherwise).
+ * Every schedule and lane count gives bit-identical results; they differ in
+ * speed only (mppi_autotune picks).  A new context uses the body schedule with
+ * the smallest lane count that holds the tree.
+ * mppi_set_lanes_per_rollout selects the body schedule with `lanes` lanes (0 =
+ * the smallest valid count); mppi_get_lanes_per_rollout reports the lane count
+ * of the current schedule. */
+typedef enum { MPPI_SCHEDULE_BODY = 0, MPPI_SCHEDULE_CHAIN = 1 } mppi_schedule;
+mppi_status mppi_set_schedule(mppi_ctx* c, int32_t schedule);
+mppi_status mppi_get_schedule(const mppi_ctx* c, int32_t* schedule);
 mppi_status mppi_set_lanes_per_rollout(mppi_ctx* c, int32_t lanes);
 mppi_status mppi_get_lanes_per_rollout(const mppi_ctx* c, int32_t* lanes);
 
@@ -185,11 +202,12 @@ mppi_status mppi_graph_create(int32_t n, mppi_ctx* const* ctxs, const float* con
 mppi_status mppi_graph_launch(mppi_graph* g, void* stream);
 mppi_status mppi_graph_destroy(mppi_graph* g);
 
-/* Autotuner: times `reps` steps of the instance from (d_state, d_knots) for each
- * valid lanes-per-rollout value and keeps the fastest; results are cached per
- * (model, N, H, K) for the process.  The instance's tick is restored.  Blocks
- * until the timing steps finish.  Writes the chosen value to *best_lanes
- * (nullable). */
+/* Autotuner: times `reps` steps of the instance from (d_state, d_knots) for the
+ * body schedule at each valid lane count and for the chain schedule, and keeps
+ * the fastest; results are cached per (model, N, H, K) for the process.  The
+ * instance's tick is restored.  Blocks until the timing steps finish.  Writes
+ * the chosen lane count to *best_lanes (nullable); mppi_get_schedule tells the
+ * schedule. */
 mppi_status mppi_autotune(mppi_ctx* c, const float* d_state, const float* d_knots, int32_t reps, void* stream,
                           int32_t* best_lanes);
 

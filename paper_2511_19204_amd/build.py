@@ -2,7 +2,9 @@
 
 The kernels and the C-ABI host runtime are compiled together into one shared
 library next to this file.  Packed-FP32 instruction selection is disabled
-(-packed-fp32-ops) and fast-math is off; FMA contraction stays on.
+(-packed-fp32-ops) and fast-math is off; multiply-adds are contracted within one
+expression only (-ffp-contract=on), so an inlined helper rounds the same way
+in every kernel that uses it.
 """
 import os
 import subprocess
@@ -16,7 +18,7 @@ ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-fno-fast-math", "-Wall", "-Wno-unused-function",
+         "-fno-fast-math", "-ffp-contract=on", "-Wall", "-Wno-unused-function",
          "-I", os.path.join(ROOT, "include")]
 
 

@@ -27,6 +27,8 @@ namespace mppi {
 // kernels (mppi_kernels.hip)
 template <int G> __global__ void rollout_kernel(const DevInst*, const int2*, int);
 template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int);
+template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
+template <int GC> __global__ void chain_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int, int);
 __global__ void reset_counters(unsigned int*, int);
 template <int G> __global__ void sample_kernel(const DevInst*, int);
 template <int G>
@@ -45,13 +47,7 @@ struct StageItem {
 };
 __global__ void stage_kernel(const StageItem*);
 __global__ void philox_kernel(const uint32_t*, const uint32_t*, uint32_t*, int);
-constexpr int kSlot = 29;
 constexpr int kUpdThreads = 1024;
-inline int group_floats(int G, int E) {
-  const int raw = G * kSlot + 16 + ((E + 3) & ~3) + G;
-  const int want = G < 32 ? G : 0;
-  return raw + ((want - raw % 32) + 64) % 32;
-}
 }  // namespace mppi
 
 using namespace mppi;
@@ -123,6 +119,89 @@ static int next_pow2(int x) {
 static bool valid_lanes(int G, const DevModel& M) { return (G == 4 || G == 8 || G == 16 || G == 32 || G == 64) && G >= M.nb; }
 
 static int lds_bytes(int G, int E) { return (64 / G) * group_floats(G, E) * (int)sizeof(float); }
+
+// ---------------------------------------------------------------------------
+// chain schedule tables: heavy-path decomposition and the per-body rows
+// ---------------------------------------------------------------------------
+static void build_chain_tables(DevModel& M) {
+  const int nb = M.nb;
+  auto bits = [](int x) {
+    float f;
+    std::memcpy(&f, &x, sizeof(f));
+    return f;
+  };
+  // subtree sizes (parents precede children) and the heavy child of every body
+  std::vector<int> size(nb, 1), heavy(nb, -1);
+  for (int i = nb - 1; i > 0; --i)
+    if (M.parent[i] >= 0) size[M.parent[i]] += size[i];
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < M.n_child[b]; ++k) {
+      const int ch = M.child[b][k];
+      if (heavy[b] < 0 || size[ch] > size[heavy[b]]) heavy[b] = ch;
+    }
+  // chains: a body starts a chain unless it is its parent's heavy child
+  std::vector<int> chain_of(nb, -1), att(nb, -1);
+  int nch = 0, natt = 0;
+  bool ok = M.n_levels <= kMaxLevels;
+  for (int b = 0; b < nb; ++b) {
+    const int lam = M.parent[b];
+    if (lam >= 0 && heavy[lam] == b) continue;
+    if (nch >= kMaxChains) { ok = false; break; }
+    const int c = nch++;
+    for (int d = 0; d < kMaxLevels; ++d) M.chain_body[c][d] = -1;
+    M.chain_first[c] = M.depth[b];
+    M.chain_att[c] = -1;
+    if (lam >= 0) {
+      if (att[lam] < 0) att[lam] = natt++;
+      M.chain_att[c] = att[lam];
+    }
+    for (int x = b; x >= 0; x = heavy[x]) {
+      chain_of[x] = c;
+      if (M.depth[x] < kMaxLevels) M.chain_body[c][M.depth[x]] = x;
+    }
+  }
+  for (int c = nch; c < kMaxChains; ++c) {
+    for (int d = 0; d < kMaxLevels; ++d) M.chain_body[c][d] = -1;
+    M.chain_first[c] = 0;
+    M.chain_att[c] = -1;
+  }
+  M.chain_ok = ok ? 1 : 0;
+  M.n_chains = ok ? nch : 0;
+  M.n_att = natt;
+  int lanes = 1;
+  while (lanes < nch) lanes <<= 1;
+  M.chain_lanes = lanes;
+  for (int b = 0; b < nb; ++b) {
+    float* r = M.rows[b];
+    for (int k = 0; k < kRow; ++k) r[k] = 0.f;
+    for (int k = 0; k < 27; ++k) r[row::P + k] = M.P[b][k];
+    for (int k = 0; k < 3; ++k) {
+      r[row::p_tree + k] = M.p_tree[b][k];
+      r[row::axis_p + k] = M.axis_p[b][k];
+      r[row::com + k] = M.com[b][k];
+    }
+    for (int k = 0; k < 6; ++k) r[row::Ic + k] = M.Ic[b][k];
+    r[row::mass] = M.mass[b];
+    const int j = b - M.fb;
+    if (j >= 0) {
+      r[row::kp] = M.kp[j]; r[row::kd] = M.kd[j]; r[row::taumax] = M.taumax[j]; r[row::arm] = M.arm[j];
+    }
+    r[row::parent] = bits(M.parent[b]);
+    r[row::c_begin] = bits(M.c_begin[b]);
+    r[row::c_count] = bits(M.c_count[b]);
+    r[row::n_child] = bits(M.n_child[b]);
+    r[row::heavy] = bits(heavy[b]);
+    r[row::att] = bits(att[b]);
+    r[row::chain] = bits(chain_of[b]);
+    r[row::depth] = bits(M.depth[b]);
+    for (int k = 0; k < kMaxChildren; ++k) r[row::child + k] = bits(k < M.n_child[b] ? M.child[b][k] : -1);
+  }
+  for (int ci = 0; ci < M.nc; ++ci) {
+    for (int k = 0; k < kCt; ++k) M.ctab[ci][k] = 0.f;
+    for (int k = 0; k < 3; ++k) M.ctab[ci][k] = M.cpos[ci][k];
+    M.ctab[ci][4] = bits(M.corig[ci]);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // model
@@ -218,6 +297,7 @@ extern "C" mppi_status mppi_model_create(const mppi_model_desc* d, mppi_model** 
     }
     M.c_count[b] = ci - M.c_begin[b];
   }
+  build_chain_tables(M);
   // base spatial inertia about its own origin (packed symmetric 6x6)
   if (fb) {
     const double mm = d->mass[0];
@@ -409,67 +489,155 @@ extern "C" mppi_status mppi_get_tick(const mppi_ctx* c, uint32_t* tick) {
   return MPPI_OK;
 }
 
-extern "C" mppi_status mppi_set_lanes_per_rollout(mppi_ctx* c, int32_t lanes) {
-  if (!c) return fail(MPPI_EINVAL, "null context");
-  const int G = lanes == 0 ? next_pow2(c->m->host.nb) : lanes;
-  if (!valid_lanes(G, c->m->host)) return fail(MPPI_EINVAL, "lanes must be a power of two in 4..64 holding every body");
-  c->lanes = G;
-  for (auto& d : c->h_insts) d.lanes = G;
+// The launch key of an instance: G > 0 selects the body schedule with G lanes per
+// rollout, -GC the chain schedule with GC lanes per rollout.
+static mppi_status set_key(mppi_ctx* c, int key) {
+  c->lanes = key;
+  for (auto& d : c->h_insts) d.lanes = key;
   HIP_TRY(hipMemcpy(c->d_insts, c->h_insts.data(), c->I * sizeof(DevInst), hipMemcpyHostToDevice));
   purge_plans(c);
   return MPPI_OK;
 }
 
+extern "C" mppi_status mppi_set_lanes_per_rollout(mppi_ctx* c, int32_t lanes) {
+  if (!c) return fail(MPPI_EINVAL, "null context");
+  const int G = lanes == 0 ? next_pow2(c->m->host.nb) : lanes;
+  if (!valid_lanes(G, c->m->host)) return fail(MPPI_EINVAL, "lanes must be a power of two in 4..64 holding every body");
+  return set_key(c, G);
+}
+
 extern "C" mppi_status mppi_get_lanes_per_rollout(const mppi_ctx* c, int32_t* lanes) {
   if (!c || !lanes) return fail(MPPI_EINVAL, "null argument");
-  *lanes = c->lanes;
+  *lanes = c->lanes > 0 ? c->lanes : -c->lanes;
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_set_schedule(mppi_ctx* c, int32_t schedule) {
+  if (!c) return fail(MPPI_EINVAL, "null context");
+  const DevModel& M = c->m->host;
+  if (schedule == MPPI_SCHEDULE_BODY) return set_key(c, next_pow2(M.nb));
+  if (schedule != MPPI_SCHEDULE_CHAIN) return fail(MPPI_EINVAL, "unknown schedule");
+  if (!M.chain_ok) return fail(MPPI_EINVAL, "tree has more than 8 chains or depth above 15");
+  return set_key(c, -M.chain_lanes);
+}
+
+extern "C" mppi_status mppi_get_schedule(const mppi_ctx* c, int32_t* schedule) {
+  if (!c || !schedule) return fail(MPPI_EINVAL, "null argument");
+  *schedule = c->lanes > 0 ? MPPI_SCHEDULE_BODY : MPPI_SCHEDULE_CHAIN;
   return MPPI_OK;
 }
 
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
+// A launch key selects the schedule: G > 0 is the body schedule with G lanes per
+// rollout, -GC < 0 the chain schedule with GC lanes per rollout.
+static int key_lanes(int key) { return key > 0 ? key : -key; }
+
+// Largest per-instance sizes of one launch (they size the LDS regions).
+struct Dims {
+  int E = 0, nb = 0, nc = 0, nch = 0, natt = 0;
+  void add(const mppi_ctx* c) {
+    const DevModel& M = c->m->host;
+    E = std::max(E, c->E);
+    nb = std::max(nb, M.nb);
+    nc = std::max(nc, M.nc);
+    nch = std::max(nch, M.n_chains);
+    natt = std::max(natt, M.n_att);
+  }
+};
+static Dims dims_of(const mppi_ctx* c) {
+  Dims d;
+  d.add(c);
+  return d;
+}
+
+// LDS a chain-schedule block may take: two blocks per compute unit (160 KiB).
+constexpr int kChainLdsBudget = 64 * 1024;
+
+struct LaunchShape {
+  int stride = 0, table = 0, lds = 0, groups = 0;  // groups = rollouts per block
+};
+static LaunchShape launch_shape(int key, const Dims& dm) {
+  LaunchShape sh;
+  if (key > 0) {
+    sh.stride = group_floats(key, dm.E);
+    sh.groups = 64 / key;
+    sh.lds = sh.groups * sh.stride * (int)sizeof(float);
+  } else {
+    const int GC = -key;
+    sh.stride = chain_group_floats(GC, dm.nb, dm.E, dm.nch, dm.natt);
+    sh.table = chain_table_floats(dm.nb, dm.nc);
+    const int fit = (kChainLdsBudget / (int)sizeof(float) - sh.table) / sh.stride;
+    sh.groups = std::max(1, std::min(64 / GC, fit));
+    sh.lds = (sh.table + sh.groups * sh.stride) * (int)sizeof(float);
+  }
+  return sh;
+}
+static int rollouts_per_block(int key, const Dims& dm) { return launch_shape(key, dm).groups; }
+
 template <int G>
-static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2* work, int E_max, hipStream_t s) {
-  const int stride = group_floats(G, E_max);
-  hipLaunchKernelGGL(rollout_kernel<G>, dim3(blocks), dim3(64), lds_bytes(G, E_max), s, insts, work, stride);
+static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(rollout_kernel<G>, dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride);
+  return hipGetLastError();
+}
+template <int GC>
+static hipError_t launch_chain_GC(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(chain_kernel<GC>, dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table, sh.groups);
   return hipGetLastError();
 }
 
-static hipError_t launch_rollout(int G, int blocks, const DevInst* insts, const int2* work, int E_max, hipStream_t s) {
-  switch (G) {
-    case 4: return launch_rollout_G<4>(blocks, insts, work, E_max, s);
-    case 8: return launch_rollout_G<8>(blocks, insts, work, E_max, s);
-    case 16: return launch_rollout_G<16>(blocks, insts, work, E_max, s);
-    case 32: return launch_rollout_G<32>(blocks, insts, work, E_max, s);
-    default: return launch_rollout_G<64>(blocks, insts, work, E_max, s);
+static hipError_t launch_rollout(int key, int blocks, const DevInst* insts, const int2* work, const Dims& dm,
+                                 hipStream_t s) {
+  const LaunchShape sh = launch_shape(key, dm);
+  switch (key) {
+    case 4: return launch_rollout_G<4>(blocks, insts, work, sh, s);
+    case 8: return launch_rollout_G<8>(blocks, insts, work, sh, s);
+    case 16: return launch_rollout_G<16>(blocks, insts, work, sh, s);
+    case 32: return launch_rollout_G<32>(blocks, insts, work, sh, s);
+    case 64: return launch_rollout_G<64>(blocks, insts, work, sh, s);
+    case -1: return launch_chain_GC<1>(blocks, insts, work, sh, s);
+    case -2: return launch_chain_GC<2>(blocks, insts, work, sh, s);
+    case -4: return launch_chain_GC<4>(blocks, insts, work, sh, s);
+    case -8: return launch_chain_GC<8>(blocks, insts, work, sh, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
-template <int G>
-static hipError_t launch_persistent_G(int n_items, const DevInst* insts, const int2* work, int E_max,
-                                      unsigned int* counter, hipStream_t s) {
-  const int stride = group_floats(G, E_max);
-  const int lds = lds_bytes(G, E_max);
+template <typename Kern, typename... Args>
+static hipError_t launch_persistent_k(Kern kern, int n_items, const LaunchShape& sh, unsigned int* counter,
+                                      hipStream_t s, Args... args) {
   int dev = 0, cus = 0, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rollout_persistent_kernel<G>, 64, lds);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, sh.lds);
   const int grid = std::min(n_items, std::max(1, cus) * std::max(1, per_cu));
   hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, counter, 1);
-  hipLaunchKernelGGL(rollout_persistent_kernel<G>, dim3(grid), dim3(64), lds, s, insts, work, n_items, counter, stride);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64), sh.lds, s, args...);
   return hipGetLastError();
 }
 
-static hipError_t launch_persistent(int G, int n_items, const DevInst* insts, const int2* work, int E_max,
+static hipError_t launch_persistent(int key, int n_items, const DevInst* insts, const int2* work, const Dims& dm,
                                     unsigned int* counter, hipStream_t s) {
-  switch (G) {
-    case 4: return launch_persistent_G<4>(n_items, insts, work, E_max, counter, s);
-    case 8: return launch_persistent_G<8>(n_items, insts, work, E_max, counter, s);
-    case 16: return launch_persistent_G<16>(n_items, insts, work, E_max, counter, s);
-    case 32: return launch_persistent_G<32>(n_items, insts, work, E_max, counter, s);
-    default: return launch_persistent_G<64>(n_items, insts, work, E_max, counter, s);
+  const LaunchShape sh = launch_shape(key, dm);
+#define BODY_P(G) launch_persistent_k(rollout_persistent_kernel<G>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride)
+#define CHAIN_P(GC) launch_persistent_k(chain_persistent_kernel<GC>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table, sh.groups)
+  switch (key) {
+    case 4: return BODY_P(4);
+    case 8: return BODY_P(8);
+    case 16: return BODY_P(16);
+    case 32: return BODY_P(32);
+    case 64: return BODY_P(64);
+    case -1: return CHAIN_P(1);
+    case -2: return CHAIN_P(2);
+    case -4: return CHAIN_P(4);
+    case -8: return CHAIN_P(8);
+    default: return hipErrorInvalidValue;
   }
+#undef BODY_P
+#undef CHAIN_P
 }
 
 static std::atomic<int> g_persistent{0};
@@ -486,7 +654,8 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(hipMemcpyAsync(c->x0, d_state, (c->nq + c->nv) * sizeof(float), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(c->nom, d_knots_in, c->E * sizeof(float), hipMemcpyDeviceToDevice, s));
-  const int R = 64 / c->lanes;
+  const Dims dm = dims_of(c);
+  const int R = rollouts_per_block(c->lanes, dm);
   const int blocks = (c->N + R - 1) / R;
   for (int it = 0; it < c->I; ++it) {
     std::pair<hipEvent_t, hipEvent_t> er{}, eu{};
@@ -495,7 +664,7 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
       if (st != MPPI_OK) return st;
       HIP_TRY(hipEventRecord(er.first, s));
     }
-    HIP_TRY(launch_rollout(c->lanes, blocks, c->d_insts + it, nullptr, c->E, s));
+    HIP_TRY(launch_rollout(c->lanes, blocks, c->d_insts + it, nullptr, dm, s));
     if (c->profile) {
       HIP_TRY(hipEventRecord(er.second, s));
       c->ev_roll.push_back(er);
@@ -521,7 +690,8 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
 // ---------------------------------------------------------------------------
 namespace {
 struct GroupLaunch {
-  int G = 0, blocks = 0, E_max = 0;
+  int G = 0, blocks = 0;
+  Dims dims;
   int2* work = nullptr;            // device [blocks]
   unsigned int* counter = nullptr; // device work counter of the persistent form
 };
@@ -597,7 +767,8 @@ static mppi_status build_plan(const std::vector<const mppi_ctx*>& ctxs, Plan** o
     for (auto& kv : byG) {
       GroupLaunch gl;
       gl.G = kv.first;
-      const int R = 64 / gl.G;
+      for (int a : kv.second) gl.dims.add(ctxs[ip.active[a]]);
+      const int R = rollouts_per_block(gl.G, gl.dims);
       std::vector<int> order = kv.second;
       std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         const mppi_ctx* cx = ctxs[ip.active[x]];
@@ -607,7 +778,6 @@ static mppi_status build_plan(const std::vector<const mppi_ctx*>& ctxs, Plan** o
       std::vector<int2> work;
       for (int a : order) {
         const mppi_ctx* c = ctxs[ip.active[a]];
-        gl.E_max = std::max(gl.E_max, c->E);
         for (int n0 = 0; n0 < c->N; n0 += R) work.push_back(make_int2(a, n0));
       }
       gl.blocks = (int)work.size();
@@ -706,9 +876,9 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
     IterPlan& ip = plan->iters[it];
     for (auto& g : ip.groups) {
       if (g_persistent)
-        HIP_TRY(launch_persistent(g.G, g.blocks, ip.insts, g.work, g.E_max, g.counter, s));
+        HIP_TRY(launch_persistent(g.G, g.blocks, ip.insts, g.work, g.dims, g.counter, s));
       else
-        HIP_TRY(launch_rollout(g.G, g.blocks, ip.insts, g.work, g.E_max, s));
+        HIP_TRY(launch_rollout(g.G, g.blocks, ip.insts, g.work, g.dims, s));
     }
     hipLaunchKernelGGL(update_kernel, dim3((unsigned)ip.active.size()), dim3(kUpdThreads), 0, s, ip.ups, d_outs + out_off[it],
                        UpdateOut{nullptr, nullptr, nullptr});
@@ -785,8 +955,8 @@ extern "C" mppi_status mppi_graph_create(int32_t n, mppi_ctx* const* ctxs, const
     for (int it = 0; it < Imax && e == hipSuccess; ++it) {
       IterPlan& ip = plan->iters[it];
       for (auto& gl : ip.groups) {
-        e = g_persistent ? launch_persistent(gl.G, gl.blocks, ip.insts, gl.work, gl.E_max, gl.counter, cs)
-                         : launch_rollout(gl.G, gl.blocks, ip.insts, gl.work, gl.E_max, cs);
+        e = g_persistent ? launch_persistent(gl.G, gl.blocks, ip.insts, gl.work, gl.dims, gl.counter, cs)
+                         : launch_rollout(gl.G, gl.blocks, ip.insts, gl.work, gl.dims, cs);
         if (e != hipSuccess) break;
       }
       hipLaunchKernelGGL(update_kernel, dim3((unsigned)ip.active.size()), dim3(kUpdThreads), 0, cs, ip.ups,
@@ -839,15 +1009,23 @@ extern "C" mppi_status mppi_autotune(mppi_ctx* c, const float* d_state, const fl
                                      void* stream, int32_t* best_lanes) {
   if (!c || !d_state || !d_knots) return fail(MPPI_EINVAL, "null argument");
   const auto key = std::make_tuple(c->m, c->N, c->H, c->K);
+  auto report = [&](int k) {
+    if (best_lanes) *best_lanes = k > 0 ? k : -k;
+  };
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) {
-      mppi_status st = mppi_set_lanes_per_rollout(c, it->second);
-      if (st == MPPI_OK && best_lanes) *best_lanes = it->second;
+      mppi_status st = set_key(c, it->second);
+      if (st == MPPI_OK) report(it->second);
       return st;
     }
   }
+  // candidates: the body schedule at every lane count that holds the tree, and the chain schedule
+  const DevModel& M = c->m->host;
+  std::vector<int> cand;
+  for (int G = next_pow2(M.nb); G <= 64; G *= 2) cand.push_back(G);
+  if (M.chain_ok) cand.push_back(-M.chain_lanes);
   hipStream_t s = (hipStream_t)stream;
   uint32_t tick0 = 0;
   HIP_TRY(hipMemcpy(&tick0, c->tick, sizeof(uint32_t), hipMemcpyDeviceToHost));
@@ -858,10 +1036,9 @@ extern "C" mppi_status mppi_autotune(mppi_ctx* c, const float* d_state, const fl
   HIP_TRY(hipEventCreate(&e1));
   int best = c->lanes;
   float best_ms = 1e30f;
-  const int first = next_pow2(c->m->host.nb);
   reps = std::max(1, reps);
-  for (int G = first; G <= 64; G *= 2) {
-    mppi_status st = mppi_set_lanes_per_rollout(c, G);
+  for (int k : cand) {
+    mppi_status st = set_key(c, k);
     if (st != MPPI_OK) break;
     st = mppi_step(c, d_state, d_knots, scratch, nullptr, nullptr, nullptr, s);  // warm-up
     if (st != MPPI_OK) break;
@@ -874,19 +1051,19 @@ extern "C" mppi_status mppi_autotune(mppi_ctx* c, const float* d_state, const fl
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) { best_ms = ms; best = G; }
+    if (ms < best_ms) { best_ms = ms; best = k; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(scratch);
   HIP_TRY(hipMemcpy(c->tick, &tick0, sizeof(uint32_t), hipMemcpyHostToDevice));
-  mppi_status st = mppi_set_lanes_per_rollout(c, best);
+  mppi_status st = set_key(c, best);
   if (st != MPPI_OK) return st;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[key] = best;
   }
-  if (best_lanes) *best_lanes = best;
+  report(best);
   return MPPI_OK;
 }
 
@@ -931,7 +1108,7 @@ extern "C" mppi_status mppi_debug_samples(mppi_ctx* c, const float* d_knots_in, 
   mppi_status st = debug_inst(h, s, &d);
   if (st != MPPI_OK) return st;
   hipError_t e;
-  switch (c->lanes) {
+  switch (c->lanes > 0 ? c->lanes : next_pow2(c->m->host.nb)) {
     case 4: e = launch_samples_G<4>(d, c->N, c->E, s); break;
     case 8: e = launch_samples_G<8>(d, c->N, c->E, s); break;
     case 16: e = launch_samples_G<16>(d, c->N, c->E, s); break;
@@ -986,8 +1163,8 @@ extern "C" mppi_status mppi_debug_rollouts(mppi_ctx* c, const float* d_state, co
   DevInst* d = nullptr;
   mppi_status st = debug_inst(h, s, &d);
   if (st != MPPI_OK) return st;
-  const int R = 64 / c->lanes;
-  HIP_TRY(launch_rollout(c->lanes, (c->N + R - 1) / R, d, nullptr, c->E, s));
+  const int R = rollouts_per_block(c->lanes, dims_of(c));
+  HIP_TRY(launch_rollout(c->lanes, (c->N + R - 1) / R, d, nullptr, dims_of(c), s));
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipFree(d));
   return MPPI_OK;
@@ -1071,7 +1248,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   const int n = (int)reqs.size();
   int Imax = 0;
   for (auto& r : reqs) Imax = std::max(Imax, r.ctx->I);
-  struct GroupDesc { int G, E_max; size_t work_off; int n_items; };
+  struct GroupDesc { int G; Dims dims; size_t work_off; int n_items; };
   struct IterDesc { size_t inst_off, up_off, out_off; int n_active; std::vector<GroupDesc> groups; };
   std::vector<IterDesc> iters(Imax);
   // sizes
@@ -1091,12 +1268,10 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
     std::map<int, std::vector<int>> byG;
     for (int a = 0; a < d.n_active; ++a) byG[reqs[active[it][a]].ctx->lanes].push_back(a);
     for (auto& kv : byG) {
-      GroupDesc g{kv.first, 0, bytes, 0};
-      const int R = 64 / g.G;
-      for (int a : kv.second) {
-        g.n_items += (reqs[active[it][a]].ctx->N + R - 1) / R;
-        g.E_max = std::max(g.E_max, reqs[active[it][a]].ctx->E);
-      }
+      GroupDesc g{kv.first, Dims{}, bytes, 0};
+      for (int a : kv.second) g.dims.add(reqs[active[it][a]].ctx);
+      const int R = rollouts_per_block(g.G, g.dims);
+      for (int a : kv.second) g.n_items += (reqs[active[it][a]].ctx->N + R - 1) / R;
       bytes = align(bytes + g.n_items * sizeof(int2));
       d.groups.push_back(g);
     }
@@ -1127,7 +1302,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
     size_t gi = 0;
     for (auto& kv : byG) {
       GroupDesc& g = d.groups[gi++];
-      const int R = 64 / g.G;
+      const int R = rollouts_per_block(g.G, g.dims);
       std::vector<int> order = kv.second;
       std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         const mppi_ctx* cx = reqs[active[it][x]].ctx;
@@ -1151,9 +1326,9 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
     for (auto& g : d.groups) {
       auto* w = reinterpret_cast<const int2*>(dv + g.work_off);
       if (persistent && counters && ci < n_counters)
-        HIP_TRY(launch_persistent(g.G, g.n_items, di, w, g.E_max, counters + ci++, s));
+        HIP_TRY(launch_persistent(g.G, g.n_items, di, w, g.dims, counters + ci++, s));
       else
-        HIP_TRY(launch_rollout(g.G, g.n_items, di, w, g.E_max, s));
+        HIP_TRY(launch_rollout(g.G, g.n_items, di, w, g.dims, s));
     }
     hipLaunchKernelGGL(update_kernel, dim3((unsigned)d.n_active), dim3(kUpdThreads), 0, s,
                        reinterpret_cast<const DevUpdate*>(dv + d.up_off), reinterpret_cast<const UpdateOut*>(dv + d.out_off),

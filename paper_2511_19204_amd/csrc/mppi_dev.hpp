@@ -10,6 +10,22 @@ constexpr int kMaxBodies = 64;
 constexpr int kMaxContacts = 32;
 constexpr int kMaxChildren = 8;
 constexpr int kMaxKnots = 64;
+constexpr int kMaxChains = 8;    // chain schedule: kinematic chains (lanes) per rollout
+constexpr int kMaxLevels = 16;   // chain schedule: tree depth + 1
+constexpr int kRow = 68;         // floats per body row of the chain schedule's table
+constexpr int kCt = 8;           // floats per contact row of that table
+
+// Body row of the chain schedule's table (floats; integer fields stored as bits):
+//   [0,27) P   [27,30) p_tree   [30,33) axis_p   [33,36) com   [36,42) Ic   42 mass
+//   43 kp  44 kd  45 tau_max  46 armature  47 q0 (running-cost posture, per instance)
+//   48 parent  49 c_begin  50 c_count  51 n_child  52 heavy child (same chain) or -1
+//   53 attach slot written by this body or -1  54 chain  55 depth  [56,64) children
+// Contact row: [0,3) position in the body frame, 3 f0z (per instance), 4 original index.
+namespace row {
+enum : int { P = 0, p_tree = 27, axis_p = 30, com = 33, Ic = 36, mass = 42, kp = 43, kd = 44, taumax = 45, arm = 46,
+             q0 = 47, parent = 48, c_begin = 49, c_count = 50, n_child = 51, heavy = 52, att = 53, chain = 54,
+             depth = 55, child = 56 };
+}
 
 // Kinematic tree in the layout the rollout lanes read: one entry per body,
 // contacts sorted by body.  Precomputed on the host from mppi_model_desc:
@@ -38,6 +54,16 @@ struct DevModel {
   float arm[kMaxBodies];    // reflected rotor inertia per joint
   float cpos[kMaxContacts][3];  // sorted by body
   int32_t corig[kMaxContacts];  // original contact index
+  // Chain schedule: heavy-path decomposition of the tree into chains (a body
+  // continues the chain of its parent when it heads the parent's largest
+  // subtree).  A chain hangs off another chain's body through an attach slot.
+  int32_t chain_ok;                             // 1 if the tree fits the chain schedule
+  int32_t n_chains, chain_lanes, n_att;
+  int32_t chain_body[kMaxChains][kMaxLevels];   // body of chain c at depth d, or -1
+  int32_t chain_first[kMaxChains];              // depth of the chain's first body
+  int32_t chain_att[kMaxChains];                // attach slot its first body reads, or -1 (a root)
+  alignas(16) float rows[kMaxBodies][kRow];     // body rows (layout above), read as float4
+  float ctab[kMaxContacts][kCt];                // contact rows
 };
 
 // One MPC instance's view for one planning iteration.
@@ -76,5 +102,44 @@ struct DevUpdate {
   int32_t N, E, iter, weight_mode, first_iter, last_iter;
   float lambda;
 };
+
+
+// ---------------------------------------------------------------------------
+// LDS layouts of the rollout kernels (floats), shared by host and device.
+// ---------------------------------------------------------------------------
+// Body schedule, one rollout group of G lanes:
+//   slot[b][29] per body: forward kinematics R(9) p(3) v(6) beta(6);
+//                         reused by the backward sweep for Ia(21) pa(6),
+//                         then by the forward sweep for a'(6)
+//   base[16]   : world rotation (9) and position (3) of frame B
+//   knots[E]   : this rollout's knots
+//   red[G]     : reduction scratch
+// The slot stride is odd and a group's size is padded to G (mod 32) floats, so
+// the 64 lanes of a wavefront (64/G groups) touch distinct LDS banks.
+constexpr int kSlot = 29;
+__host__ __device__ inline int group_floats(int G, int E) {
+  const int raw = G * kSlot + 16 + ((E + 3) & ~3) + G;
+  const int want = G < 32 ? G : 0;
+  return raw + ((want - raw % 32) + 64) % 32;
+}
+
+// Chain schedule: the model table (body rows, chain bodies, contact rows) once
+// per wavefront, then one region per rollout group:
+//   rec[nb][kRec]   per-body record (see the chain kernel)
+//   base[16]        world rotation (9) and position (3) of frame B
+//   knots[E]        this rollout's knots
+//   pub[nch][kPub]  articulated inertia and bias a chain's first body hands to
+//                   its parent on another chain
+//   att[natt][kAtt] frame (R p v beta) and a' of a body other chains hang off
+//   red[GC]         reduction scratch
+constexpr int kRec = 36;
+constexpr int kPub = 28;
+constexpr int kAtt = 32;
+__host__ __device__ inline int chain_table_floats(int nb, int nc) { return nb * kRow + kMaxChains * kMaxLevels + nc * kCt; }
+__host__ __device__ inline int chain_group_floats(int GC, int nb, int E, int nch, int natt) {
+  const int raw = nb * kRec + 16 + ((E + 3) & ~3) + nch * kPub + natt * kAtt + GC;
+  const int r4 = (raw + 3) & ~3;
+  return r4 + ((20 - r4 % 32) + 32) % 32;  // 16-byte aligned groups, staggered across LDS banks
+}
 
 }  // namespace mppi

@@ -81,22 +81,6 @@ __device__ __forceinline__ void quat_R(const float* q, float* R) {
   R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
 }
 
-// LDS layout of one rollout group (floats):
-//   slot[b][29] per body: forward kinematics R(9) p(3) v(6) beta(6);
-//                         reused by the backward sweep for Ia(21) pa(6),
-//                         then by the forward sweep for a'(6)
-//   base[16]   : world rotation (9) and position (3) of frame B
-//   knots[E]   : this rollout's knots
-//   red[G]     : reduction scratch
-// The slot stride is odd and a group's size is padded to G (mod 32) floats, so
-// the 64 lanes of a wavefront (64/G groups) touch distinct LDS banks.
-constexpr int kSlot = 29;
-__host__ __device__ inline int group_floats(int G, int E) {
-  const int raw = G * kSlot + 16 + ((E + 3) & ~3) + G;
-  const int want = G < 32 ? G : 0;
-  return raw + ((want - raw % 32) + 64) % 32;
-}
-
 // ---------------------------------------------------------------------------
 // Per-lane physics of one step.  Lane b (< nb) owns body b and its joint.
 //
@@ -207,8 +191,339 @@ __device__ __forceinline__ void shift_inertia_to_parent(const float* I, const fl
     for (int c = r; c < 3; ++c) O[SI(r + 3, c + 3)] = I[SI(r + 3, c + 3)];
 }
 
+// ---------------------------------------------------------------------------
+// Per-body physics shared by both rollout schedules.  Each helper is the
+// arithmetic of one body (or joint) in one phase; the schedules differ only in
+// which lane runs it and where its operands come from, so they produce the
+// same bits.
+// ---------------------------------------------------------------------------
+
+// PD law (eq. pd-controller) with the torque clip; on unsaturated joints the
+// damping and stiffness act implicitly through the gain dt (Kd + dt Kp).
+__device__ __forceinline__ void pd_law(float kp, float kd, float tm, float dt, float q, float v, float qref, float vref,
+                                       float& tau, float& gain) {
+  const float t = kp * (qref - q) + kd * (vref - v);
+  gain = 0.f;
+  if (t >= tm) {
+    tau = tm;
+  } else if (t <= -tm) {
+    tau = -tm;
+  } else {
+    tau = t;
+    gain = dt * (kd + dt * kp);
+  }
+}
+
+// velocity-product acceleration c = v x_m (S qd) of a revolute joint, S = (ax, 0)
+__device__ __forceinline__ void vel_product(const float* v, const float* ax, float qd, float* c) {
+  const float aq[3] = {ax[0] * qd, ax[1] * qd, ax[2] * qd};
+  cross3(v, aq, c);
+  cross3(v + 3, aq, c + 3);
+}
+
+// Forward kinematics of a revolute body from its parent's frame (Rl, pl), twist
+// vl and bias acceleration bl: rotation R = Rl C(q), origin p, lever arm
+// e = p - pl, axis ax (base axes), twist v, velocity product c and bias
+// acceleration beta, all about the body's own origin.
+__device__ __forceinline__ void fk_joint(const float* Rl, const float* pl, const float* vl, const float* bl,
+                                         const float* P, const float* p_tree, const float* axis_p, float cq, float sq,
+                                         float qd, float* R, float* p, float* e, float* ax, float* v, float* c,
+                                         float* beta) {
+  float C[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) C[k] = P[k] + cq * P[9 + k] + sq * P[18 + k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+      R[r * 3 + cc] = Rl[r * 3 + 0] * C[0 * 3 + cc] + Rl[r * 3 + 1] * C[1 * 3 + cc] + Rl[r * 3 + 2] * C[2 * 3 + cc];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    e[r] = Rl[r * 3 + 0] * p_tree[0] + Rl[r * 3 + 1] * p_tree[1] + Rl[r * 3 + 2] * p_tree[2];
+    p[r] = pl[r] + e[r];
+    ax[r] = Rl[r * 3 + 0] * axis_p[0] + Rl[r * 3 + 1] * axis_p[1] + Rl[r * 3 + 2] * axis_p[2];
+  }
+  // v = shift(v_parent) + S qd with S = (axis, 0) about the joint origin
+  shift_motion(vl, e, v);
+  v[0] += ax[0] * qd; v[1] += ax[1] * qd; v[2] += ax[2] * qd;
+  vel_product(v, ax, qd, c);
+  float bs[6];
+  shift_motion(bl, e, bs);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) beta[k] = bs[k] + c[k];
+}
+
+// Spatial inertia (packed) of a rigid body about its origin in base axes, from
+// its rotation R, com and inertia Ic about the com (body frame) and mass m.
+__device__ __forceinline__ void body_inertia(const float* R, const float* com, const float* Ic, float m, float* IA) {
+  float cw[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) cw[r] = R[r * 3 + 0] * com[0] + R[r * 3 + 1] * com[1] + R[r * 3 + 2] * com[2];
+  const float Ib[9] = {Ic[0], Ic[3], Ic[4], Ic[3], Ic[1], Ic[5], Ic[4], Ic[5], Ic[2]};
+  float RI[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+      RI[r * 3 + cc] = R[r * 3 + 0] * Ib[0 * 3 + cc] + R[r * 3 + 1] * Ib[1 * 3 + cc] + R[r * 3 + 2] * Ib[2 * 3 + cc];
+  const float c2 = cw[0] * cw[0] + cw[1] * cw[1] + cw[2] * cw[2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int cc = r; cc < 3; ++cc) {
+      const float iw = RI[r * 3 + 0] * R[cc * 3 + 0] + RI[r * 3 + 1] * R[cc * 3 + 1] + RI[r * 3 + 2] * R[cc * 3 + 2];
+      IA[SI(r, cc)] = iw + m * ((r == cc ? c2 : 0.f) - cw[r] * cw[cc]);
+    }
+  IA[SI(0, 3)] = 0.f;        IA[SI(0, 4)] = -m * cw[2]; IA[SI(0, 5)] = m * cw[1];
+  IA[SI(1, 3)] = m * cw[2];  IA[SI(1, 4)] = 0.f;        IA[SI(1, 5)] = -m * cw[0];
+  IA[SI(2, 3)] = -m * cw[1]; IA[SI(2, 4)] = m * cw[0];  IA[SI(2, 5)] = 0.f;
+  IA[SI(3, 3)] = m; IA[SI(3, 4)] = 0.f; IA[SI(3, 5)] = 0.f;
+  IA[SI(4, 4)] = m; IA[SI(4, 5)] = 0.f; IA[SI(5, 5)] = m;
+}
+
+// bias force v x_f (I v)
+__device__ __forceinline__ void bias_force(const float* IA, const float* v, float* pA) {
+  float h[6];
+  sym6_mv(IA, v, h);
+  float t0[3], t1[3], t2[3];
+  cross3(v, h, t0);
+  cross3(v + 3, h + 3, t1);
+  cross3(v, h + 3, t2);
+  pA[0] = t0[0] + t1[0]; pA[1] = t0[1] + t1[1]; pA[2] = t0[2] + t1[2];
+  pA[3] = t2[0]; pA[4] = t2[1]; pA[5] = t2[2];
+}
+
+// One soft contact point at r (body frame) on a body with frame (R, p), twist v
+// and bias acceleration beta; frame B is (Rb, pb) in the world, agl is gravity
+// in B axes.  Adds the contact force to the bias pA and, while the point
+// penetrates, the linearly implicit damping/friction terms to IA and pA.
+// Returns the normal force; vw and fw are the point's world velocity and force.
+struct ContactLaw {
+  float k, d, mu, eps;
+};
+__device__ __forceinline__ float contact_point(const float* r, const float* R, const float* p, const float* v,
+                                               const float* beta, const float* Rb, const float* pb, const float* agl,
+                                               float dt, const ContactLaw& law, float* IA, float* pA, float* vw,
+                                               float* fw) {
+  const float r0 = r[0], r1 = r[1], r2 = r[2];
+  float x[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) x[q] = R[q * 3 + 0] * r0 + R[q * 3 + 1] * r1 + R[q * 3 + 2] * r2;
+  float wx[3];
+  cross3(v, x, wx);
+  const float vB[3] = {v[3] + wx[0], v[4] + wx[1], v[5] + wx[2]};
+  const float xB[3] = {p[0] + x[0], p[1] + x[1], p[2] + x[2]};
+  float pw[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    pw[q] = pb[q] + Rb[q * 3 + 0] * xB[0] + Rb[q * 3 + 1] * xB[1] + Rb[q * 3 + 2] * xB[2];
+    vw[q] = Rb[q * 3 + 0] * vB[0] + Rb[q * 3 + 1] * vB[1] + Rb[q * 3 + 2] * vB[2];
+  }
+  float fn = 0.f;
+  if (pw[2] < 0.f) fn = fmaxf(0.f, -law.k * pw[2] - law.d * vw[2]);
+  const float n2 = vw[0] * vw[0] + vw[1] * vw[1] + law.eps * law.eps;
+  const float inv_nrm = rsq(n2);
+  const float mfn = law.mu * fn * inv_nrm;
+  fw[0] = -mfn * vw[0]; fw[1] = -mfn * vw[1]; fw[2] = fn;
+  float fB[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) fB[q] = Rb[0 * 3 + q] * fw[0] + Rb[1 * 3 + q] * fw[1] + Rb[2 * 3 + q] * fw[2];
+  float xf[3];
+  cross3(x, fB, xf);
+  pA[0] -= xf[0]; pA[1] -= xf[1]; pA[2] -= xf[2];
+  pA[3] -= fB[0]; pA[4] -= fB[1]; pA[5] -= fB[2];
+  if (fn > 0.f) {
+    // Velocity Jacobian of the contact law (world), tangential-normal coupling
+    // dropped: D_w = a I + (d - a) z z^T - a w w^T with a = mu f_n / n and
+    // w = v_t / n.  In B axes z -> zb (third row of Rb) and w -> ub = Rb^T w.
+    const float aa = mfn;
+    const float al = law.d - aa;
+    const float zb[3] = {Rb[6], Rb[7], Rb[8]};
+    const float wt[2] = {vw[0] * inv_nrm, vw[1] * inv_nrm};
+    const float ub[3] = {Rb[0] * wt[0] + Rb[3] * wt[1], Rb[1] * wt[0] + Rb[4] * wt[1], Rb[2] * wt[0] + Rb[5] * wt[1]};
+    // added inertia dt P^T D P with P = [-x^x, 1]; with w1 = x x zb, w2 = x x ub:
+    //   top-left  a (|x|^2 I - x x^T) + al w1 w1^T - a w2 w2^T
+    //   top-right a x^x + al w1 zb^T - a w2 ub^T,   bottom-right D
+    float w1[3], w2[3];
+    cross3(x, zb, w1);
+    cross3(x, ub, w2);
+    const float x2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    const float dta = dt * aa, dtal = dt * al;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int cc = q; cc < 3; ++cc) {
+        const float tl = aa * ((q == cc ? x2 : 0.f) - x[q] * x[cc]) + al * w1[q] * w1[cc] - aa * w2[q] * w2[cc];
+        IA[SI(q, cc)] += dt * tl;
+        const float br = (q == cc ? aa : 0.f) + al * zb[q] * zb[cc] - aa * ub[q] * ub[cc];
+        IA[SI(q + 3, cc + 3)] += dt * br;
+      }
+    const float Xm[9] = {0.f, -x[2], x[1], x[2], 0.f, -x[0], -x[1], x[0], 0.f};
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        IA[SI(q, cc + 3)] += dta * Xm[q * 3 + cc] + dtal * w1[q] * zb[cc] - dta * w2[q] * ub[cc];
+    // bias of the added inertia: dt P^T D P (a_g - beta) = dt (x x Dw', Dw'), w' = P (a_g - beta)
+    const float sa[3] = {-beta[0], -beta[1], -beta[2]};
+    const float sl[3] = {agl[0] - beta[3], agl[1] - beta[4], agl[2] - beta[5]};
+    float sx[3];
+    cross3(sa, x, sx);
+    const float w3[3] = {sl[0] + sx[0], sl[1] + sx[1], sl[2] + sx[2]};
+    const float zw = zb[0] * w3[0] + zb[1] * w3[1] + zb[2] * w3[2];
+    const float uw = ub[0] * w3[0] + ub[1] * w3[1] + ub[2] * w3[2];
+    float Dw3[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Dw3[q] = aa * w3[q] + al * zw * zb[q] - aa * uw * ub[q];
+    float xd[3];
+    cross3(x, Dw3, xd);
+    pA[0] += dt * xd[0]; pA[1] += dt * xd[1]; pA[2] += dt * xd[2];
+    pA[3] += dt * Dw3[0]; pA[4] += dt * Dw3[1]; pA[5] += dt * Dw3[2];
+  }
+  return fn;
+}
+
+// running-cost terms of one contact point (Sec. IV-A)
+__device__ __forceinline__ void contact_cost(const DevInst* I, float fn, const float* vw, const float* fw, float f0z,
+                                             float& lane_cost) {
+  if (fn > 0.f) lane_cost += I->w_cv * (fabsf(vw[0]) + fabsf(vw[1]) + fabsf(vw[2]));
+  lane_cost += I->w_cf * (fabsf(fw[0]) + fabsf(fw[1]) + fabsf(fw[2] - f0z));
+}
+
+// end-effector height error: world z of the point ee_pos on a body (R, p) minus z_des
+__device__ __forceinline__ float ee_height_error(const float* R, const float* p, const float* ee_pos, const float* Rb,
+                                                 const float* pb, float z_des) {
+  float xe[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) xe[r] = p[r] + R[r * 3 + 0] * ee_pos[0] + R[r * 3 + 1] * ee_pos[1] + R[r * 3 + 2] * ee_pos[2];
+  return pb[2] + Rb[6] * xe[0] + Rb[7] * xe[1] + Rb[8] * xe[2] - z_des;
+}
+
+// running-cost terms of the floating base (Sec. IV-A): height error and the
+// squared tilt angle of the base quaternion.  Both schedules evaluate it once
+// per step in straight-line code: inside a loop the compiler may hoist it and
+// drop the relaxed-precision tag of the division inside atan2f, which would
+// change its last bit.
+__device__ __forceinline__ float base_cost_term(const DevInst* I, const float* bq) {
+  const float* qt = bq + 3;
+  const float vn = sqrtf(qt[1] * qt[1] + qt[2] * qt[2] + qt[3] * qt[3]);
+  const float phi = 2.f * atan2f(vn, fabsf(qt[0]));
+  return I->w_h * fabsf(bq[2] - I->z_des) + I->w_or * phi * phi;
+}
+
+// running-cost terms of a body other than its contacts (Sec. IV-A; effort and
+// end-effector terms of the planar-chain task); base_term from base_cost_term
+__device__ __forceinline__ void body_cost(const DevInst* I, const DevModel& M, int b, bool is_base, bool is_joint,
+                                          float base_term, float q, float q0, float tau, const float* R, const float* p,
+                                          const float* Rb, const float* pb, float& lane_cost) {
+  if (I->cost_kind == 1) {
+    if (is_base) lane_cost += base_term;
+    if (is_joint) {
+      const float eq = q - q0;
+      lane_cost += I->w_q * eq * eq + I->w_eff * tau * tau;
+    }
+  } else {
+    if (is_joint) lane_cost += I->w_tau * tau * tau;
+    if (b == M.ee_body) {
+      const float dz = ee_height_error(R, p, M.ee_pos, Rb, pb, I->z_des);
+      lane_cost += I->w_ee * dz * dz;
+    }
+  }
+}
+
+// Articulated-body step of a revolute joint (Featherstone's ABA pass 2 in the
+// base-axes, own-origin frames): from the body's articulated inertia IA and
+// bias pA (children already added) computes U = IA S, 1/D, u and the inertia
+// and bias (Ip, pp) carried to the parent's origin.  D includes the armature and
+// the implicit PD gain.
+__device__ __forceinline__ void backward_joint(const float* IA, const float* pA, const float* ax, const float* c,
+                                               const float* e, float tau, float arm, float gain, float* U,
+                                               float& invD, float& u, float* Ip, float* pp) {
+  // S = (ax, 0): U = IA S, D = S.U + g, u = tau - S.pA
+#pragma unroll
+  for (int r = 0; r < 6; ++r) U[r] = IA[SI(r, 0)] * ax[0] + IA[SI(r, 1)] * ax[1] + IA[SI(r, 2)] * ax[2];
+  const float Dv = (arm + gain) + (ax[0] * U[0] + ax[1] * U[1] + ax[2] * U[2]);
+  invD = rcp(Dv);
+  u = tau - (ax[0] * pA[0] + ax[1] * pA[1] + ax[2] * pA[2]);
+  float Ia[21];
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int cc = r; cc < 6; ++cc) Ia[SI(r, cc)] = IA[SI(r, cc)] - U[r] * U[cc] * invD;
+  float Iac[6];
+  sym6_mv(Ia, c, Iac);
+  const float uD = u * invD;
+  float pa[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) pa[q] = pA[q] + Iac[q] + U[q] * uD;
+  shift_inertia_to_parent(Ia, e, Ip);
+  float ef[3];
+  cross3(e, pa + 3, ef);
+  pp[0] = pa[0] + ef[0]; pp[1] = pa[1] + ef[1]; pp[2] = pa[2] + ef[2];
+  pp[3] = pa[3]; pp[4] = pa[4]; pp[5] = pa[5];
+}
+
+// Floating-base root: solves IA0 a0' = -pA0 by Cholesky (a0' = a0 - a_g).
+__device__ __forceinline__ void base_solve(const float* IA, const float* pA, float* a0) {
+  float L[21], invL[6];
+#pragma unroll
+  for (int q = 0; q < 21; ++q) L[q] = IA[q];
+  // in-place Cholesky of the packed symmetric matrix (lower factor stored as L[SI(i,j)], j <= i)
+#pragma unroll
+  for (int jj = 0; jj < 6; ++jj) {
+    float dsum = L[SI(jj, jj)];
+#pragma unroll
+    for (int k = 0; k < jj; ++k) dsum -= L[SI(jj, k)] * L[SI(jj, k)];
+    const float inv = rsq(dsum);
+    invL[jj] = inv;
+    L[SI(jj, jj)] = dsum * inv;
+#pragma unroll
+    for (int i = jj + 1; i < 6; ++i) {
+      float sm = L[SI(i, jj)];
+#pragma unroll
+      for (int k = 0; k < jj; ++k) sm -= L[SI(i, k)] * L[SI(jj, k)];
+      L[SI(i, jj)] = sm * inv;
+    }
+  }
+  float y[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    float sm = -pA[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) sm -= L[SI(i, k)] * y[k];
+    y[i] = sm * invL[i];
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    float sm = y[i];
+#pragma unroll
+    for (int k = i + 1; k < 6; ++k) sm -= L[SI(k, i)] * a0[k];
+    a0[i] = sm * invL[i];
+  }
+}
+
+// ABA pass 3 for a revolute joint: parent acceleration al (gravity-offset, about
+// the parent origin) -> joint acceleration qdd and the body's own a'.
+__device__ __forceinline__ float forward_joint(const float* al, const float* e, const float* c, const float* U, float u,
+                                               float invD, const float* ax, float* aout) {
+  float a[6];
+  shift_motion(al, e, a);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) a[q] += c[q];
+  float Ua = 0.f;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) Ua = fmaf(U[q], a[q], Ua);
+  const float qdd = (u - Ua) * invD;
+  aout[0] = a[0] + ax[0] * qdd; aout[1] = a[1] + ax[1] * qdd; aout[2] = a[2] + ax[2] * qdd;
+  aout[3] = a[3]; aout[4] = a[4]; aout[5] = a[5];
+  return qdd;
+}
+
+// ---------------------------------------------------------------------------
+// Body schedule: one lane per body, the tree swept level by level through LDS.
 // terminal = true evaluates only the kinematics and the end-effector height term
 // of the terminal cost (end-effector task) at the current state.
+// ---------------------------------------------------------------------------
 template <int G>
 __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevInst* I, float* __restrict__ gs,
                              int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
@@ -219,21 +534,11 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
   const bool is_joint = body_lane && !is_base;
   const int j = b - fb;
 
-  // ---- PD law (linearly implicit gain on unsaturated joints)
   float tau = 0.f, gain = 0.f;
-  if (is_joint) {
-    const float t = bc.kp * (io.qref - io.q) + bc.kd * (io.vref - io.v);
-    const float tm = bc.taumax;
-    if (t >= tm) {
-      tau = tm;
-    } else if (t <= -tm) {
-      tau = -tm;
-    } else {
-      tau = t;
-      gain = io.dt * (bc.kd + io.dt * bc.kp);
-    }
-  }
+  if (is_joint) pd_law(bc.kp, bc.kd, bc.taumax, io.dt, io.q, io.v, io.qref, io.vref, tau, gain);
   io.tau = tau;
+  float base_term = 0.f;
+  if (want_cost && is_base && I->cost_kind == 1) base_term = base_cost_term(I, io.bq);
 
   // ---- frame B: world pose of the base; body 0 slot = identity frame with the base twist
   if (is_base) {
@@ -289,32 +594,7 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
 #pragma unroll
         for (int k = 0; k < 6; ++k) { vl[k] = 0.f; bl[k] = 0.f; }
       }
-      const float* P = bc.P;
-      float C[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) C[k] = P[k] + cq * P[9 + k] + sq * P[18 + k];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-          R[r * 3 + cc] = Rl[r * 3 + 0] * C[0 * 3 + cc] + Rl[r * 3 + 1] * C[1 * 3 + cc] + Rl[r * 3 + 2] * C[2 * 3 + cc];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        e[r] = Rl[r * 3 + 0] * bc.p_tree[0] + Rl[r * 3 + 1] * bc.p_tree[1] + Rl[r * 3 + 2] * bc.p_tree[2];
-        p[r] = pl[r] + e[r];
-        ax[r] = Rl[r * 3 + 0] * bc.axis_p[0] + Rl[r * 3 + 1] * bc.axis_p[1] + Rl[r * 3 + 2] * bc.axis_p[2];
-      }
-      // v = shift(v_parent) + S qd with S = (axis, 0) about the joint origin
-      shift_motion(vl, e, v);
-      v[0] += ax[0] * io.v; v[1] += ax[1] * io.v; v[2] += ax[2] * io.v;
-      // c = v x_m (S qd) = (w x a qd, v_lin x a qd)
-      const float aq[3] = {ax[0] * io.v, ax[1] * io.v, ax[2] * io.v};
-      cross3(v, aq, c);
-      cross3(v + 3, aq, c + 3);
-      float bs[6];
-      shift_motion(bl, e, bs);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) beta[k] = bs[k] + c[k];
+      fk_joint(Rl, pl, vl, bl, bc.P, bc.p_tree, bc.axis_p, cq, sq, io.v, R, p, e, ax, v, c, beta);
       float* s = slots + b * kSlot;
 #pragma unroll
       for (int k = 0; k < 9; ++k) s[k] = R[k];
@@ -336,11 +616,7 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
   pb[0] = base[9]; pb[1] = base[10]; pb[2] = base[11];
   if (terminal) {
     if (body_lane && I->cost_kind == 0 && b == M.ee_body) {
-      float xe[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-        xe[r] = p[r] + R[r * 3 + 0] * M.ee_pos[0] + R[r * 3 + 1] * M.ee_pos[1] + R[r * 3 + 2] * M.ee_pos[2];
-      const float dz = pb[2] + Rb[6] * xe[0] + Rb[7] * xe[1] + Rb[8] * xe[2] - I->z_des;
+      const float dz = ee_height_error(R, p, M.ee_pos, Rb, pb, I->z_des);
       lane_cost = I->w_ee * dz * dz;
     }
     io.cost = lane_cost;
@@ -356,153 +632,21 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
 #pragma unroll
       for (int k = 0; k < 21; ++k) IA[k] = M.base_I[k];
     } else {
-      const float m = bc.mass;
-      float cw[3];
-      const float cb[3] = {bc.com[0], bc.com[1], bc.com[2]};
-#pragma unroll
-      for (int r = 0; r < 3; ++r) cw[r] = R[r * 3 + 0] * cb[0] + R[r * 3 + 1] * cb[1] + R[r * 3 + 2] * cb[2];
-      const float* Ic = bc.Ic;
-      const float Ib[9] = {Ic[0], Ic[3], Ic[4], Ic[3], Ic[1], Ic[5], Ic[4], Ic[5], Ic[2]};
-      float RI[9];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-          RI[r * 3 + cc] = R[r * 3 + 0] * Ib[0 * 3 + cc] + R[r * 3 + 1] * Ib[1 * 3 + cc] + R[r * 3 + 2] * Ib[2 * 3 + cc];
-      const float c2 = cw[0] * cw[0] + cw[1] * cw[1] + cw[2] * cw[2];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int cc = r; cc < 3; ++cc) {
-          const float iw = RI[r * 3 + 0] * R[cc * 3 + 0] + RI[r * 3 + 1] * R[cc * 3 + 1] + RI[r * 3 + 2] * R[cc * 3 + 2];
-          IA[SI(r, cc)] = iw + m * ((r == cc ? c2 : 0.f) - cw[r] * cw[cc]);
-        }
-      IA[SI(0, 3)] = 0.f;        IA[SI(0, 4)] = -m * cw[2]; IA[SI(0, 5)] = m * cw[1];
-      IA[SI(1, 3)] = m * cw[2];  IA[SI(1, 4)] = 0.f;        IA[SI(1, 5)] = -m * cw[0];
-      IA[SI(2, 3)] = -m * cw[1]; IA[SI(2, 4)] = m * cw[0];  IA[SI(2, 5)] = 0.f;
-      IA[SI(3, 3)] = m; IA[SI(3, 4)] = 0.f; IA[SI(3, 5)] = 0.f;
-      IA[SI(4, 4)] = m; IA[SI(4, 5)] = 0.f; IA[SI(5, 5)] = m;
+      body_inertia(R, bc.com, bc.Ic, bc.mass, IA);
     }
-    // bias force v x_f (I v)
-    float h[6];
-    sym6_mv(IA, v, h);
-    float t0[3], t1[3], t2[3];
-    cross3(v, h, t0);
-    cross3(v + 3, h + 3, t1);
-    cross3(v, h + 3, t2);
-    pA[0] = t0[0] + t1[0]; pA[1] = t0[1] + t1[1]; pA[2] = t0[2] + t1[2];
-    pA[3] = t2[0]; pA[4] = t2[1]; pA[5] = t2[2];
+    bias_force(IA, v, pA);
 
     // contacts carried by this body (point x relative to the body origin)
+    const ContactLaw law{M.k, M.d, M.mu, M.eps};
     const int c0 = bc.c_begin, cn = bc.c_count;
     for (int ci = c0; ci < c0 + cn; ++ci) {
-      const float r0 = M.cpos[ci][0], r1 = M.cpos[ci][1], r2 = M.cpos[ci][2];
-      float x[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) x[r] = R[r * 3 + 0] * r0 + R[r * 3 + 1] * r1 + R[r * 3 + 2] * r2;
-      float wx[3];
-      cross3(v, x, wx);
-      const float vB[3] = {v[3] + wx[0], v[4] + wx[1], v[5] + wx[2]};
-      const float xB[3] = {p[0] + x[0], p[1] + x[1], p[2] + x[2]};
-      float pw[3], vw[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        pw[r] = pb[r] + Rb[r * 3 + 0] * xB[0] + Rb[r * 3 + 1] * xB[1] + Rb[r * 3 + 2] * xB[2];
-        vw[r] = Rb[r * 3 + 0] * vB[0] + Rb[r * 3 + 1] * vB[1] + Rb[r * 3 + 2] * vB[2];
-      }
-      float fn = 0.f;
-      if (pw[2] < 0.f) fn = fmaxf(0.f, -M.k * pw[2] - M.d * vw[2]);
-      const float n2 = vw[0] * vw[0] + vw[1] * vw[1] + M.eps * M.eps;
-      const float inv_nrm = rsq(n2);
-      const float mfn = M.mu * fn * inv_nrm;
-      const float fw[3] = {-mfn * vw[0], -mfn * vw[1], fn};
-      float fB[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) fB[r] = Rb[0 * 3 + r] * fw[0] + Rb[1 * 3 + r] * fw[1] + Rb[2 * 3 + r] * fw[2];
-      float xf[3];
-      cross3(x, fB, xf);
-      pA[0] -= xf[0]; pA[1] -= xf[1]; pA[2] -= xf[2];
-      pA[3] -= fB[0]; pA[4] -= fB[1]; pA[5] -= fB[2];
-      if (fn > 0.f) {
-        mask |= 1u << M.corig[ci];
-        // Velocity Jacobian of the contact law (world), tangential-normal coupling
-        // dropped: D_w = a I + (d - a) z z^T - a w w^T with a = mu f_n / n and
-        // w = v_t / n.  In B axes z -> zb (third row of Rb) and w -> ub = Rb^T w.
-        const float aa = mfn;
-        const float al = M.d - aa;
-        const float zb[3] = {Rb[6], Rb[7], Rb[8]};
-        const float wt[2] = {vw[0] * inv_nrm, vw[1] * inv_nrm};
-        const float ub[3] = {Rb[0] * wt[0] + Rb[3] * wt[1], Rb[1] * wt[0] + Rb[4] * wt[1],
-                             Rb[2] * wt[0] + Rb[5] * wt[1]};
-        const float dt = io.dt;
-        // added inertia dt P^T D P with P = [-x^x, 1]; with w1 = x x zb, w2 = x x ub:
-        //   top-left  a (|x|^2 I - x x^T) + al w1 w1^T - a w2 w2^T
-        //   top-right a x^x + al w1 zb^T - a w2 ub^T,   bottom-right D
-        float w1[3], w2[3];
-        cross3(x, zb, w1);
-        cross3(x, ub, w2);
-        const float x2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        const float dta = dt * aa, dtal = dt * al;
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int cc = r; cc < 3; ++cc) {
-            const float tl = aa * ((r == cc ? x2 : 0.f) - x[r] * x[cc]) + al * w1[r] * w1[cc] - aa * w2[r] * w2[cc];
-            IA[SI(r, cc)] += dt * tl;
-            const float br = (r == cc ? aa : 0.f) + al * zb[r] * zb[cc] - aa * ub[r] * ub[cc];
-            IA[SI(r + 3, cc + 3)] += dt * br;
-          }
-        const float Xm[9] = {0.f, -x[2], x[1], x[2], 0.f, -x[0], -x[1], x[0], 0.f};
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 3; ++cc)
-            IA[SI(r, cc + 3)] += dta * Xm[r * 3 + cc] + dtal * w1[r] * zb[cc] - dta * w2[r] * ub[cc];
-        // bias of the added inertia: dt P^T D P (a_g - beta) = dt (x x Dw', Dw'), w' = P (a_g - beta)
-        const float sa[3] = {-beta[0], -beta[1], -beta[2]};
-        const float sl[3] = {agl[0] - beta[3], agl[1] - beta[4], agl[2] - beta[5]};
-        float sx[3];
-        cross3(sa, x, sx);
-        const float w3[3] = {sl[0] + sx[0], sl[1] + sx[1], sl[2] + sx[2]};
-        const float zw = zb[0] * w3[0] + zb[1] * w3[1] + zb[2] * w3[2];
-        const float uw = ub[0] * w3[0] + ub[1] * w3[1] + ub[2] * w3[2];
-        float Dw3[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) Dw3[r] = aa * w3[r] + al * zw * zb[r] - aa * uw * ub[r];
-        float xd[3];
-        cross3(x, Dw3, xd);
-        pA[0] += dt * xd[0]; pA[1] += dt * xd[1]; pA[2] += dt * xd[2];
-        pA[3] += dt * Dw3[0]; pA[4] += dt * Dw3[1]; pA[5] += dt * Dw3[2];
-      }
-      if (want_cost && I->cost_kind == 1) {
-        if (fn > 0.f) lane_cost += I->w_cv * (fabsf(vw[0]) + fabsf(vw[1]) + fabsf(vw[2]));
-        lane_cost += I->w_cf * (fabsf(fw[0]) + fabsf(fw[1]) + fabsf(fw[2] - I->f0z[M.corig[ci]]));
-      }
+      float vw[3], fw[3];
+      const float fn = contact_point(M.cpos[ci], R, p, v, beta, Rb, pb, agl, io.dt, law, IA, pA, vw, fw);
+      if (fn > 0.f) mask |= 1u << M.corig[ci];
+      if (want_cost && I->cost_kind == 1) contact_cost(I, fn, vw, fw, I->f0z[M.corig[ci]], lane_cost);
     }
-    if (want_cost) {
-      if (I->cost_kind == 1) {
-        if (is_base) {
-          const float* qt = io.bq + 3;
-          const float vn = sqrtf(qt[1] * qt[1] + qt[2] * qt[2] + qt[3] * qt[3]);
-          const float phi = 2.f * atan2f(vn, fabsf(qt[0]));
-          lane_cost += I->w_h * fabsf(io.bq[2] - I->z_des) + I->w_or * phi * phi;
-        }
-        if (is_joint) {
-          const float eq = io.q - I->q0[j];
-          lane_cost += I->w_q * eq * eq + I->w_eff * tau * tau;
-        }
-      } else {
-        if (is_joint) lane_cost += I->w_tau * tau * tau;
-        if (b == M.ee_body) {
-          float xe[3];
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-            xe[r] = p[r] + R[r * 3 + 0] * M.ee_pos[0] + R[r * 3 + 1] * M.ee_pos[1] + R[r * 3 + 2] * M.ee_pos[2];
-          const float dz = pb[2] + Rb[6] * xe[0] + Rb[7] * xe[1] + Rb[8] * xe[2] - I->z_des;
-          lane_cost += I->w_ee * dz * dz;
-        }
-      }
-    }
+    if (want_cost) body_cost(I, M, b, is_base, is_joint, base_term, io.q, is_joint ? I->q0[j] : 0.f, tau, R, p, Rb,
+                             pb, lane_cost);
   }
   io.cost = lane_cost;
   io.mask = mask;
@@ -522,33 +666,13 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
         for (int q = 0; q < 6; ++q) pA[q] += s[21 + q];
       }
       if (is_joint) {
-        // S = (ax, 0): U = IA S, D = S.U + g, u = tau - S.pA
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-          U[r] = IA[SI(r, 0)] * ax[0] + IA[SI(r, 1)] * ax[1] + IA[SI(r, 2)] * ax[2];
-        const float Dv = (bc.arm + gain) + (ax[0] * U[0] + ax[1] * U[1] + ax[2] * U[2]);
-        invD = rcp(Dv);
-        u = tau - (ax[0] * pA[0] + ax[1] * pA[1] + ax[2] * pA[2]);
-        float Ia[21];
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-          for (int cc = r; cc < 6; ++cc) Ia[SI(r, cc)] = IA[SI(r, cc)] - U[r] * U[cc] * invD;
-        float Iac[6];
-        sym6_mv(Ia, c, Iac);
-        const float uD = u * invD;
-        float pa[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) pa[q] = pA[q] + Iac[q] + U[q] * uD;
+        float Ip[21], pp[6];
+        backward_joint(IA, pA, ax, c, e, tau, bc.arm, gain, U, invD, u, Ip, pp);
         float* s = slots + b * kSlot;
-        float Ip[21];
-        shift_inertia_to_parent(Ia, e, Ip);
 #pragma unroll
         for (int q = 0; q < 21; ++q) s[q] = Ip[q];
-        float ef[3];
-        cross3(e, pa + 3, ef);
-        s[21] = pa[0] + ef[0]; s[22] = pa[1] + ef[1]; s[23] = pa[2] + ef[2];
-        s[24] = pa[3]; s[25] = pa[4]; s[26] = pa[5];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s[21 + q] = pp[q];
       }
     }
     wave_sync();
@@ -556,41 +680,8 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
 
   // ---- root: floating base solves IA0 a0' = -pA0 (Cholesky); fixed roots use -a_g
   if (is_base) {
-    float L[21], invL[6];
-#pragma unroll
-    for (int q = 0; q < 21; ++q) L[q] = IA[q];
-    // in-place Cholesky of the packed symmetric matrix (lower factor stored as L[SI(i,j)], j <= i)
-#pragma unroll
-    for (int jj = 0; jj < 6; ++jj) {
-      float dsum = L[SI(jj, jj)];
-#pragma unroll
-      for (int k = 0; k < jj; ++k) dsum -= L[SI(jj, k)] * L[SI(jj, k)];
-      const float inv = rsq(dsum);
-      invL[jj] = inv;
-      L[SI(jj, jj)] = dsum * inv;
-#pragma unroll
-      for (int i = jj + 1; i < 6; ++i) {
-        float sm = L[SI(i, jj)];
-#pragma unroll
-        for (int k = 0; k < jj; ++k) sm -= L[SI(i, k)] * L[SI(jj, k)];
-        L[SI(i, jj)] = sm * inv;
-      }
-    }
-    float y[6], a0[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      float sm = -pA[i];
-#pragma unroll
-      for (int k = 0; k < i; ++k) sm -= L[SI(i, k)] * y[k];
-      y[i] = sm * invL[i];
-    }
-#pragma unroll
-    for (int i = 5; i >= 0; --i) {
-      float sm = y[i];
-#pragma unroll
-      for (int k = i + 1; k < 6; ++k) sm -= L[SI(k, i)] * a0[k];
-      a0[i] = sm * invL[i];
-    }
+    float a0[6];
+    base_solve(IA, pA, a0);
     float* s0 = slots;
 #pragma unroll
     for (int q = 0; q < 6; ++q) s0[q] = a0[q];
@@ -614,16 +705,10 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
         al[0] = al[1] = al[2] = 0.f; al[3] = 0.f; al[4] = 0.f; al[5] = g;
       }
       float a[6];
-      shift_motion(al, e, a);
-#pragma unroll
-      for (int q = 0; q < 6; ++q) a[q] += c[q];
-      float Ua = 0.f;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) Ua = fmaf(U[q], a[q], Ua);
-      qdd = (u - Ua) * invD;
+      qdd = forward_joint(al, e, c, U, u, invD, ax, a);
       float* s = slots + b * kSlot;
-      s[0] = a[0] + ax[0] * qdd; s[1] = a[1] + ax[1] * qdd; s[2] = a[2] + ax[2] * qdd;
-      s[3] = a[3]; s[4] = a[4]; s[5] = a[5];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) s[q] = a[q];
     }
     wave_sync();
   }
@@ -747,7 +832,7 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
 // w.y .. w.y + 64/G - 1 (those >= N are computed but not stored).
 // ---------------------------------------------------------------------------
 template <int G>
-__device__ void rollout_item(const DevInst& I, int first, int group_stride, float* smem) {
+__device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride, float* smem) {
   const int lane = threadIdx.x;
   const int grp = lane / G, l = lane % G;
   const DevModel& M = *I.model;
@@ -857,6 +942,437 @@ __global__ __launch_bounds__(64) void rollout_persistent_kernel(const DevInst* _
     if (item >= n_items) break;
     const int2 w = work[item];
     rollout_item<G>(insts[w.x], w.y, group_stride, smem);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chain schedule: one lane per kinematic chain (heavy-path decomposition of
+// the tree), 64/GC rollouts per wavefront.  Per step a lane walks its chain
+// root to leaf (Hermite reference, PD law, kinematics), leaf to root (inertia,
+// bias, contacts, running cost, articulated-body pass, root solve) and root to
+// leaf again (accelerations, integration).  Lanes meet only where a chain
+// hangs off another chain's body, through attach and publish slots in LDS; a
+// level loop with one body per lane keeps every parent ahead of its children.
+// Each body goes through the same helpers in the same order as in the body
+// schedule (children added in child-list order, costs summed per body in body
+// order), so the two schedules give identical results.
+//
+// LDS: the model table (body rows, chain bodies, contact rows) once per
+// wavefront, then one region per rollout group:
+//   rec[nb][kRec]  per body: [0,9) R [9,12) p [12,18) v [18,24) beta [24,27) e
+//                  [27,30) ax 30 tau 31 gain; after the backward pass [0,6) U
+//                  6 1/D 7 u [8,14) c; and, kept across steps, 32 q 33 qd
+//                  34 running cost of the body
+//   base[16]       world rotation (9) and position (3) of frame B
+//   knots[E]       this rollout's knots
+//   pub[nch][kPub] articulated inertia and bias a chain's first body hands to
+//                  its parent on another chain
+//   att[natt][kAtt] frame (R p v beta) and a' of a body other chains hang off
+//   red[GC]        reduction scratch
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ibits(float x) { return __float_as_int(x); }
+
+// Root-to-leaf pass: PD law (unless terminal) and kinematics of every body of
+// this lane's chain; publishes frames other chains hang off.
+__device__ __forceinline__ void chain_fk(const DevModel& M, const DevInst& I, const float* rows, const int* cbody,
+                                         float* rec, float* bas, const float* knots, float* att, bool act, int c,
+                                         int cfirst, int catt, int nlev, int f, int F, float dt, float inv_delta,
+                                         bool terminal, const float* bq, const float* bv) {
+  const int fb = M.fb;
+  float fR[9], fp[3], fv[6], fbt[6];  // frame of this chain's previous body
+  for (int d = 0; d < nlev; ++d) {
+    const int b = act ? cbody[c * kMaxLevels + d] : -1;
+    if (b >= 0) {
+      const float* rw = rows + b * kRow;
+      float* r = rec + b * kRec;
+      if (fb && b == 0) {
+        float Rw[9];
+        quat_R(bq + 3, Rw);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) bas[k] = Rw[k];
+        bas[9] = bq[0]; bas[10] = bq[1]; bas[11] = bq[2];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) fR[k] = (k % 4 == 0) ? 1.f : 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) fp[k] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { fv[k] = bv[k]; fbt[k] = 0.f; }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) r[k] = fR[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r[9 + k] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { r[12 + k] = fv[k]; r[18 + k] = 0.f; }
+#pragma unroll
+        for (int k = 24; k < 32; ++k) r[k] = 0.f;
+      } else {
+        const int j = b - fb;
+        const float q = r[32], qd = r[33];
+        float tau = 0.f, gain = 0.f;
+        if (!terminal) {
+          float qref, vref;
+          hermite(knots, I.K, I.nu, F, I.delta, inv_delta, f, j, &qref, &vref);
+          pd_law(rw[row::kp], rw[row::kd], rw[row::taumax], dt, q, qd, qref, vref, tau, gain);
+        }
+        float Rl[9], pl[3], vl[6], bl[6];
+        if (d == cfirst) {
+          if (catt >= 0) {
+            const float* a = att + catt * kAtt;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Rl[k] = a[k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pl[k] = a[9 + k];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) { vl[k] = a[12 + k]; bl[k] = a[18 + k]; }
+          } else {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Rl[k] = (k % 4 == 0) ? 1.f : 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pl[k] = 0.f;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) { vl[k] = 0.f; bl[k] = 0.f; }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Rl[k] = fR[k];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) pl[k] = fp[k];
+#pragma unroll
+          for (int k = 0; k < 6; ++k) { vl[k] = fv[k]; bl[k] = fbt[k]; }
+        }
+        float cq, sq;
+        sincosf(q, &sq, &cq);
+        float e[3], ax[3], cv[6];
+        fk_joint(Rl, pl, vl, bl, rw + row::P, rw + row::p_tree, rw + row::axis_p, cq, sq, qd, fR, fp, e, ax, fv, cv,
+                 fbt);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) r[k] = fR[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { r[9 + k] = fp[k]; r[24 + k] = e[k]; r[27 + k] = ax[k]; }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { r[12 + k] = fv[k]; r[18 + k] = fbt[k]; }
+        r[30] = tau;
+        r[31] = gain;
+      }
+      const int aid = ibits(rw[row::att]);
+      if (aid >= 0) {
+        float* a = att + aid * kAtt;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a[k] = fR[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a[9 + k] = fp[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { a[12 + k] = fv[k]; a[18 + k] = fbt[k]; }
+      }
+    }
+    wave_sync();
+  }
+}
+
+// Leaf-to-root pass: inertia, bias, contacts and running cost of each body,
+// then the articulated-body step; the floating base solves for its
+// acceleration.  Returns this lane's contact activity bits.
+__device__ __forceinline__ uint32_t chain_backward(const DevModel& M, const DevInst& I, const float* rows,
+                                                   const int* cbody, const float* ctab, float* rec, const float* bas,
+                                                   float* pub, float* att, bool act, int c, int cfirst, int catt,
+                                                   int nlev, float dt, bool want_cost, float base_term,
+                                                   float* ba, float* ca) {
+  const int fb = M.fb;
+  const ContactLaw law{M.k, M.d, M.mu, M.eps};
+  const float g = M.g;
+  uint32_t mask = 0u;
+  float cI[21], cp[6];  // articulated inertia and bias of this chain's deeper body, at this body's origin
+  float Rb[9], pb[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rb[k] = bas[k];
+  pb[0] = bas[9]; pb[1] = bas[10]; pb[2] = bas[11];
+  const float agl[3] = {-g * Rb[6], -g * Rb[7], -g * Rb[8]};
+  for (int d = nlev - 1; d >= 0; --d) {
+    const int b = act ? cbody[c * kMaxLevels + d] : -1;
+    if (b >= 0) {
+      const float* rw = rows + b * kRow;
+      float* r = rec + b * kRec;
+      const bool is_base = fb && b == 0;
+      float R[9], p[3], v[6], beta[6];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) R[k] = r[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) p[k] = r[9 + k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) { v[k] = r[12 + k]; beta[k] = r[18 + k]; }
+      const float tau = r[30], gain = r[31];
+      float IA[21], pA[6];
+      if (is_base) {
+#pragma unroll
+        for (int k = 0; k < 21; ++k) IA[k] = M.base_I[k];
+      } else {
+        body_inertia(R, rw + row::com, rw + row::Ic, rw[row::mass], IA);
+      }
+      bias_force(IA, v, pA);
+      float lane_cost = 0.f;
+      const int c0 = ibits(rw[row::c_begin]), cn = ibits(rw[row::c_count]);
+      for (int ci = c0; ci < c0 + cn; ++ci) {
+        const float* ct = ctab + ci * kCt;
+        float vw[3], fw[3];
+        const float fn = contact_point(ct, R, p, v, beta, Rb, pb, agl, dt, law, IA, pA, vw, fw);
+        if (fn > 0.f) mask |= 1u << ibits(ct[4]);
+        if (want_cost && I.cost_kind == 1) contact_cost(&I, fn, vw, fw, ct[3], lane_cost);
+      }
+      if (want_cost) {
+        body_cost(&I, M, b, is_base, !is_base, base_term, is_base ? 0.f : r[32], rw[row::q0], tau, R, p, Rb, pb,
+                  lane_cost);
+        r[34] += lane_cost;
+      }
+      // children in child-list order: the chain's own child from registers, others from their publish slots
+      const int nch = ibits(rw[row::n_child]), heavy = ibits(rw[row::heavy]);
+      for (int k = 0; k < nch; ++k) {
+        const int ch = ibits(rw[row::child + k]);
+        if (ch == heavy) {
+#pragma unroll
+          for (int q = 0; q < 21; ++q) IA[q] += cI[q];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) pA[q] += cp[q];
+        } else {
+          const float* s = pub + ibits(rows[ch * kRow + row::chain]) * kPub;
+#pragma unroll
+          for (int q = 0; q < 21; ++q) IA[q] += s[q];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) pA[q] += s[21 + q];
+        }
+      }
+      if (!is_base) {
+        float e[3], ax[3], cv[6];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { e[k] = r[24 + k]; ax[k] = r[27 + k]; }
+        vel_product(v, ax, r[33], cv);
+        float U[6], invD, u, Ip[21], pp[6];
+        backward_joint(IA, pA, ax, cv, e, tau, rw[row::arm], gain, U, invD, u, Ip, pp);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { r[k] = U[k]; r[8 + k] = cv[k]; }
+        r[6] = invD;
+        r[7] = u;
+        if (d == cfirst && catt >= 0) {
+          float* s = pub + c * kPub;
+#pragma unroll
+          for (int q = 0; q < 21; ++q) s[q] = Ip[q];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) s[21 + q] = pp[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 21; ++q) cI[q] = Ip[q];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) cp[q] = pp[q];
+        }
+      } else {
+        float a0[6];
+        base_solve(IA, pA, a0);
+        ba[0] = a0[0]; ba[1] = a0[1]; ba[2] = a0[2];
+        ba[3] = a0[3] + agl[0]; ba[4] = a0[4] + agl[1]; ba[5] = a0[5] + agl[2];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) ca[q] = a0[q];
+        const int aid = ibits(rw[row::att]);
+        if (aid >= 0) {
+#pragma unroll
+          for (int q = 0; q < 6; ++q) att[aid * kAtt + 24 + q] = a0[q];
+        }
+      }
+    }
+    wave_sync();
+  }
+  return mask;
+}
+
+// Root-to-leaf pass: joint accelerations and the semi-implicit Euler update of
+// the joints (v += dt qdd, q += dt v).
+__device__ __forceinline__ void chain_forward(const DevModel& M, const float* rows, const int* cbody, float* rec,
+                                              float* att, bool act, int c, int cfirst, int catt, int nlev, float dt,
+                                              float* ca) {
+  const int fb = M.fb;
+  for (int d = 0; d < nlev; ++d) {
+    const int b = act ? cbody[c * kMaxLevels + d] : -1;
+    if (b >= 0 && !(fb && b == 0)) {
+      const float* rw = rows + b * kRow;
+      float* r = rec + b * kRec;
+      float al[6];
+      if (d == cfirst) {
+        if (catt >= 0) {
+#pragma unroll
+          for (int q = 0; q < 6; ++q) al[q] = att[catt * kAtt + 24 + q];
+        } else {
+          // fixed world: a' = -a_g = (0, 0, 0, 0, 0, g)
+          al[0] = al[1] = al[2] = 0.f; al[3] = 0.f; al[4] = 0.f; al[5] = M.g;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) al[q] = ca[q];
+      }
+      float U[6], cv[6], e[3], ax[3];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) { U[k] = r[k]; cv[k] = r[8 + k]; }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) { e[k] = r[24 + k]; ax[k] = r[27 + k]; }
+      const float qdd = forward_joint(al, e, cv, U, r[7], r[6], ax, ca);
+      const int aid = ibits(rw[row::att]);
+      if (aid >= 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) att[aid * kAtt + 24 + q] = ca[q];
+      }
+      const float qd = fmaf(dt, qdd, r[33]);
+      r[33] = qd;
+      r[32] = fmaf(dt, qd, r[32]);
+    }
+    wave_sync();
+  }
+}
+
+template <int GC>
+__device__ __attribute__((always_inline)) void chain_item(const DevInst& I, int first, int group_stride,
+                                                          int table_floats, int groups, float* smem) {
+  const int lane = threadIdx.x;
+  const int grp = lane / GC, l = lane % GC;
+  const DevModel& M = *I.model;
+  const int nb = M.nb, nc = M.nc, fb = M.fb, nch = M.n_chains;
+
+  // model table of this instance (posture and nominal contact forces patched in)
+  float* rows = smem;
+  int* cbody = reinterpret_cast<int*>(smem + nb * kRow);
+  float* ctab = smem + nb * kRow + kMaxChains * kMaxLevels;
+  {
+    const float4* src = reinterpret_cast<const float4*>(&M.rows[0][0]);
+    float4* dst = reinterpret_cast<float4*>(rows);
+    for (int i = lane; i < nb * kRow / 4; i += 64) dst[i] = src[i];
+    const int* cb = &M.chain_body[0][0];
+    for (int i = lane; i < kMaxChains * kMaxLevels; i += 64) cbody[i] = cb[i];
+    const float* cs = &M.ctab[0][0];
+    for (int i = lane; i < nc * kCt; i += 64) ctab[i] = cs[i];
+  }
+  wave_sync();
+  if (I.cost_kind == 1) {
+    for (int b = fb + lane; b < nb; b += 64) rows[b * kRow + row::q0] = I.q0[b - fb];
+    for (int ci = lane; ci < nc; ci += 64) ctab[ci * kCt + 3] = I.f0z[ibits(ctab[ci * kCt + 4])];
+  }
+  wave_sync();
+  if (grp >= groups) return;  // the LDS budget holds fewer rollout groups than the wavefront has
+
+  const int n = first + grp;
+  const bool valid = n < I.N;
+  float* gs = smem + table_floats + grp * group_stride;
+  float* rec = gs;
+  float* bas = rec + nb * kRec;
+  float* knots = bas + 16;
+  float* pub = knots + ((I.E + 3) & ~3);
+  float* att = pub + nch * kPub;
+  float* red = att + M.n_att * kAtt;
+
+  if (I.generate) {
+    sample_group<GC>(M, I, valid ? n : 0, l, knots, valid);
+  } else {
+    const float* src = I.samples + (size_t)(valid ? n : 0) * I.E;
+    for (int e = l; e < I.E; e += GC) knots[e] = src[e];
+  }
+
+  const bool act = l < nch;
+  const int c = act ? l : 0;
+  const int cfirst = M.chain_first[c], catt = M.chain_att[c];
+  const int nlev = M.n_levels;
+  const int nq = fb ? 7 + M.nu : M.nu;
+  const bool base_lane = act && fb && c == 0;
+  for (int d = 0; d < nlev; ++d) {
+    const int b = act ? cbody[c * kMaxLevels + d] : -1;
+    if (b >= 0) {
+      float* r = rec + b * kRec;
+      if (!(fb && b == 0)) {
+        const int j = b - fb;
+        r[32] = I.x0[(fb ? 7 : 0) + j];
+        r[33] = I.x0[nq + (fb ? 6 : 0) + j];
+      }
+      r[34] = 0.f;
+    }
+  }
+  if (!fb && l == 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) bas[k] = (k < 9 && k % 4 == 0) ? 1.f : 0.f;
+  }
+  float bq[7], bv[6], ba[6], ca[6];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) bq[k] = fb ? I.x0[k] : 0.f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) { bv[k] = fb ? I.x0[nq + k] : 0.f; ba[k] = 0.f; ca[k] = 0.f; }
+  wave_sync();
+
+  const int nsub = M.nsub, H = I.H, F = H * nsub;
+  const float dt = I.dt / (float)nsub;
+  const float inv_delta = 1.f / I.delta;
+  for (int f = 0; f < F; ++f) {
+    const bool control = (f % nsub) == 0;
+    float base_term = 0.f;
+    if (control && base_lane && I.cost_kind == 1) base_term = base_cost_term(&I, bq);
+    chain_fk(M, I, rows, cbody, rec, bas, knots, att, act, c, cfirst, catt, nlev, f, F, dt, inv_delta, false, bq, bv);
+    const uint32_t mask = chain_backward(M, I, rows, cbody, ctab, rec, bas, pub, att, act, c, cfirst, catt, nlev, dt,
+                                         control, base_term, ba, ca);
+    chain_forward(M, rows, cbody, rec, att, act, c, cfirst, catt, nlev, dt, ca);
+    if (control && I.masks) {
+      const uint32_t mk = group_or<GC>(mask, red, l);
+      if (l == 0 && valid) I.masks[(size_t)n * H + f / nsub] = mk;
+    }
+    if (base_lane) integrate_base(bq, bv, ba, dt);
+  }
+
+  // terminal cost
+  if (I.cost_kind == 1) {
+    if (base_lane) {
+      const float T = (float)H * I.dt;
+      float e = 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) e += fabsf(bq[k] - (I.x0[k] + I.v_des[k] * T));
+      rec[34] += I.w_H * e;
+    }
+  } else {
+    // end-effector height at x_H
+    chain_fk(M, I, rows, cbody, rec, bas, knots, att, act, c, cfirst, catt, nlev, F, F, dt, inv_delta, true, bq, bv);
+    const int ee = M.ee_body;
+    if (act && ee >= 0 && ibits(rows[ee * kRow + row::chain]) == c) {
+      float* r = rec + ee * kRec;
+      const float dz = ee_height_error(r, r + 9, M.ee_pos, bas, bas + 9, I.z_des);
+      const float tc = I.w_ee * dz * dz;
+      r[34] += tc;
+    }
+  }
+  wave_sync();
+  if (l == 0 && valid) {
+    float S = 0.f;
+    for (int b = 0; b < nb; ++b) S += rec[b * kRec + 34];
+    if (!isfinite(S)) S = INFINITY;
+    I.costs[n] = S;
+  }
+  wave_sync();
+}
+
+// Block = one wavefront holding `groups` (<= 64/GC) rollout groups; work[blockIdx]
+// = (instance, first sample) or, when work is null, instance 0 and sample
+// blockIdx * groups.
+template <int GC>
+__global__ __launch_bounds__(64) void chain_kernel(const DevInst* __restrict__ insts, const int2* __restrict__ work,
+                                                   int group_stride, int table_floats, int groups) {
+  extern __shared__ float smem[];
+  const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * groups);
+  chain_item<GC>(insts[w.x], w.y, group_stride, table_floats, groups, smem);
+}
+
+template <int GC>
+__global__ __launch_bounds__(64) void chain_persistent_kernel(const DevInst* __restrict__ insts,
+                                                              const int2* __restrict__ work, int n_items,
+                                                              unsigned int* __restrict__ counter, int group_stride,
+                                                              int table_floats, int groups) {
+  extern __shared__ float smem[];
+  for (;;) {
+    int item = 0;
+    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    item = __builtin_amdgcn_readfirstlane(item);
+    if (item >= n_items) break;
+    const int2 w = work[item];
+    chain_item<GC>(insts[w.x], w.y, group_stride, table_floats, groups, smem);
+    wave_sync();
   }
 }
 
@@ -1112,5 +1628,13 @@ MPPI_INST(16)
 MPPI_INST(32)
 MPPI_INST(64)
 #undef MPPI_INST
+#define MPPI_CHAIN_INST(GC)                                                                          \
+  template __global__ void chain_kernel<GC>(const DevInst*, const int2*, int, int, int);             \
+  template __global__ void chain_persistent_kernel<GC>(const DevInst*, const int2*, int, unsigned int*, int, int, int);
+MPPI_CHAIN_INST(1)
+MPPI_CHAIN_INST(2)
+MPPI_CHAIN_INST(4)
+MPPI_CHAIN_INST(8)
+#undef MPPI_CHAIN_INST
 
 }  // namespace mppi

@@ -59,7 +59,8 @@ class StepInfo(C.Structure):
 
 EXPORTS = [
     "mppi_model_create", "mppi_model_destroy", "mppi_create", "mppi_destroy", "mppi_set_tick",
-    "mppi_get_tick", "mppi_set_lanes_per_rollout", "mppi_get_lanes_per_rollout", "mppi_step",
+    "mppi_get_tick", "mppi_set_schedule", "mppi_get_schedule", "mppi_set_lanes_per_rollout",
+    "mppi_get_lanes_per_rollout", "mppi_step",
     "mppi_step_batch", "mppi_debug_philox", "mppi_debug_samples", "mppi_debug_dynamics",
     "mppi_debug_rollouts", "mppi_debug_update", "mppi_profile_enable", "mppi_profile_read",
     "mppi_set_batch_options", "mppi_graph_create", "mppi_graph_launch", "mppi_graph_destroy",
@@ -91,6 +92,8 @@ def lib():
         L.mppi_destroy.argtypes = [vp]
         L.mppi_set_tick.argtypes = [vp, u32]
         L.mppi_get_tick.argtypes = [vp, C.POINTER(u32)]
+        L.mppi_set_schedule.argtypes = [vp, i32]
+        L.mppi_get_schedule.argtypes = [vp, C.POINTER(i32)]
         L.mppi_set_lanes_per_rollout.argtypes = [vp, i32]
         L.mppi_get_lanes_per_rollout.argtypes = [vp, C.POINTER(i32)]
         L.mppi_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
@@ -223,10 +226,15 @@ def make_params(p):
     return s, (f0, q0)
 
 
-class Controller:
-    """One MPC instance (mppi_ctx)."""
+SCHEDULES = {"body": 0, "chain": 1}
 
-    def __init__(self, model, params, seed, lanes=0):
+
+class Controller:
+    """One MPC instance (mppi_ctx).  schedule: "body" (one lane per body, with
+    `lanes` lanes per rollout) or "chain" (one lane per kinematic chain); None
+    keeps the library's default (the body schedule)."""
+
+    def __init__(self, model, params, seed, lanes=0, schedule=None):
         self.model = model
         self.params = dict(params)
         s, self._keep = make_params(params)
@@ -236,6 +244,8 @@ class Controller:
         self.N, self.H, self.K, self.I = (params["n_samples"], params["horizon"],
                                           params["n_knots"], params["n_iters"])
         self.E = 2 * self.K * model.nu
+        if schedule is not None:
+            self.set_schedule(schedule)
         if lanes:
             self.set_lanes(lanes)
 
@@ -267,7 +277,17 @@ class Controller:
         return g.value
 
     def set_lanes(self, lanes):
+        """Body schedule with `lanes` lanes per rollout."""
         _check(lib().mppi_set_lanes_per_rollout(self.h, int(lanes)), "mppi_set_lanes_per_rollout")
+
+    @property
+    def schedule(self):
+        s = C.c_int32()
+        _check(lib().mppi_get_schedule(self.h, C.byref(s)), "mppi_get_schedule")
+        return "chain" if s.value == 1 else "body"
+
+    def set_schedule(self, schedule):
+        _check(lib().mppi_set_schedule(self.h, SCHEDULES[schedule]), "mppi_set_schedule")
 
     def step(self, state, knots_in, knots_out, best_knots=None, info=None, costs=None, stream=None):
         _check(lib().mppi_step(self.h, _ptr(state), _ptr(knots_in), _ptr(knots_out),
