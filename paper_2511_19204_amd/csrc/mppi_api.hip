@@ -25,15 +25,15 @@
 
 namespace mppi {
 // kernels (mppi_kernels.hip)
-template <int G> __global__ void rollout_kernel(const DevInst*, const int2*, int);
-template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int);
+template <int G> __global__ void rollout_kernel(const DevInst*, const int2*, int, int);
+template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
 template <int GC> __global__ void chain_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int, int);
 __global__ void reset_counters(unsigned int*, int);
 template <int G> __global__ void sample_kernel(const DevInst*, int);
 template <int G>
 __global__ void dynamics_kernel(const DevModel*, int, const float*, const float*, const float*, const float*, float,
-                                float*, int);
+                                float*, int, int);
 struct UpdateOut {
   float* knots_out;
   float* best_out;
@@ -562,8 +562,9 @@ static LaunchShape launch_shape(int key, const Dims& dm) {
   LaunchShape sh;
   if (key > 0) {
     sh.stride = group_floats(key, dm.E);
+    sh.table = body_table_floats(dm.nc);
     sh.groups = 64 / key;
-    sh.lds = sh.groups * sh.stride * (int)sizeof(float);
+    sh.lds = (sh.table + sh.groups * sh.stride) * (int)sizeof(float);
   } else {
     const int GC = -key;
     sh.stride = chain_group_floats(GC, dm.nb, dm.E, dm.nch, dm.natt);
@@ -579,7 +580,7 @@ static int rollouts_per_block(int key, const Dims& dm) { return launch_shape(key
 template <int G>
 static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
                                    hipStream_t s) {
-  hipLaunchKernelGGL(rollout_kernel<G>, dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride);
+  hipLaunchKernelGGL(rollout_kernel<G>, dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
   return hipGetLastError();
 }
 template <int GC>
@@ -622,7 +623,7 @@ static hipError_t launch_persistent_k(Kern kern, int n_items, const LaunchShape&
 static hipError_t launch_persistent(int key, int n_items, const DevInst* insts, const int2* work, const Dims& dm,
                                     unsigned int* counter, hipStream_t s) {
   const LaunchShape sh = launch_shape(key, dm);
-#define BODY_P(G) launch_persistent_k(rollout_persistent_kernel<G>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride)
+#define BODY_P(G) launch_persistent_k(rollout_persistent_kernel<G>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table)
 #define CHAIN_P(GC) launch_persistent_k(chain_persistent_kernel<GC>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table, sh.groups)
   switch (key) {
     case 4: return BODY_P(4);
@@ -1125,8 +1126,10 @@ template <int G>
 static hipError_t launch_dyn_G(const mppi_model* m, int n, const float* q, const float* v, const float* qr,
                                const float* vr, float dt, float* qdd, hipStream_t s) {
   const int R = 64 / G;
-  hipLaunchKernelGGL(dynamics_kernel<G>, dim3((n + R - 1) / R), dim3(64), lds_bytes(G, 0), s, m->dev, n, q, v, qr, vr,
-                     dt, qdd, group_floats(G, 0));
+  const int table = body_table_floats(m->host.nc);
+  const int lds = (table + R * group_floats(G, 0)) * (int)sizeof(float);
+  hipLaunchKernelGGL(dynamics_kernel<G>, dim3((n + R - 1) / R), dim3(64), lds, s, m->dev, n, q, v, qr, vr, dt, qdd,
+                     group_floats(G, 0), table);
   return hipGetLastError();
 }
 

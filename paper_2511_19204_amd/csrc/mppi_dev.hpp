@@ -108,23 +108,32 @@ struct DevUpdate {
 // LDS layouts of the rollout kernels (floats), shared by host and device.
 // ---------------------------------------------------------------------------
 // Body schedule, one rollout group of G lanes:
-//   slot[b][29] per body: forward kinematics R(9) p(3) v(6) beta(6);
-//                         reused by the backward sweep for Ia(21) pa(6),
-//                         then by the forward sweep for a'(6)
+//   slot[b][36] per body, 16-byte aligned and read/written as float4:
+//               forward kinematics R(9) p(3) v(6) beta(6) in [0,24);
+//               reused by the backward sweep for Ia(21) pa(6) in [0,27),
+//               then by the forward sweep for a'(6) in [0,6)
 //   base[16]   : world rotation (9) and position (3) of frame B
 //   knots[E]   : this rollout's knots
 //   red[G]     : reduction scratch
-// The slot stride is odd and a group's size is padded to G (mod 32) floats, so
-// the 64 lanes of a wavefront (64/G groups) touch distinct LDS banks.
-constexpr int kSlot = 29;
+// A slot is 36 floats (4 LDS banks past a multiple of 32), so the slots that
+// the lanes of one level touch at once start in different banks; rollout groups
+// are staggered by 16 banks.
+constexpr int kSlot = 36;
 __host__ __device__ inline int group_floats(int G, int E) {
-  const int raw = G * kSlot + 16 + ((E + 3) & ~3) + G;
-  const int want = G < 32 ? G : 0;
+  const int raw = G * kSlot + 16 + ((E + 3) & ~3) + ((G + 3) & ~3);
+  const int want = G < 32 ? 16 : 0;
   return raw + ((want - raw % 32) + 64) % 32;
 }
 
-// Chain schedule: the model table (body rows, chain bodies, contact rows) once
-// per wavefront, then one region per rollout group:
+// Model table, staged once per work item at the start of a block's LDS:
+//   [0,24)            base spatial inertia (21, packed) and padding
+//   [24,24+nc*kCt)    contact rows (position, nominal normal force, index)
+// and, for the chain schedule only, the body rows and the chain-body table.
+constexpr int kTabContacts = 24;
+__host__ __device__ inline int body_table_floats(int nc) { return kTabContacts + nc * kCt; }
+
+// Chain schedule: after the model table (with body rows and chain bodies), one
+// region per rollout group:
 //   rec[nb][kRec]   per-body record (see the chain kernel)
 //   base[16]        world rotation (9) and position (3) of frame B
 //   knots[E]        this rollout's knots
@@ -135,7 +144,9 @@ __host__ __device__ inline int group_floats(int G, int E) {
 constexpr int kRec = 36;
 constexpr int kPub = 28;
 constexpr int kAtt = 32;
-__host__ __device__ inline int chain_table_floats(int nb, int nc) { return nb * kRow + kMaxChains * kMaxLevels + nc * kCt; }
+__host__ __device__ inline int chain_table_floats(int nb, int nc) {
+  return body_table_floats(nc) + nb * kRow + kMaxChains * kMaxLevels;
+}
 __host__ __device__ inline int chain_group_floats(int GC, int nb, int E, int nch, int natt) {
   const int raw = nb * kRec + 16 + ((E + 3) & ~3) + nch * kPub + natt * kAtt + GC;
   const int r4 = (raw + 3) & ~3;

@@ -81,6 +81,58 @@ __device__ __forceinline__ void quat_R(const float* q, float* R) {
   R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
 }
 
+// 16-byte LDS transfers of slot records (addresses are 16-byte aligned)
+__device__ __forceinline__ void put4(float* d, float a, float b, float c, float e) {
+  *reinterpret_cast<float4*>(d) = make_float4(a, b, c, e);
+}
+__device__ __forceinline__ float4 get4(const float* s) { return *reinterpret_cast<const float4*>(s); }
+
+// frame record: R (9), p (3), v (6), beta (6)
+__device__ __forceinline__ void put_frame(float* d, const float* R, const float* p, const float* v, const float* bt) {
+  put4(d, R[0], R[1], R[2], R[3]);
+  put4(d + 4, R[4], R[5], R[6], R[7]);
+  put4(d + 8, R[8], p[0], p[1], p[2]);
+  put4(d + 12, v[0], v[1], v[2], v[3]);
+  put4(d + 16, v[4], v[5], bt[0], bt[1]);
+  put4(d + 20, bt[2], bt[3], bt[4], bt[5]);
+}
+__device__ __forceinline__ void get_frame(const float* s, float* R, float* p, float* v, float* bt) {
+  const float4 a = get4(s), b = get4(s + 4), c = get4(s + 8), d = get4(s + 12), e = get4(s + 16), f = get4(s + 20);
+  R[0] = a.x; R[1] = a.y; R[2] = a.z; R[3] = a.w; R[4] = b.x; R[5] = b.y; R[6] = b.z; R[7] = b.w; R[8] = c.x;
+  p[0] = c.y; p[1] = c.z; p[2] = c.w;
+  v[0] = d.x; v[1] = d.y; v[2] = d.z; v[3] = d.w; v[4] = e.x; v[5] = e.y;
+  bt[0] = e.z; bt[1] = e.w; bt[2] = f.x; bt[3] = f.y; bt[4] = f.z; bt[5] = f.w;
+}
+// articulated inertia (21, packed) and bias (6) record, one float of padding
+__device__ __forceinline__ void put_art(float* d, const float* Ip, const float* pp) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) put4(d + 4 * k, Ip[4 * k], Ip[4 * k + 1], Ip[4 * k + 2], Ip[4 * k + 3]);
+  put4(d + 20, Ip[20], pp[0], pp[1], pp[2]);
+  put4(d + 24, pp[3], pp[4], pp[5], 0.f);
+}
+__device__ __forceinline__ void add_art(const float* s, float* IA, float* pA) {
+  float t[28];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const float4 x = get4(s + 4 * k);
+    t[4 * k] = x.x; t[4 * k + 1] = x.y; t[4 * k + 2] = x.z; t[4 * k + 3] = x.w;
+  }
+#pragma unroll
+  for (int q = 0; q < 21; ++q) IA[q] += t[q];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) pA[q] += t[21 + q];
+}
+// spatial acceleration record (6)
+__device__ __forceinline__ void put_acc(float* d, const float* a) {
+  put4(d, a[0], a[1], a[2], a[3]);
+  *reinterpret_cast<float2*>(d + 4) = make_float2(a[4], a[5]);
+}
+__device__ __forceinline__ void get_acc(const float* s, float* a) {
+  const float4 x = get4(s);
+  const float2 y = *reinterpret_cast<const float2*>(s + 4);
+  a[0] = x.x; a[1] = x.y; a[2] = x.z; a[3] = x.w; a[4] = y.x; a[5] = y.y;
+}
+
 // ---------------------------------------------------------------------------
 // Per-lane physics of one step.  Lane b (< nb) owns body b and its joint.
 //
@@ -106,15 +158,16 @@ struct StepIO {
   uint32_t mask;       // contact activity bits of this lane's contacts
 };
 
-// Per-lane constants of the body (and joint) a lane owns, loaded once per kernel.
+// Per-lane constants of the body (and joint) a lane owns, loaded once per work item.
 struct BodyConst {
   float P[27];        // joint rotation C(q) = P0 + cos q P1 + sin q P2
   float p_tree[3], axis_p[3], com[3], Ic[6];
-  float mass, kp, kd, taumax, arm;
+  float mass, kp, kd, taumax, arm, q0;
   int parent, depth, n_child, c_begin, c_count;
+  uint32_t child_lo, child_hi;  // child body indices, 8 bits each, child-list order
 };
 
-__device__ __forceinline__ void load_body(const DevModel& M, int b, bool body_lane, BodyConst& c) {
+__device__ __forceinline__ void load_body(const DevModel& M, const DevInst* I, int b, bool body_lane, BodyConst& c) {
   const int bb = body_lane ? b : 0;
   const int j = bb - M.fb;
   const bool joint = body_lane && j >= 0;
@@ -133,11 +186,21 @@ __device__ __forceinline__ void load_body(const DevModel& M, int b, bool body_la
   c.kd = joint ? M.kd[j] : 0.f;
   c.taumax = joint ? M.taumax[j] : 0.f;
   c.arm = joint ? M.arm[j] : 0.f;
+  c.q0 = (joint && I && I->cost_kind == 1) ? I->q0[j] : 0.f;
   c.parent = M.parent[bb];
   c.depth = body_lane ? M.depth[bb] : -1;
   c.n_child = body_lane ? M.n_child[bb] : 0;
   c.c_begin = M.c_begin[bb];
   c.c_count = body_lane ? M.c_count[bb] : 0;
+  c.child_lo = c.child_hi = 0u;
+  for (int k = 0; k < c.n_child; ++k) {
+    const uint32_t ch = (uint32_t)M.child[bb][k] & 0xffu;
+    if (k < 4) c.child_lo |= ch << (8 * k);
+    else c.child_hi |= ch << (8 * (k - 4));
+  }
+}
+__device__ __forceinline__ int child_of(const BodyConst& c, int k) {
+  return (int)(((k < 4 ? c.child_lo : c.child_hi) >> (8 * (k & 3))) & 0xffu);
 }
 
 // motion vector m given about point O, re-expressed about O + e: (w, v + w x e)
@@ -301,6 +364,52 @@ __device__ __forceinline__ void bias_force(const float* IA, const float* v, floa
 struct ContactLaw {
   float k, d, mu, eps;
 };
+
+// Model and instance scalars every step reads, loaded into registers once per
+// work item (read through the model pointer inside the step loop, the compiler
+// would reload them after every LDS store).
+struct StepConst {
+  int fb, max_depth, ee_body, cost_kind, K, nu, F, nsub;
+  float g, dt, delta, inv_delta;
+  ContactLaw law;
+  float ee_pos[3];
+  float w_h, w_or, w_q, w_cv, w_cf, w_eff, w_ee, w_tau, z_des;
+};
+__device__ __forceinline__ StepConst load_step_const(const DevModel& M, const DevInst* I, float dt_override) {
+  StepConst c;
+  c.fb = M.fb; c.max_depth = M.max_depth; c.ee_body = M.ee_body; c.nsub = M.nsub;
+  c.g = M.g;
+  c.law = ContactLaw{M.k, M.d, M.mu, M.eps};
+  c.ee_pos[0] = M.ee_pos[0]; c.ee_pos[1] = M.ee_pos[1]; c.ee_pos[2] = M.ee_pos[2];
+  if (I) {
+    c.cost_kind = I->cost_kind; c.K = I->K; c.nu = I->nu; c.F = I->H * M.nsub;
+    c.dt = I->dt / (float)M.nsub;
+    c.delta = I->delta; c.inv_delta = 1.f / I->delta;
+    c.w_h = I->w_h; c.w_or = I->w_or; c.w_q = I->w_q; c.w_cv = I->w_cv; c.w_cf = I->w_cf; c.w_eff = I->w_eff;
+    c.w_ee = I->w_ee; c.w_tau = I->w_tau; c.z_des = I->z_des;
+  } else {
+    c.cost_kind = -1; c.K = 2; c.nu = M.nu; c.F = 1;
+    c.dt = dt_override;
+    c.delta = 1.f; c.inv_delta = 1.f;
+    c.w_h = c.w_or = c.w_q = c.w_cv = c.w_cf = c.w_eff = c.w_ee = c.w_tau = c.z_des = 0.f;
+  }
+  return c;
+}
+
+// Stage the model table (base inertia, contact rows with the instance's nominal
+// normal forces) into LDS with all 64 lanes of the wavefront.
+__device__ __forceinline__ void stage_model_table(const DevModel& M, const DevInst* I, float* tab, int lane) {
+  if (lane < 21) tab[lane] = M.base_I[lane];
+  const float* cs = &M.ctab[0][0];
+  for (int i = lane; i < M.nc * kCt; i += 64) tab[kTabContacts + i] = cs[i];
+  wave_sync();
+  if (I && I->cost_kind == 1)
+    for (int ci = lane; ci < M.nc; ci += 64) {
+      float* ct = tab + kTabContacts + ci * kCt;
+      ct[3] = I->f0z[__float_as_int(ct[4])];
+    }
+  wave_sync();
+}
 __device__ __forceinline__ float contact_point(const float* r, const float* R, const float* p, const float* v,
                                                const float* beta, const float* Rb, const float* pb, const float* agl,
                                                float dt, const ContactLaw& law, float* IA, float* pA, float* vw,
@@ -384,10 +493,10 @@ __device__ __forceinline__ float contact_point(const float* r, const float* R, c
 }
 
 // running-cost terms of one contact point (Sec. IV-A)
-__device__ __forceinline__ void contact_cost(const DevInst* I, float fn, const float* vw, const float* fw, float f0z,
+__device__ __forceinline__ void contact_cost(const StepConst& sc, float fn, const float* vw, const float* fw, float f0z,
                                              float& lane_cost) {
-  if (fn > 0.f) lane_cost += I->w_cv * (fabsf(vw[0]) + fabsf(vw[1]) + fabsf(vw[2]));
-  lane_cost += I->w_cf * (fabsf(fw[0]) + fabsf(fw[1]) + fabsf(fw[2] - f0z));
+  if (fn > 0.f) lane_cost += sc.w_cv * (fabsf(vw[0]) + fabsf(vw[1]) + fabsf(vw[2]));
+  lane_cost += sc.w_cf * (fabsf(fw[0]) + fabsf(fw[1]) + fabsf(fw[2] - f0z));
 }
 
 // end-effector height error: world z of the point ee_pos on a body (R, p) minus z_des
@@ -404,29 +513,29 @@ __device__ __forceinline__ float ee_height_error(const float* R, const float* p,
 // per step in straight-line code: inside a loop the compiler may hoist it and
 // drop the relaxed-precision tag of the division inside atan2f, which would
 // change its last bit.
-__device__ __forceinline__ float base_cost_term(const DevInst* I, const float* bq) {
+__device__ __forceinline__ float base_cost_term(const StepConst& sc, const float* bq) {
   const float* qt = bq + 3;
   const float vn = sqrtf(qt[1] * qt[1] + qt[2] * qt[2] + qt[3] * qt[3]);
   const float phi = 2.f * atan2f(vn, fabsf(qt[0]));
-  return I->w_h * fabsf(bq[2] - I->z_des) + I->w_or * phi * phi;
+  return sc.w_h * fabsf(bq[2] - sc.z_des) + sc.w_or * phi * phi;
 }
 
 // running-cost terms of a body other than its contacts (Sec. IV-A; effort and
 // end-effector terms of the planar-chain task); base_term from base_cost_term
-__device__ __forceinline__ void body_cost(const DevInst* I, const DevModel& M, int b, bool is_base, bool is_joint,
-                                          float base_term, float q, float q0, float tau, const float* R, const float* p,
+__device__ __forceinline__ void body_cost(const StepConst& sc, int b, bool is_base, bool is_joint, float base_term,
+                                          float q, float q0, float tau, const float* R, const float* p,
                                           const float* Rb, const float* pb, float& lane_cost) {
-  if (I->cost_kind == 1) {
+  if (sc.cost_kind == 1) {
     if (is_base) lane_cost += base_term;
     if (is_joint) {
       const float eq = q - q0;
-      lane_cost += I->w_q * eq * eq + I->w_eff * tau * tau;
+      lane_cost += sc.w_q * eq * eq + sc.w_eff * tau * tau;
     }
   } else {
-    if (is_joint) lane_cost += I->w_tau * tau * tau;
-    if (b == M.ee_body) {
-      const float dz = ee_height_error(R, p, M.ee_pos, Rb, pb, I->z_des);
-      lane_cost += I->w_ee * dz * dz;
+    if (is_joint) lane_cost += sc.w_tau * tau * tau;
+    if (b == sc.ee_body) {
+      const float dz = ee_height_error(R, p, sc.ee_pos, Rb, pb, sc.z_des);
+      lane_cost += sc.w_ee * dz * dz;
     }
   }
 }
@@ -525,20 +634,19 @@ __device__ __forceinline__ float forward_joint(const float* al, const float* e, 
 // of the terminal cost (end-effector task) at the current state.
 // ---------------------------------------------------------------------------
 template <int G>
-__device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevInst* I, float* __restrict__ gs,
+__device__ void physics_step(const StepConst& sc, const BodyConst& bc, const float* tab, float* __restrict__ gs,
                              int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
   float* slots = gs;
   float* base = gs + G * kSlot;
-  const int fb = M.fb;
+  const int fb = sc.fb;
   const bool is_base = body_lane && fb && b == 0;
   const bool is_joint = body_lane && !is_base;
-  const int j = b - fb;
 
   float tau = 0.f, gain = 0.f;
   if (is_joint) pd_law(bc.kp, bc.kd, bc.taumax, io.dt, io.q, io.v, io.qref, io.vref, tau, gain);
   io.tau = tau;
   float base_term = 0.f;
-  if (want_cost && is_base && I->cost_kind == 1) base_term = base_cost_term(I, io.bq);
+  if (want_cost && is_base && sc.cost_kind == 1) base_term = base_cost_term(sc, io.bq);
 
   // ---- frame B: world pose of the base; body 0 slot = identity frame with the base twist
   if (is_base) {
@@ -547,12 +655,9 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
 #pragma unroll
     for (int k = 0; k < 9; ++k) base[k] = R[k];
     base[9] = io.bq[0]; base[10] = io.bq[1]; base[11] = io.bq[2];
-    float* s = slots;  // body 0
-#pragma unroll
-    for (int k = 0; k < 9; ++k) s[k] = (k % 4 == 0) ? 1.f : 0.f;
-    s[9] = s[10] = s[11] = 0.f;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) { s[12 + k] = io.bv[k]; s[18 + k] = 0.f; }
+    const float I3[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+    const float z6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    put_frame(slots, I3, z6, io.bv, z6);  // body 0
   }
   if (!fb && body_lane && b == 0) {
 #pragma unroll
@@ -574,18 +679,12 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
   }
   float cq = 0.f, sq = 0.f;
   if (is_joint) sincosf(io.q, &sq, &cq);
-  for (int d = 1; d <= M.max_depth; ++d) {
+  for (int d = 1; d <= sc.max_depth; ++d) {
     if (is_joint && depth == d) {
       const int lam = bc.parent;
       float Rl[9], pl[3], vl[6], bl[6];
       if (lam >= 0) {
-        const float* s = slots + lam * kSlot;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Rl[k] = s[k];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pl[k] = s[9 + k];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) { vl[k] = s[12 + k]; bl[k] = s[18 + k]; }
+        get_frame(slots + lam * kSlot, Rl, pl, vl, bl);
       } else {
 #pragma unroll
         for (int k = 0; k < 9; ++k) Rl[k] = (k % 4 == 0) ? 1.f : 0.f;
@@ -595,13 +694,7 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
         for (int k = 0; k < 6; ++k) { vl[k] = 0.f; bl[k] = 0.f; }
       }
       fk_joint(Rl, pl, vl, bl, bc.P, bc.p_tree, bc.axis_p, cq, sq, io.v, R, p, e, ax, v, c, beta);
-      float* s = slots + b * kSlot;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) s[k] = R[k];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s[9 + k] = p[k];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) { s[12 + k] = v[k]; s[18 + k] = beta[k]; }
+      put_frame(slots + b * kSlot, R, p, v, beta);
     }
     wave_sync();
   }
@@ -615,38 +708,37 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
   for (int k = 0; k < 9; ++k) Rb[k] = base[k];
   pb[0] = base[9]; pb[1] = base[10]; pb[2] = base[11];
   if (terminal) {
-    if (body_lane && I->cost_kind == 0 && b == M.ee_body) {
-      const float dz = ee_height_error(R, p, M.ee_pos, Rb, pb, I->z_des);
-      lane_cost = I->w_ee * dz * dz;
+    if (body_lane && sc.cost_kind == 0 && b == sc.ee_body) {
+      const float dz = ee_height_error(R, p, sc.ee_pos, Rb, pb, sc.z_des);
+      lane_cost = sc.w_ee * dz * dz;
     }
     io.cost = lane_cost;
     io.mask = 0u;
     wave_sync();
     return;
   }
-  const float g = M.g;
+  const float g = sc.g;
   // gravity as a spatial acceleration in B axes: (0, Rb^T (0, 0, -g)), the same about any origin
   const float agl[3] = {-g * Rb[6], -g * Rb[7], -g * Rb[8]};
   if (body_lane) {
     if (is_base) {
 #pragma unroll
-      for (int k = 0; k < 21; ++k) IA[k] = M.base_I[k];
+      for (int k = 0; k < 21; ++k) IA[k] = tab[k];
     } else {
       body_inertia(R, bc.com, bc.Ic, bc.mass, IA);
     }
     bias_force(IA, v, pA);
 
     // contacts carried by this body (point x relative to the body origin)
-    const ContactLaw law{M.k, M.d, M.mu, M.eps};
     const int c0 = bc.c_begin, cn = bc.c_count;
     for (int ci = c0; ci < c0 + cn; ++ci) {
+      const float* ct = tab + kTabContacts + ci * kCt;
       float vw[3], fw[3];
-      const float fn = contact_point(M.cpos[ci], R, p, v, beta, Rb, pb, agl, io.dt, law, IA, pA, vw, fw);
-      if (fn > 0.f) mask |= 1u << M.corig[ci];
-      if (want_cost && I->cost_kind == 1) contact_cost(I, fn, vw, fw, I->f0z[M.corig[ci]], lane_cost);
+      const float fn = contact_point(ct, R, p, v, beta, Rb, pb, agl, io.dt, sc.law, IA, pA, vw, fw);
+      if (fn > 0.f) mask |= 1u << __float_as_int(ct[4]);
+      if (want_cost && sc.cost_kind == 1) contact_cost(sc, fn, vw, fw, ct[3], lane_cost);
     }
-    if (want_cost) body_cost(I, M, b, is_base, is_joint, base_term, io.q, is_joint ? I->q0[j] : 0.f, tau, R, p, Rb,
-                             pb, lane_cost);
+    if (want_cost) body_cost(sc, b, is_base, is_joint, base_term, io.q, bc.q0, tau, R, p, Rb, pb, lane_cost);
   }
   io.cost = lane_cost;
   io.mask = mask;
@@ -655,24 +747,14 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
   // ---- backward sweep, leaves to root: each joint lane publishes its
   //      articulated inertia and bias already carried to its parent's origin
   float U[6], invD = 0.f, u = 0.f;
-  for (int d = M.max_depth; d >= 0; --d) {
+  for (int d = sc.max_depth; d >= 0; --d) {
     if (body_lane && depth == d) {
       const int nch = bc.n_child;
-      for (int k = 0; k < nch; ++k) {
-        const float* s = slots + M.child[b][k] * kSlot;
-#pragma unroll
-        for (int q = 0; q < 21; ++q) IA[q] += s[q];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) pA[q] += s[21 + q];
-      }
+      for (int k = 0; k < nch; ++k) add_art(slots + child_of(bc, k) * kSlot, IA, pA);
       if (is_joint) {
         float Ip[21], pp[6];
         backward_joint(IA, pA, ax, c, e, tau, bc.arm, gain, U, invD, u, Ip, pp);
-        float* s = slots + b * kSlot;
-#pragma unroll
-        for (int q = 0; q < 21; ++q) s[q] = Ip[q];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) s[21 + q] = pp[q];
+        put_art(slots + b * kSlot, Ip, pp);
       }
     }
     wave_sync();
@@ -682,9 +764,7 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
   if (is_base) {
     float a0[6];
     base_solve(IA, pA, a0);
-    float* s0 = slots;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) s0[q] = a0[q];
+    put_acc(slots, a0);
     io.ba[0] = a0[0]; io.ba[1] = a0[1]; io.ba[2] = a0[2];
     io.ba[3] = a0[3] + agl[0]; io.ba[4] = a0[4] + agl[1]; io.ba[5] = a0[5] + agl[2];
   }
@@ -692,23 +772,19 @@ __device__ void physics_step(const DevModel& M, const BodyConst& bc, const DevIn
 
   // ---- forward sweep: accelerations, root to leaves
   float qdd = 0.f;
-  for (int d = 1; d <= M.max_depth; ++d) {
+  for (int d = 1; d <= sc.max_depth; ++d) {
     if (is_joint && depth == d) {
       const int lam = bc.parent;
       float al[6];
       if (lam >= 0) {
-        const float* s = slots + lam * kSlot;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) al[q] = s[q];
+        get_acc(slots + lam * kSlot, al);
       } else {
         // fixed world: a' = -a_g = (0, 0, 0, 0, 0, g); its angular part is zero, so no shift term
         al[0] = al[1] = al[2] = 0.f; al[3] = 0.f; al[4] = 0.f; al[5] = g;
       }
       float a[6];
       qdd = forward_joint(al, e, c, U, u, invD, ax, a);
-      float* s = slots + b * kSlot;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) s[q] = a[q];
+      put_acc(slots + b * kSlot, a);
     }
     wave_sync();
   }
@@ -760,14 +836,13 @@ __device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, 
   }
 }
 
-// Hermite reference of joint jj at fine step f of F (eq. hermite_segment and
-// its time derivative); segment and local time from integer arithmetic.
+// Hermite reference of joint jj (eq. hermite_segment and its time
+// derivative) at fine step f of F: the segment seg = floor(f (K-1) / F) and the
+// remainder rem = f (K-1) - seg F are exact integers kept by the caller
+// (StepClock), the local time is s = rem / F.
 __device__ __forceinline__ void hermite(const float* knots, int K, int nu, int F, float delta, float inv_delta,
-                                        int f, int jj, float* qr, float* vr) {
-  const int m = f * (K - 1);
-  int seg = m / F;
-  seg = seg < K - 2 ? seg : K - 2;
-  const float s = (float)(m - seg * F) / (float)F;
+                                        int seg, int rem, int jj, float* qr, float* vr) {
+  const float s = (float)rem / (float)F;
   const float s2 = s * s, s3 = s2 * s;
   const float h00 = 2.f * s3 - 3.f * s2 + 1.f, h10 = s3 - 2.f * s2 + s, h01 = -2.f * s3 + 3.f * s2, h11 = s3 - s2;
   const float d00 = 6.f * s2 - 6.f * s, d10 = 3.f * s2 - 4.f * s + 1.f, d01 = -6.f * s2 + 6.f * s, d11 = 3.f * s2 - 2.f * s;
@@ -777,6 +852,25 @@ __device__ __forceinline__ void hermite(const float* knots, int K, int nu, int F
   *qr = h00 * q0 + h10 * delta * v0 + h01 * q1 + h11 * delta * v1;
   *vr = (d00 * q0 + d10 * delta * v0 + d01 * q1 + d11 * delta * v1) * inv_delta;
 }
+
+// Fine-step bookkeeping without integer division: the Hermite segment and
+// remainder of step f (f (K-1) = seg F + rem, 0 <= rem < F; for f < F the
+// segment never exceeds K-2), the substep within a control step and the
+// control-step index.
+struct StepClock {
+  int seg = 0, rem = 0, sub = 0, h = 0;
+  __device__ __forceinline__ void advance(int K, int F, int nsub) {
+    rem += K - 1;
+    while (rem >= F) {
+      rem -= F;
+      ++seg;
+    }
+    if (++sub == nsub) {
+      sub = 0;
+      ++h;
+    }
+  }
+};
 
 template <int G>
 __device__ __forceinline__ float group_sum(float x, float* red, int l) {
@@ -832,13 +926,16 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
 // w.y .. w.y + 64/G - 1 (those >= N are computed but not stored).
 // ---------------------------------------------------------------------------
 template <int G>
-__device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride, float* smem) {
+__device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride,
+                                                            int table_floats, float* smem) {
   const int lane = threadIdx.x;
   const int grp = lane / G, l = lane % G;
   const DevModel& M = *I.model;
+  float* tab = smem;
+  stage_model_table(M, &I, tab, lane);
   const int n = first + grp;
   const bool valid = n < I.N;
-  float* gs = smem + grp * group_stride;
+  float* gs = smem + table_floats + grp * group_stride;
   float* knots = gs + G * kSlot + 16;
   float* red = knots + ((I.E + 3) & ~3);
 
@@ -851,7 +948,8 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   }
   wave_sync();
 
-  const int fb = M.fb, nb = M.nb, nq = fb ? 7 + M.nu : M.nu;
+  const StepConst sc = load_step_const(M, &I, 0.f);
+  const int fb = sc.fb, nb = M.nb, nq = fb ? 7 + M.nu : M.nu;
   const bool body_lane = l < nb;
   const int b = l;
   const bool is_joint = body_lane && !(fb && b == 0);
@@ -869,22 +967,23 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 #pragma unroll
   for (int k = 0; k < 6; ++k) io.ba[k] = 0.f;
   io.qref = io.vref = 0.f;
+  io.dt = sc.dt;
 
-  const int nsub = M.nsub, H = I.H, F = H * nsub;
-  io.dt = I.dt / (float)nsub;
-  const float inv_delta = 1.f / I.delta;
   BodyConst bc;
-  load_body(M, b, body_lane, bc);
+  load_body(M, &I, b, body_lane, bc);
+  uint32_t* const masks = I.masks;
+  const int H = I.H, F = sc.F;
   float acc = 0.f;
+  StepClock clk;
   for (int f = 0; f < F; ++f) {
-    const bool control = (f % nsub) == 0;
-    if (is_joint) hermite(knots, I.K, I.nu, F, I.delta, inv_delta, f, j, &io.qref, &io.vref);
-    physics_step<G>(M, bc, &I, gs, b, body_lane, io, control);
+    const bool control = clk.sub == 0;
+    if (is_joint) hermite(knots, sc.K, sc.nu, F, sc.delta, sc.inv_delta, clk.seg, clk.rem, j, &io.qref, &io.vref);
+    physics_step<G>(sc, bc, tab, gs, b, body_lane, io, control);
     if (control) {
       acc += io.cost;
-      if (I.masks) {
+      if (masks) {
         const uint32_t mk = group_or<G>(io.mask, red, l);
-        if (l == 0 && valid) I.masks[(size_t)n * H + f / nsub] = mk;
+        if (l == 0 && valid) masks[(size_t)n * H + clk.h] = mk;
       }
     }
     if (is_joint) {
@@ -892,10 +991,11 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
       io.q = fmaf(io.dt, io.v, io.q);
     }
     if (fb && b == 0) integrate_base(io.bq, io.bv, io.ba, io.dt);
+    clk.advance(sc.K, F, sc.nsub);
   }
 
   // terminal cost
-  if (I.cost_kind == 1) {
+  if (sc.cost_kind == 1) {
     if (fb && b == 0) {
       const float T = (float)H * I.dt;
       float e = 0.f;
@@ -905,7 +1005,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     }
   } else {
     // end-effector height at x_H
-    physics_step<G>(M, bc, &I, gs, b, body_lane, io, false, true);
+    physics_step<G>(sc, bc, tab, gs, b, body_lane, io, false, true);
     acc += io.cost;
   }
   float S = group_sum<G>(acc, red, l);
@@ -920,11 +1020,11 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 // is null, instance 0 and sample blockIdx * 64/G.
 template <int G>
 __global__ __launch_bounds__(64) void rollout_kernel(const DevInst* __restrict__ insts, const int2* __restrict__ work,
-                                                     int group_stride) {
+                                                     int group_stride, int table_floats) {
   extern __shared__ float smem[];
   constexpr int R = 64 / G;
   const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
-  rollout_item<G>(insts[w.x], w.y, group_stride, smem);
+  rollout_item<G>(insts[w.x], w.y, group_stride, table_floats, smem);
 }
 
 // Persistent form: a grid sized to the resident wavefronts; each wavefront takes
@@ -933,7 +1033,8 @@ __global__ __launch_bounds__(64) void rollout_kernel(const DevInst* __restrict__
 template <int G>
 __global__ __launch_bounds__(64) void rollout_persistent_kernel(const DevInst* __restrict__ insts,
                                                                 const int2* __restrict__ work, int n_items,
-                                                                unsigned int* __restrict__ counter, int group_stride) {
+                                                                unsigned int* __restrict__ counter, int group_stride,
+                                                                int table_floats) {
   extern __shared__ float smem[];
   for (;;) {
     int item = 0;
@@ -941,7 +1042,7 @@ __global__ __launch_bounds__(64) void rollout_persistent_kernel(const DevInst* _
     item = __builtin_amdgcn_readfirstlane(item);
     if (item >= n_items) break;
     const int2 w = work[item];
-    rollout_item<G>(insts[w.x], w.y, group_stride, smem);
+    rollout_item<G>(insts[w.x], w.y, group_stride, table_floats, smem);
   }
 }
 
@@ -974,11 +1075,12 @@ __device__ __forceinline__ int ibits(float x) { return __float_as_int(x); }
 
 // Root-to-leaf pass: PD law (unless terminal) and kinematics of every body of
 // this lane's chain; publishes frames other chains hang off.
-__device__ __forceinline__ void chain_fk(const DevModel& M, const DevInst& I, const float* rows, const int* cbody,
-                                         float* rec, float* bas, const float* knots, float* att, bool act, int c,
-                                         int cfirst, int catt, int nlev, int f, int F, float dt, float inv_delta,
-                                         bool terminal, const float* bq, const float* bv) {
-  const int fb = M.fb;
+__device__ __forceinline__ void chain_fk(const StepConst& sc, const float* rows, const int* cbody, float* rec,
+                                         float* bas, const float* knots, float* att, bool act, int c, int cfirst,
+                                         int catt, int nlev, int seg, int rem, bool terminal, const float* bq,
+                                         const float* bv) {
+  const int fb = sc.fb;
+  const float dt = sc.dt;
   float fR[9], fp[3], fv[6], fbt[6];  // frame of this chain's previous body
   for (int d = 0; d < nlev; ++d) {
     const int b = act ? cbody[c * kMaxLevels + d] : -1;
@@ -1011,7 +1113,7 @@ __device__ __forceinline__ void chain_fk(const DevModel& M, const DevInst& I, co
         float tau = 0.f, gain = 0.f;
         if (!terminal) {
           float qref, vref;
-          hermite(knots, I.K, I.nu, F, I.delta, inv_delta, f, j, &qref, &vref);
+          hermite(knots, sc.K, sc.nu, sc.F, sc.delta, sc.inv_delta, seg, rem, j, &qref, &vref);
           pd_law(rw[row::kp], rw[row::kd], rw[row::taumax], dt, q, qd, qref, vref, tau, gain);
         }
         float Rl[9], pl[3], vl[6], bl[6];
@@ -1072,14 +1174,13 @@ __device__ __forceinline__ void chain_fk(const DevModel& M, const DevInst& I, co
 // Leaf-to-root pass: inertia, bias, contacts and running cost of each body,
 // then the articulated-body step; the floating base solves for its
 // acceleration.  Returns this lane's contact activity bits.
-__device__ __forceinline__ uint32_t chain_backward(const DevModel& M, const DevInst& I, const float* rows,
-                                                   const int* cbody, const float* ctab, float* rec, const float* bas,
-                                                   float* pub, float* att, bool act, int c, int cfirst, int catt,
-                                                   int nlev, float dt, bool want_cost, float base_term,
-                                                   float* ba, float* ca) {
-  const int fb = M.fb;
-  const ContactLaw law{M.k, M.d, M.mu, M.eps};
-  const float g = M.g;
+__device__ __forceinline__ uint32_t chain_backward(const StepConst& sc, const float* tab, const float* rows,
+                                                   const int* cbody, float* rec, const float* bas, float* pub,
+                                                   float* att, bool act, int c, int cfirst, int catt, int nlev,
+                                                   bool want_cost, float base_term, float* ba, float* ca) {
+  const int fb = sc.fb;
+  const float dt = sc.dt;
+  const float g = sc.g;
   uint32_t mask = 0u;
   float cI[21], cp[6];  // articulated inertia and bias of this chain's deeper body, at this body's origin
   float Rb[9], pb[3];
@@ -1104,7 +1205,7 @@ __device__ __forceinline__ uint32_t chain_backward(const DevModel& M, const DevI
       float IA[21], pA[6];
       if (is_base) {
 #pragma unroll
-        for (int k = 0; k < 21; ++k) IA[k] = M.base_I[k];
+        for (int k = 0; k < 21; ++k) IA[k] = tab[k];
       } else {
         body_inertia(R, rw + row::com, rw + row::Ic, rw[row::mass], IA);
       }
@@ -1112,14 +1213,14 @@ __device__ __forceinline__ uint32_t chain_backward(const DevModel& M, const DevI
       float lane_cost = 0.f;
       const int c0 = ibits(rw[row::c_begin]), cn = ibits(rw[row::c_count]);
       for (int ci = c0; ci < c0 + cn; ++ci) {
-        const float* ct = ctab + ci * kCt;
+        const float* ct = tab + kTabContacts + ci * kCt;
         float vw[3], fw[3];
-        const float fn = contact_point(ct, R, p, v, beta, Rb, pb, agl, dt, law, IA, pA, vw, fw);
+        const float fn = contact_point(ct, R, p, v, beta, Rb, pb, agl, dt, sc.law, IA, pA, vw, fw);
         if (fn > 0.f) mask |= 1u << ibits(ct[4]);
-        if (want_cost && I.cost_kind == 1) contact_cost(&I, fn, vw, fw, ct[3], lane_cost);
+        if (want_cost && sc.cost_kind == 1) contact_cost(sc, fn, vw, fw, ct[3], lane_cost);
       }
       if (want_cost) {
-        body_cost(&I, M, b, is_base, !is_base, base_term, is_base ? 0.f : r[32], rw[row::q0], tau, R, p, Rb, pb,
+        body_cost(sc, b, is_base, !is_base, base_term, is_base ? 0.f : r[32], rw[row::q0], tau, R, p, Rb, pb,
                   lane_cost);
         r[34] += lane_cost;
       }
@@ -1184,10 +1285,10 @@ __device__ __forceinline__ uint32_t chain_backward(const DevModel& M, const DevI
 
 // Root-to-leaf pass: joint accelerations and the semi-implicit Euler update of
 // the joints (v += dt qdd, q += dt v).
-__device__ __forceinline__ void chain_forward(const DevModel& M, const float* rows, const int* cbody, float* rec,
-                                              float* att, bool act, int c, int cfirst, int catt, int nlev, float dt,
-                                              float* ca) {
-  const int fb = M.fb;
+__device__ __forceinline__ void chain_forward(const StepConst& sc, const float* rows, const int* cbody, float* rec,
+                                              float* att, bool act, int c, int cfirst, int catt, int nlev, float* ca) {
+  const int fb = sc.fb;
+  const float dt = sc.dt;
   for (int d = 0; d < nlev; ++d) {
     const int b = act ? cbody[c * kMaxLevels + d] : -1;
     if (b >= 0 && !(fb && b == 0)) {
@@ -1200,7 +1301,7 @@ __device__ __forceinline__ void chain_forward(const DevModel& M, const float* ro
           for (int q = 0; q < 6; ++q) al[q] = att[catt * kAtt + 24 + q];
         } else {
           // fixed world: a' = -a_g = (0, 0, 0, 0, 0, g)
-          al[0] = al[1] = al[2] = 0.f; al[3] = 0.f; al[4] = 0.f; al[5] = M.g;
+          al[0] = al[1] = al[2] = 0.f; al[3] = 0.f; al[4] = 0.f; al[5] = sc.g;
         }
       } else {
 #pragma unroll
@@ -1234,23 +1335,20 @@ __device__ __attribute__((always_inline)) void chain_item(const DevInst& I, int 
   const int nb = M.nb, nc = M.nc, fb = M.fb, nch = M.n_chains;
 
   // model table of this instance (posture and nominal contact forces patched in)
-  float* rows = smem;
-  int* cbody = reinterpret_cast<int*>(smem + nb * kRow);
-  float* ctab = smem + nb * kRow + kMaxChains * kMaxLevels;
+  float* tab = smem;
+  stage_model_table(M, &I, tab, lane);
+  float* rows = smem + body_table_floats(nc);
+  int* cbody = reinterpret_cast<int*>(rows + nb * kRow);
   {
     const float4* src = reinterpret_cast<const float4*>(&M.rows[0][0]);
     float4* dst = reinterpret_cast<float4*>(rows);
     for (int i = lane; i < nb * kRow / 4; i += 64) dst[i] = src[i];
     const int* cb = &M.chain_body[0][0];
     for (int i = lane; i < kMaxChains * kMaxLevels; i += 64) cbody[i] = cb[i];
-    const float* cs = &M.ctab[0][0];
-    for (int i = lane; i < nc * kCt; i += 64) ctab[i] = cs[i];
   }
   wave_sync();
-  if (I.cost_kind == 1) {
+  if (I.cost_kind == 1)
     for (int b = fb + lane; b < nb; b += 64) rows[b * kRow + row::q0] = I.q0[b - fb];
-    for (int ci = lane; ci < nc; ci += 64) ctab[ci * kCt + 3] = I.f0z[ibits(ctab[ci * kCt + 4])];
-  }
   wave_sync();
   if (grp >= groups) return;  // the LDS budget holds fewer rollout groups than the wavefront has
 
@@ -1300,26 +1398,28 @@ __device__ __attribute__((always_inline)) void chain_item(const DevInst& I, int 
   for (int k = 0; k < 6; ++k) { bv[k] = fb ? I.x0[nq + k] : 0.f; ba[k] = 0.f; ca[k] = 0.f; }
   wave_sync();
 
-  const int nsub = M.nsub, H = I.H, F = H * nsub;
-  const float dt = I.dt / (float)nsub;
-  const float inv_delta = 1.f / I.delta;
+  const StepConst sc = load_step_const(M, &I, 0.f);
+  uint32_t* const masks = I.masks;
+  const int H = I.H, F = sc.F;
+  StepClock clk;
   for (int f = 0; f < F; ++f) {
-    const bool control = (f % nsub) == 0;
+    const bool control = clk.sub == 0;
     float base_term = 0.f;
-    if (control && base_lane && I.cost_kind == 1) base_term = base_cost_term(&I, bq);
-    chain_fk(M, I, rows, cbody, rec, bas, knots, att, act, c, cfirst, catt, nlev, f, F, dt, inv_delta, false, bq, bv);
-    const uint32_t mask = chain_backward(M, I, rows, cbody, ctab, rec, bas, pub, att, act, c, cfirst, catt, nlev, dt,
-                                         control, base_term, ba, ca);
-    chain_forward(M, rows, cbody, rec, att, act, c, cfirst, catt, nlev, dt, ca);
-    if (control && I.masks) {
+    if (control && base_lane && sc.cost_kind == 1) base_term = base_cost_term(sc, bq);
+    chain_fk(sc, rows, cbody, rec, bas, knots, att, act, c, cfirst, catt, nlev, clk.seg, clk.rem, false, bq, bv);
+    const uint32_t mask = chain_backward(sc, tab, rows, cbody, rec, bas, pub, att, act, c, cfirst, catt, nlev, control,
+                                         base_term, ba, ca);
+    chain_forward(sc, rows, cbody, rec, att, act, c, cfirst, catt, nlev, ca);
+    if (control && masks) {
       const uint32_t mk = group_or<GC>(mask, red, l);
-      if (l == 0 && valid) I.masks[(size_t)n * H + f / nsub] = mk;
+      if (l == 0 && valid) masks[(size_t)n * H + clk.h] = mk;
     }
-    if (base_lane) integrate_base(bq, bv, ba, dt);
+    if (base_lane) integrate_base(bq, bv, ba, sc.dt);
+    clk.advance(sc.K, F, sc.nsub);
   }
 
   // terminal cost
-  if (I.cost_kind == 1) {
+  if (sc.cost_kind == 1) {
     if (base_lane) {
       const float T = (float)H * I.dt;
       float e = 0.f;
@@ -1329,12 +1429,12 @@ __device__ __attribute__((always_inline)) void chain_item(const DevInst& I, int 
     }
   } else {
     // end-effector height at x_H
-    chain_fk(M, I, rows, cbody, rec, bas, knots, att, act, c, cfirst, catt, nlev, F, F, dt, inv_delta, true, bq, bv);
-    const int ee = M.ee_body;
+    chain_fk(sc, rows, cbody, rec, bas, knots, att, act, c, cfirst, catt, nlev, 0, 0, true, bq, bv);
+    const int ee = sc.ee_body;
     if (act && ee >= 0 && ibits(rows[ee * kRow + row::chain]) == c) {
       float* r = rec + ee * kRec;
-      const float dz = ee_height_error(r, r + 9, M.ee_pos, bas, bas + 9, I.z_des);
-      const float tc = I.w_ee * dz * dz;
+      const float dz = ee_height_error(r, r + 9, sc.ee_pos, bas, bas + 9, sc.z_des);
+      const float tc = sc.w_ee * dz * dz;
       r[34] += tc;
     }
   }
@@ -1583,16 +1683,20 @@ template <int G>
 __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict__ model, int n_states,
                                                       const float* __restrict__ q, const float* __restrict__ v,
                                                       const float* __restrict__ qref, const float* __restrict__ vref,
-                                                      float dt, float* __restrict__ qdd, int group_stride) {
+                                                      float dt, float* __restrict__ qdd, int group_stride,
+                                                      int table_floats) {
   extern __shared__ float smem[];
   constexpr int R = 64 / G;
   const int lane = threadIdx.x, grp = lane / G, l = lane % G;
   const DevModel& M = *model;
+  float* tab = smem;
+  stage_model_table(M, nullptr, tab, lane);
   const int s_raw = blockIdx.x * R + grp;
   const bool valid = s_raw < n_states;
   const int s = valid ? s_raw : 0;
-  const int fb = M.fb, nu = M.nu, nq = fb ? 7 + nu : nu, nv = fb ? 6 + nu : nu;
-  float* gs = smem + grp * group_stride;
+  const StepConst sc = load_step_const(M, nullptr, dt);
+  const int fb = sc.fb, nu = M.nu, nq = fb ? 7 + nu : nu, nv = fb ? 6 + nu : nu;
+  float* gs = smem + table_floats + grp * group_stride;
   const bool body_lane = l < M.nb;
   const bool is_joint = body_lane && !(fb && l == 0);
   const int j = l - fb;
@@ -1607,8 +1711,8 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   for (int k = 0; k < 6; ++k) { io.bv[k] = fb ? v[(size_t)s * nv + k] : 0.f; io.ba[k] = 0.f; }
   io.dt = dt;
   BodyConst bc;
-  load_body(M, l, body_lane, bc);
-  physics_step<G>(M, bc, nullptr, gs, l, body_lane, io, false);
+  load_body(M, nullptr, l, body_lane, bc);
+  physics_step<G>(sc, bc, tab, gs, l, body_lane, io, false);
   if (!valid) return;
   if (is_joint) qdd[(size_t)s * nv + (fb ? 6 : 0) + j] = io.qdd;
   if (fb && l == 0)
@@ -1617,11 +1721,11 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
 
 // explicit instantiations
 #define MPPI_INST(G)                                                                                   \
-  template __global__ void rollout_kernel<G>(const DevInst*, const int2*, int);                        \
-  template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int); \
+  template __global__ void rollout_kernel<G>(const DevInst*, const int2*, int, int);                   \
+  template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int); \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void dynamics_kernel<G>(const DevModel*, int, const float*, const float*,        \
-                                              const float*, const float*, float, float*, int);
+                                              const float*, const float*, float, float*, int, int);
 MPPI_INST(4)
 MPPI_INST(8)
 MPPI_INST(16)
