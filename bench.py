@@ -234,6 +234,8 @@ def serving(args, torch, mppi, synth, mode):
 
 
 def cpu_baseline(args, res):
+    """The FP64 oracle on the host cores: median of 5 timed runs over all cores
+    (OpenMP over samples) and, on a smaller sample, over one thread."""
     import oracle as O
     from paper_2511_19204_amd import synth
     m, p = res["model"], res["params"]
@@ -242,18 +244,27 @@ def cpu_baseline(args, res):
     except AttributeError:
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 16))
-    count = args.cpu_sample
     kn = synth.nominal_knots(m, p["n_knots"])
-    O.rollouts(m, p, m["x0"], kn, 1000, 1, 0, 0, cores, threads=cores)  # warm-up
-    reps = max(1, args.cpu_reps)
+    H = p["horizon"]
+
+    def rate(count, threads, runs=5):
+        O.rollouts(m, p, m["x0"], kn, 1000, 1, 0, 0, max(1, threads), threads=threads)  # warm-up
+        rs = []
+        for r in range(runs):
+            t0 = time.perf_counter()
+            O.rollouts(m, p, m["x0"], kn, 1000, 1 + r, 0, 0, count, threads=threads)
+            rs.append(count * H / (time.perf_counter() - t0))
+        return float(np.median(rs)), rs
+
     t0 = time.perf_counter()
-    for r in range(reps):
-        O.rollouts(m, p, m["x0"], kn, 1000, 1 + r, 0, 0, count, threads=cores)
-    dt = time.perf_counter() - t0
-    return {"value": reps * count * p["horizon"] / dt, "unit": "rollout-steps/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{reps} steps x {count} of the {p['n_samples']} rollouts (H={p['horizon']}), FP64, "
-                      f"OpenMP over samples, {dt:.1f} s wall ({dt * cores:.0f} core-s)"}
+    all_rate, _ = rate(args.cpu_sample, cores)
+    one_rate, _ = rate(args.cpu_sample_1t, 1)
+    wall = time.perf_counter() - t0
+    return {"value": all_rate, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
+            "value_1thread": one_rate,
+            "sample": f"median of 5 runs of {args.cpu_sample} of the {p['n_samples']} rollouts (H={H}) on "
+                      f"{cores} threads and of {args.cpu_sample_1t} rollouts on 1 thread; FP64, OpenMP over "
+                      f"samples; {wall:.1f} s wall in total"}
 
 
 def main():
@@ -268,7 +279,7 @@ def main():
     ap.add_argument("--robots", type=int, default=64)
     ap.add_argument("--rounds", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=4096)
-    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--cpu-sample-1t", type=int, default=96, help="rollouts per one-thread oracle run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
