@@ -74,6 +74,7 @@ def lib():
         _lib.orc_step.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, C.c_uint64, C.c_uint32, _dp,
                                   _dp, _dp, _ip, _dp, _ip, _ip, C.c_int]
         _lib.orc_step_f32.argtypes = _lib.orc_step.argtypes
+        _lib.orc_shift_knots.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, _dp]
         _lib.orc_hermite.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                      _dp, _dp]
         _lib.orc_weights.argtypes = [C.c_int, _dp, C.c_double, C.c_int, _dp, _ip]
@@ -194,6 +195,26 @@ def hermite(knots, nk, nu, H, dt, h, j):
     qr = C.c_double(); vr = C.c_double()
     _check(lib().orc_hermite(kp, nk, nu, H, dt, h, j, C.byref(qr), C.byref(vr)), "hermite")
     return qr.value, vr.value
+
+
+def shift_knots(knots, nk, nu, H, dt, n_steps):
+    """Warm-start shift of the best trajectory's knots by n_steps control steps
+    (Sec. III-E): the old spline at t_k + n_steps dt, clamped to the horizon end."""
+    k, kp = _d(knots)
+    out = np.zeros(2 * nk * nu)
+    _check(lib().orc_shift_knots(kp, nk, nu, H, dt, int(n_steps), out.ctypes.data_as(_dp)), "shift_knots")
+    return out
+
+
+def predict(model, params, x0, knots, n_steps):
+    """State prediction (Sec. III-E): the state after simulating n_steps control
+    steps of the trajectory the knots define, from x0 (the rollout's own
+    dynamics along the horizon's timeline)."""
+    H = params["horizon"]
+    if not 0 <= n_steps <= H:
+        raise ValueError("n_steps must be in 0..horizon")
+    _, traj, _, _ = rollout(model, params, x0, knots, debug=True)
+    return traj[n_steps]
 
 
 def sample_knots(model, params, nominal, seed, tick, iota, n):

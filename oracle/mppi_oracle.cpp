@@ -1015,6 +1015,25 @@ int orc_hermite(const double* knots, int nk, int nu, int H, double dt, int h, in
   return 0;
 }
 
+// Warm start (Sec. III-E, the shift of tau_best): the knots of the best
+// trajectory moved forward by n_steps control steps, i.e. the old spline
+// evaluated at t_k + n_steps dt, t_k = k Delta; past the end of the horizon the
+// final action repeats, so the time is clamped to T = H dt.  Position and
+// velocity knots are the spline's value and derivative there.
+int orc_shift_knots(const double* knots, int nk, int nu, int H, double dt, int n_steps, double* out) {
+  if (nk < 2 || nu < 1 || H < 1 || n_steps < 0 || !(dt > 0)) return -1;
+  const double T = H * dt, delta = T / (nk - 1);
+  for (int k = 0; k < nk; ++k)
+    for (int j = 0; j < nu; ++j) {
+      const double t = std::min(k * delta + n_steps * dt, T);
+      double q, v;
+      hermite_at_time<double>(knots, nk, nu, delta, t, j, &q, &v);
+      out[k * nu + j] = q;
+      out[(nk + k) * nu + j] = v;
+    }
+  return 0;
+}
+
 int orc_sample_knots(const orc_model* m, const orc_params* p, const double* nominal, uint64_t seed,
                      uint32_t tick, int iota, int n, double* out) {
   if (!model_ok(m) || !params_ok(m, p) || iota < 0 || iota >= p->n_iters || n < 0) return -1;
