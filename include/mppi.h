@@ -112,12 +112,15 @@ typedef struct {
   const float* q0_cost;      /* [n_u] reference joint configuration             */
 } mppi_params;
 
-/* Per-call results besides the knots (device memory). */
+/* Per-call results besides the knots (device memory).  best_iter == 0 and
+ * best_sample == 0 mean that no sample improved on the warm start (the
+ * "failed to improve" statistic of the best-trajectory ablation). */
 typedef struct {
   float S_best;              /* lowest cost simulated in this call (+inf if none) */
   int32_t best_iter;         /* iteration that found it, -1 if none             */
   int32_t n_nonfinite;       /* rollouts with a non-finite cost, all iterations */
   int32_t all_nonfinite_iters; /* iterations whose rollouts were all non-finite  */
+  int32_t best_sample;       /* sample index of the best within best_iter (0 = that iteration's nominal), -1 if none */
 } mppi_step_info;
 
 typedef struct mppi_model mppi_model;   /* device-resident tree (opaque)       */
@@ -172,6 +175,37 @@ mppi_status mppi_get_lanes_per_rollout(const mppi_ctx* c, int32_t* lanes);
  * iteration is non-finite the nominal is left unchanged for that iteration. */
 mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float* d_knots_in, float* d_knots_out,
                       float* d_best_knots, mppi_step_info* d_info, float* d_costs, void* stream);
+
+/* State prediction (Sec. III-E): the state reached from d_state_in
+ * [n_q + n_v] after n_steps control steps (0..H) of the trajectory that d_knots
+ * [2][K][n_u] defines (its first n_steps actions, PD-tracked with the rollout's
+ * own dynamics, soft contact and integrator), written to d_state_out
+ * [n_q + n_v] (device; may alias d_state_in).  Errors: MPPI_EINVAL. */
+mppi_status mppi_predict(mppi_ctx* c, const float* d_state_in, const float* d_knots, int32_t n_steps,
+                         float* d_state_out, void* stream);
+
+/* Warm-start shift (Sec. III-E): d_knots_out [2][K][n_u] = the spline of
+ * d_knots_in evaluated at t_k + n_steps dt (value and derivative), with the
+ * time clamped to the horizon end so the final action repeats.  n_steps >= 0;
+ * the buffers may alias. */
+mppi_status mppi_shift_knots(mppi_ctx* c, const float* d_knots_in, int32_t n_steps, float* d_knots_out,
+                             void* stream);
+
+/* One control step of Alg. 1 with state prediction and warm start, all on the
+ * stream: x_t = predict(d_state_meas, tau_best, n_delay); tau_0 = tau_best
+ * shifted by n_delay; then the I iterations of mppi_step from (x_t, tau_0).
+ *   d_state_meas [n_q + n_v] device, the last measured state (n_delay control
+ *                steps old)
+ *   d_best       [2][K][n_u] device, in: tau_best of the previous tick; out: the
+ *                best trajectory simulated in this tick (the one to execute)
+ *   d_knots_out  [2][K][n_u] device or NULL, the final nominal
+ *   d_info       device mppi_step_info or NULL (best_iter == 0 and best_sample
+ *                == 0: no sample improved on the shifted previous solution)
+ *   d_state_pred [n_q + n_v] device or NULL, the predicted state x_t
+ * Uses the context's tick, then advances it.  Errors: MPPI_EINVAL (n_delay
+ * outside 0..H, null required pointer), MPPI_EDEVICE. */
+mppi_status mppi_tick(mppi_ctx* c, const float* d_state_meas, int32_t n_delay, float* d_best, float* d_knots_out,
+                      mppi_step_info* d_info, float* d_state_pred, void* stream);
 
 /* The same for n instances in fused launches (each array has n entries;
  * d_best_knots / d_info entries may be NULL).  Instances may differ in model,

@@ -74,6 +74,7 @@ def lib():
         _lib.orc_step.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, C.c_uint64, C.c_uint32, _dp,
                                   _dp, _dp, _ip, _dp, _ip, _ip, C.c_int]
         _lib.orc_step_f32.argtypes = _lib.orc_step.argtypes
+        _lib.orc_rollout_f32_traj.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, _dp]
         _lib.orc_shift_knots.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, _dp]
         _lib.orc_hermite.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                      _dp, _dp]
@@ -214,6 +215,16 @@ def predict(model, params, x0, knots, n_steps):
     if not 0 <= n_steps <= H:
         raise ValueError("n_steps must be in 0..horizon")
     _, traj, _, _ = rollout(model, params, x0, knots, debug=True)
+    return traj[n_steps]
+
+
+def predict_f32(model, params, x0, knots, n_steps):
+    """predict() in the oracle's float instantiation (rounding reference only)."""
+    M = _Model(model); P = _Params(params, M.nu)
+    xa, xp = _d(x0); ka, kp = _d(knots)
+    traj = np.zeros((params["horizon"] + 1, M.nq + M.nv))
+    _check(lib().orc_rollout_f32_traj(C.c_void_p(M.ptr), C.c_void_p(P.ptr), xp, kp, traj.ctypes.data_as(_dp)),
+           "rollout_f32_traj")
     return traj[n_steps]
 
 

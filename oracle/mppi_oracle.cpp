@@ -1293,6 +1293,19 @@ int orc_rollout_f32(const orc_model* m, const orc_params* p, const double* x0, c
   return 0;
 }
 
+// The float instantiation's trajectory (states after each control step), for
+// the rounding reference of the GPU's state prediction.
+int orc_rollout_f32_traj(const orc_model* m, const orc_params* p, const double* x0, const double* knots,
+                         double* traj) {
+  if (!model_ok(m) || !params_ok(m, p)) return -1;
+  Model<float> M = load_model<float>(m);
+  const int nx = M.nq + M.nv, E = 2 * p->n_knots * M.nu;
+  std::vector<float> x(x0, x0 + nx), th(knots, knots + E), tr((size_t)(p->horizon + 1) * nx);
+  (void)rollout<float>(M, p, x.data(), th.data(), RolloutDebug<float>{tr.data(), nullptr, nullptr});
+  for (size_t i = 0; i < tr.size(); ++i) traj[i] = (double)tr[i];
+  return 0;
+}
+
 // Samples n0 .. n0+count-1 of iteration iota: knots generated from the
 // counter-based stream and rolled out (OpenMP over samples).  Used for sampled
 // parity at full problem sizes and for the CPU baseline timing.

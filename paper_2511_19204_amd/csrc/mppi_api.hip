@@ -31,6 +31,8 @@ template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int,
 template <int GC> __global__ void chain_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int, int);
 __global__ void reset_counters(unsigned int*, int);
 template <int G> __global__ void sample_kernel(const DevInst*, int);
+template <int G> __global__ void predict_kernel(const DevInst*, int, float*, int, int);
+__global__ void shift_knots_kernel(const float*, float*, int, int, int, int, int, float);
 template <int G>
 __global__ void dynamics_kernel(const DevModel*, int, const float*, const float*, const float*, const float*, float,
                                 float*, int, int);
@@ -89,6 +91,9 @@ struct mppi_ctx {
   // device buffers
   float *sigma = nullptr, *x0 = nullptr, *nom = nullptr, *samples = nullptr, *costs = nullptr;
   float *best_state = nullptr, *f0z = nullptr, *q0 = nullptr;
+  // state prediction: measured state, trajectory knots, a cost slot, its descriptor
+  float *x_meas = nullptr, *pred_knots = nullptr, *pred_cost = nullptr;
+  DevInst* d_pred_inst = nullptr;
   uint32_t* tick = nullptr;
   DevInst* d_insts = nullptr;   // [I]
   DevUpdate* d_ups = nullptr;   // [I]
@@ -350,7 +355,7 @@ static void free_ctx_events(mppi_ctx* c) {
 
 static void free_ctx_buffers(mppi_ctx* c) {
   void* ptrs[] = {c->sigma, c->x0, c->nom, c->samples, c->costs, c->best_state, c->f0z, c->q0,
-                  c->tick, c->d_insts, c->d_ups};
+                  c->tick, c->d_insts, c->d_ups, c->x_meas, c->pred_knots, c->pred_cost, c->d_pred_inst};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -443,7 +448,7 @@ extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, ui
   if ((e = hipMalloc(&c->nom, 3 * E * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc nominal");
   if ((e = hipMalloc(&c->samples, (size_t)c->N * E * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc samples");
   if ((e = hipMalloc(&c->costs, (size_t)c->I * c->N * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc costs");
-  if ((e = hipMalloc(&c->best_state, (E + 4) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc best");
+  if ((e = hipMalloc(&c->best_state, (E + 5) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc best");
   if ((e = hipMalloc(&c->f0z, std::max(M.nc, 1) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc f0z");
   if ((e = hipMalloc(&c->q0, c->nu * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc q0");
   if ((e = hipMalloc(&c->tick, sizeof(uint32_t))) != hipSuccess) return bail(e, "hipMalloc tick");
@@ -459,7 +464,22 @@ extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, ui
   if ((e = hipMemcpy(c->f0z, f0.data(), f0.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload f0z");
   if ((e = hipMemcpy(c->q0, q0.data(), q0.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload q0");
   if ((e = hipMemcpy(c->tick, &zero, sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload tick");
+  if ((e = hipMalloc(&c->x_meas, (c->nq + c->nv) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc x_meas");
+  if ((e = hipMalloc(&c->pred_knots, E * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc pred knots");
+  if ((e = hipMalloc(&c->pred_cost, sizeof(float))) != hipSuccess) return bail(e, "hipMalloc pred cost");
+  if ((e = hipMalloc(&c->d_pred_inst, sizeof(DevInst))) != hipSuccess) return bail(e, "hipMalloc pred inst");
   build_tables(c);
+  {
+    // prediction: one sample, knots read (not sampled) from pred_knots, from x_meas
+    DevInst d = c->h_insts[0];
+    d.x0 = c->x_meas;
+    d.samples = c->pred_knots;
+    d.costs = c->pred_cost;
+    d.masks = nullptr;
+    d.N = 1;
+    d.generate = 0;
+    if ((e = hipMemcpy(c->d_pred_inst, &d, sizeof(DevInst), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload pred inst");
+  }
   if ((e = hipMemcpy(c->d_insts, c->h_insts.data(), c->I * sizeof(DevInst), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload insts");
   if ((e = hipMemcpy(c->d_ups, c->h_ups.data(), c->I * sizeof(DevUpdate), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload ups");
   *out = c;
@@ -649,12 +669,10 @@ extern "C" mppi_status mppi_set_batch_options(const mppi_batch_opts* o) {
   return MPPI_OK;
 }
 
-extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float* d_knots_in, float* d_knots_out,
-                                 float* d_best_knots, mppi_step_info* d_info, float* d_costs, void* stream) {
-  if (!c || !d_state || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
-  hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(hipMemcpyAsync(c->x0, d_state, (c->nq + c->nv) * sizeof(float), hipMemcpyDeviceToDevice, s));
-  HIP_TRY(hipMemcpyAsync(c->nom, d_knots_in, c->E * sizeof(float), hipMemcpyDeviceToDevice, s));
+// The I planning iterations of one step from the staged state (c->x0) and
+// nominal (c->nom), as a sequence of rollout and update launches on s.
+static mppi_status run_iterations(mppi_ctx* c, float* d_knots_out, float* d_best_knots, mppi_step_info* d_info,
+                                  float* d_costs, hipStream_t s) {
   const Dims dm = dims_of(c);
   const int R = rollouts_per_block(c->lanes, dm);
   const int blocks = (c->N + R - 1) / R;
@@ -684,6 +702,97 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
   }
   if (d_costs) HIP_TRY(hipMemcpyAsync(d_costs, c->costs, (size_t)c->I * c->N * sizeof(float), hipMemcpyDeviceToDevice, s));
   return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float* d_knots_in, float* d_knots_out,
+                                 float* d_best_knots, mppi_step_info* d_info, float* d_costs, void* stream) {
+  if (!c || !d_state || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(c->x0, d_state, (c->nq + c->nv) * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->nom, d_knots_in, c->E * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return run_iterations(c, d_knots_out, d_best_knots, d_info, d_costs, s);
+}
+
+// ---------------------------------------------------------------------------
+// state prediction and warm start (Sec. III-E)
+// ---------------------------------------------------------------------------
+template <int G>
+static hipError_t launch_predict_G(const mppi_ctx* c, int steps, float* out, hipStream_t s) {
+  const int table = body_table_floats(c->nc);
+  const int stride = group_floats(G, c->E);
+  const int lds = (table + (64 / G) * stride) * (int)sizeof(float);
+  hipLaunchKernelGGL(predict_kernel<G>, dim3(1), dim3(64), lds, s, c->d_pred_inst, steps, out, stride, table);
+  return hipGetLastError();
+}
+
+// state_out <- state reached from c->x_meas along c->pred_knots after `steps` control steps
+static mppi_status launch_predict(const mppi_ctx* c, int steps, float* out, hipStream_t s) {
+  hipError_t e;
+  switch (next_pow2(c->m->host.nb)) {
+    case 4: e = launch_predict_G<4>(c, steps, out, s); break;
+    case 8: e = launch_predict_G<8>(c, steps, out, s); break;
+    case 16: e = launch_predict_G<16>(c, steps, out, s); break;
+    case 32: e = launch_predict_G<32>(c, steps, out, s); break;
+    default: e = launch_predict_G<64>(c, steps, out, s); break;
+  }
+  HIP_TRY(e);
+  return MPPI_OK;
+}
+
+static mppi_status launch_shift(const mppi_ctx* c, const float* in, int steps, float* out, hipStream_t s) {
+  const int n = c->K * c->nu;
+  hipLaunchKernelGGL(shift_knots_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, out, c->K, c->nu,
+                     c->H * c->m->host.nsub, c->m->host.nsub, std::min(steps, c->H), c->delta);
+  HIP_TRY(hipGetLastError());
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_predict(mppi_ctx* c, const float* d_state_in, const float* d_knots, int32_t n_steps,
+                                    float* d_state_out, void* stream) {
+  if (!c || !d_state_in || !d_knots || !d_state_out) return fail(MPPI_EINVAL, "null argument");
+  if (n_steps < 0 || n_steps > c->H) return fail(MPPI_EINVAL, "n_steps must be in 0..horizon");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nx = (size_t)(c->nq + c->nv) * sizeof(float);
+  HIP_TRY(hipMemcpyAsync(c->x_meas, d_state_in, nx, hipMemcpyDeviceToDevice, s));
+  if (n_steps == 0) {
+    HIP_TRY(hipMemcpyAsync(d_state_out, c->x_meas, nx, hipMemcpyDeviceToDevice, s));
+    return MPPI_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(c->pred_knots, d_knots, c->E * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return launch_predict(c, n_steps, d_state_out, s);
+}
+
+extern "C" mppi_status mppi_shift_knots(mppi_ctx* c, const float* d_knots_in, int32_t n_steps, float* d_knots_out,
+                                        void* stream) {
+  if (!c || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
+  if (n_steps < 0) return fail(MPPI_EINVAL, "n_steps must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(c->pred_knots, d_knots_in, c->E * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return launch_shift(c, c->pred_knots, n_steps, d_knots_out, s);
+}
+
+extern "C" mppi_status mppi_tick(mppi_ctx* c, const float* d_state_meas, int32_t n_delay, float* d_best,
+                                 float* d_knots_out, mppi_step_info* d_info, float* d_state_pred, void* stream) {
+  if (!c || !d_state_meas || !d_best) return fail(MPPI_EINVAL, "null argument");
+  if (n_delay < 0 || n_delay > c->H) return fail(MPPI_EINVAL, "n_delay must be in 0..horizon");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nx = (size_t)(c->nq + c->nv) * sizeof(float);
+  // x_t: the measured state carried n_delay control steps along tau_best
+  HIP_TRY(hipMemcpyAsync(c->x_meas, d_state_meas, nx, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->pred_knots, d_best, c->E * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (n_delay == 0) {
+    HIP_TRY(hipMemcpyAsync(c->x0, c->x_meas, nx, hipMemcpyDeviceToDevice, s));
+  } else {
+    mppi_status st = launch_predict(c, n_delay, c->x0, s);
+    if (st != MPPI_OK) return st;
+  }
+  if (d_state_pred) HIP_TRY(hipMemcpyAsync(d_state_pred, c->x0, nx, hipMemcpyDeviceToDevice, s));
+  // tau_0 <- tau_best shifted by n_delay actions (final action repeated)
+  mppi_status st = launch_shift(c, c->pred_knots, n_delay, c->nom, s);
+  if (st != MPPI_OK) return st;
+  // I iterations; the best simulated trajectory replaces tau_best
+  float* nominal_out = d_knots_out ? d_knots_out : c->pred_knots;  // consumed by the shift already
+  return run_iterations(c, nominal_out, d_best, d_info, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -97,7 +97,7 @@ struct DevUpdate {
   float* weights;        // [N] or null
   float* best_knots;     // [E] or null
   float* info;           // mppi_step_info (S_best, best_iter, n_nonfinite, all_nonfinite) or null
-  float* best_state;     // [E + 4] running best knots, S_best, best_iter, counters of this call
+  float* best_state;     // [E + 5] running best knots, S_best, best_iter, counters, best sample of this call
   uint32_t* tick;        // advanced by one after the last iteration of a call
   int32_t N, E, iter, weight_mode, first_iter, last_iter;
   float lambda;

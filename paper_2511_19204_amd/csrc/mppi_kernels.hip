@@ -925,9 +925,13 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
 // Fused rollout of one work item: 64/G rollouts of one instance, samples
 // w.y .. w.y + 64/G - 1 (those >= N are computed but not stored).
 // ---------------------------------------------------------------------------
+// steps control steps are simulated (the horizon for a rollout).  With state_out
+// set (state prediction, one sample) the state reached is written there and
+// no cost is formed.
 template <int G>
 __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride,
-                                                            int table_floats, float* smem) {
+                                                            int table_floats, float* smem, int steps,
+                                                            float* state_out) {
   const int lane = threadIdx.x;
   const int grp = lane / G, l = lane % G;
   const DevModel& M = *I.model;
@@ -972,10 +976,10 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   BodyConst bc;
   load_body(M, &I, b, body_lane, bc);
   uint32_t* const masks = I.masks;
-  const int H = I.H, F = sc.F;
+  const int H = I.H, F = sc.F, F_run = steps * sc.nsub;
   float acc = 0.f;
   StepClock clk;
-  for (int f = 0; f < F; ++f) {
+  for (int f = 0; f < F_run; ++f) {
     const bool control = clk.sub == 0;
     if (is_joint) hermite(knots, sc.K, sc.nu, F, sc.delta, sc.inv_delta, clk.seg, clk.rem, j, &io.qref, &io.vref);
     physics_step<G>(sc, bc, tab, gs, b, body_lane, io, control);
@@ -992,6 +996,21 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     }
     if (fb && b == 0) integrate_base(io.bq, io.bv, io.ba, io.dt);
     clk.advance(sc.K, F, sc.nsub);
+  }
+  if (state_out) {
+    if (valid) {
+      if (is_joint) {
+        state_out[(fb ? 7 : 0) + j] = io.q;
+        state_out[nq + (fb ? 6 : 0) + j] = io.v;
+      }
+      if (fb && b == 0) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) state_out[k] = io.bq[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) state_out[nq + k] = io.bv[k];
+      }
+    }
+    return;
   }
 
   // terminal cost
@@ -1024,7 +1043,18 @@ __global__ __launch_bounds__(64) void rollout_kernel(const DevInst* __restrict__
   extern __shared__ float smem[];
   constexpr int R = 64 / G;
   const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
-  rollout_item<G>(insts[w.x], w.y, group_stride, table_floats, smem);
+  const DevInst& I = insts[w.x];
+  rollout_item<G>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
+}
+
+// State prediction: sample 0 of the instance (its knots read from samples) run
+// for `steps` control steps from x0; the state reached goes to state_out.
+template <int G>
+__global__ __launch_bounds__(64) void predict_kernel(const DevInst* __restrict__ inst, int steps,
+                                                     float* __restrict__ state_out, int group_stride,
+                                                     int table_floats) {
+  extern __shared__ float smem[];
+  rollout_item<G>(*inst, 0, group_stride, table_floats, smem, steps, state_out);
 }
 
 // Persistent form: a grid sized to the resident wavefronts; each wavefront takes
@@ -1042,7 +1072,8 @@ __global__ __launch_bounds__(64) void rollout_persistent_kernel(const DevInst* _
     item = __builtin_amdgcn_readfirstlane(item);
     if (item >= n_items) break;
     const int2 w = work[item];
-    rollout_item<G>(insts[w.x], w.y, group_stride, table_floats, smem);
+    const DevInst& I = insts[w.x];
+    rollout_item<G>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
   }
 }
 
@@ -1606,7 +1637,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
   __syncthreads();
 
   // 4. best-sample tracking across the iterations of this call
-  float* bs = U.best_state;  // [E] knots, then S_best, best_iter, n_nonfinite, all_nonfinite
+  float* bs = U.best_state;  // [E] knots, then S_best, best_iter, n_nonfinite, all_nonfinite, best_sample
   if (U.first_iter) {
     for (int e = t; e < E; e += kUpdThreads) bs[e] = U.nominal_in[e];
     if (t == 0) {
@@ -1614,6 +1645,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
       reinterpret_cast<int*>(bs)[E + 1] = -1;
       reinterpret_cast<int*>(bs)[E + 2] = 0;
       reinterpret_cast<int*>(bs)[E + 3] = 0;
+      reinterpret_cast<int*>(bs)[E + 4] = -1;
     }
   }
   __syncthreads();
@@ -1626,6 +1658,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
     if (improve) {
       bs[E] = U.costs[nstar];
       reinterpret_cast<int*>(bs)[E + 1] = U.iter;
+      reinterpret_cast<int*>(bs)[E + 4] = nstar;
     }
     reinterpret_cast<int*>(bs)[E + 2] += N - nfin;
     reinterpret_cast<int*>(bs)[E + 3] += nfin == 0 ? 1 : 0;
@@ -1640,9 +1673,33 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
       reinterpret_cast<int*>(inf)[1] = reinterpret_cast<int*>(bs)[E + 1];
       reinterpret_cast<int*>(inf)[2] = reinterpret_cast<int*>(bs)[E + 2];
       reinterpret_cast<int*>(inf)[3] = reinterpret_cast<int*>(bs)[E + 3];
+      reinterpret_cast<int*>(inf)[4] = reinterpret_cast<int*>(bs)[E + 4];
     }
   }
   if (U.last_iter && t == 0 && U.tick) U.tick[0] += 1u;
+}
+
+// Warm start (Sec. III-E): the knots of a trajectory shifted forward by n_steps
+// control steps, i.e. its Hermite spline at t_k + n_steps dt clamped to the
+// horizon end (the final action repeats).  In fine steps of the horizon
+// (F = H n_sub) the knot time is k F / (K - 1), so the segment and remainder
+// come from the integer m = k F + n_steps n_sub (K - 1) = seg F + rem.
+// One thread per (knot, joint); in and out must not alias.
+__global__ void shift_knots_kernel(const float* __restrict__ in, float* __restrict__ out, int K, int nu, int F,
+                                   int nsub, int n_steps, float delta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K * nu) return;
+  const int k = i / nu, jj = i % nu;
+  const long long m = (long long)k * F + (long long)n_steps * nsub * (K - 1);
+  int seg = (int)(m / F), rem = (int)(m - (long long)seg * F);
+  if (seg > K - 2) {
+    seg = K - 2;
+    rem = F;
+  }
+  float q, v;
+  hermite(in, K, nu, F, delta, 1.f / delta, seg, rem, jj, &q, &v);
+  out[i] = q;
+  out[K * nu + i] = v;
 }
 
 // Copy per-call inputs (state, warm-start knots) into instance buffers.
@@ -1724,6 +1781,7 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   template __global__ void rollout_kernel<G>(const DevInst*, const int2*, int, int);                   \
   template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int); \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
+  template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \
   template __global__ void dynamics_kernel<G>(const DevModel*, int, const float*, const float*,        \
                                               const float*, const float*, float, float*, int, int);
 MPPI_INST(4)

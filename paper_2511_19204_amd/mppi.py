@@ -54,13 +54,16 @@ class Params(C.Structure):
 
 class StepInfo(C.Structure):
     _fields_ = [("S_best", C.c_float), ("best_iter", C.c_int32), ("n_nonfinite", C.c_int32),
-                ("all_nonfinite_iters", C.c_int32)]
+                ("all_nonfinite_iters", C.c_int32), ("best_sample", C.c_int32)]
+
+
+INFO_INTS = 5  # mppi_step_info as int32 words
 
 
 EXPORTS = [
     "mppi_model_create", "mppi_model_destroy", "mppi_create", "mppi_destroy", "mppi_set_tick",
     "mppi_get_tick", "mppi_set_schedule", "mppi_get_schedule", "mppi_set_lanes_per_rollout",
-    "mppi_get_lanes_per_rollout", "mppi_step",
+    "mppi_get_lanes_per_rollout", "mppi_step", "mppi_predict", "mppi_shift_knots", "mppi_tick",
     "mppi_step_batch", "mppi_debug_philox", "mppi_debug_samples", "mppi_debug_dynamics",
     "mppi_debug_rollouts", "mppi_debug_update", "mppi_profile_enable", "mppi_profile_read",
     "mppi_set_batch_options", "mppi_graph_create", "mppi_graph_launch", "mppi_graph_destroy",
@@ -97,6 +100,9 @@ def lib():
         L.mppi_set_lanes_per_rollout.argtypes = [vp, i32]
         L.mppi_get_lanes_per_rollout.argtypes = [vp, C.POINTER(i32)]
         L.mppi_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.mppi_predict.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.mppi_shift_knots.argtypes = [vp, vp, i32, vp, vp]
+        L.mppi_tick.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
         L.mppi_step_batch.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp]
         L.mppi_debug_philox.argtypes = [vp, vp, vp, i32, vp]
         L.mppi_debug_samples.argtypes = [vp, vp, i32, u32, vp, vp]
@@ -293,6 +299,21 @@ class Controller:
         _check(lib().mppi_step(self.h, _ptr(state), _ptr(knots_in), _ptr(knots_out),
                                _ptr(best_knots), _ptr(info), _ptr(costs), _stream(stream)),
                "mppi_step")
+
+    def predict(self, state_in, knots, n_steps, state_out, stream=None):
+        """State reached after n_steps control steps along the knots' trajectory."""
+        _check(lib().mppi_predict(self.h, _ptr(state_in), _ptr(knots), int(n_steps), _ptr(state_out),
+                                  _stream(stream)), "mppi_predict")
+
+    def shift_knots(self, knots_in, n_steps, knots_out, stream=None):
+        """Warm-start shift of a trajectory's knots by n_steps control steps."""
+        _check(lib().mppi_shift_knots(self.h, _ptr(knots_in), int(n_steps), _ptr(knots_out), _stream(stream)),
+               "mppi_shift_knots")
+
+    def run_tick(self, state_meas, n_delay, best, knots_out=None, info=None, state_pred=None, stream=None):
+        """mppi_tick: one control step (predict, shift tau_best, iterate); `best` is updated in place."""
+        _check(lib().mppi_tick(self.h, _ptr(state_meas), int(n_delay), _ptr(best), _ptr(knots_out), _ptr(info),
+                               _ptr(state_pred), _stream(stream)), "mppi_tick")
 
     def profile(self, on=True):
         """Record HIP events around this instance's kernel launches."""

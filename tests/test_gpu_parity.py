@@ -198,7 +198,7 @@ def _run_step(c, m, p, knots):
     st, ki = _t(m["x0"]), _t(knots)
     ko = torch.zeros(E, device="cuda")
     best = torch.zeros(E, device="cuda")
-    info = torch.zeros(4, dtype=torch.int32, device="cuda")
+    info = torch.zeros(5, dtype=torch.int32, device="cuda")
     costs = torch.zeros((p["n_iters"], p["n_samples"]), device="cuda")
     c.step(st, ki, ko, best, info, costs)
     inf = _np(info)
@@ -271,7 +271,7 @@ def test_batched_step_equals_plain_steps():
     kin = [_t(synth.nominal_knots(m, p["n_knots"])) for (m, p, s, model, c) in made]
     kout = [torch.zeros(c.E, device="cuda") for (m, p, s, model, c) in made]
     best = [torch.zeros(c.E, device="cuda") for (m, p, s, model, c) in made]
-    infos = [torch.zeros(4, dtype=torch.int32, device="cuda") for _ in made]
+    infos = [torch.zeros(5, dtype=torch.int32, device="cuda") for _ in made]
     for (m, p, s, model, c) in made:
         c.tick = 9
     ctrls = [c for (m, p, s, model, c) in made]
@@ -309,7 +309,7 @@ def test_non_finite_state_leaves_knots_unchanged():
     kn = synth.nominal_knots(m, p["n_knots"])
     E = c.E
     ko = torch.zeros(E, device="cuda")
-    info = torch.zeros(4, dtype=torch.int32, device="cuda")
+    info = torch.zeros(5, dtype=torch.int32, device="cuda")
     c.step(_t(x), _t(kn), ko, None, info, None)
     inf = _np(info)
     assert np.array_equal(_np(ko), kn.astype(np.float32))

@@ -71,7 +71,7 @@ def _step(c, m, p, knots, tick):
     st, ki = _t(m["x0"]), _t(knots)
     ko = torch.zeros(E, device="cuda")
     best = torch.zeros(E, device="cuda")
-    info = torch.zeros(4, dtype=torch.int32, device="cuda")
+    info = torch.zeros(5, dtype=torch.int32, device="cuda")
     costs = torch.zeros((p["n_iters"], p["n_samples"]), device="cuda")
     c.tick = tick
     c.step(st, ki, ko, best, info, costs)
