@@ -55,7 +55,7 @@ class OrcParams(C.Structure):
         ("w_or", C.c_double), ("w_q", C.c_double), ("w_cv", C.c_double), ("w_cf", C.c_double),
         ("w_eff", C.c_double), ("w_H", C.c_double), ("w_ee", C.c_double), ("w_tau", C.c_double),
         ("z_des", C.c_double), ("v_des", C.c_double * 3), ("f0z", _dp),
-        ("q0_cost", _dp),
+        ("q0_cost", _dp), ("spline_mode", C.c_int32),
     ]
 
 
@@ -75,7 +75,8 @@ def lib():
                                   _dp, _dp, _ip, _dp, _ip, _ip, C.c_int]
         _lib.orc_step_f32.argtypes = _lib.orc_step.argtypes
         _lib.orc_rollout_f32_traj.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, _dp]
-        _lib.orc_shift_knots.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, _dp]
+        _lib.orc_shift_knots.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, _dp]
+        _lib.orc_spline_slopes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, _dp]
         _lib.orc_hermite.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                      _dp, _dp]
         _lib.orc_weights.argtypes = [C.c_int, _dp, C.c_double, C.c_int, _dp, _ip]
@@ -154,6 +155,7 @@ class _Params:
         self.q0, s.q0_cost = _d(q0)
         f0 = np.asarray(p.get("f0z", np.zeros(1)), dtype=np.float64).reshape(-1)
         self.f0, s.f0z = _d(f0 if f0.size else np.zeros(1))
+        s.spline_mode = int(p.get("spline_mode", 0))
         self.s = s
 
     @property
@@ -198,12 +200,22 @@ def hermite(knots, nk, nu, H, dt, h, j):
     return qr.value, vr.value
 
 
-def shift_knots(knots, nk, nu, H, dt, n_steps):
+def shift_knots(knots, nk, nu, H, dt, n_steps, spline_mode=0):
     """Warm-start shift of the best trajectory's knots by n_steps control steps
-    (Sec. III-E): the old spline at t_k + n_steps dt, clamped to the horizon end."""
+    (Sec. III-E): the old spline at t_k + n_steps dt, clamped to the horizon end
+    (position-only variants: new knot slopes from the shifted positions)."""
     k, kp = _d(knots)
     out = np.zeros(2 * nk * nu)
-    _check(lib().orc_shift_knots(kp, nk, nu, H, dt, int(n_steps), out.ctypes.data_as(_dp)), "shift_knots")
+    _check(lib().orc_shift_knots(kp, nk, nu, H, dt, int(n_steps), int(spline_mode), out.ctypes.data_as(_dp)),
+           "shift_knots")
+    return out
+
+
+def spline_slopes(mode, knots, nk, nu, delta):
+    """Knots with the velocity block replaced by the slopes of the position-only
+    spline variant `mode` (1 natural cubic, 2 quadratic) through the positions."""
+    out = np.array(knots, dtype=np.float64)
+    _check(lib().orc_spline_slopes(int(mode), nk, nu, float(delta), out.ctypes.data_as(_dp)), "spline_slopes")
     return out
 
 

@@ -71,6 +71,7 @@ typedef struct {
   double z_des, v_des[3];
   const double* f0z;      // [nc] reference normal force of each contact point
   const double* q0_cost;  // [n_u]
+  int32_t spline_mode;    // 0 = cubic Hermite, 1 = natural cubic, 2 = quadratic (position-only, v_ref = 0)
 } orc_params;
 
 }  // extern "C"
@@ -767,6 +768,45 @@ static void sigma_table(const orc_params* p, double* sig) {
 // Perturbed, clipped and derivative-clamped knots of sample n (Alg. 1 sampling
 // step; eq. vel-clamp with the distance to the nearest bound over Delta/2).
 // Sample 0 is the nominal itself, clipped and clamped the same way.
+// Spline variants of the ablation (Sec. V, splines; the paper's comparison of
+// cubic Hermite splines with position-only cubic and quadratic splines whose
+// velocity targets are zero).  The position-only variants sample only the
+// position knots; their knot slopes (dq/dt) are derived from the positions and
+// kept in the velocity block, and the curve is evaluated in Hermite form:
+//   mode 1, natural cubic spline: C2 at the interior knots and zero second
+//     derivative at both ends, i.e. m_{k-1} + 4 m_k + m_{k+1} = 3 (q_{k+1} - q_{k-1}) / Delta,
+//     2 m_0 + m_1 = 3 (q_1 - q_0) / Delta, m_{K-2} + 2 m_{K-1} = 3 (q_{K-1} - q_{K-2}) / Delta
+//     (a cubic spline is the Hermite spline of its own knot slopes);
+//   mode 2, quadratic spline: C1 pieces q_k + m_k tau + c tau^2 with zero initial
+//     slope, m_0 = 0, m_{k+1} = 2 (q_{k+1} - q_k) / Delta - m_k (a quadratic
+//     piece is the Hermite cubic of its end values and slopes).
+template <class T> static void position_spline_slopes(int mode, int K, int nu, T delta, T* knots) {
+  const T* Q = knots;
+  T* V = knots + K * nu;
+  for (int j = 0; j < nu; ++j) {
+    if (mode == 2) {
+      V[j] = 0;
+      for (int k = 0; k + 1 < K; ++k) V[(k + 1) * nu + j] = 2 * (Q[(k + 1) * nu + j] - Q[k * nu + j]) / delta - V[k * nu + j];
+      continue;
+    }
+    // mode 1: tridiagonal system (sub/super diagonal 1), Thomas elimination
+    std::vector<T> diag(K), rhs(K);
+    for (int k = 0; k < K; ++k) {
+      const bool end = k == 0 || k == K - 1;
+      diag[k] = end ? T(2) : T(4);
+      const T qa = Q[(k == 0 ? 0 : k - 1) * nu + j], qb = Q[(k == K - 1 ? K - 1 : k + 1) * nu + j];
+      rhs[k] = 3 * (qb - qa) / delta;
+    }
+    for (int k = 1; k < K; ++k) {
+      const T w = T(1) / diag[k - 1];
+      diag[k] -= w;
+      rhs[k] -= w * rhs[k - 1];
+    }
+    V[(K - 1) * nu + j] = rhs[K - 1] / diag[K - 1];
+    for (int k = K - 2; k >= 0; --k) V[k * nu + j] = (rhs[k] - V[(k + 1) * nu + j]) / diag[k];
+  }
+}
+
 template <class T>
 static void sample_knots(const Model<T>& M, const orc_params* p, const T* nominal, const double* sig,
                          uint64_t seed, uint32_t tick, int iota, int n, T* out) {
@@ -787,6 +827,7 @@ static void sample_knots(const Model<T>& M, const orc_params* p, const T* nomina
       out[m] = tq;
       out[K * nu + m] = tv;
     }
+  if (p->spline_mode != 0) position_spline_slopes<T>(p->spline_mode, K, nu, delta, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -862,7 +903,10 @@ static T rollout(const Model<T>& M, const orc_params* p, const T* x0, const T* k
     const bool control = (f % ns) == 0;
     if (dbg.traj && control)
       for (int k = 0; k < nq + nv; ++k) dbg.traj[h * (nq + nv) + k] = k < nq ? q[k] : v[k - nq];
-    for (int j = 0; j < nu; ++j) hermite_eval(knots, K, nu, F, delta, f, j, &qref[j], &vref[j]);
+    for (int j = 0; j < nu; ++j) {
+      hermite_eval(knots, K, nu, F, delta, f, j, &qref[j], &vref[j]);
+      if (p->spline_mode != 0) vref[j] = 0;  // position-only variants: zero velocity targets
+    }
     PDOut<T> pd = pd_law(M, q.data(), v.data(), qref.data(), vref.data(), dtf);
     tau = pd.tau;
     Kin<T> Kn = kinematics(M, q.data(), v.data());
@@ -964,6 +1008,7 @@ static bool params_ok(const orc_model* m, const orc_params* p) {
   if (p->cost_kind == 0 && (m->ee_body < 0 || m->ee_body >= m->n_bodies)) return false;
   if (p->cost_kind == 1 && !m->floating_base) return false;
   if (p->cost_kind == 1 && (!p->q0_cost || (m->n_contacts > 0 && !p->f0z))) return false;
+  if (p->spline_mode < 0 || p->spline_mode > 2) return false;
   return true;
 }
 
@@ -1020,8 +1065,9 @@ int orc_hermite(const double* knots, int nk, int nu, int H, double dt, int h, in
 // evaluated at t_k + n_steps dt, t_k = k Delta; past the end of the horizon the
 // final action repeats, so the time is clamped to T = H dt.  Position and
 // velocity knots are the spline's value and derivative there.
-int orc_shift_knots(const double* knots, int nk, int nu, int H, double dt, int n_steps, double* out) {
-  if (nk < 2 || nu < 1 || H < 1 || n_steps < 0 || !(dt > 0)) return -1;
+int orc_shift_knots(const double* knots, int nk, int nu, int H, double dt, int n_steps, int spline_mode,
+                    double* out) {
+  if (nk < 2 || nu < 1 || H < 1 || n_steps < 0 || !(dt > 0) || spline_mode < 0 || spline_mode > 2) return -1;
   const double T = H * dt, delta = T / (nk - 1);
   for (int k = 0; k < nk; ++k)
     for (int j = 0; j < nu; ++j) {
@@ -1031,6 +1077,15 @@ int orc_shift_knots(const double* knots, int nk, int nu, int H, double dt, int n
       out[k * nu + j] = q;
       out[(nk + k) * nu + j] = v;
     }
+  // position-only variants: the shifted positions define a new spline of the same kind
+  if (spline_mode != 0) position_spline_slopes<double>(spline_mode, nk, nu, delta, out);
+  return 0;
+}
+
+// Knot slopes of the position-only spline variants (test access).
+int orc_spline_slopes(int mode, int nk, int nu, double delta, double* knots) {
+  if (nk < 2 || nu < 1 || (mode != 1 && mode != 2) || !(delta > 0)) return -1;
+  position_spline_slopes<double>(mode, nk, nu, delta, knots);
   return 0;
 }
 
