@@ -181,6 +181,38 @@ def batched_vs_plain(args, torch, mppi, synth):
     return out
 
 
+def closed_loop(args, torch, mppi, synth):
+    """Alg. 1 in closed loop on one robot (quadruped, K=64, H=100, I=3): every
+    tick predicts the state after the solver delay along tau_best, warm-starts
+    from tau_best shifted and iterates (mppi_tick); the delay in control steps
+    is the previous tick's measured latency rounded up, and the simulated robot
+    follows the plan (the next measured state is this tick's prediction)."""
+    m, p, seed = synth.config("quadruped", n_samples=64)
+    model = mppi.Model(m)
+    c = mppi.Controller(model, p, seed)
+    x = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
+    best = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
+    info = torch.zeros(mppi.INFO_INTS, dtype=torch.int32, device="cuda")
+    xp = torch.zeros_like(x)
+    delay, lat, failed, delays = 1, [], 0, []
+    for t in range(args.loop_ticks + 5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.run_tick(x, delay, best, None, info, xp)
+        inf = info.cpu().numpy()  # waits for the tick
+        dt_ms = (time.perf_counter() - t0) * 1e3
+        if t >= 5:
+            lat.append(dt_ms)
+            delays.append(delay)
+            failed += int(inf[1] == 0 and inf[4] == 0)
+        x, xp = xp, x
+        delay = max(1, int(np.ceil(dt_ms / 1e3 / p["dt"])))
+    lat = np.array(lat)
+    return {"robot": "quadruped18, K=64, H=100, I=3", "ticks": len(lat),
+            "tick_latency_p50_ms": float(np.percentile(lat, 50)), "tick_latency_p99_ms": float(np.percentile(lat, 99)),
+            "delay_steps_mean": float(np.mean(delays)), "failed_to_improve_frac": failed / len(lat)}
+
+
 def serving(args, torch, mppi, synth, mode):
     """Poisson MPC ticks (50 Hz per robot) from the 64-robot mix, served by the
     continuous-batching server (mode "batched") or by plain per-instance steps
@@ -281,6 +313,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--cpu-sample-1t", type=int, default=96, help="rollouts per one-thread oracle run")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-loop", action="store_true", help="skip the closed-loop tick run")
+    ap.add_argument("--loop-ticks", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-streams", type=int, default=3)
@@ -313,6 +347,7 @@ def main():
                "plain": serving(args, torch, mppi, synth, "plain"),
                "robots": args.robots, "rate_hz": 50.0, "deadline_ms": 20.0,
                "seconds": args.serve_seconds}
+    loop = None if args.no_loop else closed_loop(args, torch, mppi, synth)
     cpu = None if args.no_cpu else cpu_baseline(args, res)
     digest = kernel_source_digest()
     traffic = measured_traffic(digest)
@@ -360,6 +395,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_vs_plain": bvp,
         "serving": srv,
+        "closed_loop": loop,
     }
     print(json.dumps(out), flush=True)
 

@@ -110,6 +110,16 @@ typedef struct {
   float v_des[3];            /* commanded base velocity (terminal target)       */
   const float* f0z;          /* [n_contacts] reference normal force per point   */
   const float* q0_cost;      /* [n_u] reference joint configuration             */
+  int32_t spline_mode;       /* control parameterization (spline ablation, Sec. V):
+                              * 0 cubic Hermite: position and velocity knots,
+                              *   velocity targets = the spline's derivative;
+                              * 1 natural cubic spline through the position
+                              *   knots, velocity targets zero;
+                              * 2 C1 quadratic spline (zero initial slope)
+                              *   through the position knots, velocity targets
+                              *   zero.  Modes 1 and 2 sample positions only and
+                              *   keep the spline's knot slopes (dq/dt) in the
+                              *   velocity block of every knot vector they return. */
 } mppi_params;
 
 /* Per-call results besides the knots (device memory).  best_iter == 0 and

@@ -32,7 +32,7 @@ template <int GC> __global__ void chain_persistent_kernel(const DevInst*, const 
 __global__ void reset_counters(unsigned int*, int);
 template <int G> __global__ void sample_kernel(const DevInst*, int);
 template <int G> __global__ void predict_kernel(const DevInst*, int, float*, int, int);
-__global__ void shift_knots_kernel(const float*, float*, int, int, int, int, int, float);
+__global__ void shift_knots_kernel(const float*, float*, int, int, int, int, int, float, int);
 template <int G>
 __global__ void dynamics_kernel(const DevModel*, int, const float*, const float*, const float*, const float*, float,
                                 float*, int, int);
@@ -384,6 +384,7 @@ static void build_tables(mppi_ctx* c) {
     d.w_eff = c->p.w_eff; d.w_H = c->p.w_H; d.w_ee = c->p.w_ee; d.w_tau = c->p.w_tau; d.z_des = c->p.z_des;
     for (int k = 0; k < 3; ++k) d.v_des[k] = c->p.v_des[k];
     d.generate = 1;
+    d.spline_mode = c->p.spline_mode;
     (void)M;
     DevUpdate& u = c->h_ups[it];
     u.costs = d.costs;
@@ -411,6 +412,7 @@ extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, ui
   if (p->weight_mode != 0 && p->weight_mode != 1) return fail(MPPI_EINVAL, "weight_mode must be 0 or 1");
   if (p->noise_mode != 0 && p->noise_mode != 1) return fail(MPPI_EINVAL, "noise_mode must be 0 or 1");
   if (p->noise_mode == 0 && !(p->beta1 > 0.f && p->beta2 > 0.f)) return fail(MPPI_EINVAL, "beta1, beta2 must be positive");
+  if (p->spline_mode < 0 || p->spline_mode > 2) return fail(MPPI_EINVAL, "spline_mode must be 0, 1 or 2");
   const DevModel& M = m->host;
   if (p->cost_kind == 0 && M.ee_body < 0) return fail(MPPI_EINVAL, "end-effector cost needs ee_body");
   if (p->cost_kind == 1 && !M.fb) return fail(MPPI_EINVAL, "locomotion cost needs a floating base");
@@ -740,9 +742,8 @@ static mppi_status launch_predict(const mppi_ctx* c, int steps, float* out, hipS
 }
 
 static mppi_status launch_shift(const mppi_ctx* c, const float* in, int steps, float* out, hipStream_t s) {
-  const int n = c->K * c->nu;
-  hipLaunchKernelGGL(shift_knots_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, out, c->K, c->nu,
-                     c->H * c->m->host.nsub, c->m->host.nsub, std::min(steps, c->H), c->delta);
+  hipLaunchKernelGGL(shift_knots_kernel, dim3(1), dim3(256), 0, s, in, out, c->K, c->nu, c->H * c->m->host.nsub,
+                     c->m->host.nsub, std::min(steps, c->H), c->delta, c->p.spline_mode);
   HIP_TRY(hipGetLastError());
   return MPPI_OK;
 }
@@ -1192,7 +1193,8 @@ extern "C" mppi_status mppi_debug_philox(const uint32_t* d_ctr, const uint32_t* 
 template <int G>
 static hipError_t launch_samples_G(const DevInst* inst, int N, int E, hipStream_t s) {
   const int R = 64 / G;
-  hipLaunchKernelGGL(sample_kernel<G>, dim3((N + R - 1) / R), dim3(64), lds_bytes(G, E), s, inst, group_floats(G, E));
+  const int lds = (kTabContacts + R * group_floats(G, E)) * (int)sizeof(float);
+  hipLaunchKernelGGL(sample_kernel<G>, dim3((N + R - 1) / R), dim3(64), lds, s, inst, group_floats(G, E));
   return hipGetLastError();
 }
 

@@ -86,6 +86,7 @@ struct DevInst {
   float w_h, w_or, w_q, w_cv, w_cf, w_eff, w_H, w_ee, w_tau, z_des;
   float v_des[3];
   int32_t generate;      // 1: sample knots from the counter-based stream; 0: read samples
+  int32_t spline_mode;   // 0 cubic Hermite, 1 natural cubic, 2 quadratic (position knots, zero velocity targets)
 };
 
 // Per-instance state of the weighting/update stage.
@@ -127,9 +128,12 @@ __host__ __device__ inline int group_floats(int G, int E) {
 
 // Model table, staged once per work item at the start of a block's LDS:
 //   [0,24)            base spatial inertia (21, packed) and padding
-//   [24,24+nc*kCt)    contact rows (position, nominal normal force, index)
+//   [24,88)           modified diagonal of the natural cubic spline's slope
+//                     system (K entries; spline mode 1)
+//   [88,88+nc*kCt)    contact rows (position, nominal normal force, index)
 // and, for the chain schedule only, the body rows and the chain-body table.
-constexpr int kTabContacts = 24;
+constexpr int kTabSpline = 24;
+constexpr int kTabContacts = 88;
 __host__ __device__ inline int body_table_floats(int nc) { return kTabContacts + nc * kCt; }
 
 // Chain schedule: after the model table (with body rows and chain bodies), one

@@ -361,6 +361,55 @@ __device__ __forceinline__ void bias_force(const float* IA, const float* v, floa
 // in B axes.  Adds the contact force to the bias pA and, while the point
 // penetrates, the linearly implicit damping/friction terms to IA and pA.
 // Returns the normal force; vw and fw are the point's world velocity and force.
+// Position-only spline variants (spline ablation, Sec. V): knot slopes dq/dt
+// derived from the position knots and kept in the velocity block, so the curve
+// is evaluated in Hermite form.  Natural cubic spline (mode 1): C2 at interior
+// knots, zero end second derivatives, i.e. the tridiagonal system
+// m_{k-1} + 4 m_k + m_{k+1} = 3 (q_{k+1} - q_{k-1}) / Delta with end rows
+// (2, 1) and (1, 2); its eliminated diagonal depends on K only.  Quadratic
+// spline (mode 2): m_0 = 0, m_{k+1} = 2 (q_{k+1} - q_k) / Delta - m_k.
+__device__ __forceinline__ void natural_cubic_diagonal(int K, float* dg) {
+  float d = 2.f;
+  dg[0] = d;
+  for (int k = 1; k < K; ++k) {
+    const float w = 1.f / d;
+    d = (k == K - 1 ? 2.f : 4.f) - w;
+    dg[k] = d;
+  }
+}
+
+// Slopes of joint jj for a knot vector in LDS (positions in [0, K nu),
+// slopes written to [K nu, 2 K nu)); dg = natural_cubic_diagonal(K) for mode 1.
+__device__ __forceinline__ void position_spline_slopes(int mode, int K, int nu, int jj, float delta, const float* dg,
+                                                       float* knots) {
+  const float* Q = knots;
+  float* V = knots + K * nu;
+  if (mode == 2) {
+    float m = 0.f;
+    V[jj] = m;
+    for (int k = 0; k + 1 < K; ++k) {
+      m = 2.f * (Q[(k + 1) * nu + jj] - Q[k * nu + jj]) / delta - m;
+      V[(k + 1) * nu + jj] = m;
+    }
+    return;
+  }
+  // forward elimination (right-hand sides into V), then back substitution
+  float prev = 0.f;
+  for (int k = 0; k < K; ++k) {
+    const float qa = Q[(k == 0 ? 0 : k - 1) * nu + jj], qb = Q[(k == K - 1 ? K - 1 : k + 1) * nu + jj];
+    float r = 3.f * (qb - qa) / delta;
+    if (k > 0) r -= (1.f / dg[k - 1]) * prev;
+    V[k * nu + jj] = r;
+    prev = r;
+  }
+  float next = V[(K - 1) * nu + jj] / dg[K - 1];
+  V[(K - 1) * nu + jj] = next;
+  for (int k = K - 2; k >= 0; --k) {
+    next = (V[k * nu + jj] - next) / dg[k];
+    V[k * nu + jj] = next;
+  }
+}
+
 struct ContactLaw {
   float k, d, mu, eps;
 };
@@ -369,7 +418,7 @@ struct ContactLaw {
 // work item (read through the model pointer inside the step loop, the compiler
 // would reload them after every LDS store).
 struct StepConst {
-  int fb, max_depth, ee_body, cost_kind, K, nu, F, nsub;
+  int fb, max_depth, ee_body, cost_kind, K, nu, F, nsub, spline_mode;
   float g, dt, delta, inv_delta;
   ContactLaw law;
   float ee_pos[3];
@@ -382,13 +431,13 @@ __device__ __forceinline__ StepConst load_step_const(const DevModel& M, const De
   c.law = ContactLaw{M.k, M.d, M.mu, M.eps};
   c.ee_pos[0] = M.ee_pos[0]; c.ee_pos[1] = M.ee_pos[1]; c.ee_pos[2] = M.ee_pos[2];
   if (I) {
-    c.cost_kind = I->cost_kind; c.K = I->K; c.nu = I->nu; c.F = I->H * M.nsub;
+    c.cost_kind = I->cost_kind; c.K = I->K; c.nu = I->nu; c.F = I->H * M.nsub; c.spline_mode = I->spline_mode;
     c.dt = I->dt / (float)M.nsub;
     c.delta = I->delta; c.inv_delta = 1.f / I->delta;
     c.w_h = I->w_h; c.w_or = I->w_or; c.w_q = I->w_q; c.w_cv = I->w_cv; c.w_cf = I->w_cf; c.w_eff = I->w_eff;
     c.w_ee = I->w_ee; c.w_tau = I->w_tau; c.z_des = I->z_des;
   } else {
-    c.cost_kind = -1; c.K = 2; c.nu = M.nu; c.F = 1;
+    c.cost_kind = -1; c.K = 2; c.nu = M.nu; c.F = 1; c.spline_mode = 0;
     c.dt = dt_override;
     c.delta = 1.f; c.inv_delta = 1.f;
     c.w_h = c.w_or = c.w_q = c.w_cv = c.w_cf = c.w_eff = c.w_ee = c.w_tau = c.z_des = 0.f;
@@ -408,6 +457,7 @@ __device__ __forceinline__ void stage_model_table(const DevModel& M, const DevIn
       float* ct = tab + kTabContacts + ci * kCt;
       ct[3] = I->f0z[__float_as_int(ct[4])];
     }
+  if (I && I->spline_mode == 1 && lane == 0) natural_cubic_diagonal(I->K, tab + kTabSpline);
   wave_sync();
 }
 __device__ __forceinline__ float contact_point(const float* r, const float* R, const float* p, const float* v,
@@ -796,7 +846,8 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
 // position clip and bound-aware velocity clamp.
 // ---------------------------------------------------------------------------
 template <int G>
-__device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, float* knots, bool valid) {
+__device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, float* knots, bool valid,
+                             const float* tab) {
   const int K = I.K, nu = I.nu, KU = K * nu;
   const int nblk = (KU + 1) / 2;
   const uint2 key = make_uint2(I.seed_lo, I.seed_hi);
@@ -819,19 +870,28 @@ __device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, 
         zv = r * sinpif(2.f * ub);
       }
       const float sq = sig[k];
-      const float sv = sq / I.delta;
       const float lo = M.qmin[jj], hi = M.qmax[jj];
       float tq = fmaf(sq, zq, I.nominal[m]);
       tq = fminf(fmaxf(tq, lo), hi);
-      const float lim = 2.f * fminf(hi - tq, tq - lo) / I.delta;
-      float tv = fmaf(sv, zv, I.nominal[KU + m]);
-      tv = fminf(fmaxf(tv, -lim), lim);
       knots[m] = tq;
-      knots[KU + m] = tv;
-      if (valid) {
-        I.samples[(size_t)n * I.E + m] = tq;
-        I.samples[(size_t)n * I.E + KU + m] = tv;
+      if (valid) I.samples[(size_t)n * I.E + m] = tq;
+      if (I.spline_mode == 0) {
+        const float sv = sq / I.delta;
+        const float lim = 2.f * fminf(hi - tq, tq - lo) / I.delta;
+        float tv = fmaf(sv, zv, I.nominal[KU + m]);
+        tv = fminf(fmaxf(tv, -lim), lim);
+        knots[KU + m] = tv;
+        if (valid) I.samples[(size_t)n * I.E + KU + m] = tv;
       }
+    }
+  }
+  if (I.spline_mode != 0) {
+    // position-only variants: knot slopes of the spline through the sampled positions
+    wave_sync();
+    for (int jj = l; jj < nu; jj += G) {
+      position_spline_slopes(I.spline_mode, K, nu, jj, I.delta, tab + kTabSpline, knots);
+      if (valid)
+        for (int k = 0; k < K; ++k) I.samples[(size_t)n * I.E + KU + k * nu + jj] = knots[KU + k * nu + jj];
     }
   }
 }
@@ -945,7 +1005,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 
   // knots of this sample
   if (I.generate) {
-    sample_group<G>(M, I, valid ? n : 0, l, knots, valid);
+    sample_group<G>(M, I, valid ? n : 0, l, knots, valid, tab);
   } else {
     const float* src = I.samples + (size_t)(valid ? n : 0) * I.E;
     for (int e = l; e < I.E; e += G) knots[e] = src[e];
@@ -981,7 +1041,10 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   StepClock clk;
   for (int f = 0; f < F_run; ++f) {
     const bool control = clk.sub == 0;
-    if (is_joint) hermite(knots, sc.K, sc.nu, F, sc.delta, sc.inv_delta, clk.seg, clk.rem, j, &io.qref, &io.vref);
+    if (is_joint) {
+      hermite(knots, sc.K, sc.nu, F, sc.delta, sc.inv_delta, clk.seg, clk.rem, j, &io.qref, &io.vref);
+      if (sc.spline_mode != 0) io.vref = 0.f;  // position-only variants: zero velocity targets
+    }
     physics_step<G>(sc, bc, tab, gs, b, body_lane, io, control);
     if (control) {
       acc += io.cost;
@@ -1145,6 +1208,7 @@ __device__ __forceinline__ void chain_fk(const StepConst& sc, const float* rows,
         if (!terminal) {
           float qref, vref;
           hermite(knots, sc.K, sc.nu, sc.F, sc.delta, sc.inv_delta, seg, rem, j, &qref, &vref);
+          if (sc.spline_mode != 0) vref = 0.f;
           pd_law(rw[row::kp], rw[row::kd], rw[row::taumax], dt, q, qd, qref, vref, tau, gain);
         }
         float Rl[9], pl[3], vl[6], bl[6];
@@ -1394,7 +1458,7 @@ __device__ __attribute__((always_inline)) void chain_item(const DevInst& I, int 
   float* red = att + M.n_att * kAtt;
 
   if (I.generate) {
-    sample_group<GC>(M, I, valid ? n : 0, l, knots, valid);
+    sample_group<GC>(M, I, valid ? n : 0, l, knots, valid, tab);
   } else {
     const float* src = I.samples + (size_t)(valid ? n : 0) * I.E;
     for (int e = l; e < I.E; e += GC) knots[e] = src[e];
@@ -1680,26 +1744,35 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
 }
 
 // Warm start (Sec. III-E): the knots of a trajectory shifted forward by n_steps
-// control steps, i.e. its Hermite spline at t_k + n_steps dt clamped to the
-// horizon end (the final action repeats).  In fine steps of the horizon
-// (F = H n_sub) the knot time is k F / (K - 1), so the segment and remainder
-// come from the integer m = k F + n_steps n_sub (K - 1) = seg F + rem.
-// One thread per (knot, joint); in and out must not alias.
-__global__ void shift_knots_kernel(const float* __restrict__ in, float* __restrict__ out, int K, int nu, int F,
-                                   int nsub, int n_steps, float delta) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= K * nu) return;
-  const int k = i / nu, jj = i % nu;
-  const long long m = (long long)k * F + (long long)n_steps * nsub * (K - 1);
-  int seg = (int)(m / F), rem = (int)(m - (long long)seg * F);
-  if (seg > K - 2) {
-    seg = K - 2;
-    rem = F;
+// control steps, i.e. its spline at t_k + n_steps dt clamped to the horizon end
+// (the final action repeats).  In fine steps of the horizon (F = H n_sub) the
+// knot time is k F / (K - 1), so the segment and remainder come from the
+// integer m = k F + n_steps n_sub (K - 1) = seg F + rem.  Position-only spline
+// variants then take the slopes of the spline through the shifted positions.
+// One workgroup; in and out must not alias.
+constexpr int kShiftThreads = 256;
+__global__ __launch_bounds__(kShiftThreads) void shift_knots_kernel(const float* __restrict__ in,
+                                                                    float* __restrict__ out, int K, int nu, int F,
+                                                                    int nsub, int n_steps, float delta,
+                                                                    int spline_mode) {
+  __shared__ float dg[kMaxKnots];
+  for (int i = threadIdx.x; i < K * nu; i += kShiftThreads) {
+    const int k = i / nu, jj = i % nu;
+    const long long m = (long long)k * F + (long long)n_steps * nsub * (K - 1);
+    int seg = (int)(m / F), rem = (int)(m - (long long)seg * F);
+    if (seg > K - 2) {
+      seg = K - 2;
+      rem = F;
+    }
+    float q, v;
+    hermite(in, K, nu, F, delta, 1.f / delta, seg, rem, jj, &q, &v);
+    out[i] = q;
+    out[K * nu + i] = v;
   }
-  float q, v;
-  hermite(in, K, nu, F, delta, 1.f / delta, seg, rem, jj, &q, &v);
-  out[i] = q;
-  out[K * nu + i] = v;
+  if (spline_mode == 0) return;
+  if (threadIdx.x == 0 && spline_mode == 1) natural_cubic_diagonal(K, dg);
+  __syncthreads();
+  for (int jj = threadIdx.x; jj < nu; jj += kShiftThreads) position_spline_slopes(spline_mode, K, nu, jj, delta, dg, out);
 }
 
 // Copy per-call inputs (state, warm-start knots) into instance buffers.
@@ -1731,9 +1804,12 @@ __global__ __launch_bounds__(64) void sample_kernel(const DevInst* __restrict__ 
   constexpr int R = 64 / G;
   const int lane = threadIdx.x, grp = lane / G, l = lane % G;
   const DevInst& I = *inst;
+  float* tab = smem;  // spline diagonal only
+  if (I.spline_mode == 1 && lane == 0) natural_cubic_diagonal(I.K, tab + kTabSpline);
+  wave_sync();
   const int n = blockIdx.x * R + grp;
-  float* knots = smem + grp * group_stride + G * kSlot + 16;
-  sample_group<G>(*I.model, I, n < I.N ? n : 0, l, knots, n < I.N);
+  float* knots = smem + kTabContacts + grp * group_stride + G * kSlot + 16;
+  sample_group<G>(*I.model, I, n < I.N ? n : 0, l, knots, n < I.N, tab);
 }
 
 template <int G>

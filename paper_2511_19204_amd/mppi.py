@@ -48,7 +48,7 @@ class Params(C.Structure):
         ("w_or", C.c_float), ("w_q", C.c_float), ("w_cv", C.c_float), ("w_cf", C.c_float),
         ("w_eff", C.c_float), ("w_H", C.c_float), ("w_ee", C.c_float), ("w_tau", C.c_float),
         ("z_des", C.c_float), ("v_des", C.c_float * 3), ("f0z", C.POINTER(C.c_float)),
-        ("q0_cost", C.POINTER(C.c_float)),
+        ("q0_cost", C.POINTER(C.c_float)), ("spline_mode", C.c_int32),
     ]
 
 
@@ -229,6 +229,7 @@ def make_params(p):
         s.v_des[k] = float(p["v_des"][k])
     f0, s.f0z = _farr(p["f0z"] if len(p["f0z"]) else [0.0])
     q0, s.q0_cost = _farr(p["q0_cost"])
+    s.spline_mode = int(p.get("spline_mode", 0))
     return s, (f0, q0)
 
 
