@@ -164,8 +164,18 @@ struct BodyConst {
   float p_tree[3], axis_p[3], com[3], Ic[6];
   float mass, kp, kd, taumax, arm, q0;
   int parent, depth, n_child, c_begin, c_count;
-  uint32_t child_lo, child_hi;  // child body indices, 8 bits each, child-list order
+  uint32_t child_lo, child_hi;  // children reached through LDS, 8 bits each, child-list order
+  uint32_t flags;               // kAdjParent | kAdjChild | kFrameOut | kArtOut
 };
+
+// Transfers between a body and its first child in a depth-first numbering go
+// through registers: the child (body b + 1) sits in the next lane, so one
+// wavefront-wide shift by one lane moves a frame, an acceleration or an
+// articulated inertia.  Other parent/child pairs go through the LDS slots.
+constexpr uint32_t kAdjParent = 1u;  // joint body whose parent is the previous lane (a joint body)
+constexpr uint32_t kAdjChild = 2u;   // first child is the next lane
+constexpr uint32_t kFrameOut = 4u;   // joint body with a child that reads its frame and acceleration from LDS
+constexpr uint32_t kArtOut = 8u;     // joint body whose parent reads its articulated inertia from LDS
 
 __device__ __forceinline__ void load_body(const DevModel& M, const DevInst* I, int b, bool body_lane, BodyConst& c) {
   const int bb = body_lane ? b : 0;
@@ -189,18 +199,40 @@ __device__ __forceinline__ void load_body(const DevModel& M, const DevInst* I, i
   c.q0 = (joint && I && I->cost_kind == 1) ? I->q0[j] : 0.f;
   c.parent = M.parent[bb];
   c.depth = body_lane ? M.depth[bb] : -1;
-  c.n_child = body_lane ? M.n_child[bb] : 0;
   c.c_begin = M.c_begin[bb];
   c.c_count = body_lane ? M.c_count[bb] : 0;
+  // children are numbered after their parent in increasing order, so body b + 1,
+  // when it is a child of b, is b's first child
+  const int par = body_lane ? M.parent[bb] : -1;
+  const int nch = body_lane ? M.n_child[bb] : 0;
+  const bool adj_child = nch > 0 && M.child[bb][0] == bb + 1;
+  c.flags = 0u;
+  if (adj_child) c.flags |= kAdjChild;
+  if (joint && par >= 0 && par == bb - 1 && !(M.fb && par == 0)) c.flags |= kAdjParent;
+  if (joint && par >= 0 && bb != par + 1) c.flags |= kArtOut;
+  c.n_child = 0;
   c.child_lo = c.child_hi = 0u;
-  for (int k = 0; k < c.n_child; ++k) {
-    const uint32_t ch = (uint32_t)M.child[bb][k] & 0xffu;
-    if (k < 4) c.child_lo |= ch << (8 * k);
-    else c.child_hi |= ch << (8 * (k - 4));
+  for (int k = 0; k < nch; ++k) {
+    const int chb = M.child[bb][k];
+    if (joint && chb != bb + 1) c.flags |= kFrameOut;
+    if (k == 0 && adj_child) continue;
+    const uint32_t ch = (uint32_t)chb & 0xffu;
+    if (c.n_child < 4) c.child_lo |= ch << (8 * c.n_child);
+    else c.child_hi |= ch << (8 * (c.n_child - 4));
+    ++c.n_child;
   }
 }
 __device__ __forceinline__ int child_of(const BodyConst& c, int k) {
   return (int)(((k < 4 ? c.child_lo : c.child_hi) >> (8 * (k & 3))) & 0xffu);
+}
+
+// value held by the previous / next lane of the wavefront (DPP wave shift by one
+// lane; every lane must be active; lanes past the wavefront's ends read 0)
+__device__ __forceinline__ float from_prev_lane(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_next_lane(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x130, 0xf, 0xf, true));
 }
 
 // motion vector m given about point O, re-expressed about O + e: (w, v + w x e)
@@ -213,7 +245,8 @@ __device__ __forceinline__ void shift_motion(const float* m, const float* e, flo
 
 // Articulated inertia I (packed) about the child origin carried to the parent
 // origin, e = child origin - parent origin: with E = e^x,
-// A' = A - B E - (B E)^T - E C E,  B' = B + E C,  C' = C.
+// C' = C,  B' = B + E C,  A' = A - B E - (B E)^T - E C E = A - B' E - (B E)^T
+// (row r of X E is row r of X crossed with e).
 __device__ __forceinline__ void shift_inertia_to_parent(const float* I, const float* e, float* O) {
   float B[9], C[9];
 #pragma unroll
@@ -223,31 +256,28 @@ __device__ __forceinline__ void shift_inertia_to_parent(const float* I, const fl
       B[r * 3 + c] = I[SI(r, c + 3)];
       C[r * 3 + c] = I[SI(r + 3, c + 3)];
     }
-  // BE: row r of B crossed with e
-  float BE[9];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) cross3(B + r * 3, e, BE + r * 3);
-  // EC: column k of C is e x C[:, k]
-  float EC[9];
+  // B' = B + E C: column k of E C is e x C[:, k]
+  float Bp[9];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const float col[3] = {C[k], C[3 + k], C[6 + k]};
     float o[3];
     cross3(e, col, o);
-    EC[k] = o[0]; EC[3 + k] = o[1]; EC[6 + k] = o[2];
+    Bp[k] = B[k] + o[0]; Bp[3 + k] = B[3 + k] + o[1]; Bp[6 + k] = B[6 + k] + o[2];
   }
-  // ECE: row r of EC crossed with e
-  float ECE[9];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) cross3(EC + r * 3, e, ECE + r * 3);
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = r; c < 3; ++c) O[SI(r, c)] = I[SI(r, c)] - BE[r * 3 + c] - BE[c * 3 + r] - ECE[r * 3 + c];
+  // (x cross e)[c] = x[c+1] e[c+2] - x[c+2] e[c+1]
+  auto xe = [&](const float* x, int c) {
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    return x[c1] * e[c2] - x[c2] * e[c1];
+  };
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) O[SI(r, c + 3)] = B[r * 3 + c] + EC[r * 3 + c];
+    for (int c = r; c < 3; ++c) O[SI(r, c)] = I[SI(r, c)] - xe(Bp + r * 3, c) - xe(B + c * 3, r);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) O[SI(r, c + 3)] = Bp[r * 3 + c];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -604,11 +634,15 @@ __device__ __forceinline__ void backward_joint(const float* IA, const float* pA,
   const float Dv = (arm + gain) + (ax[0] * U[0] + ax[1] * U[1] + ax[2] * U[2]);
   invD = rcp(Dv);
   u = tau - (ax[0] * pA[0] + ax[1] * pA[1] + ax[2] * pA[2]);
+  // Ia = IA - U U^T / D, with W = U / D
+  float W[6];
+#pragma unroll
+  for (int r = 0; r < 6; ++r) W[r] = U[r] * invD;
   float Ia[21];
 #pragma unroll
   for (int r = 0; r < 6; ++r)
 #pragma unroll
-    for (int cc = r; cc < 6; ++cc) Ia[SI(r, cc)] = IA[SI(r, cc)] - U[r] * U[cc] * invD;
+    for (int cc = r; cc < 6; ++cc) Ia[SI(r, cc)] = IA[SI(r, cc)] - U[r] * W[cc];
   float Iac[6];
   sym6_mv(Ia, c, Iac);
   const float uD = u * invD;
@@ -729,11 +763,19 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   }
   float cq = 0.f, sq = 0.f;
   if (is_joint) sincosf(io.q, &sq, &cq);
+  float sR[9], sp[3], sv[6], sb[6];  // the previous lane's frame
   for (int d = 1; d <= sc.max_depth; ++d) {
     if (is_joint && depth == d) {
       const int lam = bc.parent;
       float Rl[9], pl[3], vl[6], bl[6];
-      if (lam >= 0) {
+      if (bc.flags & kAdjParent) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Rl[k] = sR[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pl[k] = sp[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { vl[k] = sv[k]; bl[k] = sb[k]; }
+      } else if (lam >= 0) {
         get_frame(slots + lam * kSlot, Rl, pl, vl, bl);
       } else {
 #pragma unroll
@@ -744,9 +786,17 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
         for (int k = 0; k < 6; ++k) { vl[k] = 0.f; bl[k] = 0.f; }
       }
       fk_joint(Rl, pl, vl, bl, bc.P, bc.p_tree, bc.axis_p, cq, sq, io.v, R, p, e, ax, v, c, beta);
-      put_frame(slots + b * kSlot, R, p, v, beta);
+      if (bc.flags & kFrameOut) put_frame(slots + b * kSlot, R, p, v, beta);
     }
     wave_sync();
+    if (d < sc.max_depth) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sR[k] = from_prev_lane(R[k]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sp[k] = from_prev_lane(p[k]);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) { sv[k] = from_prev_lane(v[k]); sb[k] = from_prev_lane(beta[k]); }
+    }
   }
 
   // ---- rigid-body inertia, bias force, contacts (all body lanes in parallel)
@@ -797,17 +847,29 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // ---- backward sweep, leaves to root: each joint lane publishes its
   //      articulated inertia and bias already carried to its parent's origin
   float U[6], invD = 0.f, u = 0.f;
+  float Ip[21], pp[6], sI[21], spp[6];  // this lane's and the next lane's carried inertia and bias
   for (int d = sc.max_depth; d >= 0; --d) {
     if (body_lane && depth == d) {
+      if (bc.flags & kAdjChild) {
+#pragma unroll
+        for (int q = 0; q < 21; ++q) IA[q] += sI[q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) pA[q] += spp[q];
+      }
       const int nch = bc.n_child;
       for (int k = 0; k < nch; ++k) add_art(slots + child_of(bc, k) * kSlot, IA, pA);
       if (is_joint) {
-        float Ip[21], pp[6];
         backward_joint(IA, pA, ax, c, e, tau, bc.arm, gain, U, invD, u, Ip, pp);
-        put_art(slots + b * kSlot, Ip, pp);
+        if (bc.flags & kArtOut) put_art(slots + b * kSlot, Ip, pp);
       }
     }
     wave_sync();
+    if (d > 0) {
+#pragma unroll
+      for (int q = 0; q < 21; ++q) sI[q] = from_next_lane(Ip[q]);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) spp[q] = from_next_lane(pp[q]);
+    }
   }
 
   // ---- root: floating base solves IA0 a0' = -pA0 (Cholesky); fixed roots use -a_g
@@ -822,21 +884,28 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
 
   // ---- forward sweep: accelerations, root to leaves
   float qdd = 0.f;
+  float a[6], sa[6];  // this lane's and the previous lane's acceleration
   for (int d = 1; d <= sc.max_depth; ++d) {
     if (is_joint && depth == d) {
       const int lam = bc.parent;
       float al[6];
-      if (lam >= 0) {
+      if (bc.flags & kAdjParent) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) al[k] = sa[k];
+      } else if (lam >= 0) {
         get_acc(slots + lam * kSlot, al);
       } else {
         // fixed world: a' = -a_g = (0, 0, 0, 0, 0, g); its angular part is zero, so no shift term
         al[0] = al[1] = al[2] = 0.f; al[3] = 0.f; al[4] = 0.f; al[5] = g;
       }
-      float a[6];
       qdd = forward_joint(al, e, c, U, u, invD, ax, a);
-      put_acc(slots + b * kSlot, a);
+      if (bc.flags & kFrameOut) put_acc(slots + b * kSlot, a);
     }
     wave_sync();
+    if (d < sc.max_depth) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) sa[k] = from_prev_lane(a[k]);
+    }
   }
   io.qdd = qdd;
 }
