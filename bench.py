@@ -215,9 +215,13 @@ def closed_loop(args, torch, mppi, synth):
 
 def serving(args, torch, mppi, synth, mode):
     """Poisson MPC ticks (50 Hz per robot) from the 64-robot mix, served by the
-    continuous-batching server (mode "batched") or by plain per-instance steps
+    continuous-batching server (mode "batched") or by plain per-instance ticks
     (mode "plain"); at most one outstanding tick per robot, so a tick that arrives
-    while the robot's previous one runs waits, and its latency counts from arrival."""
+    while the robot's previous one runs waits, and its latency counts from arrival.
+    Each tick is a full mppi_tick: the measured state (the robot's x0) is predicted
+    forward by the robot's previous tick latency rounded up to control steps,
+    tau_best (on the device) is shifted into the warm start, and the iterations
+    replace it."""
     robots = synth.serving_mix(args.robots, seed=0)
     ticks = synth.poisson_ticks(len(robots), args.serve_seconds, rate_hz=50.0, seed=0)
     made = []
@@ -227,9 +231,12 @@ def serving(args, torch, mppi, synth, mode):
         st = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
         k = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
         made.append((model, c, st, k, p["n_samples"] * p["horizon"] * p["n_iters"]))
+    dts = [p["dt"] for (m, p, seed) in robots]
+    Hs = [p["horizon"] for (m, p, seed) in robots]
+    delay = [1] * len(made)
     srv = mppi.Server(n_streams=args.serve_streams, max_batch=len(made), mode=mode)
     # warm-up: one tick per robot
-    tk = [srv.submit(c, st, k, k) for (_, c, st, k, _) in made]
+    tk = [srv.submit_tick(c, st, 1, k) for (_, c, st, k, _) in made]
     srv.drain()
     for t in tk:
         srv.poll(t)
@@ -243,13 +250,14 @@ def serving(args, torch, mppi, synth, mode):
         for i, (_, c, st, k, w) in enumerate(made):
             if i not in live and nxt[i] < len(ticks[i]) and ticks[i][nxt[i]] <= now:
                 arrival = ticks[i][nxt[i]]
-                live[i] = (srv.submit(c, st, k, k), arrival, time.perf_counter() - t0, w)
+                live[i] = (srv.submit_tick(c, st, delay[i], k), arrival, time.perf_counter() - t0, w)
                 nxt[i] += 1
         for i in list(live):
             ticket, arrival, sub, w = live[i]
             srv_lat = srv.poll(ticket)
             if srv_lat is not None:
                 lat.append((sub - arrival) + srv_lat)
+                delay[i] = min(Hs[i], max(1, int(np.ceil(srv_lat / dts[i]))))
                 work_done += w
                 del live[i]
         if not live and all(nxt[i] >= len(ticks[i]) for i in range(len(made))):

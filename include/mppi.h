@@ -279,6 +279,17 @@ mppi_status mppi_server_create(const mppi_server_cfg* cfg, mppi_server** out);
 /* Non-blocking; *ticket identifies the tick.  MPPI_ENOSLOT when the queue is full. */
 mppi_status mppi_server_submit(mppi_server* s, mppi_ctx* c, const float* d_state, const float* d_knots_in,
                                float* d_knots_out, uint64_t* ticket);
+/* A tick as mppi_tick (state prediction and warm-start shift of Sec. III-E, then
+ * the iterations of Alg. 1), served like mppi_server_submit: the measured state
+ * d_state_meas is carried n_delay (0..H) control steps along d_best, d_best
+ * shifted by n_delay actions is the warm start, and the best trajectory of the
+ * iterations replaces d_best (device, [2][K][n_u], owned by the caller).
+ * d_knots_out (nominal after the last iteration) and d_info are nullable.  In a
+ * batch the prefixes run on the batch's stream before its fused iterations; the
+ * result equals the instance's own mppi_tick.  MPPI_EINVAL for a delay outside
+ * 0..H, MPPI_ENOSLOT when the queue is full. */
+mppi_status mppi_server_submit_tick(mppi_server* s, mppi_ctx* c, const float* d_state_meas, int32_t n_delay,
+                                    float* d_best, float* d_knots_out, mppi_step_info* d_info, uint64_t* ticket);
 /* *done = 1 once the tick's outputs are complete on the device; then *latency_s is
  * submit-to-completion wall time and the ticket is released. */
 mppi_status mppi_server_poll(mppi_server* s, uint64_t ticket, int32_t* done, double* latency_s);

@@ -5,8 +5,15 @@ library next to this file.  Packed-FP32 instruction selection is disabled
 (-packed-fp32-ops) and fast-math is off; multiply-adds are contracted within one
 expression only (-ffp-contract=on), so an inlined helper rounds the same way
 in every kernel that uses it.
+
+The compiler's per-kernel resource remarks are checked: no kernel may use
+scratch memory (register spills), and the body-schedule rollout kernel must fit
+two wavefronts per SIMD (at most 256 VGPRs), which launches of more than one
+wavefront per SIMD rely on (the persistent form sizes its grid to the occupancy
+it gets).
 """
 import os
+import re
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -22,20 +29,50 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          "-I", os.path.join(ROOT, "include")]
 
 
+def resource_usage(remarks: str) -> dict:
+    """{kernel: {"VGPRs": n, "AGPRs": n, "ScratchSize": n, "Occupancy": n}} from
+    -Rpass-analysis=kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for ln in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", ln)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark:\s+(VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]): (\d+)", ln)
+        if m and cur is not None:
+            cur[m.group(1).split()[0]] = int(m.group(2))
+    return out
+
+
+def check_resources(usage: dict) -> None:
+    bad = []
+    for name, u in usage.items():
+        if u.get("ScratchSize", 0) != 0:
+            bad.append(f"{name}: {u['ScratchSize']} bytes/lane of scratch (register spills)")
+        if "rollout_kernel" in name and "persistent" not in name and u.get("Occupancy", 0) < 2:
+            bad.append(f"{name}: {u.get('VGPRs')} VGPRs + {u.get('AGPRs')} AGPRs, occupancy {u.get('Occupancy')} < 2")
+    if not usage:
+        bad.append("no kernel resource remarks were produced")
+    if bad:
+        raise RuntimeError("kernel resource check failed:\n" + "\n".join(bad))
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
     if not force and os.path.exists(LIB):
         mt = os.path.getmtime(LIB)
         if all(os.path.getmtime(f) <= mt for f in SOURCES + HEADERS):
             return LIB
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, *SOURCES, "-o", tmp]
+    cmd = ["hipcc", *FLAGS, "-Rpass-analysis=kernel-resource-usage", *SOURCES, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
-    noise = "packed-fp32-ops"
-    msgs = [ln for ln in (res.stdout + res.stderr).splitlines() if noise not in ln and ln.strip()]
+    noise = ("packed-fp32-ops", "kernel-resource-usage")
+    msgs = [ln for ln in (res.stdout + res.stderr).splitlines()
+            if not any(n in ln for n in noise) and ln.strip() and not ln.startswith(" ") and ln.strip() != "^"]
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
     if verbose and msgs:
         print("\n".join(msgs))
+    check_resources(resource_usage(res.stderr))
     os.replace(tmp, LIB)
     return LIB
 

@@ -772,11 +772,11 @@ extern "C" mppi_status mppi_shift_knots(mppi_ctx* c, const float* d_knots_in, in
   return launch_shift(c, c->pred_knots, n_steps, d_knots_out, s);
 }
 
-extern "C" mppi_status mppi_tick(mppi_ctx* c, const float* d_state_meas, int32_t n_delay, float* d_best,
-                                 float* d_knots_out, mppi_step_info* d_info, float* d_state_pred, void* stream) {
-  if (!c || !d_state_meas || !d_best) return fail(MPPI_EINVAL, "null argument");
-  if (n_delay < 0 || n_delay > c->H) return fail(MPPI_EINVAL, "n_delay must be in 0..horizon");
-  hipStream_t s = (hipStream_t)stream;
+// The part of a tick before the iterations: the instance's x0 becomes the
+// measured state carried n_delay control steps along tau_best, and its nominal
+// becomes tau_best shifted by n_delay actions.
+static mppi_status tick_prefix(mppi_ctx* c, const float* d_state_meas, int32_t n_delay, const float* d_best,
+                               float* d_state_pred, hipStream_t s) {
   const size_t nx = (size_t)(c->nq + c->nv) * sizeof(float);
   // x_t: the measured state carried n_delay control steps along tau_best
   HIP_TRY(hipMemcpyAsync(c->x_meas, d_state_meas, nx, hipMemcpyDeviceToDevice, s));
@@ -789,7 +789,15 @@ extern "C" mppi_status mppi_tick(mppi_ctx* c, const float* d_state_meas, int32_t
   }
   if (d_state_pred) HIP_TRY(hipMemcpyAsync(d_state_pred, c->x0, nx, hipMemcpyDeviceToDevice, s));
   // tau_0 <- tau_best shifted by n_delay actions (final action repeated)
-  mppi_status st = launch_shift(c, c->pred_knots, n_delay, c->nom, s);
+  return launch_shift(c, c->pred_knots, n_delay, c->nom, s);
+}
+
+extern "C" mppi_status mppi_tick(mppi_ctx* c, const float* d_state_meas, int32_t n_delay, float* d_best,
+                                 float* d_knots_out, mppi_step_info* d_info, float* d_state_pred, void* stream) {
+  if (!c || !d_state_meas || !d_best) return fail(MPPI_EINVAL, "null argument");
+  if (n_delay < 0 || n_delay > c->H) return fail(MPPI_EINVAL, "n_delay must be in 0..horizon");
+  hipStream_t s = (hipStream_t)stream;
+  mppi_status st = tick_prefix(c, d_state_meas, n_delay, d_best, d_state_pred, s);
   if (st != MPPI_OK) return st;
   // I iterations; the best simulated trajectory replaces tau_best
   float* nominal_out = d_knots_out ? d_knots_out : c->pred_knots;  // consumed by the shift already
@@ -1352,9 +1360,12 @@ extern "C" mppi_status mppi_profile_read(mppi_ctx* c, double* rollout_ms, int32_
 // ---------------------------------------------------------------------------
 struct BatchReq {
   mppi_ctx* ctx;
-  const float* state;
+  const float* state;     // nullptr: the instance's x0 and nominal are already in place (a tick)
   const float* knots_in;
-  float* knots_out;
+  float* knots_out;       // outputs of the last iteration (each nullable)
+  float* best_out = nullptr;        // set for a tick (tau_best, in/out)
+  mppi_step_info* info_out = nullptr;
+  int32_t n_delay = 0;              // a tick's prediction steps
 };
 
 static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsigned int* counters, int n_counters,
@@ -1397,8 +1408,9 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   char* dv = reinterpret_cast<char*>(r->dev);
   auto* items = reinterpret_cast<StageItem*>(h);
   for (int i = 0; i < n; ++i) {
-    items[2 * i] = StageItem{reqs[i].state, reqs[i].ctx->x0, reqs[i].ctx->nq + reqs[i].ctx->nv};
-    items[2 * i + 1] = StageItem{reqs[i].knots_in, reqs[i].ctx->nom, reqs[i].ctx->E};
+    const bool staged = reqs[i].state == nullptr;
+    items[2 * i] = StageItem{reqs[i].state, reqs[i].ctx->x0, staged ? 0 : reqs[i].ctx->nq + reqs[i].ctx->nv};
+    items[2 * i + 1] = StageItem{reqs[i].knots_in, reqs[i].ctx->nom, staged ? 0 : reqs[i].ctx->E};
   }
   for (int it = 0; it < Imax; ++it) {
     IterDesc& d = iters[it];
@@ -1409,7 +1421,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
       const BatchReq& q = reqs[active[it][a]];
       hi[a] = q.ctx->h_insts[it];
       hu[a] = q.ctx->h_ups[it];
-      ho[a] = q.ctx->I - 1 == it ? UpdateOut{q.knots_out, nullptr, nullptr} : UpdateOut{nullptr, nullptr, nullptr};
+      ho[a] = q.ctx->I - 1 == it ? UpdateOut{q.knots_out, q.best_out, q.info_out} : UpdateOut{nullptr, nullptr, nullptr};
     }
     std::map<int, std::vector<int>> byG;
     for (int a = 0; a < d.n_active; ++a) byG[reqs[active[it][a]].ctx->lanes].push_back(a);
@@ -1461,11 +1473,15 @@ using Clock = std::chrono::steady_clock;
 struct SrvReq {
   mppi_ctx* ctx;
   const float* state;
-  const float* knots_in;
+  const float* knots_in;  // a step's warm start; nullptr for a tick
   float* knots_out;
   Clock::time_point t_submit;
   double latency = 0;
   int status = 0;  // 0 pending, 1 on the device, 2 done
+  // a tick (mppi_tick): delay in control steps, tau_best (in/out), step info
+  int32_t n_delay = 0;
+  float* best = nullptr;
+  mppi_step_info* info = nullptr;
 };
 struct SrvSlot {
   hipStream_t stream = nullptr;
@@ -1523,7 +1539,10 @@ static void server_loop(mppi_server* S) {
           if (S->busy.count(r.ctx)) { ++it; continue; }
           S->busy[r.ctx] = 1;
           r.status = 1;
-          batch.push_back(BatchReq{r.ctx, r.state, r.knots_in, r.knots_out});
+          if (r.best)  // a tick: its prefix runs first, then the iterations read x0 and the nominal in place
+            batch.push_back(BatchReq{r.ctx, r.state, nullptr, r.knots_out, r.best, r.info, r.n_delay});
+          else
+            batch.push_back(BatchReq{r.ctx, r.state, r.knots_in, r.knots_out});
           sl.tickets.push_back(*it);
           it = S->pending.erase(it);
         }
@@ -1532,12 +1551,24 @@ static void server_loop(mppi_server* S) {
       mppi_status st = MPPI_OK;
       if (S->cfg.mode == 1) {
         for (auto& b : batch) {
-          st = mppi_step(b.ctx, b.state, b.knots_in, b.knots_out, nullptr, nullptr, nullptr, sl.stream);
+          if (b.best_out)
+            st = mppi_tick(b.ctx, b.state, b.n_delay, b.best_out, b.knots_out, b.info_out, nullptr, sl.stream);
+          else
+            st = mppi_step(b.ctx, b.state, b.knots_in, b.knots_out, nullptr, nullptr, nullptr, sl.stream);
           if (st != MPPI_OK) break;
         }
       } else {
-        std::lock_guard<std::mutex> lk(g_mu);
-        st = launch_batch_dynamic(batch, sl.counters, 64 * 5, S->cfg.persistent != 0, sl.stream);
+        for (auto& b : batch) {
+          if (!b.best_out) continue;
+          st = tick_prefix(b.ctx, b.state, b.n_delay, b.best_out, nullptr, sl.stream);
+          if (st != MPPI_OK) break;
+          b.state = nullptr;
+          if (!b.knots_out) b.knots_out = b.ctx->pred_knots;  // as mppi_tick: consumed by the shift already
+        }
+        if (st == MPPI_OK) {
+          std::lock_guard<std::mutex> lk(g_mu);
+          st = launch_batch_dynamic(batch, sl.counters, 64 * 5, S->cfg.persistent != 0, sl.stream);
+        }
       }
       if (st == MPPI_OK && hipEventRecord(sl.ev, sl.stream) != hipSuccess) st = MPPI_EDEVICE;
       if (st != MPPI_OK) {
@@ -1585,6 +1616,26 @@ extern "C" mppi_status mppi_server_submit(mppi_server* S, mppi_ctx* c, const flo
   if ((int)S->pending.size() >= S->cfg.max_pending) return fail(MPPI_ENOSLOT, "pending queue full");
   const uint64_t t = S->next_ticket++;
   S->reqs[t] = SrvReq{c, d_state, d_knots_in, d_knots_out, Clock::now()};
+  S->pending.push_back(t);
+  *ticket = t;
+  S->cv.notify_one();
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_server_submit_tick(mppi_server* S, mppi_ctx* c, const float* d_state_meas,
+                                               int32_t n_delay, float* d_best, float* d_knots_out,
+                                               mppi_step_info* d_info, uint64_t* ticket) {
+  if (!S || !c || !d_state_meas || !d_best || !ticket) return fail(MPPI_EINVAL, "null argument");
+  if (n_delay < 0 || n_delay > c->H) return fail(MPPI_EINVAL, "n_delay must be in 0..horizon");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stop) return fail(MPPI_EDEVICE, "server stopped: " + S->error);
+  if ((int)S->pending.size() >= S->cfg.max_pending) return fail(MPPI_ENOSLOT, "pending queue full");
+  const uint64_t t = S->next_ticket++;
+  SrvReq r{c, d_state_meas, nullptr, d_knots_out, Clock::now()};
+  r.n_delay = n_delay;
+  r.best = d_best;
+  r.info = d_info;
+  S->reqs[t] = r;
   S->pending.push_back(t);
   *ticket = t;
   S->cv.notify_one();

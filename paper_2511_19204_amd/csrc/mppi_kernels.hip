@@ -763,8 +763,16 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   }
   float cq = 0.f, sq = 0.f;
   if (is_joint) sincosf(io.q, &sq, &cq);
-  float sR[9], sp[3], sv[6], sb[6];  // the previous lane's frame
   for (int d = 1; d <= sc.max_depth; ++d) {
+    float sR[9], sp[3], sv[6], sb[6];  // the previous lane's frame (level d - 1)
+    if (d > 1) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sR[k] = from_prev_lane(R[k]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sp[k] = from_prev_lane(p[k]);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) { sv[k] = from_prev_lane(v[k]); sb[k] = from_prev_lane(beta[k]); }
+    }
     if (is_joint && depth == d) {
       const int lam = bc.parent;
       float Rl[9], pl[3], vl[6], bl[6];
@@ -789,14 +797,6 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
       if (bc.flags & kFrameOut) put_frame(slots + b * kSlot, R, p, v, beta);
     }
     wave_sync();
-    if (d < sc.max_depth) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) sR[k] = from_prev_lane(R[k]);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) sp[k] = from_prev_lane(p[k]);
-#pragma unroll
-      for (int k = 0; k < 6; ++k) { sv[k] = from_prev_lane(v[k]); sb[k] = from_prev_lane(beta[k]); }
-    }
   }
 
   // ---- rigid-body inertia, bias force, contacts (all body lanes in parallel)
@@ -847,15 +847,14 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // ---- backward sweep, leaves to root: each joint lane publishes its
   //      articulated inertia and bias already carried to its parent's origin
   float U[6], invD = 0.f, u = 0.f;
-  float Ip[21], pp[6], sI[21], spp[6];  // this lane's and the next lane's carried inertia and bias
   for (int d = sc.max_depth; d >= 0; --d) {
+    // inertia and bias carried to the parent by the lanes of level d (any value elsewhere)
+    float Ip[21], pp[6];
+#pragma unroll
+    for (int q = 0; q < 21; ++q) Ip[q] = __builtin_nondeterministic_value(0.f);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) pp[q] = __builtin_nondeterministic_value(0.f);
     if (body_lane && depth == d) {
-      if (bc.flags & kAdjChild) {
-#pragma unroll
-        for (int q = 0; q < 21; ++q) IA[q] += sI[q];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) pA[q] += spp[q];
-      }
       const int nch = bc.n_child;
       for (int k = 0; k < nch; ++k) add_art(slots + child_of(bc, k) * kSlot, IA, pA);
       if (is_joint) {
@@ -865,10 +864,18 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
     }
     wave_sync();
     if (d > 0) {
+      // a parent at level d - 1 adds its first child's contribution first, then the others'
+      float sI[21], spp[6];
 #pragma unroll
       for (int q = 0; q < 21; ++q) sI[q] = from_next_lane(Ip[q]);
 #pragma unroll
       for (int q = 0; q < 6; ++q) spp[q] = from_next_lane(pp[q]);
+      if (body_lane && depth == d - 1 && (bc.flags & kAdjChild)) {
+#pragma unroll
+        for (int q = 0; q < 21; ++q) IA[q] += sI[q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) pA[q] += spp[q];
+      }
     }
   }
 
@@ -1170,7 +1177,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 // Block = one wavefront; work[blockIdx] = (instance, first sample) or, when work
 // is null, instance 0 and sample blockIdx * 64/G.
 template <int G>
-__global__ __launch_bounds__(64) void rollout_kernel(const DevInst* __restrict__ insts, const int2* __restrict__ work,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_kernel(const DevInst* __restrict__ insts, const int2* __restrict__ work,
                                                      int group_stride, int table_floats) {
   extern __shared__ float smem[];
   constexpr int R = 64 / G;

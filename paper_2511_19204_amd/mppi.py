@@ -67,7 +67,7 @@ EXPORTS = [
     "mppi_step_batch", "mppi_debug_philox", "mppi_debug_samples", "mppi_debug_dynamics",
     "mppi_debug_rollouts", "mppi_debug_update", "mppi_profile_enable", "mppi_profile_read",
     "mppi_set_batch_options", "mppi_graph_create", "mppi_graph_launch", "mppi_graph_destroy",
-    "mppi_autotune", "mppi_server_create", "mppi_server_submit", "mppi_server_poll",
+    "mppi_autotune", "mppi_server_create", "mppi_server_submit", "mppi_server_submit_tick", "mppi_server_poll",
     "mppi_server_drain", "mppi_server_stats", "mppi_server_destroy",
     "mppi_last_error", "mppi_version",
 ]
@@ -119,6 +119,7 @@ def lib():
         L.mppi_autotune.argtypes = [vp, vp, vp, i32, vp, C.POINTER(i32)]
         L.mppi_server_create.argtypes = [C.POINTER(ServerCfg), C.POINTER(vp)]
         L.mppi_server_submit.argtypes = [vp, vp, vp, vp, vp, C.POINTER(u64)]
+        L.mppi_server_submit_tick.argtypes = [vp, vp, vp, i32, vp, vp, vp, C.POINTER(u64)]
         L.mppi_server_poll.argtypes = [vp, u64, C.POINTER(i32), C.POINTER(C.c_double)]
         L.mppi_server_drain.argtypes = [vp, C.c_double]
         L.mppi_server_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -415,6 +416,16 @@ class Server:
         t = C.c_uint64()
         _check(lib().mppi_server_submit(self.h, ctrl.h, _ptr(state), _ptr(knots_in), _ptr(knots_out),
                                         C.byref(t)), "mppi_server_submit")
+        return t.value
+
+    def submit_tick(self, ctrl, state, n_delay, best, knots_out=None, info=None):
+        """A tick as Controller.run_tick (prediction by n_delay control steps along
+        best, warm-start shift, iterations; best updated in place), served."""
+        t = C.c_uint64()
+        _check(lib().mppi_server_submit_tick(self.h, ctrl.h, _ptr(state), int(n_delay), _ptr(best),
+                                             _ptr(knots_out) if knots_out is not None else None,
+                                             _ptr(info) if info is not None else None, C.byref(t)),
+               "mppi_server_submit_tick")
         return t.value
 
     def poll(self, ticket):

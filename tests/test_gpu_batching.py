@@ -209,3 +209,72 @@ def test_server_three_streams_many_uneven_batches():
         assert requests == ticks * len(robots) and batches > 8
     finally:
         srv.close()
+
+
+def _tick_reference(robots, ticks, delay):
+    """Per-instance mppi_tick: (tau_best, nominal, step info) after each tick, the
+    measured state being x0 at every tick."""
+    refs = []
+    for i, (m, p, s, model, c) in enumerate(robots):
+        c.tick = 0
+        x = _t(m["x0"])
+        best = _t(synth.nominal_knots(m, p["n_knots"]))
+        seq = []
+        for t in range(ticks):
+            ko = torch.zeros_like(best)
+            info = torch.zeros(mppi.INFO_INTS, dtype=torch.int32, device="cuda")
+            c.run_tick(x, delay(i, t, p), best, ko, info)
+            torch.cuda.synchronize()
+            seq.append((best.cpu().numpy().copy(), ko.cpu().numpy(), info.cpu().numpy()))
+        refs.append(seq)
+    return refs
+
+
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_server_ticks_equal_the_instance_ticks(mode):
+    """Served ticks (prediction by a per-tick delay, warm-start shift, iterations,
+    tau_best carried on the device) of an uneven mix, submitted staggered with at
+    most one outstanding per robot: every robot's tau_best, nominal and step info
+    after every tick equal its own mppi_tick sequence bit for bit."""
+    robots = _robots(10, seed=5)
+    ticks = 3
+    delay = lambda i, t, p: (i + 2 * t) % 5 if t != 1 else p["horizon"]  # includes 0 and the full horizon
+    refs = _tick_reference(robots, ticks, delay)
+    srv = mppi.Server(n_streams=2, max_batch=6, mode=mode)
+    try:
+        for (*_, c) in robots:
+            c.tick = 0
+        xs = [_t(m["x0"]) for (m, *_rest) in robots]
+        bests = [_t(synth.nominal_knots(m, p["n_knots"])) for (m, p, *_r) in robots]
+        kos = [[torch.zeros_like(bests[i]) for _ in range(ticks)] for i in range(len(robots))]
+        infos = [[torch.zeros(mppi.INFO_INTS, dtype=torch.int32, device="cuda") for _ in range(ticks)]
+                 for _ in range(len(robots))]
+        got_best = [[None] * ticks for _ in range(len(robots))]
+        nxt = [0] * len(robots)
+        live = {}
+        rng = np.random.default_rng(2)
+        while any(n < ticks for n in nxt) or live:
+            for i in rng.permutation(len(robots)):
+                if i not in live and nxt[i] < ticks:
+                    t = nxt[i]
+                    p = robots[i][1]
+                    live[i] = (t, srv.submit_tick(robots[i][4], xs[i], delay(i, t, p), bests[i], kos[i][t],
+                                                  infos[i][t]))
+                    nxt[i] += 1
+            for i in list(live):
+                t, tk = live[i]
+                if srv.poll(tk) is not None:
+                    got_best[i][t] = bests[i].cpu().numpy().copy()
+                    del live[i]
+            time.sleep(2e-4)
+        srv.drain()
+        for i in range(len(robots)):
+            for t in range(ticks):
+                rb, rk, ri = refs[i][t]
+                assert np.array_equal(got_best[i][t], rb), (mode, i, t, "best")
+                assert np.array_equal(kos[i][t].cpu().numpy(), rk), (mode, i, t, "nominal")
+                assert np.array_equal(infos[i][t].cpu().numpy(), ri), (mode, i, t, "info")
+        with pytest.raises(mppi.MppiError):
+            srv.submit_tick(robots[0][4], xs[0], robots[0][1]["horizon"] + 1, bests[0])
+    finally:
+        srv.close()
