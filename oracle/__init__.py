@@ -55,7 +55,8 @@ class OrcParams(C.Structure):
         ("w_or", C.c_double), ("w_q", C.c_double), ("w_cv", C.c_double), ("w_cf", C.c_double),
         ("w_eff", C.c_double), ("w_H", C.c_double), ("w_ee", C.c_double), ("w_tau", C.c_double),
         ("z_des", C.c_double), ("v_des", C.c_double * 3), ("f0z", _dp),
-        ("q0_cost", _dp), ("spline_mode", C.c_int32),
+        ("q0_cost", _dp), ("spline_mode", C.c_int32), ("q_des", C.c_double * 4),
+        ("terminal_z_abs", C.c_int32), ("z_terminal", C.c_double),
     ]
 
 
@@ -156,6 +157,11 @@ class _Params:
         f0 = np.asarray(p.get("f0z", np.zeros(1)), dtype=np.float64).reshape(-1)
         self.f0, s.f0z = _d(f0 if f0.size else np.zeros(1))
         s.spline_mode = int(p.get("spline_mode", 0))
+        qd = p.get("q_des", (0.0, 0.0, 0.0, 0.0))
+        for k in range(4):
+            s.q_des[k] = float(qd[k])
+        s.terminal_z_abs = int(p.get("terminal_z_abs", 0))
+        s.z_terminal = float(p.get("z_terminal", 0.0))
         self.s = s
 
     @property

@@ -72,6 +72,9 @@ typedef struct {
   const double* f0z;      // [nc] reference normal force of each contact point
   const double* q0_cost;  // [n_u]
   int32_t spline_mode;    // 0 = cubic Hermite, 1 = natural cubic, 2 = quadratic (position-only, v_ref = 0)
+  double q_des[4];        // base orientation target R_des (w, x, y, z); all zero = identity
+  int32_t terminal_z_abs; // 1: the terminal target height is z_terminal instead of p_z(x0) + v_des,z H dt
+  double z_terminal;
 } orc_params;
 
 }  // extern "C"
@@ -846,6 +849,20 @@ template <class T> static T orientation_angle(const T* quat) {
   return 2 * std::atan2(vn, std::fabs(quat[0]));
 }
 
+// ||log3(R_base^T R_des)||: the rotation angle of the relative rotation, i.e. of
+// the quaternion conj(q_base) * q_des (Sec. IV-A, orientation residual); an
+// all-zero target stands for the identity.
+template <class T> static T orientation_error(const T* qb, const double* qd) {
+  const bool id = qd[0] == 0 && qd[1] == 0 && qd[2] == 0 && qd[3] == 0;
+  const T d0 = id ? T(1) : (T)qd[0], d1 = id ? T(0) : (T)qd[1], d2 = id ? T(0) : (T)qd[2], d3 = id ? T(0) : (T)qd[3];
+  // conj(qb) = (w, -x, -y, -z); Hamilton product with (d0, d1, d2, d3)
+  const T r[4] = {qb[0] * d0 + qb[1] * d1 + qb[2] * d2 + qb[3] * d3,
+                  qb[0] * d1 - qb[1] * d0 - qb[2] * d3 + qb[3] * d2,
+                  qb[0] * d2 + qb[1] * d3 - qb[2] * d0 - qb[3] * d1,
+                  qb[0] * d3 - qb[1] * d2 + qb[2] * d1 - qb[3] * d0};
+  return orientation_angle(r);
+}
+
 template <class T> static V3<T> point_world(const Kin<T>& K, int b, const V3<T>& r) {
   V3<T> pr = m3_v(K.Rw[b], r), p{};
   for (int k = 0; k < 3; ++k) p[k] = K.pw[b][k] + pr[k];
@@ -921,7 +938,7 @@ static T rollout(const Model<T>& M, const orc_params* p, const T* x0, const T* k
         T dz = ee[2] - (T)p->z_des;
         c = (T)p->w_ee * dz * dz + (T)p->w_tau * eff;
       } else {
-        T phi = orientation_angle(q.data() + 3);
+        T phi = orientation_error(q.data() + 3, p->q_des);
         T dq2 = 0;
         for (int j = 0; j < nu; ++j) {
           T e = q[qo + j] - (T)p->q0_cost[j];
@@ -951,7 +968,10 @@ static T rollout(const Model<T>& M, const orc_params* p, const T* x0, const T* k
     cT = (T)p->w_ee * dz * dz;
   } else {
     T Th = (T)(p->horizon * p->dt);
-    for (int k = 0; k < 3; ++k) cT += std::fabs(q[k] - (x0[k] + (T)p->v_des[k] * Th));
+    for (int k = 0; k < 3; ++k) {
+      const T target = (k == 2 && p->terminal_z_abs) ? (T)p->z_terminal : x0[k] + (T)p->v_des[k] * Th;
+      cT += std::fabs(q[k] - target);
+    }
     cT *= (T)p->w_H;
   }
   if (dbg.stage) dbg.stage[H] = cT;
