@@ -213,6 +213,66 @@ def closed_loop(args, torch, mppi, synth):
             "delay_steps_mean": float(np.mean(delays)), "failed_to_improve_frac": failed / len(lat)}
 
 
+def _angle(q1, q2):
+    """Rotation angle between two unit quaternions, radians."""
+    return 2.0 * float(np.arccos(min(1.0, abs(float(np.dot(q1, q2))))))
+
+
+def tasks(args, torch, mppi, synth):
+    """The tasks of Sec. IV-B (weights of Tab. cost-weights, targets as in synth)
+    in closed loop: every tick is mppi_tick with a one-step delay and the simulated
+    robot follows the plan (next state = the tick's one-step prediction).
+    Sampling as synth.TASK_SAMPLING.  Behavioural only: the synthetic robots are
+    not the paper's, so nothing here is compared with the paper's results.  The
+    jumping task's height target is a step in time that enters the horizon after
+    50 ticks."""
+    out = {}
+    for name in synth.TASKS:
+        base = "humanoid" if name == "bipedal" else "quadruped"
+        m, p, seed = synth.config(base)
+        p = synth.task_params(m, p, name)
+        p.update(synth.TASK_SAMPLING)
+        z_jump = p["z_terminal"]
+        if name == "jumping":
+            p["z_terminal"] = float(m["x0"][2])  # the step is not in the horizon yet
+        model = mppi.Model(m)
+        c = mppi.Controller(model, p, seed)
+        x = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
+        best = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
+        info = torch.zeros(mppi.INFO_INTS, dtype=torch.int32, device="cuda")
+        xp = torch.zeros_like(x)
+        q0 = np.asarray(m["x0"][3:7], float)
+        qd = np.asarray(p["q_des"], float) if any(p["q_des"]) else np.array([1.0, 0, 0, 0])
+        zs, rot, lat, failed = [], [], [], 0
+        t_step_on = 50
+        for t in range(args.task_ticks):
+            if name == "jumping" and t == t_step_on:
+                c.set_targets(terminal_z_abs=1, z_terminal=z_jump)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.run_tick(x, 1, best, None, info, xp)
+            inf = info.cpu().numpy()
+            lat.append((time.perf_counter() - t0) * 1e3)
+            failed += int(inf[1] == 0 and inf[4] == 0)
+            x, xp = xp, x
+            xs = x.cpu().numpy().astype(float)
+            zs.append(xs[2])
+            qn = xs[3:7] / np.linalg.norm(xs[3:7])
+            rot.append((_angle(q0, qn), _angle(qd, qn)))
+        zs, rot = np.asarray(zs), np.asarray(rot)
+        xs = x.cpu().numpy().astype(float)
+        T = args.task_ticks * p["dt"]
+        out[name] = {"robot": base, "K": p["n_samples"], "H": p["horizon"], "I": p["n_iters"], "ticks": args.task_ticks,
+                     "z0": float(m["x0"][2]), "z_max": float(zs.max()), "z_min": float(zs.min()),
+                     "vx_mean": float((xs[0] - m["x0"][0]) / T),
+                     "rotation_max_deg": float(np.rad2deg(rot[:, 0].max())),
+                     "target_error_final_deg": float(np.rad2deg(rot[-1, 1])),
+                     "failed_to_improve_frac": failed / args.task_ticks,
+                     "tick_ms_p50": float(np.percentile(lat, 50))}
+        c.close()
+    return out
+
+
 def serving(args, torch, mppi, synth, mode):
     """Poisson MPC ticks (50 Hz per robot) from the 64-robot mix, served by the
     continuous-batching server (mode "batched") or by plain per-instance ticks
@@ -323,6 +383,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-loop", action="store_true", help="skip the closed-loop tick run")
     ap.add_argument("--loop-ticks", type=int, default=200)
+    ap.add_argument("--no-tasks", action="store_true", help="skip the task presets in closed loop")
+    ap.add_argument("--task-ticks", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-streams", type=int, default=3)
@@ -356,6 +418,7 @@ def main():
                "robots": args.robots, "rate_hz": 50.0, "deadline_ms": 20.0,
                "seconds": args.serve_seconds}
     loop = None if args.no_loop else closed_loop(args, torch, mppi, synth)
+    task_res = None if args.no_tasks else tasks(args, torch, mppi, synth)
     cpu = None if args.no_cpu else cpu_baseline(args, res)
     digest = kernel_source_digest()
     traffic = measured_traffic(digest)
@@ -404,6 +467,7 @@ def main():
         "batched_vs_plain": bvp,
         "serving": srv,
         "closed_loop": loop,
+        "tasks": task_res,
     }
     print(json.dumps(out), flush=True)
 

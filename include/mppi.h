@@ -120,7 +120,25 @@ typedef struct {
                               *   zero.  Modes 1 and 2 sample positions only and
                               *   keep the spline's knot slopes (dq/dt) in the
                               *   velocity block of every knot vector they return. */
+  /* Task targets (Sec. IV-A, Tab. cost-weights): */
+  float q_des[4];            /* base orientation target R_des as a unit quaternion
+                              * (w, x, y, z); the orientation term is w_or times the
+                              * squared rotation angle of R_base^T R_des.  All zero
+                              * stands for the identity (level base, any yaw 0).  */
+  int32_t terminal_z_abs;    /* 0: terminal target p_base(x0) + v_des H dt;
+                              * 1: its height is z_terminal instead (jumping)      */
+  float z_terminal;
 } mppi_params;
+
+/* Task targets that may change between calls (e.g. the height step of the
+ * jumping task): the same fields as in mppi_params. */
+typedef struct {
+  float z_des;
+  float v_des[3];
+  float q_des[4];
+  int32_t terminal_z_abs;
+  float z_terminal;
+} mppi_targets;
 
 /* Per-call results besides the knots (device memory).  best_iter == 0 and
  * best_sample == 0 mean that no sample improved on the warm start (the
@@ -254,6 +272,13 @@ mppi_status mppi_graph_destroy(mppi_graph* g);
  * schedule. */
 mppi_status mppi_autotune(mppi_ctx* c, const float* d_state, const float* d_knots, int32_t reps, void* stream,
                           int32_t* best_lanes);
+
+/* Replace the instance's task targets (cost definition of Sec. IV-A) for the
+ * calls issued after this one.  Waits until the device is idle (kernels of
+ * earlier calls may still read the instance's tables), then updates them.
+ * Graphs captured before the call keep the old targets.  MPPI_EINVAL for a
+ * non-unit orientation target. */
+mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t);
 
 /* ---- Serving: continuous batching of MPC ticks --------------------------- */
 

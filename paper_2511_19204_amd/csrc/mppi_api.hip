@@ -360,6 +360,11 @@ static void free_ctx_buffers(mppi_ctx* c) {
     if (p) (void)hipFree(p);
 }
 
+static bool valid_target(const float* q) {
+  const double n2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
+  return n2 == 0.0 || std::fabs(n2 - 1.0) <= 1e-4;
+}
+
 static void build_tables(mppi_ctx* c) {
   const DevModel& M = c->m->host;
   c->h_insts.assign(c->I, DevInst{});
@@ -385,6 +390,13 @@ static void build_tables(mppi_ctx* c) {
     for (int k = 0; k < 3; ++k) d.v_des[k] = c->p.v_des[k];
     d.generate = 1;
     d.spline_mode = c->p.spline_mode;
+    const float* qd = c->p.q_des;
+    const bool zero = qd[0] == 0.f && qd[1] == 0.f && qd[2] == 0.f && qd[3] == 0.f;
+    const bool ident = zero || (qd[0] == 1.f && qd[1] == 0.f && qd[2] == 0.f && qd[3] == 0.f);
+    d.or_target = ident ? 0 : 1;
+    for (int k = 0; k < 4; ++k) d.q_des[k] = zero ? (k == 0 ? 1.f : 0.f) : qd[k];
+    d.terminal_z_abs = c->p.terminal_z_abs ? 1 : 0;
+    d.z_terminal = c->p.z_terminal;
     (void)M;
     DevUpdate& u = c->h_ups[it];
     u.costs = d.costs;
@@ -413,6 +425,7 @@ extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, ui
   if (p->noise_mode != 0 && p->noise_mode != 1) return fail(MPPI_EINVAL, "noise_mode must be 0 or 1");
   if (p->noise_mode == 0 && !(p->beta1 > 0.f && p->beta2 > 0.f)) return fail(MPPI_EINVAL, "beta1, beta2 must be positive");
   if (p->spline_mode < 0 || p->spline_mode > 2) return fail(MPPI_EINVAL, "spline_mode must be 0, 1 or 2");
+  if (!valid_target(p->q_des)) return fail(MPPI_EINVAL, "q_des must be a unit quaternion or all zero");
   const DevModel& M = m->host;
   if (p->cost_kind == 0 && M.ee_body < 0) return fail(MPPI_EINVAL, "end-effector cost needs ee_body");
   if (p->cost_kind == 1 && !M.fb) return fail(MPPI_EINVAL, "locomotion cost needs a floating base");
@@ -508,6 +521,22 @@ extern "C" mppi_status mppi_set_tick(mppi_ctx* c, uint32_t tick) {
 extern "C" mppi_status mppi_get_tick(const mppi_ctx* c, uint32_t* tick) {
   if (!c || !tick) return fail(MPPI_EINVAL, "null argument");
   HIP_TRY(hipMemcpy(tick, c->tick, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t) {
+  if (!c || !t) return fail(MPPI_EINVAL, "null argument");
+  if (!valid_target(t->q_des)) return fail(MPPI_EINVAL, "q_des must be a unit quaternion or all zero");
+  HIP_TRY(hipDeviceSynchronize());
+  c->p.z_des = t->z_des;
+  for (int k = 0; k < 3; ++k) c->p.v_des[k] = t->v_des[k];
+  for (int k = 0; k < 4; ++k) c->p.q_des[k] = t->q_des[k];
+  c->p.terminal_z_abs = t->terminal_z_abs;
+  c->p.z_terminal = t->z_terminal;
+  build_tables(c);
+  HIP_TRY(hipMemcpy(c->d_insts, c->h_insts.data(), c->I * sizeof(DevInst), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_ups, c->h_ups.data(), c->I * sizeof(DevUpdate), hipMemcpyHostToDevice));
+  purge_plans(c);
   return MPPI_OK;
 }
 

@@ -87,6 +87,10 @@ struct DevInst {
   float v_des[3];
   int32_t generate;      // 1: sample knots from the counter-based stream; 0: read samples
   int32_t spline_mode;   // 0 cubic Hermite, 1 natural cubic, 2 quadratic (position knots, zero velocity targets)
+  float q_des[4];        // base orientation target (w, x, y, z)
+  int32_t or_target;     // 0: identity target (the orientation term uses q_base directly)
+  int32_t terminal_z_abs;  // 1: terminal target height z_terminal
+  float z_terminal;
 };
 
 // Per-instance state of the weighting/update stage.

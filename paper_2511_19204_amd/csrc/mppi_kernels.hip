@@ -453,6 +453,8 @@ struct StepConst {
   ContactLaw law;
   float ee_pos[3];
   float w_h, w_or, w_q, w_cv, w_cf, w_eff, w_ee, w_tau, z_des;
+  int or_target;
+  float q_des[4];
 };
 __device__ __forceinline__ StepConst load_step_const(const DevModel& M, const DevInst* I, float dt_override) {
   StepConst c;
@@ -466,11 +468,15 @@ __device__ __forceinline__ StepConst load_step_const(const DevModel& M, const De
     c.delta = I->delta; c.inv_delta = 1.f / I->delta;
     c.w_h = I->w_h; c.w_or = I->w_or; c.w_q = I->w_q; c.w_cv = I->w_cv; c.w_cf = I->w_cf; c.w_eff = I->w_eff;
     c.w_ee = I->w_ee; c.w_tau = I->w_tau; c.z_des = I->z_des;
+    c.or_target = I->or_target;
+    c.q_des[0] = I->q_des[0]; c.q_des[1] = I->q_des[1]; c.q_des[2] = I->q_des[2]; c.q_des[3] = I->q_des[3];
   } else {
     c.cost_kind = -1; c.K = 2; c.nu = M.nu; c.F = 1; c.spline_mode = 0;
     c.dt = dt_override;
     c.delta = 1.f; c.inv_delta = 1.f;
     c.w_h = c.w_or = c.w_q = c.w_cv = c.w_cf = c.w_eff = c.w_ee = c.w_tau = c.z_des = 0.f;
+    c.or_target = 0;
+    c.q_des[0] = 1.f; c.q_des[1] = c.q_des[2] = c.q_des[3] = 0.f;
   }
   return c;
 }
@@ -589,14 +595,24 @@ __device__ __forceinline__ float ee_height_error(const float* R, const float* p,
 }
 
 // running-cost terms of the floating base (Sec. IV-A): height error and the
-// squared tilt angle of the base quaternion.  Both schedules evaluate it once
+// squared rotation angle between the base and the task's orientation target
+// (the identity unless a target is set).  Both schedules evaluate it once
 // per step in straight-line code: inside a loop the compiler may hoist it and
 // drop the relaxed-precision tag of the division inside atan2f, which would
 // change its last bit.
 __device__ __forceinline__ float base_cost_term(const StepConst& sc, const float* bq) {
+  // orientation residual: rotation angle of R_base^T R_des, i.e. of conj(q_base) q_des
   const float* qt = bq + 3;
-  const float vn = sqrtf(qt[1] * qt[1] + qt[2] * qt[2] + qt[3] * qt[3]);
-  const float phi = 2.f * atan2f(vn, fabsf(qt[0]));
+  float r0 = qt[0], r1 = qt[1], r2 = qt[2], r3 = qt[3];
+  if (sc.or_target) {
+    const float d0 = sc.q_des[0], d1 = sc.q_des[1], d2 = sc.q_des[2], d3 = sc.q_des[3];
+    r0 = qt[0] * d0 + qt[1] * d1 + qt[2] * d2 + qt[3] * d3;
+    r1 = qt[0] * d1 - qt[1] * d0 - qt[2] * d3 + qt[3] * d2;
+    r2 = qt[0] * d2 + qt[1] * d3 - qt[2] * d0 - qt[3] * d1;
+    r3 = qt[0] * d3 - qt[1] * d2 + qt[2] * d1 - qt[3] * d0;
+  }
+  const float vn = sqrtf(r1 * r1 + r2 * r2 + r3 * r3);
+  const float phi = 2.f * atan2f(vn, fabsf(r0));
   return sc.w_h * fabsf(bq[2] - sc.z_des) + sc.w_or * phi * phi;
 }
 
@@ -1158,7 +1174,10 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
       const float T = (float)H * I.dt;
       float e = 0.f;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) e += fabsf(io.bq[k] - (I.x0[k] + I.v_des[k] * T));
+      for (int k = 0; k < 3; ++k) {
+        const float target = (k == 2 && I.terminal_z_abs) ? I.z_terminal : I.x0[k] + I.v_des[k] * T;
+        e += fabsf(io.bq[k] - target);
+      }
       acc += I.w_H * e;
     }
   } else {
@@ -1595,7 +1614,10 @@ __device__ __attribute__((always_inline)) void chain_item(const DevInst& I, int 
       const float T = (float)H * I.dt;
       float e = 0.f;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) e += fabsf(bq[k] - (I.x0[k] + I.v_des[k] * T));
+      for (int k = 0; k < 3; ++k) {
+        const float target = (k == 2 && I.terminal_z_abs) ? I.z_terminal : I.x0[k] + I.v_des[k] * T;
+        e += fabsf(bq[k] - target);
+      }
       rec[34] += I.w_H * e;
     }
   } else {

@@ -49,7 +49,13 @@ class Params(C.Structure):
         ("w_eff", C.c_float), ("w_H", C.c_float), ("w_ee", C.c_float), ("w_tau", C.c_float),
         ("z_des", C.c_float), ("v_des", C.c_float * 3), ("f0z", C.POINTER(C.c_float)),
         ("q0_cost", C.POINTER(C.c_float)), ("spline_mode", C.c_int32),
+        ("q_des", C.c_float * 4), ("terminal_z_abs", C.c_int32), ("z_terminal", C.c_float),
     ]
+
+
+class Targets(C.Structure):
+    _fields_ = [("z_des", C.c_float), ("v_des", C.c_float * 3), ("q_des", C.c_float * 4),
+                ("terminal_z_abs", C.c_int32), ("z_terminal", C.c_float)]
 
 
 class StepInfo(C.Structure):
@@ -63,7 +69,7 @@ INFO_INTS = 5  # mppi_step_info as int32 words
 EXPORTS = [
     "mppi_model_create", "mppi_model_destroy", "mppi_create", "mppi_destroy", "mppi_set_tick",
     "mppi_get_tick", "mppi_set_schedule", "mppi_get_schedule", "mppi_set_lanes_per_rollout",
-    "mppi_get_lanes_per_rollout", "mppi_step", "mppi_predict", "mppi_shift_knots", "mppi_tick",
+    "mppi_get_lanes_per_rollout", "mppi_set_targets", "mppi_step", "mppi_predict", "mppi_shift_knots", "mppi_tick",
     "mppi_step_batch", "mppi_debug_philox", "mppi_debug_samples", "mppi_debug_dynamics",
     "mppi_debug_rollouts", "mppi_debug_update", "mppi_profile_enable", "mppi_profile_read",
     "mppi_set_batch_options", "mppi_graph_create", "mppi_graph_launch", "mppi_graph_destroy",
@@ -100,6 +106,7 @@ def lib():
         L.mppi_set_lanes_per_rollout.argtypes = [vp, i32]
         L.mppi_get_lanes_per_rollout.argtypes = [vp, C.POINTER(i32)]
         L.mppi_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.mppi_set_targets.argtypes = [vp, C.POINTER(Targets)]
         L.mppi_predict.argtypes = [vp, vp, vp, i32, vp, vp]
         L.mppi_shift_knots.argtypes = [vp, vp, i32, vp, vp]
         L.mppi_tick.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
@@ -231,6 +238,11 @@ def make_params(p):
     f0, s.f0z = _farr(p["f0z"] if len(p["f0z"]) else [0.0])
     q0, s.q0_cost = _farr(p["q0_cost"])
     s.spline_mode = int(p.get("spline_mode", 0))
+    qd = p.get("q_des", (0.0, 0.0, 0.0, 0.0))
+    for k in range(4):
+        s.q_des[k] = float(qd[k])
+    s.terminal_z_abs = int(p.get("terminal_z_abs", 0))
+    s.z_terminal = float(p.get("z_terminal", 0.0))
     return s, (f0, q0)
 
 
@@ -283,6 +295,23 @@ class Controller:
         g = C.c_int32()
         _check(lib().mppi_get_lanes_per_rollout(self.h, C.byref(g)), "mppi_get_lanes_per_rollout")
         return g.value
+
+    def set_targets(self, z_des=None, v_des=None, q_des=None, terminal_z_abs=None, z_terminal=None):
+        """mppi_set_targets: change the task targets (fields left None keep their values)."""
+        for k, v in (("z_des", z_des), ("v_des", v_des), ("q_des", q_des), ("terminal_z_abs", terminal_z_abs),
+                     ("z_terminal", z_terminal)):
+            if v is not None:
+                self.params[k] = list(v) if k in ("v_des", "q_des") else v
+        t = Targets()
+        t.z_des = float(self.params["z_des"])
+        for k in range(3):
+            t.v_des[k] = float(self.params["v_des"][k])
+        qd = self.params.get("q_des", (0.0, 0.0, 0.0, 0.0))
+        for k in range(4):
+            t.q_des[k] = float(qd[k])
+        t.terminal_z_abs = int(self.params.get("terminal_z_abs", 0))
+        t.z_terminal = float(self.params.get("z_terminal", 0.0))
+        _check(lib().mppi_set_targets(self.h, C.byref(t)), "mppi_set_targets")
 
     def set_lanes(self, lanes):
         """Body schedule with `lanes` lanes per rollout."""

@@ -267,6 +267,53 @@ def params(model, n_samples, horizon, dt, n_knots, n_iters, noise, cost, lam=1.0
     return p
 
 
+# Targets of the tasks of Sec. IV-B (the paper gives the weights, Tab. cost-weights,
+# and describes the targets in words; the numbers below are this synthetic stand-in's):
+#   walking   commanded forward velocity 0.5 m/s, level base;
+#   jumping   terminal base height raised by JUMP_RISE (the paper's 0.325 -> 0.7 m step);
+#   handstand base pitched 45 degrees nose down;
+#   backflip  base pitched 180 degrees;
+#   bipedal   humanoid walking at 0.5 m/s, level pelvis.
+JUMP_RISE = 0.375
+TASKS = ("walking", "jumping", "handstand", "backflip", "bipedal")
+# Sampling of the closed-loop task runs on the synthetic robots (the paper gives no
+# temperature; with 64 samples and the 0.4 rad kernel no sample ever beats the held
+# stance on these models, so the runs use more samples, a smaller noise scale and a
+# sharper softmax).
+TASK_SAMPLING = {"n_samples": 1024, "scale_q": 0.1, "lambda": 0.1}
+
+
+def pitch_quaternion(deg):
+    """Unit quaternion (w, x, y, z) of a rotation by deg about the base y axis
+    (positive: nose down for x forward, z up)."""
+    h = np.deg2rad(deg) / 2
+    return [float(np.float32(np.cos(h))), 0.0, float(np.float32(np.sin(h))), 0.0]
+
+
+def task_params(model, p, name):
+    """Parameters p with the weights of the task's row of the cost-weights table and
+    the task's targets."""
+    p = dict(p)
+    p["cost_kind"] = 1
+    p["w_h"], p["w_or"], p["w_q"], p["w_cv"], p["w_cf"], p["w_H"] = COST_WEIGHTS[name]
+    z0 = float(model["x0"][2])
+    p["z_des"] = z0
+    p["v_des"] = [0.0, 0.0, 0.0]
+    p["q_des"] = [0.0, 0.0, 0.0, 0.0]
+    p["terminal_z_abs"], p["z_terminal"] = 0, 0.0
+    if name in ("walking", "bipedal"):
+        p["v_des"] = [0.5, 0.0, 0.0]
+    elif name == "jumping":
+        p["terminal_z_abs"], p["z_terminal"] = 1, float(np.float32(z0 + JUMP_RISE))
+    elif name == "handstand":
+        p["q_des"] = pitch_quaternion(45.0)
+    elif name == "backflip":
+        p["q_des"] = pitch_quaternion(180.0)
+    else:
+        raise KeyError(name)
+    return p
+
+
 # The five workloads: shapes, sizes and noise/cost settings of each configuration.
 def config(name, n_samples=None, seed=0):
     """(model, params, seed) of a named workload.
