@@ -374,7 +374,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--samples", type=int, default=4096)
     ap.add_argument("--lanes", type=int, default=0, help="body schedule with this many lanes per rollout")
-    ap.add_argument("--schedule", choices=["body", "chain"], default=None,
+    ap.add_argument("--schedule", choices=["body", "chain", "team"], default=None,
                     help="rollout schedule (default: the library's choice)")
     ap.add_argument("--robots", type=int, default=64)
     ap.add_argument("--rounds", type=int, default=10)
@@ -456,8 +456,8 @@ def main():
             "frac": res["achieved_tflops"] / FP32_PEAK_TFLOPS,
             "frac_nonpacked_peak": res["achieved_tflops"] / FP32_PEAK_NONPACKED,
             "traffic": traffic,
-            "kernel": (f"chain_kernel<{res['lanes']}>" if res["schedule"] == "chain"
-                       else f"rollout_kernel<{res['lanes']}>"),
+            "kernel": {"chain": "chain_kernel", "team": "team_kernel"}.get(res["schedule"], "rollout_kernel")
+                      + f"<{res['lanes']}>",
             "kernel_ms": res["kernel_ms"],
             "update_kernel_ms": res["update_ms"],
             "flops_per_rollout_step": res["flops_per_rollout_step"],

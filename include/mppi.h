@@ -180,13 +180,23 @@ mppi_status mppi_get_tick(const mppi_ctx* c, uint32_t* tick);
  *                        its chain, lanes per rollout = the next power of two
  *                        >= the number of chains.  Needs at most 8 chains and
  *                        tree depth <= 15 (MPPI_EINVAL otherwise).
- * Every schedule and lane count gives bit-identical results; they differ in
- * speed only (mppi_autotune picks).  A new context uses the body schedule with
- * the smallest lane count that holds the tree.
+ *   MPPI_SCHEDULE_TEAM   the chains of MPPI_SCHEDULE_CHAIN, each on a block of
+ *                        4 or 8 lanes: one body per lane for the per-body work,
+ *                        and the block's first three lanes together (one
+ *                        spatial coordinate each) for the sweeps; lanes per
+ *                        rollout = the next power of two >= chains x block.
+ *                        Same conditions as the chain schedule, and at most 64
+ *                        lanes per rollout.
+ * The body and chain schedules and every lane count give bit-identical
+ * results; the team schedule evaluates the same formulas with sums taken in
+ * another order, so its results differ from theirs by rounding (its own results
+ * are deterministic and independent of batching).  A new context uses the team
+ * schedule where the tree allows it, else the body schedule with the smallest
+ * lane count that holds the tree; mppi_autotune times all of them.
  * mppi_set_lanes_per_rollout selects the body schedule with `lanes` lanes (0 =
  * the smallest valid count); mppi_get_lanes_per_rollout reports the lane count
  * of the current schedule. */
-typedef enum { MPPI_SCHEDULE_BODY = 0, MPPI_SCHEDULE_CHAIN = 1 } mppi_schedule;
+typedef enum { MPPI_SCHEDULE_BODY = 0, MPPI_SCHEDULE_CHAIN = 1, MPPI_SCHEDULE_TEAM = 2 } mppi_schedule;
 mppi_status mppi_set_schedule(mppi_ctx* c, int32_t schedule);
 mppi_status mppi_get_schedule(const mppi_ctx* c, int32_t* schedule);
 mppi_status mppi_set_lanes_per_rollout(mppi_ctx* c, int32_t lanes);

@@ -28,6 +28,8 @@ namespace mppi {
 template <int G> __global__ void rollout_kernel(const DevInst*, const int2*, int, int);
 template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
+template <int G> __global__ void team_kernel(const DevInst*, const int2*, int, int);
+template <int G> __global__ void team_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int, int);
 __global__ void reset_counters(unsigned int*, int);
 template <int G> __global__ void sample_kernel(const DevInst*, int);
@@ -53,6 +55,12 @@ constexpr int kUpdThreads = 1024;
 }  // namespace mppi
 
 using namespace mppi;
+
+// A launch key selects the schedule: 0 < G <= 64 is the body schedule with G
+// lanes per rollout, -GC < 0 the chain schedule with GC lanes per rollout, and
+// kTeamKey + G the team schedule with G lanes per rollout.
+constexpr int kTeamKey = 128;
+static int key_lanes(int key) { return key > kTeamKey ? key - kTeamKey : key > 0 ? key : -key; }
 
 // ---------------------------------------------------------------------------
 // errors
@@ -205,6 +213,56 @@ static void build_chain_tables(DevModel& M) {
     for (int k = 0; k < kCt; ++k) M.ctab[ci][k] = 0.f;
     for (int k = 0; k < 3; ++k) M.ctab[ci][k] = M.cpos[ci][k];
     M.ctab[ci][4] = bits(M.corig[ci]);
+  }
+  // team schedule: blocks of B lanes per chain (B holds the chain's bodies and at
+  // least the three coordinate lanes), a power of two of them per rollout
+  int longest = 0;
+  for (int c = 0; c < kMaxChains; ++c) {
+    int len = 0;
+    for (int d = 0; d < kMaxLevels; ++d) len += (c < M.n_chains && M.chain_body[c][d] >= 0) ? 1 : 0;
+    M.chain_len[c] = len;
+    longest = std::max(longest, len);
+    const int first = c < M.n_chains ? M.chain_body[c][M.chain_first[c]] : -1;
+    M.chain_parent[c] = first >= 0 ? M.parent[first] : -1;
+  }
+  int B = 4;
+  while (B < longest) B <<= 1;
+  int G = 1;
+  while (G < M.n_chains * B) G <<= 1;
+  M.team_block = B;
+  M.team_lanes = G;
+  M.team_ok = (M.chain_ok && M.n_chains > 0 && G <= 64) ? 1 : 0;
+  // slots: bodies ranked by (depth, chain), so one level's bodies are consecutive
+  M.team_slots = nb;
+  for (int b = 0; b < kMaxBodies; ++b) M.team_slot[b] = 0;
+  {
+    std::vector<int> order(nb);
+    for (int b = 0; b < nb; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return M.depth[x] != M.depth[y] ? M.depth[x] < M.depth[y] : chain_of[x] < chain_of[y];
+    });
+    for (int s = 0; s < nb; ++s) M.team_slot[order[s]] = s;
+  }
+  for (int b = 0; b < kMaxBodies; ++b)
+    for (int k = 0; k < kTeamRow; ++k) M.team_rows[b][k] = 0.f;
+  for (int b = 0; b < nb; ++b) {
+    float* t = M.team_rows[b];
+    for (int k = 0; k < 3; ++k) {
+      for (int i = 0; i < 3; ++i) {
+        const int col = (k + i) % 3;
+        t[16 * k + i] = M.P[b][3 * k + col];
+        t[16 * k + 3 + i] = M.P[b][9 + 3 * k + col];
+        t[16 * k + 6 + i] = M.P[b][18 + 3 * k + col];
+        t[16 * k + 9 + i] = M.p_tree[b][col];
+        t[16 * k + 12 + i] = M.axis_p[b][col];
+      }
+    }
+    const int j = b - M.fb;
+    t[15] = j >= 0 ? M.arm[j] : 0.f;
+    int side = 0;
+    for (int c = 0; c < M.n_chains; ++c)
+      if (M.chain_parent[c] == b) side |= 1 << c;
+    t[16 + 15] = bits(side);
   }
 }
 
@@ -559,7 +617,7 @@ extern "C" mppi_status mppi_set_lanes_per_rollout(mppi_ctx* c, int32_t lanes) {
 
 extern "C" mppi_status mppi_get_lanes_per_rollout(const mppi_ctx* c, int32_t* lanes) {
   if (!c || !lanes) return fail(MPPI_EINVAL, "null argument");
-  *lanes = c->lanes > 0 ? c->lanes : -c->lanes;
+  *lanes = key_lanes(c->lanes);
   return MPPI_OK;
 }
 
@@ -567,6 +625,10 @@ extern "C" mppi_status mppi_set_schedule(mppi_ctx* c, int32_t schedule) {
   if (!c) return fail(MPPI_EINVAL, "null context");
   const DevModel& M = c->m->host;
   if (schedule == MPPI_SCHEDULE_BODY) return set_key(c, next_pow2(M.nb));
+  if (schedule == MPPI_SCHEDULE_TEAM) {
+    if (!M.team_ok) return fail(MPPI_EINVAL, "tree has more than 8 chains, depth above 15 or needs more than 64 lanes");
+    return set_key(c, kTeamKey + M.team_lanes);
+  }
   if (schedule != MPPI_SCHEDULE_CHAIN) return fail(MPPI_EINVAL, "unknown schedule");
   if (!M.chain_ok) return fail(MPPI_EINVAL, "tree has more than 8 chains or depth above 15");
   return set_key(c, -M.chain_lanes);
@@ -574,20 +636,18 @@ extern "C" mppi_status mppi_set_schedule(mppi_ctx* c, int32_t schedule) {
 
 extern "C" mppi_status mppi_get_schedule(const mppi_ctx* c, int32_t* schedule) {
   if (!c || !schedule) return fail(MPPI_EINVAL, "null argument");
-  *schedule = c->lanes > 0 ? MPPI_SCHEDULE_BODY : MPPI_SCHEDULE_CHAIN;
+  *schedule = c->lanes > kTeamKey ? MPPI_SCHEDULE_TEAM : c->lanes > 0 ? MPPI_SCHEDULE_BODY : MPPI_SCHEDULE_CHAIN;
   return MPPI_OK;
 }
 
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
-// A launch key selects the schedule: G > 0 is the body schedule with G lanes per
-// rollout, -GC < 0 the chain schedule with GC lanes per rollout.
-static int key_lanes(int key) { return key > 0 ? key : -key; }
+
 
 // Largest per-instance sizes of one launch (they size the LDS regions).
 struct Dims {
-  int E = 0, nb = 0, nc = 0, nch = 0, natt = 0;
+  int E = 0, nb = 0, nc = 0, nch = 0, natt = 0, ns = 0;
   void add(const mppi_ctx* c) {
     const DevModel& M = c->m->host;
     E = std::max(E, c->E);
@@ -595,6 +655,7 @@ struct Dims {
     nc = std::max(nc, M.nc);
     nch = std::max(nch, M.n_chains);
     natt = std::max(natt, M.n_att);
+    ns = std::max(ns, M.team_slots);
   }
 };
 static Dims dims_of(const mppi_ctx* c) {
@@ -611,7 +672,13 @@ struct LaunchShape {
 };
 static LaunchShape launch_shape(int key, const Dims& dm) {
   LaunchShape sh;
-  if (key > 0) {
+  if (key > kTeamKey) {
+    const int G = key - kTeamKey;
+    sh.stride = team_layout(G, dm.ns, dm.E, dm.nch).total;
+    sh.table = team_table_floats(dm.ns, dm.nc);
+    sh.groups = 64 / G;
+    sh.lds = (sh.table + sh.groups * sh.stride) * (int)sizeof(float);
+  } else if (key > 0) {
     sh.stride = group_floats(key, dm.E);
     sh.table = body_table_floats(dm.nc);
     sh.groups = 64 / key;
@@ -634,6 +701,12 @@ static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2*
   hipLaunchKernelGGL(rollout_kernel<G>, dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
   return hipGetLastError();
 }
+template <int G>
+static hipError_t launch_team_G(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(team_kernel<G>, dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+  return hipGetLastError();
+}
 template <int GC>
 static hipError_t launch_chain_GC(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
                                   hipStream_t s) {
@@ -650,6 +723,11 @@ static hipError_t launch_rollout(int key, int blocks, const DevInst* insts, cons
     case 16: return launch_rollout_G<16>(blocks, insts, work, sh, s);
     case 32: return launch_rollout_G<32>(blocks, insts, work, sh, s);
     case 64: return launch_rollout_G<64>(blocks, insts, work, sh, s);
+    case kTeamKey + 4: return launch_team_G<4>(blocks, insts, work, sh, s);
+    case kTeamKey + 8: return launch_team_G<8>(blocks, insts, work, sh, s);
+    case kTeamKey + 16: return launch_team_G<16>(blocks, insts, work, sh, s);
+    case kTeamKey + 32: return launch_team_G<32>(blocks, insts, work, sh, s);
+    case kTeamKey + 64: return launch_team_G<64>(blocks, insts, work, sh, s);
     case -1: return launch_chain_GC<1>(blocks, insts, work, sh, s);
     case -2: return launch_chain_GC<2>(blocks, insts, work, sh, s);
     case -4: return launch_chain_GC<4>(blocks, insts, work, sh, s);
@@ -676,12 +754,18 @@ static hipError_t launch_persistent(int key, int n_items, const DevInst* insts, 
   const LaunchShape sh = launch_shape(key, dm);
 #define BODY_P(G) launch_persistent_k(rollout_persistent_kernel<G>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table)
 #define CHAIN_P(GC) launch_persistent_k(chain_persistent_kernel<GC>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table, sh.groups)
+#define TEAM_P(G) launch_persistent_k(team_persistent_kernel<G>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table)
   switch (key) {
     case 4: return BODY_P(4);
     case 8: return BODY_P(8);
     case 16: return BODY_P(16);
     case 32: return BODY_P(32);
     case 64: return BODY_P(64);
+    case kTeamKey + 4: return TEAM_P(4);
+    case kTeamKey + 8: return TEAM_P(8);
+    case kTeamKey + 16: return TEAM_P(16);
+    case kTeamKey + 32: return TEAM_P(32);
+    case kTeamKey + 64: return TEAM_P(64);
     case -1: return CHAIN_P(1);
     case -2: return CHAIN_P(2);
     case -4: return CHAIN_P(4);
@@ -690,6 +774,7 @@ static hipError_t launch_persistent(int key, int n_items, const DevInst* insts, 
   }
 #undef BODY_P
 #undef CHAIN_P
+#undef TEAM_P
 }
 
 static std::atomic<int> g_persistent{0};
@@ -1174,6 +1259,7 @@ extern "C" mppi_status mppi_autotune(mppi_ctx* c, const float* d_state, const fl
   std::vector<int> cand;
   for (int G = next_pow2(M.nb); G <= 64; G *= 2) cand.push_back(G);
   if (M.chain_ok) cand.push_back(-M.chain_lanes);
+  if (M.team_ok) cand.push_back(kTeamKey + M.team_lanes);
   hipStream_t s = (hipStream_t)stream;
   uint32_t tick0 = 0;
   HIP_TRY(hipMemcpy(&tick0, c->tick, sizeof(uint32_t), hipMemcpyDeviceToHost));
@@ -1257,7 +1343,7 @@ extern "C" mppi_status mppi_debug_samples(mppi_ctx* c, const float* d_knots_in, 
   mppi_status st = debug_inst(h, s, &d);
   if (st != MPPI_OK) return st;
   hipError_t e;
-  switch (c->lanes > 0 ? c->lanes : next_pow2(c->m->host.nb)) {
+  switch (c->lanes > 0 && c->lanes <= 64 ? c->lanes : next_pow2(c->m->host.nb)) {
     case 4: e = launch_samples_G<4>(d, c->N, c->E, s); break;
     case 8: e = launch_samples_G<8>(d, c->N, c->E, s); break;
     case 16: e = launch_samples_G<16>(d, c->N, c->E, s); break;

@@ -27,6 +27,20 @@ enum : int { P = 0, p_tree = 27, axis_p = 30, com = 33, Ic = 36, mass = 42, kp =
              depth = 55, child = 56 };
 }
 
+// Team schedule records are indexed by slot: the bodies numbered by (depth,
+// chain), so the bodies one level works on sit in consecutive slots.  Per slot and coordinate
+// lane k the constants of its joint take 16 floats (stride kTeamK): rows k of P0,
+// P1, P2 with columns in rotated order (entry i = column k + i), then p_tree and
+// axis_p in the same order (components k, k+1, k+2), then [15] = the joint's
+// armature (k = 0) or the bit mask of the chains whose first body hangs off
+// this body (k = 1, as integer bits).  The strides (20 floats per lane, 60 per
+// slot; 8 and 28 for the frame records) put the three lanes of a team and the
+// teams of two neighbouring chains on different LDS banks.
+constexpr int kTeamK = 20;
+constexpr int kTeamSlot = 60;
+constexpr int kTeamRow = 3 * 16;   // host copy per body
+constexpr int kFrSlot = 28;
+
 // Kinematic tree in the layout the rollout lanes read: one entry per body,
 // contacts sorted by body.  Precomputed on the host from mppi_model_desc:
 //  * the joint rotation C(q) = R_tree Rot(axis, q) is stored as
@@ -64,6 +78,14 @@ struct DevModel {
   int32_t chain_att[kMaxChains];                // attach slot its first body reads, or -1 (a root)
   alignas(16) float rows[kMaxBodies][kRow];     // body rows (layout above), read as float4
   float ctab[kMaxContacts][kCt];                // contact rows
+  // Team schedule: the chains above, each on a block of team_block lanes
+  // (team_lanes per rollout); per body and coordinate lane k the constants of
+  // its joint in rotated order (see team_table_floats).
+  int32_t team_ok, team_block, team_lanes, team_slots;
+  int32_t chain_len[kMaxChains];                // bodies of chain c
+  int32_t chain_parent[kMaxChains];             // parent body of its first body, or -1
+  int32_t team_slot[kMaxBodies];                // rank of (depth, chain) among the bodies
+  alignas(16) float team_rows[kMaxBodies][kTeamRow];
 };
 
 // One MPC instance's view for one planning iteration.
@@ -159,6 +181,42 @@ __host__ __device__ inline int chain_group_floats(int GC, int nb, int E, int nch
   const int raw = nb * kRec + 16 + ((E + 3) & ~3) + nch * kPub + natt * kAtt + GC;
   const int r4 = (raw + 3) & ~3;
   return r4 + ((20 - r4 % 32) + 32) % 32;  // 16-byte aligned groups, staggered across LDS banks
+}
+
+// Team schedule: after the model table (then the team constants [slots][60] and
+// the slot of chain c's body at depth d [kMaxChains][kMaxLevels] as integer
+// bits), one region per rollout group (ns = slots = bodies):
+//   br[ns][8]       per body: cos q, sin q, qd, tau | PD gain, qdd
+//   fr[ns][28]      per body, lane k at 8k: rotated row of R, p, v (2), beta (2)
+//   lr[ns][28]      lane k at 8k: e, axis, c (2) | U (2), 1/D, u
+//   ir[ns][60]      lane k at 20k: articulated inertia rows (A, B, column of B, C;
+//                   rotated) and bias (2)
+//   pr[nch][60]     the same, carried to its parent by a chain's first body
+//   ar[ns][8]       lane k at 2k: acceleration (2) of a body other chains hang off
+//   bs[32]          frame B (R 9, p 3), base twist (6), base a' (6)
+//   gr[60]          the base's articulated inertia rows, for its solve
+//   knots[E], red[G]
+__host__ __device__ inline int team_table_floats(int ns, int nc) {
+  return body_table_floats(nc) + ns * kTeamSlot + kMaxChains * kMaxLevels;
+}
+struct TeamLayout {
+  int br, fr, lr, ir, pr, ar, bs, gr, knots, red, total;
+};
+__host__ __device__ inline TeamLayout team_layout(int G, int ns, int E, int nch) {
+  TeamLayout t;
+  int o = 0;
+  t.br = o; o += ns * 8;
+  t.fr = o; o += ns * kFrSlot;
+  t.lr = o; o += ns * kFrSlot;
+  t.ir = o; o += ns * kTeamSlot;
+  t.pr = o; o += nch * kTeamSlot;
+  t.ar = o; o += ns * 8;
+  t.bs = o; o += 32;
+  t.gr = o; o += kTeamSlot;
+  t.knots = o; o += (E + 3) & ~3;
+  t.red = o; o += (G + 3) & ~3;
+  t.total = o + ((16 - o % 32) + 32) % 32;  // 16-byte aligned groups, staggered across LDS banks
+  return t;
 }
 
 }  // namespace mppi

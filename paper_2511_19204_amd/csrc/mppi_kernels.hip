@@ -1236,6 +1236,650 @@ __global__ __launch_bounds__(64) void rollout_persistent_kernel(const DevInst* _
 }
 
 // ---------------------------------------------------------------------------
+// Team schedule: every chain of the heavy-path decomposition owns a block of B
+// lanes (B = 4 or 8, holding the chain's bodies).  The per-body work runs one
+// body per lane of its chain's block (PD law, inertia, bias, contacts, running
+// cost, integration); the three sweeps run per chain, one body per level, on the
+// block's first three lanes together: lane k holds component k of every
+// 3-vector and row k of every 3x3 block with its columns in rotated order
+// (entry i is column k + i), and the lanes meet through DPP permutations inside
+// their quad.  A cyclic relabelling of the axes is a proper rotation, so a cross
+// product keeps its form in every lane: (a x b)_k = a_{k+1} b_{k+2} - a_{k+2} b_{k+1}.
+// Sums over the three lanes are taken in the order 0, 1, 2 in every lane, so the
+// lanes of a team agree bit for bit on every shared scalar.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float qperm(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float qr1(float x) { return qperm<0xC9>(x); }  // component k + 1 (quad_perm 1,2,0,3)
+__device__ __forceinline__ float qr2(float x) { return qperm<0xD2>(x); }  // component k + 2 (quad_perm 2,0,1,3)
+__device__ __forceinline__ float qsum3(float x) { return (qperm<0x00>(x) + qperm<0x55>(x)) + qperm<0xAA>(x); }
+
+// frame of one body as seen by coordinate lane k: rotated row k of R, p_k, v_k, beta_k
+struct TFrame {
+  float R[3], p, va, vl, ba, bl;
+};
+
+// Forward kinematics of a revolute body (as fk_joint) from the parent's frame P:
+// tc = the body's team constants for this lane; outputs the frame O, e_k, ax_k, c_k.
+__device__ __forceinline__ void team_fk(const float* tc, float cq, float sq, float qd, const TFrame& P, TFrame& O,
+                                        float& e, float& ax, float& ca, float& cl) {
+  float C[3], C1[3], C2[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) C[i] = tc[i] + cq * tc[3 + i] + sq * tc[6 + i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { C1[i] = qr1(C[i]); C2[i] = qr2(C[i]); }
+  // R = Rl C: entry j = sum_m Rl[k][k+m] C[k+m][k+j]; lane k+m holds C[k+m][.] rotated by its own index
+#pragma unroll
+  for (int j = 0; j < 3; ++j) O.R[j] = P.R[0] * C[j] + P.R[1] * C1[(j + 2) % 3] + P.R[2] * C2[(j + 1) % 3];
+  e = P.R[0] * tc[9] + P.R[1] * tc[10] + P.R[2] * tc[11];
+  ax = P.R[0] * tc[12] + P.R[1] * tc[13] + P.R[2] * tc[14];
+  O.p = P.p + e;
+  const float e1 = qr1(e), e2 = qr2(e);
+  const float w1 = qr1(P.va), w2 = qr2(P.va);
+  O.va = P.va + ax * qd;
+  O.vl = P.vl + (w1 * e2 - w2 * e1);
+  const float aq = ax * qd, aq1 = qr1(aq), aq2 = qr2(aq);
+  const float va1 = qr1(O.va), va2 = qr2(O.va), vl1 = qr1(O.vl), vl2 = qr2(O.vl);
+  ca = va1 * aq2 - va2 * aq1;
+  cl = vl1 * aq2 - vl2 * aq1;
+  const float b1 = qr1(P.ba), b2 = qr2(P.ba);
+  O.ba = P.ba + ca;
+  O.bl = P.bl + (b1 * e2 - b2 * e1) + cl;
+}
+
+// Articulated-body step of a revolute joint (as backward_joint).  Rows of lane k:
+// A[i] = A[k][k+i], B[i] = B[k][k+i], T[i] = B[k+i][k], C[i] = C[k][k+i] of the
+// articulated inertia [[A, B], [B^T, C]] and the bias (pa, pl); the carried
+// inertia and bias come out in the same form.
+__device__ __forceinline__ void team_backward(const float* A, const float* B, const float* T, const float* C,
+                                              float pa, float pl, float ax, float e, float ca, float cl, float tau,
+                                              float arm, float gain, float& Ua, float& Ul, float& invD, float& u,
+                                              float* Ap, float* Bp, float* Tp, float* Cp, float& ppa, float& ppl) {
+  const float ax1 = qr1(ax), ax2 = qr2(ax);
+  Ua = A[0] * ax + A[1] * ax1 + A[2] * ax2;
+  Ul = T[0] * ax + T[1] * ax1 + T[2] * ax2;
+  const float Dv = (arm + gain) + qsum3(ax * Ua);
+  invD = rcp(Dv);
+  u = tau - qsum3(ax * pa);
+  // Ia = IA - U W^T, W = U / D
+  const float Wa = Ua * invD, Wl = Ul * invD;
+  const float Wa1 = qr1(Wa), Wa2 = qr2(Wa), Wl1 = qr1(Wl), Wl2 = qr2(Wl), Ua1 = qr1(Ua), Ua2 = qr2(Ua);
+  const float IA_[3] = {A[0] - Ua * Wa, A[1] - Ua * Wa1, A[2] - Ua * Wa2};
+  const float IB[3] = {B[0] - Ua * Wl, B[1] - Ua * Wl1, B[2] - Ua * Wl2};
+  const float IT[3] = {T[0] - Ua * Wl, T[1] - Ua1 * Wl, T[2] - Ua2 * Wl};
+  const float IC[3] = {C[0] - Ul * Wl, C[1] - Ul * Wl1, C[2] - Ul * Wl2};
+  // pa = pA + Ia c + U u / D
+  const float ca1 = qr1(ca), ca2 = qr2(ca), cl1 = qr1(cl), cl2 = qr2(cl);
+  const float iqa = IA_[0] * ca + IA_[1] * ca1 + IA_[2] * ca2 + IB[0] * cl + IB[1] * cl1 + IB[2] * cl2;
+  const float iql = IT[0] * ca + IT[1] * ca1 + IT[2] * ca2 + IC[0] * cl + IC[1] * cl1 + IC[2] * cl2;
+  const float uD = u * invD;
+  const float pa2 = pa + iqa + Ua * uD, pl2 = pl + iql + Ul * uD;
+  // carried to the parent origin: B' = B + E C, A' = A - B'E - (BE)^T, C' = C (E = e^x)
+  const float e1 = qr1(e), e2 = qr2(e);
+  float IC1[3], IC2[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { IC1[i] = qr1(IC[i]); IC2[i] = qr2(IC[i]); }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Bp[i] = IB[i] + e1 * IC2[(i + 1) % 3] - e2 * IC1[(i + 2) % 3];
+  Tp[0] = Bp[0];
+  Tp[1] = qr1(Bp[2]);
+  Tp[2] = qr2(Bp[1]);
+  const float er[3] = {e, e1, e2};
+  float y[3], z[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    y[j] = Bp[(j + 1) % 3] * er[(j + 2) % 3] - Bp[(j + 2) % 3] * er[(j + 1) % 3];
+    z[j] = IB[(j + 1) % 3] * er[(j + 2) % 3] - IB[(j + 2) % 3] * er[(j + 1) % 3];
+  }
+  Ap[0] = IA_[0] - y[0] - z[0];
+  Ap[1] = IA_[1] - y[1] - qr1(z[2]);
+  Ap[2] = IA_[2] - y[2] - qr2(z[1]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Cp[i] = IC[i];
+  const float p1 = qr1(pl2), p2 = qr2(pl2);
+  ppa = pa2 + (e1 * p2 - e2 * p1);
+  ppl = pl2;
+}
+
+// Accelerations of a revolute joint (as forward_joint) from the parent's a' (ala, all).
+__device__ __forceinline__ float team_forward(float ala, float all, float e, float ax, float ca, float cl, float Ua,
+                                              float Ul, float invD, float u, float& aa, float& al) {
+  const float a1 = qr1(ala), a2 = qr2(ala), e1 = qr1(e), e2 = qr2(e);
+  aa = ala + ca;
+  al = all + (a1 * e2 - a2 * e1) + cl;
+  const float qdd = (u - qsum3(Ua * aa + Ul * al)) * invD;
+  aa = aa + ax * qdd;
+  return qdd;
+}
+
+// Per-lane roles of the team schedule.
+struct TeamRole {
+  int c, bl, k;            // chain, lane in the chain's block, coordinate lane (0 for lanes past the third)
+  int b, slot;             // body of a body lane and its record slot (0 otherwise: never written)
+  int cfirst, cpar, pslot; // depth of the chain's first body, its parent (-1: a root) and the parent's slot
+  bool body_lane, team;
+};
+
+// Body constants a body lane of the team schedule reads.
+struct TeamBody {
+  float com[3], Ic[6], mass, kp, kd, taumax, q0;
+  int c_begin, c_count;
+};
+__device__ __forceinline__ void load_team_body(const DevModel& M, const DevInst* I, const TeamRole& r, TeamBody& c) {
+  const int bb = r.b;
+  const int j = bb - M.fb;
+  const bool joint = r.body_lane && j >= 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c.com[k] = M.com[bb][k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) c.Ic[k] = M.Ic[bb][k];
+  c.mass = M.mass[bb];
+  c.kp = joint ? M.kp[j] : 0.f;
+  c.kd = joint ? M.kd[j] : 0.f;
+  c.taumax = joint ? M.taumax[j] : 0.f;
+  c.q0 = (joint && I && I->cost_kind == 1) ? I->q0[j] : 0.f;
+  c.c_begin = M.c_begin[bb];
+  c.c_count = r.body_lane ? M.c_count[bb] : 0;
+}
+
+// Stage the team constants (by slot) and the table of the slot of chain c's body at
+// depth d (or -1) after the model table.
+__device__ __forceinline__ void stage_team_table(const DevModel& M, float* tab, int lane) {
+  float* tt = tab + body_table_floats(M.nc);
+  const int n = M.nb * kTeamRow;
+  for (int i = lane; i < n; i += 64) {
+    const int b = i / kTeamRow, w = i % kTeamRow;
+    tt[M.team_slot[b] * kTeamSlot + (w / 16) * kTeamK + (w % 16)] = M.team_rows[b][w];
+  }
+  int* tcb = reinterpret_cast<int*>(tt + M.team_slots * kTeamSlot);
+  for (int i = lane; i < kMaxChains * kMaxLevels; i += 64) {
+    const int bb = M.chain_body[i / kMaxLevels][i % kMaxLevels];
+    tcb[i] = bb >= 0 ? M.team_slot[bb] : -1;
+  }
+  wave_sync();
+}
+
+__device__ __forceinline__ void get16(const float* s, float* d) {
+  const float4 a = get4(s), b = get4(s + 4), c = get4(s + 8), e = get4(s + 12);
+  d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w; d[4] = b.x; d[5] = b.y; d[6] = b.z; d[7] = b.w;
+  d[8] = c.x; d[9] = c.y; d[10] = c.z; d[11] = c.w; d[12] = e.x; d[13] = e.y; d[14] = e.z; d[15] = e.w;
+}
+
+// What a coordinate lane reads for one level of the backward sweep (loaded a
+// level ahead; zeros where the chain has no body at that depth).
+struct TeamBwdIn {
+  float ir[16], lr[4], tau, gain, arm;
+  uint32_t side;
+  bool act;
+};
+__device__ __forceinline__ int team_load_bwd(const TeamRole& r, const int* tcb, const float* tt, const float* ir,
+                                             const float* lr, const float* br, int d, int k, TeamBwdIn& o) {
+  const int s = r.team ? tcb[r.c * kMaxLevels + d] : -1;
+  o.act = s >= 0;
+  if (o.act) {
+    get16(ir + s * kTeamSlot + k * kTeamK, o.ir);
+    const float4 l4 = get4(lr + s * kFrSlot + k * 8);
+    o.lr[0] = l4.x; o.lr[1] = l4.y; o.lr[2] = l4.z; o.lr[3] = l4.w;
+    const float4 b4 = get4(br + s * 8);
+    o.tau = b4.w;
+    o.gain = br[s * 8 + 4];
+    o.arm = tt[s * kTeamSlot + 15];
+    o.side = (uint32_t)__float_as_int(tt[s * kTeamSlot + kTeamK + 15]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) o.ir[q] = 0.f;
+    o.lr[0] = o.lr[1] = o.lr[2] = o.lr[3] = 0.f;
+    o.tau = o.gain = o.arm = 0.f;
+    o.side = 0u;
+  }
+  return s;
+}
+// the same for the forward sweep
+struct TeamFwdIn {
+  float lr[8];
+  uint32_t side;
+  bool act;
+};
+__device__ __forceinline__ int team_load_fwd(const TeamRole& r, const int* tcb, const float* tt, const float* lr,
+                                             int d, int k, TeamFwdIn& o) {
+  const int s = r.team ? tcb[r.c * kMaxLevels + d] : -1;
+  o.act = s >= 0;
+  if (o.act) {
+    const float4 l0 = get4(lr + s * kFrSlot + k * 8), l1 = get4(lr + s * kFrSlot + k * 8 + 4);
+    o.lr[0] = l0.x; o.lr[1] = l0.y; o.lr[2] = l0.z; o.lr[3] = l0.w;
+    o.lr[4] = l1.x; o.lr[5] = l1.y; o.lr[6] = l1.z; o.lr[7] = l1.w;
+    o.side = (uint32_t)__float_as_int(tt[s * kTeamSlot + kTeamK + 15]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o.lr[q] = 0.f;
+    o.side = 0u;
+  }
+  return s;
+}
+
+// One physics step of the team schedule (same stages and formulas as physics_step):
+// tt = team constants and tcb = chain-body table in LDS.  Every coordinate-lane
+// computation runs with all lanes active (the DPP permutations need them); the
+// lanes of a level without a body compute on zeros and store nothing.
+__device__ __attribute__((always_inline)) void team_step(const StepConst& sc, const TeamBody& tb, const float* tab,
+                                                         const float* tt, const int* tcb,
+                          float* __restrict__ gs, const TeamLayout& L, const TeamRole& r, StepIO& io, bool want_cost,
+                          bool terminal = false) {
+  float* br = gs + L.br;
+  float* fr = gs + L.fr;
+  float* lr = gs + L.lr;
+  float* ir = gs + L.ir;
+  float* pr = gs + L.pr;
+  float* ar = gs + L.ar;
+  float* bs = gs + L.bs;
+  float* gr = gs + L.gr;
+  const int fb = sc.fb, b = r.b, k = r.k, sl = r.slot;
+  const bool is_base = r.body_lane && fb && b == 0;
+  const bool is_joint = r.body_lane && !is_base;
+
+  // ---- PD law, joint trigonometry, frame B
+  float tau = 0.f, gain = 0.f;
+  if (is_joint) pd_law(tb.kp, tb.kd, tb.taumax, io.dt, io.q, io.v, io.qref, io.vref, tau, gain);
+  io.tau = tau;
+  float base_term = 0.f;
+  if (want_cost && is_base && sc.cost_kind == 1) base_term = base_cost_term(sc, io.bq);
+  if (is_joint) {
+    float cq, sq;
+    sincosf(io.q, &sq, &cq);
+    put4(br + sl * 8, cq, sq, io.v, tau);
+    br[sl * 8 + 4] = gain;
+  }
+  if (is_base) {
+    float R[9];
+    quat_R(io.bq + 3, R);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) bs[q] = R[q];
+    bs[9] = io.bq[0]; bs[10] = io.bq[1]; bs[11] = io.bq[2];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) bs[12 + q] = io.bv[q];
+  }
+  if (!fb && r.c == 0 && r.bl == 0) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) bs[q] = (q % 4 == 0) ? 1.f : 0.f;
+#pragma unroll
+    for (int q = 9; q < 18; ++q) bs[q] = 0.f;
+  }
+  wave_sync();
+
+  // ---- forward kinematics, one body of each chain per level, on the chain's coordinate lanes
+  TFrame F;  // this chain's previous body (the base for chain 0 of a floating base)
+  F.R[0] = 1.f; F.R[1] = 0.f; F.R[2] = 0.f;
+  F.p = 0.f; F.ba = 0.f; F.bl = 0.f;
+  F.va = fb ? bs[12 + k] : 0.f;
+  F.vl = fb ? bs[15 + k] : 0.f;
+  for (int d = 1; d <= sc.max_depth; ++d) {
+    const int sd = r.team ? tcb[r.c * kMaxLevels + d] : -1;  // slot of this chain's body at depth d
+    const bool act = sd >= 0;
+    float tc[16];
+    float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (act) {
+      get16(tt + sd * kTeamSlot + k * kTeamK, tc);
+      s4 = get4(br + sd * 8);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) tc[q] = 0.f;
+    }
+    TFrame P = F;
+    if (act && d == r.cfirst) {  // a chain's first body: its parent is elsewhere
+      if (r.cpar < 0) {
+        P.R[0] = 1.f; P.R[1] = 0.f; P.R[2] = 0.f;
+        P.p = P.va = P.vl = P.ba = P.bl = 0.f;
+      } else if (fb && r.cpar == 0) {
+        P.R[0] = 1.f; P.R[1] = 0.f; P.R[2] = 0.f;
+        P.p = 0.f; P.va = bs[12 + k]; P.vl = bs[15 + k]; P.ba = 0.f; P.bl = 0.f;
+      } else {
+        const float4 f0 = get4(fr + r.pslot * kFrSlot + k * 8), f1 = get4(fr + r.pslot * kFrSlot + k * 8 + 4);
+        P.R[0] = f0.x; P.R[1] = f0.y; P.R[2] = f0.z; P.p = f0.w;
+        P.va = f1.x; P.vl = f1.y; P.ba = f1.z; P.bl = f1.w;
+      }
+    }
+    TFrame O;
+    float e, ax, ca, cl;
+    team_fk(tc, s4.x, s4.y, s4.z, P, O, e, ax, ca, cl);
+    if (act) {
+      put4(fr + sd * kFrSlot + k * 8, O.R[0], O.R[1], O.R[2], O.p);
+      put4(fr + sd * kFrSlot + k * 8 + 4, O.va, O.vl, O.ba, O.bl);
+      put4(lr + sd * kFrSlot + k * 8, e, ax, ca, cl);
+    }
+    F = O;
+    wave_sync();
+  }
+
+  // ---- every body lane: its frame, rigid inertia, bias force, contacts and running cost
+  // (every lane reads its slot's record, so the values are chosen, not the memory)
+  float R[9], p[3], v[6], beta[6];
+#pragma unroll
+  for (int kk = 0; kk < 3; ++kk) {
+    const float4 f0 = get4(fr + sl * kFrSlot + kk * 8), f1 = get4(fr + sl * kFrSlot + kk * 8 + 4);
+    R[kk * 3 + kk] = is_joint ? f0.x : 1.f;
+    R[kk * 3 + (kk + 1) % 3] = is_joint ? f0.y : 0.f;
+    R[kk * 3 + (kk + 2) % 3] = is_joint ? f0.z : 0.f;
+    p[kk] = is_joint ? f0.w : 0.f;
+    v[kk] = is_joint ? f1.x : bs[12 + kk];  // the base: its twist (frame B)
+    v[3 + kk] = is_joint ? f1.y : bs[15 + kk];
+    beta[kk] = is_joint ? f1.z : 0.f;
+    beta[3 + kk] = is_joint ? f1.w : 0.f;
+  }
+  float Rb[9], pb[3];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) Rb[q] = bs[q];
+  pb[0] = bs[9]; pb[1] = bs[10]; pb[2] = bs[11];
+  float lane_cost = 0.f;
+  if (terminal) {
+    if (r.body_lane && sc.cost_kind == 0 && b == sc.ee_body) {
+      const float dz = ee_height_error(R, p, sc.ee_pos, Rb, pb, sc.z_des);
+      lane_cost = sc.w_ee * dz * dz;
+    }
+    io.cost = lane_cost;
+    io.mask = 0u;
+    wave_sync();
+    return;
+  }
+  const float g = sc.g;
+  const float agl[3] = {-g * Rb[6], -g * Rb[7], -g * Rb[8]};
+  uint32_t mask = 0u;
+  if (r.body_lane) {
+    float IA[21], pA[6];
+    if (is_base) {
+#pragma unroll
+      for (int q = 0; q < 21; ++q) IA[q] = tab[q];
+    } else {
+      body_inertia(R, tb.com, tb.Ic, tb.mass, IA);
+    }
+    bias_force(IA, v, pA);
+    const int c0 = tb.c_begin, cn = tb.c_count;
+    for (int ci = c0; ci < c0 + cn; ++ci) {
+      const float* ct = tab + kTabContacts + ci * kCt;
+      float vw[3], fw[3];
+      const float fn = contact_point(ct, R, p, v, beta, Rb, pb, agl, io.dt, sc.law, IA, pA, vw, fw);
+      if (fn > 0.f) mask |= 1u << __float_as_int(ct[4]);
+      if (want_cost && sc.cost_kind == 1) contact_cost(sc, fn, vw, fw, ct[3], lane_cost);
+    }
+    if (want_cost) body_cost(sc, b, is_base, is_joint, base_term, io.q, tb.q0, tau, R, p, Rb, pb, lane_cost);
+    // rows for the coordinate lanes
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      float* d = ir + sl * kTeamSlot + kk * kTeamK;
+      const int c1 = (kk + 1) % 3, c2 = (kk + 2) % 3;
+      put4(d, IA[SI(kk, kk)], IA[SI(kk, c1)], IA[SI(kk, c2)], IA[SI(kk, 3 + kk)]);
+      put4(d + 4, IA[SI(kk, 3 + c1)], IA[SI(kk, 3 + c2)], IA[SI(kk, 3 + kk)], IA[SI(c1, 3 + kk)]);
+      put4(d + 8, IA[SI(c2, 3 + kk)], IA[SI(3 + kk, 3 + kk)], IA[SI(3 + kk, 3 + c1)], IA[SI(3 + kk, 3 + c2)]);
+      put4(d + 12, pA[kk], pA[3 + kk], 0.f, 0.f);
+    }
+  }
+  io.cost = lane_cost;
+  io.mask = mask;
+  wave_sync();
+
+  // ---- backward sweep, leaves to root, on the coordinate lanes
+  float cA[3] = {0.f, 0.f, 0.f}, cB[3] = {0.f, 0.f, 0.f}, cT[3] = {0.f, 0.f, 0.f}, cC[3] = {0.f, 0.f, 0.f};
+  float cpa = 0.f, cpl = 0.f;  // carried by this chain's deeper body
+
+  for (int d = sc.max_depth; d >= 0; --d) {
+    TeamBwdIn cur;
+    const int sd = team_load_bwd(r, tcb, tt, ir, lr, br, d, k, cur);
+    const bool act = cur.act;
+    float A[3] = {cur.ir[0], cur.ir[1], cur.ir[2]}, B[3] = {cur.ir[3], cur.ir[4], cur.ir[5]};
+    float T[3] = {cur.ir[6], cur.ir[7], cur.ir[8]}, C[3] = {cur.ir[9], cur.ir[10], cur.ir[11]};
+    float pa = cur.ir[12], pl = cur.ir[13];
+    const float e = cur.lr[0], ax = cur.lr[1], ca = cur.lr[2], cl = cur.lr[3];
+    const float tau_d = cur.tau, gain_d = cur.gain, arm_d = cur.arm;
+    uint32_t side = cur.side;
+    const bool deeper = act && d < sc.max_depth && tcb[r.c * kMaxLevels + d + 1] >= 0;  // the chain goes on
+    if (deeper) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) { A[i] += cA[i]; B[i] += cB[i]; T[i] += cT[i]; C[i] += cC[i]; }
+      pa += cpa;
+      pl += cpl;
+    }
+    while (side) {
+      const int c2 = __builtin_ctz(side);
+      side &= side - 1u;
+      float q[16];
+      get16(pr + c2 * kTeamSlot + k * kTeamK, q);
+      A[0] += q[0]; A[1] += q[1]; A[2] += q[2]; B[0] += q[3];
+      B[1] += q[4]; B[2] += q[5]; T[0] += q[6]; T[1] += q[7];
+      T[2] += q[8]; C[0] += q[9]; C[1] += q[10]; C[2] += q[11];
+      pa += q[12]; pl += q[13];
+    }
+    float Ua, Ul, invD, u, nA[3], nB[3], nT[3], nC[3], npa, npl;
+    team_backward(A, B, T, C, pa, pl, ax, e, ca, cl, tau_d, arm_d, gain_d, Ua, Ul, invD, u, nA, nB, nT, nC, npa,
+                  npl);
+    const bool base_here = act && fb && d == 0;
+    if (act && !base_here) {
+      put4(lr + sd * kFrSlot + k * 8 + 4, Ua, Ul, invD, u);
+      if (d == r.cfirst && r.cpar >= 0) {
+        float* q = pr + r.c * kTeamSlot + k * kTeamK;
+        put4(q, nA[0], nA[1], nA[2], nB[0]);
+        put4(q + 4, nB[1], nB[2], nT[0], nT[1]);
+        put4(q + 8, nT[2], nC[0], nC[1], nC[2]);
+        put4(q + 12, npa, npl, 0.f, 0.f);
+      }
+    }
+    if (base_here) {  // the floating base: its rows go to the solve
+      float* q = gr + k * kTeamK;
+      put4(q, A[0], A[1], A[2], B[0]);
+      put4(q + 4, B[1], B[2], T[0], T[1]);
+      put4(q + 8, T[2], C[0], C[1], C[2]);
+      put4(q + 12, pa, pl, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { cA[i] = nA[i]; cB[i] = nB[i]; cT[i] = nT[i]; cC[i] = nC[i]; }
+    cpa = npa;
+    cpl = npl;
+    wave_sync();
+  }
+
+  // ---- root: floating base solves IA0 a0' = -pA0
+  if (is_base) {
+    float IA[21], pA[6], a0[6];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      const float* q = gr + kk * kTeamK;
+      const int c1 = (kk + 1) % 3, c2 = (kk + 2) % 3;
+      IA[SI(kk, kk)] = q[0];
+      if (kk <= c1) IA[SI(kk, c1)] = q[1];
+      if (kk <= c2) IA[SI(kk, c2)] = q[2];
+      IA[SI(kk, 3 + kk)] = q[3]; IA[SI(kk, 3 + c1)] = q[4]; IA[SI(kk, 3 + c2)] = q[5];
+      IA[SI(3 + kk, 3 + kk)] = q[9];
+      if (kk <= c1) IA[SI(3 + kk, 3 + c1)] = q[10];
+      if (kk <= c2) IA[SI(3 + kk, 3 + c2)] = q[11];
+      pA[kk] = q[12];
+      pA[3 + kk] = q[13];
+    }
+    base_solve(IA, pA, a0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) bs[18 + q] = a0[q];
+    io.ba[0] = a0[0]; io.ba[1] = a0[1]; io.ba[2] = a0[2];
+    io.ba[3] = a0[3] + agl[0]; io.ba[4] = a0[4] + agl[1]; io.ba[5] = a0[5] + agl[2];
+  }
+  wave_sync();
+
+  // ---- forward sweep, root to leaves, on the coordinate lanes
+  float Fa = fb ? bs[18 + k] : 0.f, Fl = fb ? bs[21 + k] : 0.f;  // chain 0 starts at the base
+  for (int d = 1; d <= sc.max_depth; ++d) {
+    TeamFwdIn cur;
+    const int sd = team_load_fwd(r, tcb, tt, lr, d, k, cur);
+    const bool act = cur.act;
+    const float* lf = cur.lr;
+    const uint32_t side = cur.side;
+    float ala = Fa, all = Fl;
+    if (act && d == r.cfirst) {
+      if (r.cpar < 0) {  // fixed world: a' = -a_g = (0, 0, 0, 0, 0, g)
+        ala = 0.f;
+        all = k == 2 ? g : 0.f;
+      } else if (fb && r.cpar == 0) {
+        ala = bs[18 + k];
+        all = bs[21 + k];
+      } else {
+        const float2 a2 = *reinterpret_cast<const float2*>(ar + r.pslot * 8 + k * 2);
+        ala = a2.x;
+        all = a2.y;
+      }
+    }
+    float aa, al;
+    const float qdd = team_forward(ala, all, lf[0], lf[1], lf[2], lf[3], lf[4], lf[5], lf[6], lf[7], aa, al);
+    if (act) {
+      if (side != 0u) *reinterpret_cast<float2*>(ar + sd * 8 + k * 2) = make_float2(aa, al);
+      if (k == 0) br[sd * 8 + 5] = qdd;
+    }
+    Fa = aa;
+    Fl = al;
+    wave_sync();
+  }
+  io.qdd = is_joint ? br[sl * 8 + 5] : 0.f;
+}
+
+// Fused rollout of one work item on the team schedule (as rollout_item).
+template <int G>
+__device__ __attribute__((always_inline)) void team_item(const DevInst& I, int first, int group_stride,
+                                                         int table_floats, float* smem) {
+  const int lane = threadIdx.x;
+  const int grp = lane / G, l = lane % G;
+  const DevModel& M = *I.model;
+  float* tab = smem;
+  stage_model_table(M, &I, tab, lane);
+  stage_team_table(M, tab, lane);
+  const float* tt = tab + body_table_floats(M.nc);
+  const int* tcb = reinterpret_cast<const int*>(tt + M.team_slots * kTeamSlot);
+  const int n = first + grp;
+  const bool valid = n < I.N;
+  const TeamLayout L = team_layout(G, M.team_slots, I.E, M.n_chains);
+  float* gs = smem + table_floats + grp * group_stride;
+  float* knots = gs + L.knots;
+  float* red = gs + L.red;
+
+  if (I.generate) {
+    sample_group<G>(M, I, valid ? n : 0, l, knots, valid, tab);
+  } else {
+    const float* src = I.samples + (size_t)(valid ? n : 0) * I.E;
+    for (int e = l; e < I.E; e += G) knots[e] = src[e];
+  }
+  wave_sync();
+
+  const StepConst sc = load_step_const(M, &I, 0.f);
+  TeamRole r;
+  const int B = M.team_block;
+  r.c = l / B;
+  r.bl = l % B;
+  const bool in_chain = r.c < M.n_chains;
+  r.team = in_chain && r.bl < 3;
+  r.k = r.bl < 3 ? r.bl : 0;
+  r.cfirst = in_chain ? M.chain_first[r.c] : 0;
+  r.cpar = in_chain ? M.chain_parent[r.c] : -1;
+  r.body_lane = in_chain && r.bl < M.chain_len[r.c];
+  r.b = r.body_lane ? M.chain_body[r.c][r.cfirst + r.bl] : 0;
+  r.slot = r.body_lane ? M.team_slot[r.b] : 0;
+  r.pslot = r.cpar >= 0 ? M.team_slot[r.cpar] : 0;
+  const int fb = sc.fb, nq = fb ? 7 + M.nu : M.nu;
+  const int b = r.b;
+  const bool is_joint = r.body_lane && !(fb && b == 0);
+  const bool is_base = r.body_lane && fb && b == 0;
+  const int j = b - fb;
+  StepIO io;
+  io.q = io.v = 0.f;
+  if (is_joint) {
+    io.q = I.x0[(fb ? 7 : 0) + j];
+    io.v = I.x0[nq + (fb ? 6 : 0) + j];
+  }
+#pragma unroll
+  for (int q = 0; q < 7; ++q) io.bq[q] = fb ? I.x0[q] : 0.f;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) io.bv[q] = fb ? I.x0[nq + q] : 0.f;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) io.ba[q] = 0.f;
+  io.qref = io.vref = 0.f;
+  io.dt = sc.dt;
+
+  TeamBody tb;
+  load_team_body(M, &I, r, tb);
+  uint32_t* const masks = I.masks;
+  const int H = I.H, F = sc.F, F_run = H * sc.nsub;
+  float acc = 0.f;
+  StepClock clk;
+  for (int f = 0; f < F_run; ++f) {
+    const bool control = clk.sub == 0;
+    if (is_joint) {
+      hermite(knots, sc.K, sc.nu, F, sc.delta, sc.inv_delta, clk.seg, clk.rem, j, &io.qref, &io.vref);
+      if (sc.spline_mode != 0) io.vref = 0.f;
+    }
+    team_step(sc, tb, tab, tt, tcb, gs, L, r, io, control);
+    if (control) {
+      acc += io.cost;
+      if (masks) {
+        const uint32_t mk = group_or<G>(io.mask, red, l);
+        if (l == 0 && valid) masks[(size_t)n * H + clk.h] = mk;
+      }
+    }
+    if (is_joint) {
+      io.v = fmaf(io.dt, io.qdd, io.v);
+      io.q = fmaf(io.dt, io.v, io.q);
+    }
+    if (is_base) integrate_base(io.bq, io.bv, io.ba, io.dt);
+    clk.advance(sc.K, F, sc.nsub);
+  }
+  // terminal cost
+  if (sc.cost_kind == 1) {
+    if (is_base) {
+      const float T = (float)H * I.dt;
+      float e = 0.f;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const float target = (q == 2 && I.terminal_z_abs) ? I.z_terminal : I.x0[q] + I.v_des[q] * T;
+        e += fabsf(io.bq[q] - target);
+      }
+      acc += I.w_H * e;
+    }
+  } else {
+    team_step(sc, tb, tab, tt, tcb, gs, L, r, io, false, true);
+    acc += io.cost;
+  }
+  float S = group_sum<G>(acc, red, l);
+  if (l == 0 && valid) {
+    if (!isfinite(S)) S = INFINITY;
+    I.costs[n] = S;
+  }
+  wave_sync();
+}
+
+// Block = one wavefront; work[blockIdx] = (instance, first sample) or, when work
+// is null, instance 0 and sample blockIdx * 64/G.
+template <int G>
+__global__ __launch_bounds__(64) void team_kernel(const DevInst* __restrict__ insts, const int2* __restrict__ work,
+                                                  int group_stride, int table_floats) {
+  extern __shared__ float smem[];
+  constexpr int R = 64 / G;
+  const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
+  const DevInst& I = insts[w.x];
+  team_item<G>(I, w.y, group_stride, table_floats, smem);
+}
+
+// Persistent form (as rollout_persistent_kernel).
+template <int G>
+__global__ __launch_bounds__(64) void team_persistent_kernel(const DevInst* __restrict__ insts,
+                                                             const int2* __restrict__ work, int n_items,
+                                                             unsigned int* __restrict__ counter, int group_stride,
+                                                             int table_floats) {
+  extern __shared__ float smem[];
+  for (;;) {
+    int item = 0;
+    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    item = __builtin_amdgcn_readfirstlane(item);
+    if (item >= n_items) break;
+    const int2 w = work[item];
+    const DevInst& I = insts[w.x];
+    team_item<G>(I, w.y, group_stride, table_floats, smem);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Chain schedule: one lane per kinematic chain (heavy-path decomposition of
 // the tree), 64/GC rollouts per wavefront.  Per step a lane walks its chain
 // root to leaf (Hermite reference, PD law, kinematics), leaf to root (inertia,
@@ -1957,7 +2601,9 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \
   template __global__ void dynamics_kernel<G>(const DevModel*, int, const float*, const float*,        \
-                                              const float*, const float*, float, float*, int, int);
+                                              const float*, const float*, float, float*, int, int);  \
+  template __global__ void team_kernel<G>(const DevInst*, const int2*, int, int);                      \
+  template __global__ void team_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int);
 MPPI_INST(4)
 MPPI_INST(8)
 MPPI_INST(16)

@@ -246,7 +246,7 @@ def make_params(p):
     return s, (f0, q0)
 
 
-SCHEDULES = {"body": 0, "chain": 1}
+SCHEDULES = {"body": 0, "chain": 1, "team": 2}
 
 
 class Controller:
@@ -321,7 +321,7 @@ class Controller:
     def schedule(self):
         s = C.c_int32()
         _check(lib().mppi_get_schedule(self.h, C.byref(s)), "mppi_get_schedule")
-        return "chain" if s.value == 1 else "body"
+        return {v: k for k, v in SCHEDULES.items()}[s.value]
 
     def set_schedule(self, schedule):
         _check(lib().mppi_set_schedule(self.h, SCHEDULES[schedule]), "mppi_set_schedule")

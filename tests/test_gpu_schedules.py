@@ -33,31 +33,9 @@ def _gpu():
     mppi.lib()
 
 
-def ytree_model(seed=0):
-    """Fixed-base branching arm: a yaw root joint carrying a 2-link branch and a
-    3-link branch (the shorter one hangs off the root joint body, so its chain
-    attaches to a joint, not to a floating base)."""
-    rng = np.random.default_rng(seed)
-    L = 0.25 * (1 + rng.uniform(-0.1, 0.1, 5))
-    ms = 1.0 * (1 + rng.uniform(-0.2, 0.2, 6))
-    jt = (-2.5, 2.5, 30.0, 30.0, 0.3, 0.0)
-    t = synth._Tree()
-    r = t.body(-1, (0, 0, 1), (0, 0, 0), ms[0], (0, 0, 0.05), (0.1, 0.1, 0.1), joint=jt)
-    a = t.body(r, (0, 1, 0), (0, 0.1, 0.1), ms[1], (L[0] / 2, 0, 0), (L[0], 0.04, 0.04), joint=jt)
-    b = t.body(a, (0, 1, 0), (L[0], 0, 0), ms[2], (L[1] / 2, 0, 0), (L[1], 0.04, 0.04), joint=jt)
-    c = t.body(b, (1, 0, 0), (L[1], 0, 0), ms[3], (L[2] / 2, 0, 0), (L[2], 0.04, 0.04), joint=jt)
-    d = t.body(r, (0, 1, 0), (0, -0.1, 0.1), ms[4], (L[3] / 2, 0, 0), (L[3], 0.04, 0.04), joint=jt)
-    t.body(d, (0, 1, 0), (L[3], 0, 0), ms[5], (L[4] / 2, 0, 0), (L[4], 0.04, 0.04), joint=jt)
-    m = t.finish("ytree6", False, [], np.zeros((0, 3)), ee_body=c, ee_pos=(L[2], 0, 0))
-    m["n_substeps"] = 1
-    m["armature"] = synth.f32(np.full(6, 0.01))
-    m["x0"] = synth.f32(np.zeros(12))
-    return m
-
-
 def _cfg(name, n_samples, seed=0, **over):
     if name == "ytree":
-        m = ytree_model(seed)
+        m = synth.ytree_model(seed)
         p = synth.params(m, n_samples, 50, 0.01, 5, 2, ("linear", 0.1, 0.3), "ee")
         s = 3000 + seed
     else:
