@@ -2331,6 +2331,7 @@ struct UpdateOut {
 constexpr int kUpdThreads = 1024;
 constexpr int kUpdWaves = kUpdThreads / 64;
 constexpr int kUpdChunk = 4096;  // samples whose weights sit in LDS at a time
+constexpr int kUpdEB = 4;        // blocks of 64 knot elements per pass of the weighted average
 
 // Block-wide reductions in a fixed order (tree over threads), deterministic.
 __device__ __forceinline__ float block_sum(float x, float* buf) {
@@ -2354,7 +2355,7 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
   __shared__ int s_i[kUpdThreads];
   __shared__ float s_x[kUpdThreads];
   __shared__ float s_w[kUpdChunk];
-  __shared__ float s_part[kUpdWaves][64];
+  __shared__ __align__(16) float s_part[kUpdWaves][64 * kUpdEB];
 
   // 1. finite minimum (lowest index), maximum and count
   float mn = INFINITY, mx = -INFINITY;
@@ -2400,45 +2401,126 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
     for (int n = t; n < N; n += kUpdThreads) U.weights[n] = weight(U.costs[n]) * invZ;
 
   // 3. weighted knot average: waves split the samples, lanes the knot elements
+  //    (kUpdEB blocks of 64 elements per pass, so each lane keeps 4 x kUpdEB loads
+  //    in flight); every element's sum runs over the samples of a wave in index
+  //    order, then over the waves in index order
   const UpdateOut* o = outs ? outs + blockIdx.x : &single;
   float* dst = (U.last_iter && o && o->knots_out) ? o->knots_out : U.nominal_out;
   const int wv = t / 64, ln = t % 64;
-  const int n_e = (E + 63) / 64;
-  // accumulate each element's sum across chunks in registers of wave 0 after the reduction
-  for (int eb = 0; eb < n_e; ++eb) {
-    const int e = eb * 64 + ln;
-    float total = 0.f;
+  if ((E & 3) == 0) {
+    // rows of a multiple of 4 floats: a lane reads 4 consecutive elements per
+    // 128-bit load, 8 samples in flight; the same sums in the same order
+    const int E4 = E / 4;
+    float4* part4 = reinterpret_cast<float4*>(&s_part[0][0]);
+    for (int e40 = 0; e40 < E4; e40 += 64) {
+      const int e4 = e40 + ln;
+      const bool ok = e4 < E4;
+      float4 total = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int c0 = 0; c0 < N; c0 += kUpdChunk) {
+        const int cn = min(kUpdChunk, N - c0);
+        __syncthreads();
+        for (int n = t; n < cn; n += kUpdThreads) s_w[n] = weight(U.costs[c0 + n]) * invZ;
+        __syncthreads();
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (nfin > 0 && ok) {
+          const float4* col = reinterpret_cast<const float4*>(U.samples + (size_t)c0 * E) + e4;
+          int n = wv;
+          for (; n + 7 * kUpdWaves < cn; n += 8 * kUpdWaves) {
+            float4 a[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[q] = col[(size_t)(n + q * kUpdWaves) * E4];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const float w = s_w[n + q * kUpdWaves];
+              acc.x = fmaf(w, a[q].x, acc.x); acc.y = fmaf(w, a[q].y, acc.y);
+              acc.z = fmaf(w, a[q].z, acc.z); acc.w = fmaf(w, a[q].w, acc.w);
+            }
+          }
+          for (; n < cn; n += kUpdWaves) {
+            const float w = s_w[n];
+            const float4 a = col[(size_t)n * E4];
+            acc.x = fmaf(w, a.x, acc.x); acc.y = fmaf(w, a.y, acc.y);
+            acc.z = fmaf(w, a.z, acc.z); acc.w = fmaf(w, a.w, acc.w);
+          }
+        }
+        part4[wv * 64 + ln] = acc;
+        __syncthreads();
+        if (wv == 0) {
+          float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+          for (int k = 0; k < kUpdWaves; ++k) {
+            const float4 v = part4[k * 64 + ln];
+            sum.x += v.x; sum.y += v.y; sum.z += v.z; sum.w += v.w;
+          }
+          total.x += sum.x; total.y += sum.y; total.z += sum.z; total.w += sum.w;
+        }
+      }
+      if (wv == 0 && ok) {
+        const float tv[4] = {total.x, total.y, total.z, total.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[4 * e4 + q] = nfin > 0 ? tv[q] : U.nominal_in[4 * e4 + q];
+      }
+    }
+  }
+  for (int e0 = 0; (E & 3) != 0 && e0 < E; e0 += 64 * kUpdEB) {
+    float total[kUpdEB];
+#pragma unroll
+    for (int b = 0; b < kUpdEB; ++b) total[b] = 0.f;
     for (int c0 = 0; c0 < N; c0 += kUpdChunk) {
       const int cn = min(kUpdChunk, N - c0);
       __syncthreads();
       for (int n = t; n < cn; n += kUpdThreads) s_w[n] = weight(U.costs[c0 + n]) * invZ;
       __syncthreads();
-      float acc = 0.f;
-      if (e < E && nfin > 0) {
-        const float* col = U.samples + (size_t)c0 * E + e;
+      float acc[kUpdEB];
+#pragma unroll
+      for (int b = 0; b < kUpdEB; ++b) acc[b] = 0.f;
+      if (nfin > 0) {
+        const float* col = U.samples + (size_t)c0 * E + e0 + ln;
+        bool ok[kUpdEB];
+#pragma unroll
+        for (int b = 0; b < kUpdEB; ++b) ok[b] = e0 + b * 64 + ln < E;
         int n = wv;
         for (; n + 3 * kUpdWaves < cn; n += 4 * kUpdWaves) {
-          const float a0 = col[(size_t)n * E];
-          const float a1 = col[(size_t)(n + kUpdWaves) * E];
-          const float a2 = col[(size_t)(n + 2 * kUpdWaves) * E];
-          const float a3 = col[(size_t)(n + 3 * kUpdWaves) * E];
-          acc = fmaf(s_w[n], a0, acc);
-          acc = fmaf(s_w[n + kUpdWaves], a1, acc);
-          acc = fmaf(s_w[n + 2 * kUpdWaves], a2, acc);
-          acc = fmaf(s_w[n + 3 * kUpdWaves], a3, acc);
+          float a[4][kUpdEB];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int b = 0; b < kUpdEB; ++b)
+              a[q][b] = ok[b] ? col[(size_t)(n + q * kUpdWaves) * E + b * 64] : 0.f;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float w = s_w[n + q * kUpdWaves];
+#pragma unroll
+            for (int b = 0; b < kUpdEB; ++b) acc[b] = fmaf(w, a[q][b], acc[b]);
+          }
         }
-        for (; n < cn; n += kUpdWaves) acc = fmaf(s_w[n], col[(size_t)n * E], acc);
+        for (; n < cn; n += kUpdWaves) {
+          const float w = s_w[n];
+#pragma unroll
+          for (int b = 0; b < kUpdEB; ++b)
+            if (ok[b]) acc[b] = fmaf(w, col[(size_t)n * E + b * 64], acc[b]);
+        }
       }
-      s_part[wv][ln] = acc;
+#pragma unroll
+      for (int b = 0; b < kUpdEB; ++b) s_part[wv][b * 64 + ln] = acc[b];
       __syncthreads();
       if (wv == 0) {
-        float sum = 0.f;
 #pragma unroll
-        for (int k = 0; k < kUpdWaves; ++k) sum += s_part[k][ln];
-        total += sum;
+        for (int b = 0; b < kUpdEB; ++b) {
+          float sum = 0.f;
+#pragma unroll
+          for (int k = 0; k < kUpdWaves; ++k) sum += s_part[k][b * 64 + ln];
+          total[b] += sum;
+        }
       }
     }
-    if (wv == 0 && e < E) dst[e] = nfin > 0 ? total : U.nominal_in[e];
+    if (wv == 0) {
+#pragma unroll
+      for (int b = 0; b < kUpdEB; ++b) {
+        const int e = e0 + b * 64 + ln;
+        if (e < E) dst[e] = nfin > 0 ? total[b] : U.nominal_in[e];
+      }
+    }
   }
   __syncthreads();
 
