@@ -346,6 +346,27 @@ __device__ __forceinline__ void fk_joint(const float* Rl, const float* pl, const
   for (int k = 0; k < 6; ++k) beta[k] = bs[k] + c[k];
 }
 
+// fk_joint for a child of the floating base, whose frame in base axes is the
+// identity at the origin with twist bv and no bias acceleration: R = C(q),
+// e = p = p_tree, ax = axis_p (the same values fk_joint gives for that parent).
+__device__ __forceinline__ void fk_base_child(const float* bv, const float* P, const float* p_tree,
+                                              const float* axis_p, float cq, float sq, float qd, float* R, float* p,
+                                              float* e, float* ax, float* v, float* c, float* beta) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = P[k] + cq * P[9 + k] + sq * P[18 + k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    e[r] = p_tree[r];
+    p[r] = p_tree[r];
+    ax[r] = axis_p[r];
+  }
+  shift_motion(bv, e, v);
+  v[0] += ax[0] * qd; v[1] += ax[1] * qd; v[2] += ax[2] * qd;
+  vel_product(v, ax, qd, c);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) beta[k] = c[k];
+}
+
 // Spatial inertia (packed) of a rigid body about its origin in base axes, from
 // its rotation R, com and inertia Ic about the com (body frame) and mass m.
 __device__ __forceinline__ void body_inertia(const float* R, const float* com, const float* Ic, float m, float* IA) {
@@ -791,25 +812,31 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
     }
     if (is_joint && depth == d) {
       const int lam = bc.parent;
-      float Rl[9], pl[3], vl[6], bl[6];
-      if (bc.flags & kAdjParent) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Rl[k] = sR[k];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) pl[k] = sp[k];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) { vl[k] = sv[k]; bl[k] = sb[k]; }
-      } else if (lam >= 0) {
-        get_frame(slots + lam * kSlot, Rl, pl, vl, bl);
+      if (fb && d == 1) {  // a child of the floating base: frame identity, twist bv (from the base slot)
+        const float4 v0 = get4(slots + 12), v1 = get4(slots + 16);
+        const float bvl[6] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y};
+        fk_base_child(bvl, bc.P, bc.p_tree, bc.axis_p, cq, sq, io.v, R, p, e, ax, v, c, beta);
       } else {
+        float Rl[9], pl[3], vl[6], bl[6];
+        if (bc.flags & kAdjParent) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Rl[k] = (k % 4 == 0) ? 1.f : 0.f;
+          for (int k = 0; k < 9; ++k) Rl[k] = sR[k];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) pl[k] = 0.f;
+          for (int k = 0; k < 3; ++k) pl[k] = sp[k];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) { vl[k] = 0.f; bl[k] = 0.f; }
+          for (int k = 0; k < 6; ++k) { vl[k] = sv[k]; bl[k] = sb[k]; }
+        } else if (lam >= 0) {
+          get_frame(slots + lam * kSlot, Rl, pl, vl, bl);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Rl[k] = (k % 4 == 0) ? 1.f : 0.f;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) pl[k] = 0.f;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) { vl[k] = 0.f; bl[k] = 0.f; }
+        }
+        fk_joint(Rl, pl, vl, bl, bc.P, bc.p_tree, bc.axis_p, cq, sq, io.v, R, p, e, ax, v, c, beta);
       }
-      fk_joint(Rl, pl, vl, bl, bc.P, bc.p_tree, bc.axis_p, cq, sq, io.v, R, p, e, ax, v, c, beta);
       if (bc.flags & kFrameOut) put_frame(slots + b * kSlot, R, p, v, beta);
     }
     wave_sync();
@@ -1056,14 +1083,22 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
 #pragma unroll
   for (int r = 0; r < 3; ++r) bq[r] += dt * (R[r * 3 + 0] * bv[3] + R[r * 3 + 1] * bv[4] + R[r * 3 + 2] * bv[5]);
   const float wn = sqrtf(bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2]);
-  float e0 = 1.f, e1 = 0.f, e2 = 0.f, e3 = 0.f;
-  if (wn > 0.f) {
-    const float th = 0.5f * wn * dt;
+  // exp of the half rotation: (cos th, sin th w / |w|), th = |w| dt / 2; below
+  // th = 1/4 by the Taylor series of cos th and sin th / th to the th^6 term
+  // (truncation below 5e-10, under float rounding)
+  const float th = 0.5f * wn * dt;
+  float e0, k;
+  if (th < 0.25f) {
+    const float t2 = th * th;
+    e0 = 1.f + t2 * (-0.5f + t2 * (1.f / 24.f + t2 * (-1.f / 720.f)));
+    k = (0.5f * dt) * (1.f + t2 * (-1.f / 6.f + t2 * (1.f / 120.f + t2 * (-1.f / 5040.f))));
+  } else {
     float sn, cs;
     sincosf(th, &sn, &cs);
-    const float k = sn * rcp(wn);
-    e0 = cs; e1 = k * bv[0]; e2 = k * bv[1]; e3 = k * bv[2];
+    e0 = cs;
+    k = sn * rcp(wn);
   }
+  const float e1 = k * bv[0], e2 = k * bv[1], e3 = k * bv[2];
   const float a0 = bq[3], a1 = bq[4], a2 = bq[5], a3 = bq[6];
   const float r0 = a0 * e0 - a1 * e1 - a2 * e2 - a3 * e3;
   const float r1 = a0 * e1 + a1 * e0 + a2 * e3 - a3 * e2;
