@@ -25,7 +25,7 @@
 
 namespace mppi {
 // kernels (mppi_kernels.hip)
-template <int G> __global__ void rollout_kernel(const DevInst*, const int2*, int, int);
+template <int G, int D> __global__ void rollout_kernel(const DevInst*, const int2*, int, int);
 template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
 template <int G> __global__ void team_kernel(const DevInst*, const int2*, int, int);
@@ -647,7 +647,7 @@ extern "C" mppi_status mppi_get_schedule(const mppi_ctx* c, int32_t* schedule) {
 
 // Largest per-instance sizes of one launch (they size the LDS regions).
 struct Dims {
-  int E = 0, nb = 0, nc = 0, nch = 0, natt = 0, ns = 0;
+  int E = 0, nb = 0, nc = 0, nch = 0, natt = 0, ns = 0, depth = 0;
   void add(const mppi_ctx* c) {
     const DevModel& M = c->m->host;
     E = std::max(E, c->E);
@@ -656,6 +656,7 @@ struct Dims {
     nch = std::max(nch, M.n_chains);
     natt = std::max(natt, M.n_att);
     ns = std::max(ns, M.team_slots);
+    depth = std::max(depth, M.max_depth);
   }
 };
 static Dims dims_of(const mppi_ctx* c) {
@@ -695,10 +696,17 @@ static LaunchShape launch_shape(int key, const Dims& dm) {
 }
 static int rollouts_per_block(int key, const Dims& dm) { return launch_shape(key, dm).groups; }
 
+// the body schedule's kernel for trees at most 3 or 6 levels deep has its level
+// loops unrolled; deeper trees take the general one
 template <int G>
 static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
-                                   hipStream_t s) {
-  hipLaunchKernelGGL(rollout_kernel<G>, dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+                                   int depth, hipStream_t s) {
+  if (depth <= 3)
+    hipLaunchKernelGGL((rollout_kernel<G, 3>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+  else if (depth <= 6)
+    hipLaunchKernelGGL((rollout_kernel<G, 6>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+  else
+    hipLaunchKernelGGL((rollout_kernel<G, 0>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
   return hipGetLastError();
 }
 template <int G>
@@ -718,11 +726,11 @@ static hipError_t launch_rollout(int key, int blocks, const DevInst* insts, cons
                                  hipStream_t s) {
   const LaunchShape sh = launch_shape(key, dm);
   switch (key) {
-    case 4: return launch_rollout_G<4>(blocks, insts, work, sh, s);
-    case 8: return launch_rollout_G<8>(blocks, insts, work, sh, s);
-    case 16: return launch_rollout_G<16>(blocks, insts, work, sh, s);
-    case 32: return launch_rollout_G<32>(blocks, insts, work, sh, s);
-    case 64: return launch_rollout_G<64>(blocks, insts, work, sh, s);
+    case 4: return launch_rollout_G<4>(blocks, insts, work, sh, dm.depth, s);
+    case 8: return launch_rollout_G<8>(blocks, insts, work, sh, dm.depth, s);
+    case 16: return launch_rollout_G<16>(blocks, insts, work, sh, dm.depth, s);
+    case 32: return launch_rollout_G<32>(blocks, insts, work, sh, dm.depth, s);
+    case 64: return launch_rollout_G<64>(blocks, insts, work, sh, dm.depth, s);
     case kTeamKey + 4: return launch_team_G<4>(blocks, insts, work, sh, s);
     case kTeamKey + 8: return launch_team_G<8>(blocks, insts, work, sh, s);
     case kTeamKey + 16: return launch_team_G<16>(blocks, insts, work, sh, s);

@@ -754,9 +754,12 @@ __device__ __forceinline__ float forward_joint(const float* al, const float* e, 
 // terminal = true evaluates only the kinematics and the end-effector height term
 // of the terminal cost (end-effector task) at the current state.
 // ---------------------------------------------------------------------------
-template <int G>
+// D > 0: the tree is at most D levels deep, fixed at compile time so the level
+// loops unroll (levels below the tree have no body and cost only their shifts).
+template <int G, int D = 0>
 __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const float* tab, float* __restrict__ gs,
                              int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
+  const int maxd = D > 0 ? D : sc.max_depth;
   float* slots = gs;
   float* base = gs + G * kSlot;
   const int fb = sc.fb;
@@ -800,7 +803,8 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   }
   float cq = 0.f, sq = 0.f;
   if (is_joint) sincosf(io.q, &sq, &cq);
-  for (int d = 1; d <= sc.max_depth; ++d) {
+#pragma unroll (D > 0 ? D : 1)
+  for (int d = 1; d <= maxd; ++d) {
     float sR[9], sp[3], sv[6], sb[6];  // the previous lane's frame (level d - 1)
     if (d > 1) {
 #pragma unroll
@@ -890,7 +894,8 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // ---- backward sweep, leaves to root: each joint lane publishes its
   //      articulated inertia and bias already carried to its parent's origin
   float U[6], invD = 0.f, u = 0.f;
-  for (int d = sc.max_depth; d >= 0; --d) {
+#pragma unroll (D > 0 ? D + 1 : 1)
+  for (int d = maxd; d >= 0; --d) {
     // inertia and bias carried to the parent by the lanes of level d (any value elsewhere)
     float Ip[21], pp[6];
 #pragma unroll
@@ -935,7 +940,8 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // ---- forward sweep: accelerations, root to leaves
   float qdd = 0.f;
   float a[6], sa[6];  // this lane's and the previous lane's acceleration
-  for (int d = 1; d <= sc.max_depth; ++d) {
+#pragma unroll (D > 0 ? D : 1)
+  for (int d = 1; d <= maxd; ++d) {
     if (is_joint && depth == d) {
       const int lam = bc.parent;
       float al[6];
@@ -952,7 +958,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
       if (bc.flags & kFrameOut) put_acc(slots + b * kSlot, a);
     }
     wave_sync();
-    if (d < sc.max_depth) {
+    if (d < maxd) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) sa[k] = from_prev_lane(a[k]);
     }
@@ -1115,7 +1121,7 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
 // steps control steps are simulated (the horizon for a rollout).  With state_out
 // set (state prediction, one sample) the state reached is written there and
 // no cost is formed.
-template <int G>
+template <int G, int D = 0>
 __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride,
                                                             int table_floats, float* smem, int steps,
                                                             float* state_out) {
@@ -1172,7 +1178,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
       hermite(knots, sc.K, sc.nu, F, sc.delta, sc.inv_delta, clk.seg, clk.rem, j, &io.qref, &io.vref);
       if (sc.spline_mode != 0) io.vref = 0.f;  // position-only variants: zero velocity targets
     }
-    physics_step<G>(sc, bc, tab, gs, b, body_lane, io, control);
+    physics_step<G, D>(sc, bc, tab, gs, b, body_lane, io, control);
     if (control) {
       acc += io.cost;
       if (masks) {
@@ -1217,7 +1223,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     }
   } else {
     // end-effector height at x_H
-    physics_step<G>(sc, bc, tab, gs, b, body_lane, io, false, true);
+    physics_step<G, D>(sc, bc, tab, gs, b, body_lane, io, false, true);
     acc += io.cost;
   }
   float S = group_sum<G>(acc, red, l);
@@ -1230,14 +1236,15 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 
 // Block = one wavefront; work[blockIdx] = (instance, first sample) or, when work
 // is null, instance 0 and sample blockIdx * 64/G.
-template <int G>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_kernel(const DevInst* __restrict__ insts, const int2* __restrict__ work,
-                                                     int group_stride, int table_floats) {
+// D > 0: every instance of the launch is at most D levels deep.
+template <int G, int D>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_kernel(
+    const DevInst* __restrict__ insts, const int2* __restrict__ work, int group_stride, int table_floats) {
   extern __shared__ float smem[];
   constexpr int R = 64 / G;
   const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
   const DevInst& I = insts[w.x];
-  rollout_item<G>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
+  rollout_item<G, D>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
 }
 
 // State prediction: sample 0 of the instance (its knots read from samples) run
@@ -2713,7 +2720,9 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
 
 // explicit instantiations
 #define MPPI_INST(G)                                                                                   \
-  template __global__ void rollout_kernel<G>(const DevInst*, const int2*, int, int);                   \
+  template __global__ void rollout_kernel<G, 0>(const DevInst*, const int2*, int, int);                \
+  template __global__ void rollout_kernel<G, 3>(const DevInst*, const int2*, int, int);                \
+  template __global__ void rollout_kernel<G, 6>(const DevInst*, const int2*, int, int);                \
   template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int); \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \
