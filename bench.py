@@ -73,6 +73,22 @@ def measured_traffic(digest):
         return None
 
 
+def kernel_label(m, schedule, lanes):
+    """Name of the rollout kernel instance the library launches for model m: the
+    body and team kernels are specialised on tree depth (at most 3 or 6 levels
+    below the root, else the generic loop, 0)."""
+    par = [int(x) for x in m["parent"]]
+    depth = []
+    for i, lam in enumerate(par):
+        depth.append((0 if m["floating_base"] else 1) if lam < 0 else depth[lam] + 1)
+    d = max(depth)
+    spec = 3 if d <= 3 else 6 if d <= 6 else 0
+    if schedule == "chain":
+        return f"chain_kernel<{lanes}>"
+    name = "team_kernel" if schedule == "team" else "rollout_kernel"
+    return f"{name}<{lanes}, {spec}>"
+
+
 def primary(args, torch, mppi, synth, flops):
     m, p, seed = synth.config("quadruped_tp", n_samples=args.samples)
     model = mppi.Model(m)
@@ -456,8 +472,7 @@ def main():
             "frac": res["achieved_tflops"] / FP32_PEAK_TFLOPS,
             "frac_nonpacked_peak": res["achieved_tflops"] / FP32_PEAK_NONPACKED,
             "traffic": traffic,
-            "kernel": {"chain": "chain_kernel", "team": "team_kernel"}.get(res["schedule"], "rollout_kernel")
-                      + f"<{res['lanes']}>",
+            "kernel": kernel_label(res["model"], res["schedule"], res["lanes"]),
             "kernel_ms": res["kernel_ms"],
             "update_kernel_ms": res["update_ms"],
             "flops_per_rollout_step": res["flops_per_rollout_step"],

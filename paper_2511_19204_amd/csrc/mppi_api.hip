@@ -28,7 +28,7 @@ namespace mppi {
 template <int G, int D> __global__ void rollout_kernel(const DevInst*, const int2*, int, int);
 template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
-template <int G> __global__ void team_kernel(const DevInst*, const int2*, int, int);
+template <int G, int D> __global__ void team_kernel(const DevInst*, const int2*, int, int);
 template <int G> __global__ void team_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int, int);
 __global__ void reset_counters(unsigned int*, int);
@@ -710,9 +710,14 @@ static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2*
   return hipGetLastError();
 }
 template <int G>
-static hipError_t launch_team_G(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
+static hipError_t launch_team_G(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh, int depth,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(team_kernel<G>, dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+  if (depth <= 3)
+    hipLaunchKernelGGL((team_kernel<G, 3>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+  else if (depth <= 6)
+    hipLaunchKernelGGL((team_kernel<G, 6>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+  else
+    hipLaunchKernelGGL((team_kernel<G, 0>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
   return hipGetLastError();
 }
 template <int GC>
@@ -731,11 +736,11 @@ static hipError_t launch_rollout(int key, int blocks, const DevInst* insts, cons
     case 16: return launch_rollout_G<16>(blocks, insts, work, sh, dm.depth, s);
     case 32: return launch_rollout_G<32>(blocks, insts, work, sh, dm.depth, s);
     case 64: return launch_rollout_G<64>(blocks, insts, work, sh, dm.depth, s);
-    case kTeamKey + 4: return launch_team_G<4>(blocks, insts, work, sh, s);
-    case kTeamKey + 8: return launch_team_G<8>(blocks, insts, work, sh, s);
-    case kTeamKey + 16: return launch_team_G<16>(blocks, insts, work, sh, s);
-    case kTeamKey + 32: return launch_team_G<32>(blocks, insts, work, sh, s);
-    case kTeamKey + 64: return launch_team_G<64>(blocks, insts, work, sh, s);
+    case kTeamKey + 4: return launch_team_G<4>(blocks, insts, work, sh, dm.depth, s);
+    case kTeamKey + 8: return launch_team_G<8>(blocks, insts, work, sh, dm.depth, s);
+    case kTeamKey + 16: return launch_team_G<16>(blocks, insts, work, sh, dm.depth, s);
+    case kTeamKey + 32: return launch_team_G<32>(blocks, insts, work, sh, dm.depth, s);
+    case kTeamKey + 64: return launch_team_G<64>(blocks, insts, work, sh, dm.depth, s);
     case -1: return launch_chain_GC<1>(blocks, insts, work, sh, s);
     case -2: return launch_chain_GC<2>(blocks, insts, work, sh, s);
     case -4: return launch_chain_GC<4>(blocks, insts, work, sh, s);

@@ -1505,6 +1505,7 @@ __device__ __forceinline__ int team_load_fwd(const TeamRole& r, const int* tcb, 
 // tt = team constants and tcb = chain-body table in LDS.  Every coordinate-lane
 // computation runs with all lanes active (the DPP permutations need them); the
 // lanes of a level without a body compute on zeros and store nothing.
+template <int D>
 __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, const TeamBody& tb, const float* tab,
                                                          const float* tt, const int* tcb,
                           float* __restrict__ gs, const TeamLayout& L, const TeamRole& r, StepIO& io, bool want_cost,
@@ -1520,6 +1521,7 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
   const int fb = sc.fb, b = r.b, k = r.k, sl = r.slot;
   const bool is_base = r.body_lane && fb && b == 0;
   const bool is_joint = r.body_lane && !is_base;
+  const int maxd = D > 0 ? D : sc.max_depth;
 
   // ---- PD law, joint trigonometry, frame B
   float tau = 0.f, gain = 0.f;
@@ -1556,7 +1558,8 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
   F.p = 0.f; F.ba = 0.f; F.bl = 0.f;
   F.va = fb ? bs[12 + k] : 0.f;
   F.vl = fb ? bs[15 + k] : 0.f;
-  for (int d = 1; d <= sc.max_depth; ++d) {
+#pragma unroll (D > 0 ? D : 1)
+  for (int d = 1; d <= maxd; ++d) {
     const int sd = r.team ? tcb[r.c * kMaxLevels + d] : -1;  // slot of this chain's body at depth d
     const bool act = sd >= 0;
     float tc[16];
@@ -1664,7 +1667,8 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
   float cA[3] = {0.f, 0.f, 0.f}, cB[3] = {0.f, 0.f, 0.f}, cT[3] = {0.f, 0.f, 0.f}, cC[3] = {0.f, 0.f, 0.f};
   float cpa = 0.f, cpl = 0.f;  // carried by this chain's deeper body
 
-  for (int d = sc.max_depth; d >= 0; --d) {
+#pragma unroll (D > 0 ? D + 1 : 1)
+  for (int d = maxd; d >= 0; --d) {
     TeamBwdIn cur;
     const int sd = team_load_bwd(r, tcb, tt, ir, lr, br, d, k, cur);
     const bool act = cur.act;
@@ -1674,7 +1678,7 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
     const float e = cur.lr[0], ax = cur.lr[1], ca = cur.lr[2], cl = cur.lr[3];
     const float tau_d = cur.tau, gain_d = cur.gain, arm_d = cur.arm;
     uint32_t side = cur.side;
-    const bool deeper = act && d < sc.max_depth && tcb[r.c * kMaxLevels + d + 1] >= 0;  // the chain goes on
+    const bool deeper = act && d < maxd && tcb[r.c * kMaxLevels + d + 1] >= 0;  // the chain goes on
     if (deeper) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) { A[i] += cA[i]; B[i] += cB[i]; T[i] += cT[i]; C[i] += cC[i]; }
@@ -1746,7 +1750,8 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
 
   // ---- forward sweep, root to leaves, on the coordinate lanes
   float Fa = fb ? bs[18 + k] : 0.f, Fl = fb ? bs[21 + k] : 0.f;  // chain 0 starts at the base
-  for (int d = 1; d <= sc.max_depth; ++d) {
+#pragma unroll (D > 0 ? D : 1)
+  for (int d = 1; d <= maxd; ++d) {
     TeamFwdIn cur;
     const int sd = team_load_fwd(r, tcb, tt, lr, d, k, cur);
     const bool act = cur.act;
@@ -1780,7 +1785,7 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
 }
 
 // Fused rollout of one work item on the team schedule (as rollout_item).
-template <int G>
+template <int G, int D = 0>
 __device__ __attribute__((always_inline)) void team_item(const DevInst& I, int first, int group_stride,
                                                          int table_floats, float* smem) {
   const int lane = threadIdx.x;
@@ -1852,7 +1857,7 @@ __device__ __attribute__((always_inline)) void team_item(const DevInst& I, int f
       hermite(knots, sc.K, sc.nu, F, sc.delta, sc.inv_delta, clk.seg, clk.rem, j, &io.qref, &io.vref);
       if (sc.spline_mode != 0) io.vref = 0.f;
     }
-    team_step(sc, tb, tab, tt, tcb, gs, L, r, io, control);
+    team_step<D>(sc, tb, tab, tt, tcb, gs, L, r, io, control);
     if (control) {
       acc += io.cost;
       if (masks) {
@@ -1880,7 +1885,7 @@ __device__ __attribute__((always_inline)) void team_item(const DevInst& I, int f
       acc += I.w_H * e;
     }
   } else {
-    team_step(sc, tb, tab, tt, tcb, gs, L, r, io, false, true);
+    team_step<D>(sc, tb, tab, tt, tcb, gs, L, r, io, false, true);
     acc += io.cost;
   }
   float S = group_sum<G>(acc, red, l);
@@ -1893,14 +1898,14 @@ __device__ __attribute__((always_inline)) void team_item(const DevInst& I, int f
 
 // Block = one wavefront; work[blockIdx] = (instance, first sample) or, when work
 // is null, instance 0 and sample blockIdx * 64/G.
-template <int G>
+template <int G, int D>
 __global__ __launch_bounds__(64) void team_kernel(const DevInst* __restrict__ insts, const int2* __restrict__ work,
                                                   int group_stride, int table_floats) {
   extern __shared__ float smem[];
   constexpr int R = 64 / G;
   const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
   const DevInst& I = insts[w.x];
-  team_item<G>(I, w.y, group_stride, table_floats, smem);
+  team_item<G, D>(I, w.y, group_stride, table_floats, smem);
 }
 
 // Persistent form (as rollout_persistent_kernel).
@@ -2728,7 +2733,9 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \
   template __global__ void dynamics_kernel<G>(const DevModel*, int, const float*, const float*,        \
                                               const float*, const float*, float, float*, int, int);  \
-  template __global__ void team_kernel<G>(const DevInst*, const int2*, int, int);                      \
+  template __global__ void team_kernel<G, 0>(const DevInst*, const int2*, int, int);                   \
+  template __global__ void team_kernel<G, 3>(const DevInst*, const int2*, int, int);                   \
+  template __global__ void team_kernel<G, 6>(const DevInst*, const int2*, int, int);                   \
   template __global__ void team_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int);
 MPPI_INST(4)
 MPPI_INST(8)
