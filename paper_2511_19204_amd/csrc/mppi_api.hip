@@ -681,7 +681,7 @@ static LaunchShape launch_shape(int key, const Dims& dm) {
     sh.lds = (sh.table + sh.groups * sh.stride) * (int)sizeof(float);
   } else if (key > 0) {
     sh.stride = group_floats(key, dm.E);
-    sh.table = body_table_floats(dm.nc);
+    sh.table = body_sched_table_floats(dm.nb, dm.nc);
     sh.groups = 64 / key;
     sh.lds = (sh.table + sh.groups * sh.stride) * (int)sizeof(float);
   } else {
@@ -847,7 +847,7 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
 // ---------------------------------------------------------------------------
 template <int G>
 static hipError_t launch_predict_G(const mppi_ctx* c, int steps, float* out, hipStream_t s) {
-  const int table = body_table_floats(c->nc);
+  const int table = body_sched_table_floats(c->m->host.nb, c->nc);
   const int stride = group_floats(G, c->E);
   const int lds = (table + (64 / G) * stride) * (int)sizeof(float);
   hipLaunchKernelGGL(predict_kernel<G>, dim3(1), dim3(64), lds, s, c->d_pred_inst, steps, out, stride, table);
@@ -1373,7 +1373,7 @@ template <int G>
 static hipError_t launch_dyn_G(const mppi_model* m, int n, const float* q, const float* v, const float* qr,
                                const float* vr, float dt, float* qdd, hipStream_t s) {
   const int R = 64 / G;
-  const int table = body_table_floats(m->host.nc);
+  const int table = body_sched_table_floats(m->host.nb, m->host.nc);
   const int lds = (table + R * group_floats(G, 0)) * (int)sizeof(float);
   hipLaunchKernelGGL(dynamics_kernel<G>, dim3((n + R - 1) / R), dim3(64), lds, s, m->dev, n, q, v, qr, vr, dt, qdd,
                      group_floats(G, 0), table);

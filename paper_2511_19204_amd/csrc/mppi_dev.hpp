@@ -162,6 +162,12 @@ constexpr int kTabSpline = 24;
 constexpr int kTabContacts = 88;
 __host__ __device__ inline int body_table_floats(int nc) { return kTabContacts + nc * kCt; }
 
+// Body schedule: the model table is followed by every body's joint-rotation
+// constants P0 | P1 | P2 (27 floats, rows 16-byte aligned), read once per
+// physics step instead of being held in registers.
+constexpr int kPRow = 28;
+__host__ __device__ inline int body_sched_table_floats(int nb, int nc) { return body_table_floats(nc) + nb * kPRow; }
+
 // Chain schedule: after the model table (with body rows and chain bodies), one
 // region per rollout group:
 //   rec[nb][kRec]   per-body record (see the chain kernel)

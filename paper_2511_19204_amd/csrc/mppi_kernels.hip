@@ -160,7 +160,7 @@ struct StepIO {
 
 // Per-lane constants of the body (and joint) a lane owns, loaded once per work item.
 struct BodyConst {
-  float P[27];        // joint rotation C(q) = P0 + cos q P1 + sin q P2
+  const float* P;     // joint rotation C(q) = P0 + cos q P1 + sin q P2, a row of the LDS table
   float p_tree[3], axis_p[3], com[3], Ic[6];
   float mass, kp, kd, taumax, arm, q0;
   int parent, depth, n_child, c_begin, c_count;
@@ -177,12 +177,12 @@ constexpr uint32_t kAdjChild = 2u;   // first child is the next lane
 constexpr uint32_t kFrameOut = 4u;   // joint body with a child that reads its frame and acceleration from LDS
 constexpr uint32_t kArtOut = 8u;     // joint body whose parent reads its articulated inertia from LDS
 
-__device__ __forceinline__ void load_body(const DevModel& M, const DevInst* I, int b, bool body_lane, BodyConst& c) {
+__device__ __forceinline__ void load_body(const DevModel& M, const DevInst* I, int b, bool body_lane, const float* tab,
+                                          BodyConst& c) {
   const int bb = body_lane ? b : 0;
   const int j = bb - M.fb;
   const bool joint = body_lane && j >= 0;
-#pragma unroll
-  for (int k = 0; k < 27; ++k) c.P[k] = M.P[bb][k];
+  c.P = tab + body_table_floats(M.nc) + bb * kPRow;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     c.p_tree[k] = M.p_tree[bb][k];
@@ -314,17 +314,26 @@ __device__ __forceinline__ void vel_product(const float* v, const float* ax, flo
   cross3(v + 3, aq, c + 3);
 }
 
-// Forward kinematics of a revolute body from its parent's frame (Rl, pl), twist
-// vl and bias acceleration bl: rotation R = Rl C(q), origin p, lever arm
-// e = p - pl, axis ax (base axes), twist v, velocity product c and bias
-// acceleration beta, all about the body's own origin.
-__device__ __forceinline__ void fk_joint(const float* Rl, const float* pl, const float* vl, const float* bl,
-                                         const float* P, const float* p_tree, const float* axis_p, float cq, float sq,
-                                         float qd, float* R, float* p, float* e, float* ax, float* v, float* c,
-                                         float* beta) {
-  float C[9];
+// Joint rotation C(q) = P0 + cos q P1 + sin q P2 (row-major 3x3) from the 27
+// constants P0 | P1 | P2 at a 16-byte aligned address.
+__device__ __forceinline__ void joint_rotation(const float* P, float cq, float sq, float* C) {
+  float t[28];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) C[k] = P[k] + cq * P[9 + k] + sq * P[18 + k];
+  for (int k = 0; k < 7; ++k) {
+    const float4 x = *reinterpret_cast<const float4*>(P + 4 * k);
+    t[4 * k] = x.x; t[4 * k + 1] = x.y; t[4 * k + 2] = x.z; t[4 * k + 3] = x.w;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) C[k] = t[k] + cq * t[9 + k] + sq * t[18 + k];
+}
+
+// Forward kinematics of a revolute body from its parent's frame (Rl, pl), twist
+// vl and bias acceleration bl, with joint rotation C: rotation R = Rl C, origin
+// p, lever arm e = p - pl, axis ax (base axes), twist v, velocity product c and
+// bias acceleration beta, all about the body's own origin.
+__device__ __forceinline__ void fk_joint(const float* Rl, const float* pl, const float* vl, const float* bl,
+                                         const float* C, const float* p_tree, const float* axis_p, float qd, float* R,
+                                         float* p, float* e, float* ax, float* v, float* c, float* beta) {
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -349,11 +358,11 @@ __device__ __forceinline__ void fk_joint(const float* Rl, const float* pl, const
 // fk_joint for a child of the floating base, whose frame in base axes is the
 // identity at the origin with twist bv and no bias acceleration: R = C(q),
 // e = p = p_tree, ax = axis_p (the same values fk_joint gives for that parent).
-__device__ __forceinline__ void fk_base_child(const float* bv, const float* P, const float* p_tree,
-                                              const float* axis_p, float cq, float sq, float qd, float* R, float* p,
-                                              float* e, float* ax, float* v, float* c, float* beta) {
+__device__ __forceinline__ void fk_base_child(const float* bv, const float* C, const float* p_tree,
+                                              const float* axis_p, float qd, float* R, float* p, float* e, float* ax,
+                                              float* v, float* c, float* beta) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) R[k] = P[k] + cq * P[9 + k] + sq * P[18 + k];
+  for (int k = 0; k < 9; ++k) R[k] = C[k];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
     e[r] = p_tree[r];
@@ -470,7 +479,7 @@ struct ContactLaw {
 // would reload them after every LDS store).
 struct StepConst {
   int fb, max_depth, ee_body, cost_kind, K, nu, F, nsub, spline_mode;
-  float g, dt, delta, inv_delta;
+  float g, dt, delta, inv_delta, inv_F;
   ContactLaw law;
   float ee_pos[3];
   float w_h, w_or, w_q, w_cv, w_cf, w_eff, w_ee, w_tau, z_des;
@@ -486,7 +495,7 @@ __device__ __forceinline__ StepConst load_step_const(const DevModel& M, const De
   if (I) {
     c.cost_kind = I->cost_kind; c.K = I->K; c.nu = I->nu; c.F = I->H * M.nsub; c.spline_mode = I->spline_mode;
     c.dt = I->dt / (float)M.nsub;
-    c.delta = I->delta; c.inv_delta = 1.f / I->delta;
+    c.delta = I->delta; c.inv_delta = 1.f / I->delta; c.inv_F = 1.f / (float)c.F;
     c.w_h = I->w_h; c.w_or = I->w_or; c.w_q = I->w_q; c.w_cv = I->w_cv; c.w_cf = I->w_cf; c.w_eff = I->w_eff;
     c.w_ee = I->w_ee; c.w_tau = I->w_tau; c.z_des = I->z_des;
     c.or_target = I->or_target;
@@ -494,7 +503,7 @@ __device__ __forceinline__ StepConst load_step_const(const DevModel& M, const De
   } else {
     c.cost_kind = -1; c.K = 2; c.nu = M.nu; c.F = 1; c.spline_mode = 0;
     c.dt = dt_override;
-    c.delta = 1.f; c.inv_delta = 1.f;
+    c.delta = 1.f; c.inv_delta = 1.f; c.inv_F = 1.f;
     c.w_h = c.w_or = c.w_q = c.w_cv = c.w_cf = c.w_eff = c.w_ee = c.w_tau = c.z_des = 0.f;
     c.or_target = 0;
     c.q_des[0] = 1.f; c.q_des[1] = c.q_des[2] = c.q_des[3] = 0.f;
@@ -504,10 +513,15 @@ __device__ __forceinline__ StepConst load_step_const(const DevModel& M, const De
 
 // Stage the model table (base inertia, contact rows with the instance's nominal
 // normal forces) into LDS with all 64 lanes of the wavefront.
-__device__ __forceinline__ void stage_model_table(const DevModel& M, const DevInst* I, float* tab, int lane) {
+__device__ __forceinline__ void stage_model_table(const DevModel& M, const DevInst* I, float* tab, int lane,
+                                                  bool joint_rows = false) {
   if (lane < 21) tab[lane] = M.base_I[lane];
   const float* cs = &M.ctab[0][0];
   for (int i = lane; i < M.nc * kCt; i += 64) tab[kTabContacts + i] = cs[i];
+  if (joint_rows) {
+    float* rows = tab + body_table_floats(M.nc);
+    for (int i = lane; i < M.nb * 27; i += 64) rows[(i / 27) * kPRow + i % 27] = M.P[i / 27][i % 27];
+  }
   wave_sync();
   if (I && I->cost_kind == 1)
     for (int ci = lane; ci < M.nc; ci += 64) {
@@ -756,6 +770,10 @@ __device__ __forceinline__ float forward_joint(const float* al, const float* e, 
 // ---------------------------------------------------------------------------
 // D > 0: the tree is at most D levels deep, fixed at compile time so the level
 // loops unroll (levels below the tree have no body and cost only their shifts).
+// Unroll counts of the loops over levels 1..D and D..0 (1: a run-time loop).
+template <int D> constexpr int kLevelUnroll = D > 0 ? D : 1;
+template <int D> constexpr int kLevelUnrollRoot = D > 0 ? D + 1 : 1;
+
 template <int G, int D = 0>
 __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const float* tab, float* __restrict__ gs,
                              int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
@@ -801,9 +819,13 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
 #pragma unroll
     for (int k = 0; k < 6; ++k) { v[k] = io.bv[k]; c[k] = 0.f; beta[k] = 0.f; }
   }
-  float cq = 0.f, sq = 0.f;
-  if (is_joint) sincosf(io.q, &sq, &cq);
-#pragma unroll (D > 0 ? D : 1)
+  float C[9];
+  if (is_joint) {
+    float cq, sq;
+    sincosf(io.q, &sq, &cq);
+    joint_rotation(bc.P, cq, sq, C);
+  }
+#pragma unroll kLevelUnroll<D>
   for (int d = 1; d <= maxd; ++d) {
     float sR[9], sp[3], sv[6], sb[6];  // the previous lane's frame (level d - 1)
     if (d > 1) {
@@ -819,7 +841,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
       if (fb && d == 1) {  // a child of the floating base: frame identity, twist bv (from the base slot)
         const float4 v0 = get4(slots + 12), v1 = get4(slots + 16);
         const float bvl[6] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y};
-        fk_base_child(bvl, bc.P, bc.p_tree, bc.axis_p, cq, sq, io.v, R, p, e, ax, v, c, beta);
+        fk_base_child(bvl, C, bc.p_tree, bc.axis_p, io.v, R, p, e, ax, v, c, beta);
       } else {
         float Rl[9], pl[3], vl[6], bl[6];
         if (bc.flags & kAdjParent) {
@@ -839,7 +861,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
 #pragma unroll
           for (int k = 0; k < 6; ++k) { vl[k] = 0.f; bl[k] = 0.f; }
         }
-        fk_joint(Rl, pl, vl, bl, bc.P, bc.p_tree, bc.axis_p, cq, sq, io.v, R, p, e, ax, v, c, beta);
+        fk_joint(Rl, pl, vl, bl, C, bc.p_tree, bc.axis_p, io.v, R, p, e, ax, v, c, beta);
       }
       if (bc.flags & kFrameOut) put_frame(slots + b * kSlot, R, p, v, beta);
     }
@@ -894,14 +916,12 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // ---- backward sweep, leaves to root: each joint lane publishes its
   //      articulated inertia and bias already carried to its parent's origin
   float U[6], invD = 0.f, u = 0.f;
-#pragma unroll (D > 0 ? D + 1 : 1)
+#pragma unroll kLevelUnrollRoot<D>
   for (int d = maxd; d >= 0; --d) {
-    // inertia and bias carried to the parent by the lanes of level d (any value elsewhere)
+    // inertia and bias carried to the parent by the lanes of level d; other lanes
+    // leave them unset (their values are never read: a parent takes them only
+    // from a child of level d)
     float Ip[21], pp[6];
-#pragma unroll
-    for (int q = 0; q < 21; ++q) Ip[q] = __builtin_nondeterministic_value(0.f);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) pp[q] = __builtin_nondeterministic_value(0.f);
     if (body_lane && depth == d) {
       const int nch = bc.n_child;
       for (int k = 0; k < nch; ++k) add_art(slots + child_of(bc, k) * kSlot, IA, pA);
@@ -940,7 +960,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // ---- forward sweep: accelerations, root to leaves
   float qdd = 0.f;
   float a[6], sa[6];  // this lane's and the previous lane's acceleration
-#pragma unroll (D > 0 ? D : 1)
+#pragma unroll kLevelUnroll<D>
   for (int d = 1; d <= maxd; ++d) {
     if (is_joint && depth == d) {
       const int lam = bc.parent;
@@ -1021,21 +1041,34 @@ __device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, 
   }
 }
 
-// Hermite reference of joint jj (eq. hermite_segment and its time
-// derivative) at fine step f of F: the segment seg = floor(f (K-1) / F) and the
-// remainder rem = f (K-1) - seg F are exact integers kept by the caller
-// (StepClock), the local time is s = rem / F.
-__device__ __forceinline__ void hermite(const float* knots, int K, int nu, int F, float delta, float inv_delta,
-                                        int seg, int rem, int jj, float* qr, float* vr) {
-  const float s = (float)rem / (float)F;
+// Hermite reference of joint jj (eq. hermite_segment and its time derivative).
+// The knots of one segment, slopes scaled by the knot spacing delta, are loaded
+// once per segment; the curve is then evaluated at local time s in [0, 1].
+struct HermiteSeg {
+  float q0, q1, m0, m1;
+};
+__device__ __forceinline__ HermiteSeg hermite_segment(const float* knots, int K, int nu, int seg, int jj, float delta) {
+  const int KU = K * nu;
+  HermiteSeg h;
+  h.q0 = knots[seg * nu + jj];
+  h.q1 = knots[(seg + 1) * nu + jj];
+  h.m0 = delta * knots[KU + seg * nu + jj];
+  h.m1 = delta * knots[KU + (seg + 1) * nu + jj];
+  return h;
+}
+__device__ __forceinline__ void hermite_eval(const HermiteSeg& h, float s, float inv_delta, float* qr, float* vr) {
   const float s2 = s * s, s3 = s2 * s;
   const float h00 = 2.f * s3 - 3.f * s2 + 1.f, h10 = s3 - 2.f * s2 + s, h01 = -2.f * s3 + 3.f * s2, h11 = s3 - s2;
   const float d00 = 6.f * s2 - 6.f * s, d10 = 3.f * s2 - 4.f * s + 1.f, d01 = -6.f * s2 + 6.f * s, d11 = 3.f * s2 - 2.f * s;
-  const int KU = K * nu;
-  const float q0 = knots[seg * nu + jj], q1 = knots[(seg + 1) * nu + jj];
-  const float v0 = knots[KU + seg * nu + jj], v1 = knots[KU + (seg + 1) * nu + jj];
-  *qr = h00 * q0 + h10 * delta * v0 + h01 * q1 + h11 * delta * v1;
-  *vr = (d00 * q0 + d10 * delta * v0 + d01 * q1 + d11 * delta * v1) * inv_delta;
+  *qr = h00 * h.q0 + h10 * h.m0 + h01 * h.q1 + h11 * h.m1;
+  *vr = (d00 * h.q0 + d10 * h.m0 + d01 * h.q1 + d11 * h.m1) * inv_delta;
+}
+// At fine step f of F inside a rollout: the segment seg = floor(f (K-1) / F) and
+// the remainder rem = f (K-1) - seg F are exact integers kept by the caller
+// (StepClock); the local time is s = rem (1/F).
+__device__ __forceinline__ void hermite(const float* knots, int K, int nu, float inv_F, float delta, float inv_delta,
+                                        int seg, int rem, int jj, float* qr, float* vr) {
+  hermite_eval(hermite_segment(knots, K, nu, seg, jj, delta), (float)rem * inv_F, inv_delta, qr, vr);
 }
 
 // Fine-step bookkeeping without integer division: the Hermite segment and
@@ -1088,19 +1121,20 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
   quat_R(bq + 3, R);
 #pragma unroll
   for (int r = 0; r < 3; ++r) bq[r] += dt * (R[r * 3 + 0] * bv[3] + R[r * 3 + 1] * bv[4] + R[r * 3 + 2] * bv[5]);
-  const float wn = sqrtf(bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2]);
+  const float wn2 = bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2];
   // exp of the half rotation: (cos th, sin th w / |w|), th = |w| dt / 2; below
   // th = 1/4 by the Taylor series of cos th and sin th / th to the th^6 term
-  // (truncation below 5e-10, under float rounding)
-  const float th = 0.5f * wn * dt;
+  // (truncation below 5e-10, under float rounding), which needs th^2 only
+  const float hdt = 0.5f * dt;
+  const float t2 = (hdt * hdt) * wn2;
   float e0, k;
-  if (th < 0.25f) {
-    const float t2 = th * th;
+  if (t2 < 0.0625f) {
     e0 = 1.f + t2 * (-0.5f + t2 * (1.f / 24.f + t2 * (-1.f / 720.f)));
-    k = (0.5f * dt) * (1.f + t2 * (-1.f / 6.f + t2 * (1.f / 120.f + t2 * (-1.f / 5040.f))));
+    k = hdt * (1.f + t2 * (-1.f / 6.f + t2 * (1.f / 120.f + t2 * (-1.f / 5040.f))));
   } else {
+    const float wn = sqrtf(wn2);
     float sn, cs;
-    sincosf(th, &sn, &cs);
+    sincosf(hdt * wn, &sn, &cs);
     e0 = cs;
     k = sn * rcp(wn);
   }
@@ -1129,7 +1163,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   const int grp = lane / G, l = lane % G;
   const DevModel& M = *I.model;
   float* tab = smem;
-  stage_model_table(M, &I, tab, lane);
+  stage_model_table(M, &I, tab, lane, true);
   const int n = first + grp;
   const bool valid = n < I.N;
   float* gs = smem + table_floats + grp * group_stride;
@@ -1167,15 +1201,24 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   io.dt = sc.dt;
 
   BodyConst bc;
-  load_body(M, &I, b, body_lane, bc);
+  load_body(M, &I, b, body_lane, tab, bc);
   uint32_t* const masks = I.masks;
   const int H = I.H, F = sc.F, F_run = steps * sc.nsub;
   float acc = 0.f;
   StepClock clk;
+  // this joint's knots on the current segment, kept in registers across steps
+  // where the register budget allows (depth-specialised kernels), else reloaded
+  // every step (the same values)
+  HermiteSeg hs{0.f, 0.f, 0.f, 0.f};
+  int hseg = -1;
   for (int f = 0; f < F_run; ++f) {
     const bool control = clk.sub == 0;
+    if (D == 0 || clk.seg != hseg) {
+      hseg = clk.seg;
+      if (is_joint) hs = hermite_segment(knots, sc.K, sc.nu, hseg, j, sc.delta);
+    }
     if (is_joint) {
-      hermite(knots, sc.K, sc.nu, F, sc.delta, sc.inv_delta, clk.seg, clk.rem, j, &io.qref, &io.vref);
+      hermite_eval(hs, (float)clk.rem * sc.inv_F, sc.inv_delta, &io.qref, &io.vref);
       if (sc.spline_mode != 0) io.vref = 0.f;  // position-only variants: zero velocity targets
     }
     physics_step<G, D>(sc, bc, tab, gs, b, body_lane, io, control);
@@ -1558,7 +1601,7 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
   F.p = 0.f; F.ba = 0.f; F.bl = 0.f;
   F.va = fb ? bs[12 + k] : 0.f;
   F.vl = fb ? bs[15 + k] : 0.f;
-#pragma unroll (D > 0 ? D : 1)
+#pragma unroll kLevelUnroll<D>
   for (int d = 1; d <= maxd; ++d) {
     const int sd = r.team ? tcb[r.c * kMaxLevels + d] : -1;  // slot of this chain's body at depth d
     const bool act = sd >= 0;
@@ -1667,7 +1710,7 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
   float cA[3] = {0.f, 0.f, 0.f}, cB[3] = {0.f, 0.f, 0.f}, cT[3] = {0.f, 0.f, 0.f}, cC[3] = {0.f, 0.f, 0.f};
   float cpa = 0.f, cpl = 0.f;  // carried by this chain's deeper body
 
-#pragma unroll (D > 0 ? D + 1 : 1)
+#pragma unroll kLevelUnrollRoot<D>
   for (int d = maxd; d >= 0; --d) {
     TeamBwdIn cur;
     const int sd = team_load_bwd(r, tcb, tt, ir, lr, br, d, k, cur);
@@ -1750,7 +1793,7 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
 
   // ---- forward sweep, root to leaves, on the coordinate lanes
   float Fa = fb ? bs[18 + k] : 0.f, Fl = fb ? bs[21 + k] : 0.f;  // chain 0 starts at the base
-#pragma unroll (D > 0 ? D : 1)
+#pragma unroll kLevelUnroll<D>
   for (int d = 1; d <= maxd; ++d) {
     TeamFwdIn cur;
     const int sd = team_load_fwd(r, tcb, tt, lr, d, k, cur);
@@ -1851,10 +1894,16 @@ __device__ __attribute__((always_inline)) void team_item(const DevInst& I, int f
   const int H = I.H, F = sc.F, F_run = H * sc.nsub;
   float acc = 0.f;
   StepClock clk;
+  HermiteSeg hs{0.f, 0.f, 0.f, 0.f};
+  int hseg = -1;
   for (int f = 0; f < F_run; ++f) {
     const bool control = clk.sub == 0;
+    if (clk.seg != hseg) {
+      hseg = clk.seg;
+      if (is_joint) hs = hermite_segment(knots, sc.K, sc.nu, hseg, j, sc.delta);
+    }
     if (is_joint) {
-      hermite(knots, sc.K, sc.nu, F, sc.delta, sc.inv_delta, clk.seg, clk.rem, j, &io.qref, &io.vref);
+      hermite_eval(hs, (float)clk.rem * sc.inv_F, sc.inv_delta, &io.qref, &io.vref);
       if (sc.spline_mode != 0) io.vref = 0.f;
     }
     team_step<D>(sc, tb, tab, tt, tcb, gs, L, r, io, control);
@@ -1993,7 +2042,7 @@ __device__ __forceinline__ void chain_fk(const StepConst& sc, const float* rows,
         float tau = 0.f, gain = 0.f;
         if (!terminal) {
           float qref, vref;
-          hermite(knots, sc.K, sc.nu, sc.F, sc.delta, sc.inv_delta, seg, rem, j, &qref, &vref);
+          hermite(knots, sc.K, sc.nu, sc.inv_F, sc.delta, sc.inv_delta, seg, rem, j, &qref, &vref);
           if (sc.spline_mode != 0) vref = 0.f;
           pd_law(rw[row::kp], rw[row::kd], rw[row::taumax], dt, q, qd, qref, vref, tau, gain);
         }
@@ -2023,11 +2072,11 @@ __device__ __forceinline__ void chain_fk(const StepConst& sc, const float* rows,
 #pragma unroll
           for (int k = 0; k < 6; ++k) { vl[k] = fv[k]; bl[k] = fbt[k]; }
         }
-        float cq, sq;
+        float cq, sq, C[9];
         sincosf(q, &sq, &cq);
+        joint_rotation(rw + row::P, cq, sq, C);
         float e[3], ax[3], cv[6];
-        fk_joint(Rl, pl, vl, bl, rw + row::P, rw + row::p_tree, rw + row::axis_p, cq, sq, qd, fR, fp, e, ax, fv, cv,
-                 fbt);
+        fk_joint(Rl, pl, vl, bl, C, rw + row::p_tree, rw + row::axis_p, qd, fR, fp, e, ax, fv, cv, fbt);
 #pragma unroll
         for (int k = 0; k < 9; ++k) r[k] = fR[k];
 #pragma unroll
@@ -2636,7 +2685,7 @@ __global__ __launch_bounds__(kShiftThreads) void shift_knots_kernel(const float*
       rem = F;
     }
     float q, v;
-    hermite(in, K, nu, F, delta, 1.f / delta, seg, rem, jj, &q, &v);
+    hermite_eval(hermite_segment(in, K, nu, seg, jj, delta), (float)rem / (float)F, 1.f / delta, &q, &v);
     out[i] = q;
     out[K * nu + i] = v;
   }
@@ -2694,7 +2743,7 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   const int lane = threadIdx.x, grp = lane / G, l = lane % G;
   const DevModel& M = *model;
   float* tab = smem;
-  stage_model_table(M, nullptr, tab, lane);
+  stage_model_table(M, nullptr, tab, lane, true);
   const int s_raw = blockIdx.x * R + grp;
   const bool valid = s_raw < n_states;
   const int s = valid ? s_raw : 0;
@@ -2715,7 +2764,7 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   for (int k = 0; k < 6; ++k) { io.bv[k] = fb ? v[(size_t)s * nv + k] : 0.f; io.ba[k] = 0.f; }
   io.dt = dt;
   BodyConst bc;
-  load_body(M, nullptr, l, body_lane, bc);
+  load_body(M, nullptr, l, body_lane, tab, bc);
   physics_step<G>(sc, bc, tab, gs, l, body_lane, io, false);
   if (!valid) return;
   if (is_joint) qdd[(size_t)s * nv + (fb ? 6 : 0) + j] = io.qdd;
