@@ -139,7 +139,7 @@ struct DevUpdate {
 //               forward kinematics R(9) p(3) v(6) beta(6) in [0,24);
 //               reused by the backward sweep for Ia(21) pa(6) in [0,27),
 //               then by the forward sweep for a'(6) in [0,6)
-//   base[16]   : world rotation (9) and position (3) of frame B
+//   pad[16]    : unused (keeps the groups' bank stagger)
 //   knots[E]   : this rollout's knots
 //   red[G]     : reduction scratch
 // A slot is 36 floats (4 LDS banks past a multiple of 32), so the slots that

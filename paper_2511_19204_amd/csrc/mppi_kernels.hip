@@ -164,6 +164,7 @@ struct BodyConst {
   float p_tree[3], axis_p[3], com[3], Ic[6];
   float mass, kp, kd, taumax, arm, q0;
   int parent, depth, n_child, c_begin, c_count;
+  float ct0[5];                 // first contact row: position (body frame), nominal normal force, index bits
   uint32_t child_lo, child_hi;  // children reached through LDS, 8 bits each, child-list order
   uint32_t flags;               // kAdjParent | kAdjChild | kFrameOut | kArtOut
 };
@@ -201,6 +202,11 @@ __device__ __forceinline__ void load_body(const DevModel& M, const DevInst* I, i
   c.depth = body_lane ? M.depth[bb] : -1;
   c.c_begin = M.c_begin[bb];
   c.c_count = body_lane ? M.c_count[bb] : 0;
+  {
+    const float* ct = tab + kTabContacts + (c.c_count > 0 ? c.c_begin : 0) * kCt;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) c.ct0[k] = ct[k];
+  }
   // children are numbered after their parent in increasing order, so body b + 1,
   // when it is a child of b, is b's first child
   const int par = body_lane ? M.parent[bb] : -1;
@@ -779,7 +785,6 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
                              int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
   const int maxd = D > 0 ? D : sc.max_depth;
   float* slots = gs;
-  float* base = gs + G * kSlot;
   const int fb = sc.fb;
   const bool is_base = body_lane && fb && b == 0;
   const bool is_joint = body_lane && !is_base;
@@ -790,23 +795,17 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   float base_term = 0.f;
   if (want_cost && is_base && sc.cost_kind == 1) base_term = base_cost_term(sc, io.bq);
 
-  // ---- frame B: world pose of the base; body 0 slot = identity frame with the base twist
-  if (is_base) {
-    float R[9];
-    quat_R(io.bq + 3, R);
+  // ---- frame B: world pose of the base.  Every lane carries the base state
+  //      (position, quaternion, twist), so every lane forms it in registers.
+  float Rb[9], pb[3];
+  if (fb) {
+    quat_R(io.bq + 3, Rb);
+    pb[0] = io.bq[0]; pb[1] = io.bq[1]; pb[2] = io.bq[2];
+  } else {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) base[k] = R[k];
-    base[9] = io.bq[0]; base[10] = io.bq[1]; base[11] = io.bq[2];
-    const float I3[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
-    const float z6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    put_frame(slots, I3, z6, io.bv, z6);  // body 0
+    for (int k = 0; k < 9; ++k) Rb[k] = (k % 4 == 0) ? 1.f : 0.f;
+    pb[0] = pb[1] = pb[2] = 0.f;
   }
-  if (!fb && body_lane && b == 0) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) base[k] = (k % 4 == 0) ? 1.f : 0.f;
-    base[9] = base[10] = base[11] = 0.f;
-  }
-  wave_sync();
 
   // ---- forward kinematics, level by level (slot: R, p, v, beta about the body origin)
   float R[9], p[3], e[3], ax[3], v[6], c[6], beta[6];
@@ -838,10 +837,8 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
     }
     if (is_joint && depth == d) {
       const int lam = bc.parent;
-      if (fb && d == 1) {  // a child of the floating base: frame identity, twist bv (from the base slot)
-        const float4 v0 = get4(slots + 12), v1 = get4(slots + 16);
-        const float bvl[6] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y};
-        fk_base_child(bvl, C, bc.p_tree, bc.axis_p, io.v, R, p, e, ax, v, c, beta);
+      if (fb && d == 1) {  // a child of the floating base: frame identity, twist bv
+        fk_base_child(io.bv, C, bc.p_tree, bc.axis_p, io.v, R, p, e, ax, v, c, beta);
       } else {
         float Rl[9], pl[3], vl[6], bl[6];
         if (bc.flags & kAdjParent) {
@@ -872,10 +869,6 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   float IA[21], pA[6];
   float lane_cost = 0.f;
   uint32_t mask = 0u;
-  float Rb[9], pb[3];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) Rb[k] = base[k];
-  pb[0] = base[9]; pb[1] = base[10]; pb[2] = base[11];
   if (terminal) {
     if (body_lane && sc.cost_kind == 0 && b == sc.ee_body) {
       const float dz = ee_height_error(R, p, sc.ee_pos, Rb, pb, sc.z_des);
@@ -898,10 +891,18 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
     }
     bias_force(IA, v, pA);
 
-    // contacts carried by this body (point x relative to the body origin)
+    // contacts carried by this body (point x relative to the body origin); the
+    // first one's row is held in registers, further ones are read from the table
     const int c0 = bc.c_begin, cn = bc.c_count;
     for (int ci = c0; ci < c0 + cn; ++ci) {
-      const float* ct = tab + kTabContacts + ci * kCt;
+      float ct[5];
+      if (ci == c0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ct[k] = bc.ct0[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ct[k] = tab[kTabContacts + ci * kCt + k];
+      }
       float vw[3], fw[3];
       const float fn = contact_point(ct, R, p, v, beta, Rb, pb, agl, io.dt, sc.law, IA, pA, vw, fw);
       if (fn > 0.f) mask |= 1u << __float_as_int(ct[4]);
@@ -948,14 +949,17 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   }
 
   // ---- root: floating base solves IA0 a0' = -pA0 (Cholesky); fixed roots use -a_g
+  float a0[6];  // the base's a' = a0 - a_g, then in every lane
   if (is_base) {
-    float a0[6];
     base_solve(IA, pA, a0);
     put_acc(slots, a0);
+  }
+  wave_sync();
+  if (fb) {
+    get_acc(slots, a0);
     io.ba[0] = a0[0]; io.ba[1] = a0[1]; io.ba[2] = a0[2];
     io.ba[3] = a0[3] + agl[0]; io.ba[4] = a0[4] + agl[1]; io.ba[5] = a0[5] + agl[2];
   }
-  wave_sync();
 
   // ---- forward sweep: accelerations, root to leaves
   float qdd = 0.f;
@@ -965,7 +969,10 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
     if (is_joint && depth == d) {
       const int lam = bc.parent;
       float al[6];
-      if (bc.flags & kAdjParent) {
+      if (fb && d == 1) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) al[k] = a0[k];
+      } else if (bc.flags & kAdjParent) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) al[k] = sa[k];
       } else if (lam >= 0) {
@@ -1233,7 +1240,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
       io.v = fmaf(io.dt, io.qdd, io.v);
       io.q = fmaf(io.dt, io.v, io.q);
     }
-    if (fb && b == 0) integrate_base(io.bq, io.bv, io.ba, io.dt);
+    if (fb) integrate_base(io.bq, io.bv, io.ba, io.dt);  // every lane: the same base state
     clk.advance(sc.K, F, sc.nsub);
   }
   if (state_out) {
