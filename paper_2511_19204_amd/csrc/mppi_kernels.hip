@@ -240,6 +240,19 @@ __device__ __forceinline__ float from_prev_lane(float x) {
 __device__ __forceinline__ float from_next_lane(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x130, 0xf, 0xf, true));
 }
+// value held by the first lane of this lane's rollout group of G lanes (groups
+// are aligned): a swizzle in bit-mask mode that clears the low lane-index bits
+// within each 32-lane half, or the first lane for a whole wavefront; every lane
+// must be active
+template <int G>
+__device__ __forceinline__ float from_group_lane0(float x) {
+  if constexpr (G == 64) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+  } else {
+    constexpr int and_mask = 0x1f & ~(G - 1);
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), and_mask));
+  }
+}
 
 // motion vector m given about point O, re-expressed about O + e: (w, v + w x e)
 __device__ __forceinline__ void shift_motion(const float* m, const float* e, float* out) {
@@ -302,15 +315,9 @@ __device__ __forceinline__ void shift_inertia_to_parent(const float* I, const fl
 __device__ __forceinline__ void pd_law(float kp, float kd, float tm, float dt, float q, float v, float qref, float vref,
                                        float& tau, float& gain) {
   const float t = kp * (qref - q) + kd * (vref - v);
-  gain = 0.f;
-  if (t >= tm) {
-    tau = tm;
-  } else if (t <= -tm) {
-    tau = -tm;
-  } else {
-    tau = t;
-    gain = dt * (kd + dt * kp);
-  }
+  const bool inside = t < tm && t > -tm;
+  tau = fminf(fmaxf(t, -tm), tm);
+  gain = inside ? dt * (kd + dt * kp) : 0.f;
 }
 
 // velocity-product acceleration c = v x_m (S qd) of a revolute joint, S = (ax, 0)
@@ -321,16 +328,22 @@ __device__ __forceinline__ void vel_product(const float* v, const float* ax, flo
 }
 
 // Joint rotation C(q) = P0 + cos q P1 + sin q P2 (row-major 3x3) from the 27
-// constants P0 | P1 | P2 at a 16-byte aligned address.
-__device__ __forceinline__ void joint_rotation(const float* P, float cq, float sq, float* C) {
-  float t[28];
+// constants P0 | P1 | P2 (read as 28 floats from a 16-byte aligned address).
+__device__ __forceinline__ void load_rotation_constants(const float* P, float* t) {
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
     const float4 x = *reinterpret_cast<const float4*>(P + 4 * k);
     t[4 * k] = x.x; t[4 * k + 1] = x.y; t[4 * k + 2] = x.z; t[4 * k + 3] = x.w;
   }
+}
+__device__ __forceinline__ void joint_rotation_of(const float* t, float cq, float sq, float* C) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) C[k] = t[k] + cq * t[9 + k] + sq * t[18 + k];
+}
+__device__ __forceinline__ void joint_rotation(const float* P, float cq, float sq, float* C) {
+  float t[28];
+  load_rotation_constants(P, t);
+  joint_rotation_of(t, cq, sq, C);
 }
 
 // Forward kinematics of a revolute body from its parent's frame (Rl, pl), twist
@@ -635,12 +648,31 @@ __device__ __forceinline__ float ee_height_error(const float* R, const float* p,
   return pb[2] + Rb[6] * xe[0] + Rb[7] * xe[1] + Rb[8] * xe[2] - z_des;
 }
 
+// atan2(y, x) for y, x >= 0: t = min / max in [0, 1], reduced to |u| <= tan(pi/12)
+// by atan t = pi/6 + atan((sqrt(3) t - 1) / (t + sqrt(3))) where t > tan(pi/12),
+// then the Taylor series of atan u to the u^13 term (truncation below 2e-10);
+// atan2 = pi/2 - atan t when y > x.
+__device__ __forceinline__ float atan2_pos(float y, float x) {
+  const float hi = fmaxf(y, x), lo = fminf(y, x);
+  const float t = hi > 0.f ? lo * rcp(hi) : 0.f;
+  const float kTan15 = 0.267949192f, kSqrt3 = 1.73205081f;
+  const bool big = t > kTan15;
+  const float u = big ? (kSqrt3 * t - 1.f) * rcp(t + kSqrt3) : t;
+  const float u2 = u * u;
+  float sr = 1.f / 13.f;
+  sr = fmaf(sr, u2, -1.f / 11.f);
+  sr = fmaf(sr, u2, 1.f / 9.f);
+  sr = fmaf(sr, u2, -1.f / 7.f);
+  sr = fmaf(sr, u2, 1.f / 5.f);
+  sr = fmaf(sr, u2, -1.f / 3.f);
+  float a = fmaf(sr * u2, u, u);
+  if (big) a += 0.523598776f;  // pi/6
+  return y > x ? 1.57079633f - a : a;
+}
+
 // running-cost terms of the floating base (Sec. IV-A): height error and the
 // squared rotation angle between the base and the task's orientation target
-// (the identity unless a target is set).  Both schedules evaluate it once
-// per step in straight-line code: inside a loop the compiler may hoist it and
-// drop the relaxed-precision tag of the division inside atan2f, which would
-// change its last bit.
+// (the identity unless a target is set).
 __device__ __forceinline__ float base_cost_term(const StepConst& sc, const float* bq) {
   // orientation residual: rotation angle of R_base^T R_des, i.e. of conj(q_base) q_des
   const float* qt = bq + 3;
@@ -652,8 +684,9 @@ __device__ __forceinline__ float base_cost_term(const StepConst& sc, const float
     r2 = qt[0] * d2 + qt[1] * d3 - qt[2] * d0 - qt[3] * d1;
     r3 = qt[0] * d3 - qt[1] * d2 + qt[2] * d1 - qt[3] * d0;
   }
-  const float vn = sqrtf(r1 * r1 + r2 * r2 + r3 * r3);
-  const float phi = 2.f * atan2f(vn, fabsf(r0));
+  const float vn2 = r1 * r1 + r2 * r2 + r3 * r3;
+  const float vn = vn2 > 0.f ? vn2 * rsq(vn2) : 0.f;
+  const float phi = 2.f * atan2_pos(vn, fabsf(r0));
   return sc.w_h * fabsf(bq[2] - sc.z_des) + sc.w_or * phi * phi;
 }
 
@@ -784,6 +817,16 @@ template <int G, int D = 0>
 __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const float* tab, float* __restrict__ gs,
                              int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
   const int maxd = D > 0 ? D : sc.max_depth;
+  // the joint-rotation constants are read first so the LDS latency passes
+  // under the PD law, the base cost and frame B
+  float Pt[28];
+  load_rotation_constants(bc.P, Pt);
+  float Ib[24];  // the base's rigid inertia (packed), for the same reason
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float4 x = get4(tab + 4 * k);
+    Ib[4 * k] = x.x; Ib[4 * k + 1] = x.y; Ib[4 * k + 2] = x.z; Ib[4 * k + 3] = x.w;
+  }
   float* slots = gs;
   const int fb = sc.fb;
   const bool is_base = body_lane && fb && b == 0;
@@ -822,7 +865,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   if (is_joint) {
     float cq, sq;
     sincosf(io.q, &sq, &cq);
-    joint_rotation(bc.P, cq, sq, C);
+    joint_rotation_of(Pt, cq, sq, C);
   }
 #pragma unroll kLevelUnroll<D>
   for (int d = 1; d <= maxd; ++d) {
@@ -885,7 +928,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   if (body_lane) {
     if (is_base) {
 #pragma unroll
-      for (int k = 0; k < 21; ++k) IA[k] = tab[k];
+      for (int k = 0; k < 21; ++k) IA[k] = Ib[k];
     } else {
       body_inertia(R, bc.com, bc.Ic, bc.mass, IA);
     }
@@ -949,14 +992,11 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   }
 
   // ---- root: floating base solves IA0 a0' = -pA0 (Cholesky); fixed roots use -a_g
-  float a0[6];  // the base's a' = a0 - a_g, then in every lane
-  if (is_base) {
-    base_solve(IA, pA, a0);
-    put_acc(slots, a0);
-  }
-  wave_sync();
+  float a0[6];  // the base's a' = a0 - a_g, then in every lane of its rollout
+  if (is_base) base_solve(IA, pA, a0);
   if (fb) {
-    get_acc(slots, a0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a0[k] = from_group_lane0<G>(a0[k]);
     io.ba[0] = a0[0]; io.ba[1] = a0[1]; io.ba[2] = a0[2];
     io.ba[3] = a0[3] + agl[0]; io.ba[4] = a0[4] + agl[1]; io.ba[5] = a0[5] + agl[2];
   }
@@ -1134,11 +1174,9 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
   // (truncation below 5e-10, under float rounding), which needs th^2 only
   const float hdt = 0.5f * dt;
   const float t2 = (hdt * hdt) * wn2;
-  float e0, k;
-  if (t2 < 0.0625f) {
-    e0 = 1.f + t2 * (-0.5f + t2 * (1.f / 24.f + t2 * (-1.f / 720.f)));
-    k = hdt * (1.f + t2 * (-1.f / 6.f + t2 * (1.f / 120.f + t2 * (-1.f / 5040.f))));
-  } else {
+  float e0 = 1.f + t2 * (-0.5f + t2 * (1.f / 24.f + t2 * (-1.f / 720.f)));
+  float k = hdt * (1.f + t2 * (-1.f / 6.f + t2 * (1.f / 120.f + t2 * (-1.f / 5040.f))));
+  if (!(t2 < 0.0625f)) {
     const float wn = sqrtf(wn2);
     float sn, cs;
     sincosf(hdt * wn, &sn, &cs);
@@ -1224,10 +1262,9 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
       hseg = clk.seg;
       if (is_joint) hs = hermite_segment(knots, sc.K, sc.nu, hseg, j, sc.delta);
     }
-    if (is_joint) {
-      hermite_eval(hs, (float)clk.rem * sc.inv_F, sc.inv_delta, &io.qref, &io.vref);
-      if (sc.spline_mode != 0) io.vref = 0.f;  // position-only variants: zero velocity targets
-    }
+    // (lanes without a joint evaluate zero knots and never use the result)
+    hermite_eval(hs, (float)clk.rem * sc.inv_F, sc.inv_delta, &io.qref, &io.vref);
+    if (sc.spline_mode != 0) io.vref = 0.f;  // position-only variants: zero velocity targets
     physics_step<G, D>(sc, bc, tab, gs, b, body_lane, io, control);
     if (control) {
       acc += io.cost;
@@ -1236,10 +1273,9 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
         if (l == 0 && valid) masks[(size_t)n * H + clk.h] = mk;
       }
     }
-    if (is_joint) {
-      io.v = fmaf(io.dt, io.qdd, io.v);
-      io.q = fmaf(io.dt, io.v, io.q);
-    }
+    // joints (other lanes hold q = qd = qdd = 0)
+    io.v = fmaf(io.dt, io.qdd, io.v);
+    io.q = fmaf(io.dt, io.v, io.q);
     if (fb) integrate_base(io.bq, io.bv, io.ba, io.dt);  // every lane: the same base state
     clk.advance(sc.K, F, sc.nsub);
   }
