@@ -50,8 +50,8 @@ struct StageItem {
   int32_t count;
 };
 __global__ void stage_kernel(const StageItem*);
+__global__ void copy2_kernel(const float*, float*, int, const float*, float*, int);
 __global__ void philox_kernel(const uint32_t*, const uint32_t*, uint32_t*, int);
-constexpr int kUpdThreads = 1024;
 }  // namespace mppi
 
 using namespace mppi;
@@ -103,6 +103,8 @@ struct mppi_ctx {
   float *x_meas = nullptr, *pred_knots = nullptr, *pred_cost = nullptr;
   DevInst* d_pred_inst = nullptr;
   uint32_t* tick = nullptr;
+  float* upd_partial = nullptr;  // [update_parts(N)][E] update scratch
+  uint32_t* upd_done = nullptr;  // update parts finished (0 between launches)
   DevInst* d_insts = nullptr;   // [I]
   DevUpdate* d_ups = nullptr;   // [I]
   std::vector<DevInst> h_insts;
@@ -413,7 +415,8 @@ static void free_ctx_events(mppi_ctx* c) {
 
 static void free_ctx_buffers(mppi_ctx* c) {
   void* ptrs[] = {c->sigma, c->x0, c->nom, c->samples, c->costs, c->best_state, c->f0z, c->q0,
-                  c->tick, c->d_insts, c->d_ups, c->x_meas, c->pred_knots, c->pred_cost, c->d_pred_inst};
+                  c->tick, c->d_insts, c->d_ups, c->x_meas, c->pred_knots, c->pred_cost, c->d_pred_inst,
+                  c->upd_partial, c->upd_done};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -466,8 +469,11 @@ static void build_tables(mppi_ctx* c) {
     u.info = nullptr;
     u.best_state = c->best_state;
     u.tick = c->tick;
+    u.partial = c->upd_partial;
+    u.done = c->upd_done;
     u.N = c->N; u.E = c->E; u.iter = it; u.weight_mode = c->p.weight_mode;
     u.first_iter = it == 0; u.last_iter = it == c->I - 1;
+    u.parts = update_parts(c->N);
     u.lambda = c->p.lambda;
   }
 }
@@ -525,6 +531,9 @@ extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, ui
   if ((e = hipMalloc(&c->f0z, std::max(M.nc, 1) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc f0z");
   if ((e = hipMalloc(&c->q0, c->nu * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc q0");
   if ((e = hipMalloc(&c->tick, sizeof(uint32_t))) != hipSuccess) return bail(e, "hipMalloc tick");
+  if ((e = hipMalloc(&c->upd_partial, (size_t)update_parts(c->N) * E * sizeof(float))) != hipSuccess)
+    return bail(e, "hipMalloc update scratch");
+  if ((e = hipMalloc(&c->upd_done, sizeof(uint32_t))) != hipSuccess) return bail(e, "hipMalloc update counter");
   if ((e = hipMalloc(&c->d_insts, c->I * sizeof(DevInst))) != hipSuccess) return bail(e, "hipMalloc insts");
   if ((e = hipMalloc(&c->d_ups, c->I * sizeof(DevUpdate))) != hipSuccess) return bail(e, "hipMalloc ups");
   std::vector<float> f0(std::max(M.nc, 1), 0.f), q0(c->nu, 0.f);
@@ -537,6 +546,8 @@ extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, ui
   if ((e = hipMemcpy(c->f0z, f0.data(), f0.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload f0z");
   if ((e = hipMemcpy(c->q0, q0.data(), q0.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload q0");
   if ((e = hipMemcpy(c->tick, &zero, sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess) return bail(e, "upload tick");
+  if ((e = hipMemcpy(c->upd_done, &zero, sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(e, "upload update counter");
   if ((e = hipMalloc(&c->x_meas, (c->nq + c->nv) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc x_meas");
   if ((e = hipMalloc(&c->pred_knots, E * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc pred knots");
   if ((e = hipMalloc(&c->pred_cost, sizeof(float))) != hipSuccess) return bail(e, "hipMalloc pred cost");
@@ -822,7 +833,7 @@ static mppi_status run_iterations(mppi_ctx* c, float* d_knots_out, float* d_best
     }
     UpdateOut o{nullptr, nullptr, nullptr};
     if (it == c->I - 1) o = UpdateOut{d_knots_out, d_best_knots, d_info};
-    hipLaunchKernelGGL(update_kernel, dim3(1), dim3(kUpdThreads), 0, s, c->d_ups + it, nullptr, o);
+    hipLaunchKernelGGL(update_kernel, dim3(update_parts(c->N), 1), dim3(kUpdThreads), 0, s, c->d_ups + it, nullptr, o);
     HIP_TRY(hipGetLastError());
     if (c->profile) {
       HIP_TRY(hipEventRecord(eu.second, s));
@@ -837,8 +848,9 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
                                  float* d_best_knots, mppi_step_info* d_info, float* d_costs, void* stream) {
   if (!c || !d_state || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(hipMemcpyAsync(c->x0, d_state, (c->nq + c->nv) * sizeof(float), hipMemcpyDeviceToDevice, s));
-  HIP_TRY(hipMemcpyAsync(c->nom, d_knots_in, c->E * sizeof(float), hipMemcpyDeviceToDevice, s));
+  // state and warm-start knots into the instance's buffers, one launch
+  hipLaunchKernelGGL(copy2_kernel, dim3(2), dim3(256), 0, s, d_state, c->x0, c->nq + c->nv, d_knots_in, c->nom, c->E);
+  HIP_TRY(hipGetLastError());
   return run_iterations(c, d_knots_out, d_best_knots, d_info, d_costs, s);
 }
 
@@ -906,8 +918,9 @@ static mppi_status tick_prefix(mppi_ctx* c, const float* d_state_meas, int32_t n
                                float* d_state_pred, hipStream_t s) {
   const size_t nx = (size_t)(c->nq + c->nv) * sizeof(float);
   // x_t: the measured state carried n_delay control steps along tau_best
-  HIP_TRY(hipMemcpyAsync(c->x_meas, d_state_meas, nx, hipMemcpyDeviceToDevice, s));
-  HIP_TRY(hipMemcpyAsync(c->pred_knots, d_best, c->E * sizeof(float), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(copy2_kernel, dim3(2), dim3(256), 0, s, d_state_meas, c->x_meas, c->nq + c->nv, d_best,
+                     c->pred_knots, c->E);
+  HIP_TRY(hipGetLastError());
   if (n_delay == 0) {
     HIP_TRY(hipMemcpyAsync(c->x0, c->x_meas, nx, hipMemcpyDeviceToDevice, s));
   } else {
@@ -1126,7 +1139,8 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
       else
         HIP_TRY(launch_rollout(g.G, g.blocks, ip.insts, g.work, g.dims, s));
     }
-    hipLaunchKernelGGL(update_kernel, dim3((unsigned)ip.active.size()), dim3(kUpdThreads), 0, s, ip.ups, d_outs + out_off[it],
+    hipLaunchKernelGGL(update_kernel, dim3(kUpdMaxParts, (unsigned)ip.active.size()), dim3(kUpdThreads), 0, s, ip.ups,
+                       d_outs + out_off[it],
                        UpdateOut{nullptr, nullptr, nullptr});
     HIP_TRY(hipGetLastError());
   }
@@ -1205,7 +1219,7 @@ extern "C" mppi_status mppi_graph_create(int32_t n, mppi_ctx* const* ctxs, const
                          : launch_rollout(gl.G, gl.blocks, ip.insts, gl.work, gl.dims, cs);
         if (e != hipSuccess) break;
       }
-      hipLaunchKernelGGL(update_kernel, dim3((unsigned)ip.active.size()), dim3(kUpdThreads), 0, cs, ip.ups,
+      hipLaunchKernelGGL(update_kernel, dim3(kUpdMaxParts, (unsigned)ip.active.size()), dim3(kUpdThreads), 0, cs, ip.ups,
                          d_outs + out_off[it], UpdateOut{nullptr, nullptr, nullptr});
     }
     hipGraph_t graph = nullptr;
@@ -1436,7 +1450,8 @@ extern "C" mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, cons
   DevUpdate* d = nullptr;
   HIP_TRY(hipMalloc(&d, sizeof(DevUpdate)));
   HIP_TRY(hipMemcpyAsync(d, &h, sizeof(DevUpdate), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(update_kernel, dim3(1), dim3(kUpdThreads), 0, s, d, nullptr, UpdateOut{nullptr, nullptr, nullptr});
+  hipLaunchKernelGGL(update_kernel, dim3(update_parts(c->N), 1), dim3(kUpdThreads), 0, s, d, nullptr,
+                     UpdateOut{nullptr, nullptr, nullptr});
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipFree(d));
@@ -1584,7 +1599,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
       else
         HIP_TRY(launch_rollout(g.G, g.n_items, di, w, g.dims, s));
     }
-    hipLaunchKernelGGL(update_kernel, dim3((unsigned)d.n_active), dim3(kUpdThreads), 0, s,
+    hipLaunchKernelGGL(update_kernel, dim3(kUpdMaxParts, (unsigned)d.n_active), dim3(kUpdThreads), 0, s,
                        reinterpret_cast<const DevUpdate*>(dv + d.up_off), reinterpret_cast<const UpdateOut*>(dv + d.out_off),
                        UpdateOut{nullptr, nullptr, nullptr});
     HIP_TRY(hipGetLastError());

@@ -126,9 +126,21 @@ struct DevUpdate {
   float* info;           // mppi_step_info (S_best, best_iter, n_nonfinite, all_nonfinite) or null
   float* best_state;     // [E + 5] running best knots, S_best, best_iter, counters, best sample of this call
   uint32_t* tick;        // advanced by one after the last iteration of a call
-  int32_t N, E, iter, weight_mode, first_iter, last_iter;
+  float* partial;        // [update_parts(N)][E] per-part weighted sums (scratch)
+  uint32_t* done;        // parts finished in the current launch (0 between launches)
+  int32_t N, E, iter, weight_mode, first_iter, last_iter, parts;
   float lambda;
 };
+
+// The update splits an instance's samples into `parts` consecutive slices, one
+// workgroup each; the last workgroup to finish sums the slices in order.
+constexpr int kUpdThreads = 256;
+constexpr int kUpdMaxParts = 64;
+constexpr int kUpdMinSlice = 64;  // samples per part at least
+__host__ __device__ inline int update_parts(int N) {
+  const int p = (N + kUpdMinSlice - 1) / kUpdMinSlice;
+  return p < 1 ? 1 : (p > kUpdMaxParts ? kUpdMaxParts : p);
+}
 
 
 // ---------------------------------------------------------------------------

@@ -2458,7 +2458,9 @@ __global__ void reset_counters(unsigned int* __restrict__ c, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Weighting, update and best tracking: one 256-thread workgroup per instance.
+// Weighting, update and best tracking.  Grid (kUpdMaxParts, instances): the
+// workgroups of an instance each take one slice of its samples (parts of
+// update_parts(N)); the workgroups beyond that return at once.
 // out (per call): the final nominal, best knots and info of the last iteration.
 // ---------------------------------------------------------------------------
 struct UpdateOut {
@@ -2467,12 +2469,9 @@ struct UpdateOut {
   void* info_out;     // mppi_step_info or null
 };
 
-constexpr int kUpdThreads = 1024;
 constexpr int kUpdWaves = kUpdThreads / 64;
-constexpr int kUpdChunk = 4096;  // samples whose weights sit in LDS at a time
-constexpr int kUpdEB = 4;        // blocks of 64 knot elements per pass of the weighted average
 
-// Block-wide reductions in a fixed order (tree over threads), deterministic.
+// Block-wide sum in a fixed order (tree over threads), deterministic.
 __device__ __forceinline__ float block_sum(float x, float* buf) {
   const int t = threadIdx.x;
   buf[t] = x;
@@ -2486,25 +2485,111 @@ __device__ __forceinline__ float block_sum(float x, float* buf) {
   return r;
 }
 
+// Sums over one index range of a row-major [*, E] array, V consecutive floats
+// (V = 4 or 1) per element block.  The workgroup covers up to kUpdThreads
+// element blocks at a time; the G = kUpdThreads / (blocks in the chunk) thread
+// groups take the rows in turn (group g: rows g, g + G, ...), each in index
+// order, and their sums are added in group order.
+template <int V>
+struct VecT;
+template <>
+struct VecT<4> {
+  using T = float4;
+  static __device__ __forceinline__ float4 zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  static __device__ __forceinline__ void fma(float w, const float4& a, float4& acc) {
+    acc.x = fmaf(w, a.x, acc.x); acc.y = fmaf(w, a.y, acc.y); acc.z = fmaf(w, a.z, acc.z); acc.w = fmaf(w, a.w, acc.w);
+  }
+  static __device__ __forceinline__ void add(const float4& a, float4& acc) {
+    acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
+  }
+};
+template <>
+struct VecT<1> {
+  using T = float;
+  static __device__ __forceinline__ float zero() { return 0.f; }
+  static __device__ __forceinline__ void fma(float w, float a, float& acc) { acc = fmaf(w, a, acc); }
+  static __device__ __forceinline__ void add(float a, float& acc) { acc += a; }
+};
+
+// sum_{n < cnt} w[n] rows[n][:] (w null: weight 1); the result goes to
+// emit(element block, value) on threads t < blocks in the chunk.
+template <int V, typename Emit>
+__device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows, int cnt, int E, const float* w,
+                                                  float* s_part, Emit emit) {
+  using VT = VecT<V>;
+  using T = typename VT::T;
+  const int t = threadIdx.x, EV = E / V;
+  T* part = reinterpret_cast<T*>(s_part);
+  const T* col = reinterpret_cast<const T*>(rows);
+  constexpr int kIn = 8;  // loads in flight per thread
+  for (int e0 = 0; e0 < EV; e0 += kUpdThreads) {
+    const int ec = min(kUpdThreads, EV - e0);
+    const int G = kUpdThreads / ec;
+    const int el = t % ec, g = t / ec, e = e0 + el;
+    T acc = VT::zero();
+    if (g < G) {
+      int n = g;
+      for (; n + (kIn - 1) * G < cnt; n += kIn * G) {
+        T a[kIn];
+#pragma unroll
+        for (int q = 0; q < kIn; ++q) a[q] = col[(size_t)(n + q * G) * EV + e];
+#pragma unroll
+        for (int q = 0; q < kIn; ++q) {
+          if (w) VT::fma(w[n + q * G], a[q], acc);
+          else VT::add(a[q], acc);
+        }
+      }
+      for (; n < cnt; n += G) {
+        if (w) VT::fma(w[n], col[(size_t)n * EV + e], acc);
+        else VT::add(col[(size_t)n * EV + e], acc);
+      }
+    }
+    __syncthreads();
+    if (g < G) part[g * ec + el] = acc;
+    __syncthreads();
+    if (t < ec) {
+      T sum = VT::zero();
+      for (int k = 0; k < G; ++k) VT::add(part[k * ec + t], sum);
+      emit(e0 + t, sum);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __restrict__ ups,
                                                              const UpdateOut* __restrict__ outs, UpdateOut single) {
-  const DevUpdate& U = ups[blockIdx.x];
+  const DevUpdate& U = ups[blockIdx.y];
+  const int part = blockIdx.x, parts = U.parts;
+  if (part >= parts) return;
   const int t = threadIdx.x, N = U.N, E = U.E;
   __shared__ float s_v[kUpdThreads];
   __shared__ int s_i[kUpdThreads];
   __shared__ float s_x[kUpdThreads];
-  __shared__ float s_w[kUpdChunk];
-  __shared__ __align__(16) float s_part[kUpdWaves][64 * kUpdEB];
+  __shared__ __align__(16) float s_part[kUpdWaves * 64 * 4];
+  __shared__ int s_last;
+  __shared__ float s_w[(65536 + kUpdMaxParts - 1) / kUpdMaxParts];  // this part's normalised weights (N <= 65536)
 
-  // 1. finite minimum (lowest index), maximum and count
+  // 1. over all samples (every part the same way, so every part gets the same
+  //    values): finite minimum (lowest index), maximum and count
+  // (each thread takes samples t, t + kUpdThreads, ... in order, kIn loads in flight)
+  constexpr int kIn = 8;
+  const float* costs = U.costs;
   float mn = INFINITY, mx = -INFINITY;
   int arg = 0x7fffffff, nf = 0;
-  for (int n = t; n < N; n += kUpdThreads) {
-    const float S = U.costs[n];
-    if (isfinite(S)) {
-      ++nf;
-      if (S < mn) { mn = S; arg = n; }
-      mx = fmaxf(mx, S);
+  for (int n0 = t; n0 < N; n0 += kIn * kUpdThreads) {
+    float Sq[kIn];
+#pragma unroll
+    for (int q = 0; q < kIn; ++q) {
+      const int n = n0 + q * kUpdThreads;
+      Sq[q] = n < N ? costs[n] : INFINITY;
+    }
+#pragma unroll
+    for (int q = 0; q < kIn; ++q) {
+      const float S = Sq[q];
+      if (isfinite(S)) {
+        ++nf;
+        if (S < mn) { mn = S; arg = n0 + q * kUpdThreads; }
+        mx = fmaxf(mx, S);
+      }
     }
   }
   s_v[t] = mn; s_i[t] = arg; s_x[t] = mx;
@@ -2533,137 +2618,57 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
     return expf(-sh * inv_lam);
   };
   float zs = 0.f;
-  for (int n = t; n < N; n += kUpdThreads) zs += weight(U.costs[n]);
+  for (int n0 = t; n0 < N; n0 += kIn * kUpdThreads) {
+    float Sq[kIn];
+#pragma unroll
+    for (int q = 0; q < kIn; ++q) {
+      const int n = n0 + q * kUpdThreads;
+      Sq[q] = n < N ? costs[n] : INFINITY;
+    }
+#pragma unroll
+    for (int q = 0; q < kIn; ++q) zs += weight(Sq[q]);
+  }
   const float Z = block_sum(zs, s_x);
   const float invZ = nfin > 0 ? 1.f / Z : 0.f;
-  if (U.weights)
-    for (int n = t; n < N; n += kUpdThreads) U.weights[n] = weight(U.costs[n]) * invZ;
 
-  // 3. weighted knot average: waves split the samples, lanes the knot elements
-  //    (kUpdEB blocks of 64 elements per pass, so each lane keeps 4 x kUpdEB loads
-  //    in flight); every element's sum runs over the samples of a wave in index
-  //    order, then over the waves in index order
-  const UpdateOut* o = outs ? outs + blockIdx.x : &single;
-  float* dst = (U.last_iter && o && o->knots_out) ? o->knots_out : U.nominal_out;
-  const int wv = t / 64, ln = t % 64;
-  if ((E & 3) == 0) {
-    // rows of a multiple of 4 floats: a lane reads 4 consecutive elements per
-    // 128-bit load, 8 samples in flight; the same sums in the same order
-    const int E4 = E / 4;
-    float4* part4 = reinterpret_cast<float4*>(&s_part[0][0]);
-    for (int e40 = 0; e40 < E4; e40 += 64) {
-      const int e4 = e40 + ln;
-      const bool ok = e4 < E4;
-      float4 total = make_float4(0.f, 0.f, 0.f, 0.f);
-      for (int c0 = 0; c0 < N; c0 += kUpdChunk) {
-        const int cn = min(kUpdChunk, N - c0);
-        __syncthreads();
-        for (int n = t; n < cn; n += kUpdThreads) s_w[n] = weight(U.costs[c0 + n]) * invZ;
-        __syncthreads();
-        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (nfin > 0 && ok) {
-          const float4* col = reinterpret_cast<const float4*>(U.samples + (size_t)c0 * E) + e4;
-          int n = wv;
-          for (; n + 7 * kUpdWaves < cn; n += 8 * kUpdWaves) {
-            float4 a[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) a[q] = col[(size_t)(n + q * kUpdWaves) * E4];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const float w = s_w[n + q * kUpdWaves];
-              acc.x = fmaf(w, a[q].x, acc.x); acc.y = fmaf(w, a[q].y, acc.y);
-              acc.z = fmaf(w, a[q].z, acc.z); acc.w = fmaf(w, a[q].w, acc.w);
-            }
-          }
-          for (; n < cn; n += kUpdWaves) {
-            const float w = s_w[n];
-            const float4 a = col[(size_t)n * E4];
-            acc.x = fmaf(w, a.x, acc.x); acc.y = fmaf(w, a.y, acc.y);
-            acc.z = fmaf(w, a.z, acc.z); acc.w = fmaf(w, a.w, acc.w);
-          }
-        }
-        part4[wv * 64 + ln] = acc;
-        __syncthreads();
-        if (wv == 0) {
-          float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-          for (int k = 0; k < kUpdWaves; ++k) {
-            const float4 v = part4[k * 64 + ln];
-            sum.x += v.x; sum.y += v.y; sum.z += v.z; sum.w += v.w;
-          }
-          total.x += sum.x; total.y += sum.y; total.z += sum.z; total.w += sum.w;
-        }
-      }
-      if (wv == 0 && ok) {
-        const float tv[4] = {total.x, total.y, total.z, total.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) dst[4 * e4 + q] = nfin > 0 ? tv[q] : U.nominal_in[4 * e4 + q];
-      }
-    }
-  }
-  for (int e0 = 0; (E & 3) != 0 && e0 < E; e0 += 64 * kUpdEB) {
-    float total[kUpdEB];
-#pragma unroll
-    for (int b = 0; b < kUpdEB; ++b) total[b] = 0.f;
-    for (int c0 = 0; c0 < N; c0 += kUpdChunk) {
-      const int cn = min(kUpdChunk, N - c0);
-      __syncthreads();
-      for (int n = t; n < cn; n += kUpdThreads) s_w[n] = weight(U.costs[c0 + n]) * invZ;
-      __syncthreads();
-      float acc[kUpdEB];
-#pragma unroll
-      for (int b = 0; b < kUpdEB; ++b) acc[b] = 0.f;
-      if (nfin > 0) {
-        const float* col = U.samples + (size_t)c0 * E + e0 + ln;
-        bool ok[kUpdEB];
-#pragma unroll
-        for (int b = 0; b < kUpdEB; ++b) ok[b] = e0 + b * 64 + ln < E;
-        int n = wv;
-        for (; n + 3 * kUpdWaves < cn; n += 4 * kUpdWaves) {
-          float a[4][kUpdEB];
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int b = 0; b < kUpdEB; ++b)
-              a[q][b] = ok[b] ? col[(size_t)(n + q * kUpdWaves) * E + b * 64] : 0.f;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float w = s_w[n + q * kUpdWaves];
-#pragma unroll
-            for (int b = 0; b < kUpdEB; ++b) acc[b] = fmaf(w, a[q][b], acc[b]);
-          }
-        }
-        for (; n < cn; n += kUpdWaves) {
-          const float w = s_w[n];
-#pragma unroll
-          for (int b = 0; b < kUpdEB; ++b)
-            if (ok[b]) acc[b] = fmaf(w, col[(size_t)n * E + b * 64], acc[b]);
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < kUpdEB; ++b) s_part[wv][b * 64 + ln] = acc[b];
-      __syncthreads();
-      if (wv == 0) {
-#pragma unroll
-        for (int b = 0; b < kUpdEB; ++b) {
-          float sum = 0.f;
-#pragma unroll
-          for (int k = 0; k < kUpdWaves; ++k) sum += s_part[k][b * 64 + ln];
-          total[b] += sum;
-        }
-      }
-    }
-    if (wv == 0) {
-#pragma unroll
-      for (int b = 0; b < kUpdEB; ++b) {
-        const int e = e0 + b * 64 + ln;
-        if (e < E) dst[e] = nfin > 0 ? total[b] : U.nominal_in[e];
-      }
-    }
+  // 3. this part's slice: normalised weights, then its weighted knot sum
+  const int slice = (N + parts - 1) / parts;
+  const int n0 = part * slice, cnt = max(0, min(N, n0 + slice) - n0);
+  for (int i = t; i < cnt; i += kUpdThreads) {
+    const float w = weight(costs[n0 + i]) * invZ;
+    s_w[i] = w;
+    if (U.weights) U.weights[n0 + i] = w;
   }
   __syncthreads();
+  float* mine = U.partial + (size_t)part * E;
+  if ((E & 3) == 0)
+    rows_weighted_sum<4>(U.samples + (size_t)n0 * E, cnt, E, s_w, s_part,
+                         [&](int e, float4 v) { reinterpret_cast<float4*>(mine)[e] = v; });
+  else
+    rows_weighted_sum<1>(U.samples + (size_t)n0 * E, cnt, E, s_w, s_part, [&](int e, float v) { mine[e] = v; });
 
-  // 4. best-sample tracking across the iterations of this call
+  // 4. the last part to finish adds the slices in part order
+  __threadfence();
+  __syncthreads();
+  if (t == 0) s_last = atomicAdd(U.done, 1u) == (uint32_t)(parts - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (t == 0) U.done[0] = 0u;  // ready for the next launch
+  const UpdateOut* o = outs ? outs + blockIdx.y : &single;
+  float* dst = (U.last_iter && o && o->knots_out) ? o->knots_out : U.nominal_out;
+  if ((E & 3) == 0)
+    rows_weighted_sum<4>(U.partial, parts, E, nullptr, s_part, [&](int e, float4 v) {
+      const float c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dst[4 * e + k] = nfin > 0 ? c[k] : U.nominal_in[4 * e + k];
+    });
+  else
+    rows_weighted_sum<1>(U.partial, parts, E, nullptr, s_part,
+                         [&](int e, float v) { dst[e] = nfin > 0 ? v : U.nominal_in[e]; });
+  __syncthreads();
+
+  // 5. best-sample tracking across the iterations of this call
   float* bs = U.best_state;  // [E] knots, then S_best, best_iter, n_nonfinite, all_nonfinite, best_sample
   if (U.first_iter) {
     for (int e = t; e < E; e += kUpdThreads) bs[e] = U.nominal_in[e];
@@ -2747,6 +2752,15 @@ struct StageItem {
 __global__ void stage_kernel(const StageItem* __restrict__ items) {
   const StageItem it = items[blockIdx.x];
   for (int i = threadIdx.x; i < it.count; i += blockDim.x) it.dst[i] = it.src[i];
+}
+
+// Two device copies in one launch (block 0: src0 -> dst0, block 1: src1 -> dst1).
+__global__ void copy2_kernel(const float* __restrict__ src0, float* __restrict__ dst0, int n0,
+                             const float* __restrict__ src1, float* __restrict__ dst1, int n1) {
+  const float* src = blockIdx.x == 0 ? src0 : src1;
+  float* dst = blockIdx.x == 0 ? dst0 : dst1;
+  const int n = blockIdx.x == 0 ? n0 : n1;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
 // ---------------------------------------------------------------------------
