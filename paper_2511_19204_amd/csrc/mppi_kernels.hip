@@ -147,12 +147,13 @@ __device__ __forceinline__ void get_acc(const float* s, float* a) {
 struct StepIO {
   // inputs
   float q, v;          // joint state (revolute lanes)
-  float bq[7], bv[6];  // base state (lane 0 of a floating-base group)
+  float bq[7], bv[6];  // base state (every lane of a floating-base rollout in the body schedule)
   float qref, vref;    // reference (revolute lanes)
   float dt;
   // outputs
   float qdd;           // joint acceleration
   float ba[6];         // base spatial acceleration, base coordinates (lane 0)
+  float Rb[9];         // rotation of the base quaternion at the start of the step
   float tau;           // clipped PD torque
   float cost;          // running-cost terms of this lane (when want_cost)
   uint32_t mask;       // contact activity bits of this lane's contacts
@@ -840,7 +841,8 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
 
   // ---- frame B: world pose of the base.  Every lane carries the base state
   //      (position, quaternion, twist), so every lane forms it in registers.
-  float Rb[9], pb[3];
+  float* Rb = io.Rb;
+  float pb[3];
   if (fb) {
     quat_R(io.bq + 3, Rb);
     pb[0] = io.bq[0]; pb[1] = io.bq[1]; pb[2] = io.bq[2];
@@ -1161,11 +1163,10 @@ __device__ __forceinline__ uint32_t group_or(uint32_t x, float* red, int l) {
 }
 
 // semi-implicit Euler on the base: v += dt a, p += dt R(quat) v_lin, quat <- quat (x) exp(dt w)
-__device__ __forceinline__ void integrate_base(float* bq, float* bv, const float* ba, float dt) {
+// (R: the rotation of the quaternion bq[3..6], as quat_R gives it)
+__device__ __forceinline__ void integrate_base_R(float* bq, float* bv, const float* ba, float dt, const float* R) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) bv[k] = fmaf(dt, ba[k], bv[k]);
-  float R[9];
-  quat_R(bq + 3, R);
 #pragma unroll
   for (int r = 0; r < 3; ++r) bq[r] += dt * (R[r * 3 + 0] * bv[3] + R[r * 3 + 1] * bv[4] + R[r * 3 + 2] * bv[5]);
   const float wn2 = bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2];
@@ -1191,6 +1192,11 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
   const float r3 = a0 * e3 + a1 * e2 - a2 * e1 + a3 * e0;
   const float inv = rsq(r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
   bq[3] = r0 * inv; bq[4] = r1 * inv; bq[5] = r2 * inv; bq[6] = r3 * inv;
+}
+__device__ __forceinline__ void integrate_base(float* bq, float* bv, const float* ba, float dt) {
+  float R[9];
+  quat_R(bq + 3, R);
+  integrate_base_R(bq, bv, ba, dt, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -1276,7 +1282,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     // joints (other lanes hold q = qd = qdd = 0)
     io.v = fmaf(io.dt, io.qdd, io.v);
     io.q = fmaf(io.dt, io.v, io.q);
-    if (fb) integrate_base(io.bq, io.bv, io.ba, io.dt);  // every lane: the same base state
+    if (fb) integrate_base_R(io.bq, io.bv, io.ba, io.dt, io.Rb);  // every lane: the same base state
     clk.advance(sc.K, F, sc.nsub);
   }
   if (state_out) {

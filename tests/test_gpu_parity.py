@@ -193,6 +193,33 @@ def test_update_on_oracle_costs_and_knots():
     assert np.array_equal(_np(out), nom.astype(np.float32))
 
 
+@pytest.mark.parametrize("N", [1, 63, 65, 4097, 20000])
+def test_update_slices_match_oracle(N):
+    """The update splits the samples into slices of at least 64 (at most 64
+    slices, the last one ragged); sizes around those edges give the oracle's
+    weights and weighted average, and a second call gives the same bits (the
+    finished-slice counter resets itself)."""
+    m, p, seed, model, c = _ctrl("quadruped", n_samples=N)
+    rng = np.random.default_rng(N)
+    nom = synth.f32(rng.normal(0.0, 0.3, c.E))
+    smp = synth.f32(rng.normal(0.0, 0.3, (N, c.E)))
+    S = synth.f32(rng.exponential(200.0, N) + 500.0)
+    if N > 10:
+        S[N // 3] = np.inf
+        S[N - 2] = np.nan
+    out = torch.zeros(c.E, device="cuda")
+    w = torch.zeros(N, device="cuda")
+    c.update(_t(S), _t(smp), _t(nom), out, w)
+    wr, nstar, nf = O.weights(S, p["lambda"])
+    ref = O.weighted_average(wr, smp)
+    got = _np(out)
+    assert np.max(np.abs(_np(w) - wr)) <= 1e-6
+    assert np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-4
+    out2 = torch.zeros(c.E, device="cuda")
+    c.update(_t(S), _t(smp), _t(nom), out2, w)
+    assert np.array_equal(_np(out2), got)
+
+
 def _run_step(c, m, p, knots):
     E = c.E
     st, ki = _t(m["x0"]), _t(knots)
