@@ -103,19 +103,21 @@ def primary(args, torch, mppi, synth, flops):
     ctrl.profile(True)
     ctrl.profile_read()
     stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # step boundaries: step i runs between marks i and i + 1 (one event per step,
+    # since the end of a step is the start of the next on the stream)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks[0].record(stream)
     for i in range(args.steps):
-        evs[i][0].record(stream)
         ctrl.step(st, ka, kb)
-        evs[i][1].record(stream)
+        marks[i + 1].record(stream)
         ka, kb = kb, ka
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     roll_ms, n_roll, upd_ms, n_upd = ctrl.profile_read()
     ctrl.profile(False)
-    lat = [a.elapsed_time(b) for a, b in evs]
+    lat = [marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)]
     N, H, I = p["n_samples"], p["horizon"], p["n_iters"]
     steps_rollout = N * H * I
     fl = flops.flops_per_rollout_step(m)

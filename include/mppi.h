@@ -364,10 +364,11 @@ mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, const float* d_
 
 /* ---- Kernel timing ------------------------------------------------------- */
 
-/* When enabled, mppi_step records a HIP event pair around every rollout and
- * update launch on its stream.  mppi_profile_read waits for the recorded events,
- * returns the summed kernel time (ms) and launch counts since the last read, and
- * recycles the events.  Costs a few microseconds per launch; off by default. */
+/* When enabled, mppi_step records three HIP events per iteration on its stream:
+ * before the rollout launch, between the rollout and the update launch, and after
+ * the update launch.  mppi_profile_read waits for the recorded events, returns the
+ * summed rollout and update time (ms) and launch counts since the last read, and
+ * recycles the events.  Costs a few microseconds per event; off by default. */
 mppi_status mppi_profile_enable(mppi_ctx* c, int32_t on);
 mppi_status mppi_profile_read(mppi_ctx* c, double* rollout_ms, int32_t* n_rollout, double* update_ms,
                               int32_t* n_update);

@@ -18,6 +18,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <array>
 #include <vector>
 
 #include "../../include/mppi.h"
@@ -111,17 +112,18 @@ struct mppi_ctx {
   std::vector<DevUpdate> h_ups;
   // kernel timing (HIP events around each launch on the launch stream) when enabled
   bool profile = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_roll, ev_upd, ev_pool;
+  // per iteration: before the rollout, between rollout and update, after the update
+  std::vector<std::array<hipEvent_t, 3>> ev_marks;
+  std::vector<hipEvent_t> ev_pool;
 };
 
-static mppi_status ev_pair(mppi_ctx* c, std::pair<hipEvent_t, hipEvent_t>* out) {
+static mppi_status ev_get(mppi_ctx* c, hipEvent_t* out) {
   if (!c->ev_pool.empty()) {
     *out = c->ev_pool.back();
     c->ev_pool.pop_back();
     return MPPI_OK;
   }
-  HIP_TRY(hipEventCreate(&out->first));
-  HIP_TRY(hipEventCreate(&out->second));
+  HIP_TRY(hipEventCreate(out));
   return MPPI_OK;
 }
 
@@ -406,11 +408,9 @@ extern "C" mppi_status mppi_model_destroy(mppi_model* m) {
 // context
 // ---------------------------------------------------------------------------
 static void free_ctx_events(mppi_ctx* c) {
-  for (auto* v : {&c->ev_roll, &c->ev_upd, &c->ev_pool})
-    for (auto& e : *v) {
-      (void)hipEventDestroy(e.first);
-      (void)hipEventDestroy(e.second);
-    }
+  for (auto& m : c->ev_marks)
+    for (hipEvent_t e : m) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
 }
 
 static void free_ctx_buffers(mppi_ctx* c) {
@@ -817,27 +817,24 @@ static mppi_status run_iterations(mppi_ctx* c, float* d_knots_out, float* d_best
   const int R = rollouts_per_block(c->lanes, dm);
   const int blocks = (c->N + R - 1) / R;
   for (int it = 0; it < c->I; ++it) {
-    std::pair<hipEvent_t, hipEvent_t> er{}, eu{};
+    // timing marks: the rollout runs between marks 0 and 1, the update between 1 and 2
+    std::array<hipEvent_t, 3> mk{};
     if (c->profile) {
-      mppi_status st = ev_pair(c, &er);
-      if (st != MPPI_OK) return st;
-      HIP_TRY(hipEventRecord(er.first, s));
+      for (hipEvent_t& e : mk) {
+        mppi_status st = ev_get(c, &e);
+        if (st != MPPI_OK) return st;
+      }
+      HIP_TRY(hipEventRecord(mk[0], s));
     }
     HIP_TRY(launch_rollout(c->lanes, blocks, c->d_insts + it, nullptr, dm, s));
-    if (c->profile) {
-      HIP_TRY(hipEventRecord(er.second, s));
-      c->ev_roll.push_back(er);
-      mppi_status st = ev_pair(c, &eu);
-      if (st != MPPI_OK) return st;
-      HIP_TRY(hipEventRecord(eu.first, s));
-    }
+    if (c->profile) HIP_TRY(hipEventRecord(mk[1], s));
     UpdateOut o{nullptr, nullptr, nullptr};
     if (it == c->I - 1) o = UpdateOut{d_knots_out, d_best_knots, d_info};
     hipLaunchKernelGGL(update_kernel, dim3(update_parts(c->N), 1), dim3(kUpdThreads), 0, s, c->d_ups + it, nullptr, o);
     HIP_TRY(hipGetLastError());
     if (c->profile) {
-      HIP_TRY(hipEventRecord(eu.second, s));
-      c->ev_upd.push_back(eu);
+      HIP_TRY(hipEventRecord(mk[2], s));
+      c->ev_marks.push_back(mk);
     }
   }
   if (d_costs) HIP_TRY(hipMemcpyAsync(d_costs, c->costs, (size_t)c->I * c->N * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -1474,26 +1471,21 @@ extern "C" mppi_status mppi_profile_read(mppi_ctx* c, double* rollout_ms, int32_
                                          int32_t* n_update) {
   if (!c || !rollout_ms || !n_rollout || !update_ms || !n_update) return fail(MPPI_EINVAL, "null argument");
   double tr = 0, tu = 0;
-  for (auto& e : c->ev_roll) {
-    HIP_TRY(hipEventSynchronize(e.second));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
-    tr += ms;
-  }
-  for (auto& e : c->ev_upd) {
-    HIP_TRY(hipEventSynchronize(e.second));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
-    tu += ms;
+  for (auto& m : c->ev_marks) {
+    HIP_TRY(hipEventSynchronize(m[2]));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(hipEventElapsedTime(&a, m[0], m[1]));
+    HIP_TRY(hipEventElapsedTime(&b, m[1], m[2]));
+    tr += a;
+    tu += b;
   }
   *rollout_ms = tr;
-  *n_rollout = (int32_t)c->ev_roll.size();
+  *n_rollout = (int32_t)c->ev_marks.size();
   *update_ms = tu;
-  *n_update = (int32_t)c->ev_upd.size();
-  for (auto* v : {&c->ev_roll, &c->ev_upd}) {
-    for (auto& e : *v) c->ev_pool.push_back(e);
-    v->clear();
-  }
+  *n_update = (int32_t)c->ev_marks.size();
+  for (auto& m : c->ev_marks)
+    for (hipEvent_t e : m) c->ev_pool.push_back(e);
+  c->ev_marks.clear();
   return MPPI_OK;
 }
 

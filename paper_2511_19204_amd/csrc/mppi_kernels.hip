@@ -2574,28 +2574,46 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
   __shared__ int s_last;
   __shared__ float s_w[(65536 + kUpdMaxParts - 1) / kUpdMaxParts];  // this part's normalised weights (N <= 65536)
 
+  // this part's slice of the samples
+  const int slice = (N + parts - 1) / parts;
+  const int n0 = part * slice, cnt = max(0, min(N, n0 + slice) - n0);
+
   // 1. over all samples (every part the same way, so every part gets the same
-  //    values): finite minimum (lowest index), maximum and count
-  // (each thread takes samples t, t + kUpdThreads, ... in order, kIn loads in flight)
-  constexpr int kIn = 8;
+  //    values): finite minimum (lowest index), maximum and count.  Each thread
+  //    takes samples t, t + kUpdThreads, ... in order; up to kReg of them stay in
+  //    registers for the weight sum, and the slice's costs go to s_w.
+  constexpr int kIn = 8, kReg = 16;
+  const bool in_regs = N <= kReg * kUpdThreads;
   const float* costs = U.costs;
+  float Sv[kReg];
   float mn = INFINITY, mx = -INFINITY;
   int arg = 0x7fffffff, nf = 0;
-  for (int n0 = t; n0 < N; n0 += kIn * kUpdThreads) {
-    float Sq[kIn];
+  auto visit = [&](float S, int n) {
+    if (n >= n0 && n < n0 + cnt) s_w[n - n0] = S;
+    if (isfinite(S)) {
+      ++nf;
+      if (S < mn) { mn = S; arg = n; }
+      mx = fmaxf(mx, S);
+    }
+  };
+  if (in_regs) {
 #pragma unroll
-    for (int q = 0; q < kIn; ++q) {
-      const int n = n0 + q * kUpdThreads;
-      Sq[q] = n < N ? costs[n] : INFINITY;
+    for (int q = 0; q < kReg; ++q) {
+      const int n = t + q * kUpdThreads;
+      Sv[q] = n < N ? costs[n] : INFINITY;
     }
 #pragma unroll
-    for (int q = 0; q < kIn; ++q) {
-      const float S = Sq[q];
-      if (isfinite(S)) {
-        ++nf;
-        if (S < mn) { mn = S; arg = n0 + q * kUpdThreads; }
-        mx = fmaxf(mx, S);
+    for (int q = 0; q < kReg; ++q) visit(Sv[q], t + q * kUpdThreads);
+  } else {
+    for (int m0 = t; m0 < N; m0 += kIn * kUpdThreads) {
+      float Sq[kIn];
+#pragma unroll
+      for (int q = 0; q < kIn; ++q) {
+        const int n = m0 + q * kUpdThreads;
+        Sq[q] = n < N ? costs[n] : INFINITY;
       }
+#pragma unroll
+      for (int q = 0; q < kIn; ++q) visit(Sq[q], m0 + q * kUpdThreads);
     }
   }
   s_v[t] = mn; s_i[t] = arg; s_x[t] = mx;
@@ -2624,24 +2642,28 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
     return expf(-sh * inv_lam);
   };
   float zs = 0.f;
-  for (int n0 = t; n0 < N; n0 += kIn * kUpdThreads) {
-    float Sq[kIn];
+  if (in_regs) {
 #pragma unroll
-    for (int q = 0; q < kIn; ++q) {
-      const int n = n0 + q * kUpdThreads;
-      Sq[q] = n < N ? costs[n] : INFINITY;
+    for (int q = 0; q < kReg; ++q) zs += weight(Sv[q]);
+  } else {
+    for (int m0 = t; m0 < N; m0 += kIn * kUpdThreads) {
+      float Sq[kIn];
+#pragma unroll
+      for (int q = 0; q < kIn; ++q) {
+        const int n = m0 + q * kUpdThreads;
+        Sq[q] = n < N ? costs[n] : INFINITY;
+      }
+#pragma unroll
+      for (int q = 0; q < kIn; ++q) zs += weight(Sq[q]);
     }
-#pragma unroll
-    for (int q = 0; q < kIn; ++q) zs += weight(Sq[q]);
   }
   const float Z = block_sum(zs, s_x);
   const float invZ = nfin > 0 ? 1.f / Z : 0.f;
 
-  // 3. this part's slice: normalised weights, then its weighted knot sum
-  const int slice = (N + parts - 1) / parts;
-  const int n0 = part * slice, cnt = max(0, min(N, n0 + slice) - n0);
+  // 3. this part's slice: normalised weights (from the costs in s_w), then its
+  //    weighted knot sum
   for (int i = t; i < cnt; i += kUpdThreads) {
-    const float w = weight(costs[n0 + i]) * invZ;
+    const float w = weight(s_w[i]) * invZ;
     s_w[i] = w;
     if (U.weights) U.weights[n0 + i] = w;
   }
