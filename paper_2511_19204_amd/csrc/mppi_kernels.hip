@@ -591,29 +591,34 @@ __device__ __forceinline__ float contact_point(const float* r, const float* R, c
     const float zb[3] = {Rb[6], Rb[7], Rb[8]};
     const float wt[2] = {vw[0] * inv_nrm, vw[1] * inv_nrm};
     const float ub[3] = {Rb[0] * wt[0] + Rb[3] * wt[1], Rb[1] * wt[0] + Rb[4] * wt[1], Rb[2] * wt[0] + Rb[5] * wt[1]};
-    // added inertia dt P^T D P with P = [-x^x, 1]; with w1 = x x zb, w2 = x x ub:
-    //   top-left  a (|x|^2 I - x x^T) + al w1 w1^T - a w2 w2^T
-    //   top-right a x^x + al w1 zb^T - a w2 ub^T,   bottom-right D
+    // added inertia dt P^T D P with P = [-x^x, 1]: with P^T zb = (x x zb, zb) = y1 and
+    // P^T ub = (x x ub, ub) = y2 it is dt (al y1 y1^T - a y2 y2^T + a P^T P), where
+    // P^T P has blocks |x|^2 I - x x^T, x^x and I
     float w1[3], w2[3];
     cross3(x, zb, w1);
     cross3(x, ub, w2);
     const float x2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
     const float dta = dt * aa, dtal = dt * al;
+    const float y1[6] = {w1[0], w1[1], w1[2], zb[0], zb[1], zb[2]};
+    const float y2[6] = {w2[0], w2[1], w2[2], ub[0], ub[1], ub[2]};
+    float t1[6], t2[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) { t1[r] = dtal * y1[r]; t2[r] = dta * y2[r]; }
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int cc = r; cc < 6; ++cc) IA[SI(r, cc)] += t1[r] * y1[cc] - t2[r] * y2[cc];
+    const float dax[3] = {dta * x[0], dta * x[1], dta * x[2]};
+    const float dx2 = dta * x2;
 #pragma unroll
     for (int q = 0; q < 3; ++q)
 #pragma unroll
-      for (int cc = q; cc < 3; ++cc) {
-        const float tl = aa * ((q == cc ? x2 : 0.f) - x[q] * x[cc]) + al * w1[q] * w1[cc] - aa * w2[q] * w2[cc];
-        IA[SI(q, cc)] += dt * tl;
-        const float br = (q == cc ? aa : 0.f) + al * zb[q] * zb[cc] - aa * ub[q] * ub[cc];
-        IA[SI(q + 3, cc + 3)] += dt * br;
-      }
-    const float Xm[9] = {0.f, -x[2], x[1], x[2], 0.f, -x[0], -x[1], x[0], 0.f};
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc)
-        IA[SI(q, cc + 3)] += dta * Xm[q * 3 + cc] + dtal * w1[q] * zb[cc] - dta * w2[q] * ub[cc];
+      for (int cc = q; cc < 3; ++cc) IA[SI(q, cc)] += (q == cc ? dx2 : 0.f) - dax[q] * x[cc];
+    // dt a x^x in the top-right block, dt a I in the bottom-right block
+    IA[SI(0, 4)] -= dax[2]; IA[SI(0, 5)] += dax[1];
+    IA[SI(1, 3)] += dax[2]; IA[SI(1, 5)] -= dax[0];
+    IA[SI(2, 3)] -= dax[1]; IA[SI(2, 4)] += dax[0];
+    IA[SI(3, 3)] += dta; IA[SI(4, 4)] += dta; IA[SI(5, 5)] += dta;
     // bias of the added inertia: dt P^T D P (a_g - beta) = dt (x x Dw', Dw'), w' = P (a_g - beta)
     const float sa[3] = {-beta[0], -beta[1], -beta[2]};
     const float sl[3] = {agl[0] - beta[3], agl[1] - beta[4], agl[2] - beta[5]};
@@ -855,13 +860,13 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // ---- forward kinematics, level by level (slot: R, p, v, beta about the body origin)
   float R[9], p[3], e[3], ax[3], v[6], c[6], beta[6];
   const int depth = bc.depth;
-  if (is_base) {
+  if (is_base) {  // (lever arm, axis and velocity product are never read for the base)
 #pragma unroll
     for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.f : 0.f;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { p[k] = 0.f; e[k] = 0.f; ax[k] = 0.f; }
+    for (int k = 0; k < 3; ++k) p[k] = 0.f;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) { v[k] = io.bv[k]; c[k] = 0.f; beta[k] = 0.f; }
+    for (int k = 0; k < 6; ++k) { v[k] = io.bv[k]; beta[k] = 0.f; }
   }
   float C[9];
   if (is_joint) {
