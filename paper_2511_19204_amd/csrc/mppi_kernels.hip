@@ -975,7 +975,32 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
     float Ip[21], pp[6];
     if (body_lane && depth == d) {
       const int nch = bc.n_child;
-      for (int k = 0; k < nch; ++k) add_art(slots + child_of(bc, k) * kSlot, IA, pA);
+      if (nch > 0) {
+        // children reached through LDS: the first kFold records are read together
+        // (a missing child reads this lane's own slot and is not added), then
+        // added in child order; more children follow one by one
+        constexpr int kFold = D > 0 ? 3 : 2;  // (the generic kernels have fewer registers to spare)
+        float t[kFold][28];
+#pragma unroll
+        for (int k = 0; k < kFold; ++k) {
+          const float* src = slots + (k < nch ? child_of(bc, k) : b) * kSlot;
+#pragma unroll
+          for (int q = 0; q < 7; ++q) {
+            const float4 x = get4(src + 4 * q);
+            t[k][4 * q] = x.x; t[k][4 * q + 1] = x.y; t[k][4 * q + 2] = x.z; t[k][4 * q + 3] = x.w;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kFold; ++k)
+          if (k < nch) {
+#pragma unroll
+            for (int q = 0; q < 21; ++q) IA[q] += t[k][q];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) pA[q] += t[k][21 + q];
+          }
+#pragma unroll 1
+        for (int k = kFold; k < nch; ++k) add_art(slots + child_of(bc, k) * kSlot, IA, pA);
+      }
       if (is_joint) {
         backward_joint(IA, pA, ax, c, e, tau, bc.arm, gain, U, invD, u, Ip, pp);
         if (bc.flags & kArtOut) put_art(slots + b * kSlot, Ip, pp);
