@@ -152,7 +152,7 @@ struct StepIO {
   float dt;
   // outputs
   float qdd;           // joint acceleration
-  float ba[6];         // base spatial acceleration, base coordinates (lane 0)
+  float ba[6];         // base spatial acceleration, base coordinates (every lane of the rollout)
   float Rb[9];         // rotation of the base quaternion at the start of the step
   float tau;           // clipped PD torque
   float cost;          // running-cost terms of this lane (when want_cost)

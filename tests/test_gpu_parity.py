@@ -153,6 +153,30 @@ def test_rollout_costs_strict(name, count, H):
     assert rel[same].max() <= 1e-3
 
 
+def test_rollout_costs_contact_on_floating_base():
+    """Contact points on the floating base itself (its frame is the identity in
+    base axes, its twist the base twist): two points under the trunk, one of
+    them penetrating from the start, with the strict bar of the test above."""
+    m, p, s = synth.config("quadruped", n_samples=32)
+    p["horizon"] = 20
+    m = dict(m)
+    m["contact_body"] = np.concatenate([np.asarray(m["contact_body"]), [0, 0]]).astype(m["contact_body"].dtype)
+    m["contact_pos"] = np.concatenate([np.asarray(m["contact_pos"]),
+                                       [[0.05, 0.02, -0.32], [-0.08, -0.03, -0.29]]]).astype(np.asarray(m["contact_pos"]).dtype)
+    m["support"] = np.concatenate([np.asarray(m["support"]), [False, False]])
+    model = mppi.Model(m)
+    c = mppi.Controller(model, p, s)
+    smp = _oracle_samples(m, p, s, 32)
+    got, gm = _gpu_rollouts(c, m, p, smp)
+    ref, rm, _, _ = _oracle_rollouts(m, p, m["x0"], smp)
+    assert np.all(gm[:, 0] & (1 << 4)), "the penetrating trunk point is in contact at the first step"
+    same = np.all(gm == rm, axis=1)
+    rel = np.abs(got - ref) / np.abs(ref)
+    assert np.all(np.isfinite(got)) and np.all(np.isfinite(ref))
+    assert same.mean() >= 0.9
+    assert rel[same].max() <= 1e-3
+
+
 @pytest.mark.parametrize("name,count", [("quadruped", 64), ("humanoid", 48)])
 def test_rollout_costs_full_horizon_match_fp32_statistics(name, count):
     """Full horizon of the contact configurations: rounding differences are amplified
