@@ -26,7 +26,8 @@
 
 namespace mppi {
 // kernels (mppi_kernels.hip)
-template <int G, int D> __global__ void rollout_kernel(const DevInst*, const int2*, int, int);
+template <int G, int D>
+__global__ void rollout_kernel(const DevInst*, const int2*, int, int, const float*, const float*);
 template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
 template <int G, int D> __global__ void team_kernel(const DevInst*, const int2*, int, int);
@@ -39,11 +40,6 @@ __global__ void shift_knots_kernel(const float*, float*, int, int, int, int, int
 template <int G>
 __global__ void dynamics_kernel(const DevModel*, int, const float*, const float*, const float*, const float*, float,
                                 float*, int, int);
-struct UpdateOut {
-  float* knots_out;
-  float* best_out;
-  void* info_out;
-};
 __global__ void update_kernel(const DevUpdate*, const UpdateOut*, UpdateOut);
 struct StageItem {
   const float* src;
@@ -711,13 +707,16 @@ static int rollouts_per_block(int key, const Dims& dm) { return launch_shape(key
 // loops unrolled; deeper trees take the general one
 template <int G>
 static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
-                                   int depth, hipStream_t s) {
+                                   int depth, hipStream_t s, const float* x0_in, const float* nominal_in) {
   if (depth <= 3)
-    hipLaunchKernelGGL((rollout_kernel<G, 3>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+    hipLaunchKernelGGL((rollout_kernel<G, 3>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
+                       x0_in, nominal_in);
   else if (depth <= 6)
-    hipLaunchKernelGGL((rollout_kernel<G, 6>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+    hipLaunchKernelGGL((rollout_kernel<G, 6>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
+                       x0_in, nominal_in);
   else
-    hipLaunchKernelGGL((rollout_kernel<G, 0>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table);
+    hipLaunchKernelGGL((rollout_kernel<G, 0>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
+                       x0_in, nominal_in);
   return hipGetLastError();
 }
 template <int G>
@@ -738,15 +737,18 @@ static hipError_t launch_chain_GC(int blocks, const DevInst* insts, const int2* 
   return hipGetLastError();
 }
 
+// x0_in / nominal_in (body schedule, one instance; else null): state and nominal to
+// use instead of the instance's staged copies.
 static hipError_t launch_rollout(int key, int blocks, const DevInst* insts, const int2* work, const Dims& dm,
-                                 hipStream_t s) {
+                                 hipStream_t s, const float* x0_in = nullptr, const float* nominal_in = nullptr) {
+  if ((x0_in || nominal_in) && !(key > 0 && key < kTeamKey)) return hipErrorInvalidValue;
   const LaunchShape sh = launch_shape(key, dm);
   switch (key) {
-    case 4: return launch_rollout_G<4>(blocks, insts, work, sh, dm.depth, s);
-    case 8: return launch_rollout_G<8>(blocks, insts, work, sh, dm.depth, s);
-    case 16: return launch_rollout_G<16>(blocks, insts, work, sh, dm.depth, s);
-    case 32: return launch_rollout_G<32>(blocks, insts, work, sh, dm.depth, s);
-    case 64: return launch_rollout_G<64>(blocks, insts, work, sh, dm.depth, s);
+    case 4: return launch_rollout_G<4>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
+    case 8: return launch_rollout_G<8>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
+    case 16: return launch_rollout_G<16>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
+    case 32: return launch_rollout_G<32>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
+    case 64: return launch_rollout_G<64>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
     case kTeamKey + 4: return launch_team_G<4>(blocks, insts, work, sh, dm.depth, s);
     case kTeamKey + 8: return launch_team_G<8>(blocks, insts, work, sh, dm.depth, s);
     case kTeamKey + 16: return launch_team_G<16>(blocks, insts, work, sh, dm.depth, s);
@@ -811,8 +813,11 @@ extern "C" mppi_status mppi_set_batch_options(const mppi_batch_opts* o) {
 
 // The I planning iterations of one step from the staged state (c->x0) and
 // nominal (c->nom), as a sequence of rollout and update launches on s.
+// x0_in / nominal_in (nullable, body schedule only): the call's state and initial
+// nominal read in place, instead of staged copies.
 static mppi_status run_iterations(mppi_ctx* c, float* d_knots_out, float* d_best_knots, mppi_step_info* d_info,
-                                  float* d_costs, hipStream_t s) {
+                                  float* d_costs, hipStream_t s, const float* x0_in = nullptr,
+                                  const float* nominal_in = nullptr) {
   const Dims dm = dims_of(c);
   const int R = rollouts_per_block(c->lanes, dm);
   const int blocks = (c->N + R - 1) / R;
@@ -826,10 +831,11 @@ static mppi_status run_iterations(mppi_ctx* c, float* d_knots_out, float* d_best
       }
       HIP_TRY(hipEventRecord(mk[0], s));
     }
-    HIP_TRY(launch_rollout(c->lanes, blocks, c->d_insts + it, nullptr, dm, s));
+    const float* nom0 = it == 0 ? nominal_in : nullptr;
+    HIP_TRY(launch_rollout(c->lanes, blocks, c->d_insts + it, nullptr, dm, s, x0_in, nom0));
     if (c->profile) HIP_TRY(hipEventRecord(mk[1], s));
-    UpdateOut o{nullptr, nullptr, nullptr};
-    if (it == c->I - 1) o = UpdateOut{d_knots_out, d_best_knots, d_info};
+    UpdateOut o{nullptr, nullptr, nullptr, nom0};
+    if (it == c->I - 1) o = UpdateOut{d_knots_out, d_best_knots, d_info, nom0};
     hipLaunchKernelGGL(update_kernel, dim3(update_parts(c->N), 1), dim3(kUpdThreads), 0, s, c->d_ups + it, nullptr, o);
     HIP_TRY(hipGetLastError());
     if (c->profile) {
@@ -845,7 +851,10 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
                                  float* d_best_knots, mppi_step_info* d_info, float* d_costs, void* stream) {
   if (!c || !d_state || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
-  // state and warm-start knots into the instance's buffers, one launch
+  // the body schedule reads the state and the warm-start knots in place; the
+  // others take copies in the instance's buffers (one launch)
+  if (c->lanes > 0 && c->lanes < kTeamKey)
+    return run_iterations(c, d_knots_out, d_best_knots, d_info, d_costs, s, d_state, d_knots_in);
   hipLaunchKernelGGL(copy2_kernel, dim3(2), dim3(256), 0, s, d_state, c->x0, c->nq + c->nv, d_knots_in, c->nom, c->E);
   HIP_TRY(hipGetLastError());
   return run_iterations(c, d_knots_out, d_best_knots, d_info, d_costs, s);

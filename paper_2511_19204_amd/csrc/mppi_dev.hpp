@@ -132,6 +132,14 @@ struct DevUpdate {
   float lambda;
 };
 
+// Per-call outputs of an instance's update launch (null fields: not wanted).
+struct UpdateOut {
+  float* knots_out;         // nominal output of the last iteration
+  float* best_out;          // best knots
+  void* info_out;           // mppi_step_info
+  const float* nominal_in;  // replaces the descriptor's nominal input
+};
+
 // The update splits an instance's samples into `parts` consecutive slices, one
 // workgroup each; the last workgroup to finish sums the slices in order.
 constexpr int kUpdThreads = 256;

@@ -1071,7 +1071,8 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
 // ---------------------------------------------------------------------------
 template <int G>
 __device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, float* knots, bool valid,
-                             const float* tab) {
+                             const float* tab, const float* nominal = nullptr) {
+  const float* nom = nominal ? nominal : I.nominal;
   const int K = I.K, nu = I.nu, KU = K * nu;
   const int nblk = (KU + 1) / 2;
   const uint2 key = make_uint2(I.seed_lo, I.seed_hi);
@@ -1095,14 +1096,14 @@ __device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, 
       }
       const float sq = sig[k];
       const float lo = M.qmin[jj], hi = M.qmax[jj];
-      float tq = fmaf(sq, zq, I.nominal[m]);
+      float tq = fmaf(sq, zq, nom[m]);
       tq = fminf(fmaxf(tq, lo), hi);
       knots[m] = tq;
       if (valid) I.samples[(size_t)n * I.E + m] = tq;
       if (I.spline_mode == 0) {
         const float sv = sq / I.delta;
         const float lim = 2.f * fminf(hi - tq, tq - lo) / I.delta;
-        float tv = fmaf(sv, zv, I.nominal[KU + m]);
+        float tv = fmaf(sv, zv, nom[KU + m]);
         tv = fminf(fmaxf(tv, -lim), lim);
         knots[KU + m] = tv;
         if (valid) I.samples[(size_t)n * I.E + KU + m] = tv;
@@ -1237,9 +1238,12 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
 // set (state prediction, one sample) the state reached is written there and
 // no cost is formed.
 template <int G, int D = 0>
+// x0_in / nominal_in (nullable) replace the instance's staged state and nominal.
 __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride,
                                                             int table_floats, float* smem, int steps,
-                                                            float* state_out) {
+                                                            float* state_out, const float* x0_in = nullptr,
+                                                            const float* nominal_in = nullptr) {
+  const float* x0 = x0_in ? x0_in : I.x0;
   const int lane = threadIdx.x;
   const int grp = lane / G, l = lane % G;
   const DevModel& M = *I.model;
@@ -1253,7 +1257,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 
   // knots of this sample
   if (I.generate) {
-    sample_group<G>(M, I, valid ? n : 0, l, knots, valid, tab);
+    sample_group<G>(M, I, valid ? n : 0, l, knots, valid, tab, nominal_in);
   } else {
     const float* src = I.samples + (size_t)(valid ? n : 0) * I.E;
     for (int e = l; e < I.E; e += G) knots[e] = src[e];
@@ -1269,13 +1273,13 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   StepIO io;
   io.q = io.v = 0.f;
   if (is_joint) {
-    io.q = I.x0[(fb ? 7 : 0) + j];
-    io.v = I.x0[nq + (fb ? 6 : 0) + j];
+    io.q = x0[(fb ? 7 : 0) + j];
+    io.v = x0[nq + (fb ? 6 : 0) + j];
   }
 #pragma unroll
-  for (int k = 0; k < 7; ++k) io.bq[k] = fb ? I.x0[k] : 0.f;
+  for (int k = 0; k < 7; ++k) io.bq[k] = fb ? x0[k] : 0.f;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) io.bv[k] = fb ? I.x0[nq + k] : 0.f;
+  for (int k = 0; k < 6; ++k) io.bv[k] = fb ? x0[nq + k] : 0.f;
 #pragma unroll
   for (int k = 0; k < 6; ++k) io.ba[k] = 0.f;
   io.qref = io.vref = 0.f;
@@ -1338,7 +1342,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
       float e = 0.f;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const float target = (k == 2 && I.terminal_z_abs) ? I.z_terminal : I.x0[k] + I.v_des[k] * T;
+        const float target = (k == 2 && I.terminal_z_abs) ? I.z_terminal : x0[k] + I.v_des[k] * T;
         e += fabsf(io.bq[k] - target);
       }
       acc += I.w_H * e;
@@ -1359,14 +1363,17 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 // Block = one wavefront; work[blockIdx] = (instance, first sample) or, when work
 // is null, instance 0 and sample blockIdx * 64/G.
 // D > 0: every instance of the launch is at most D levels deep.
+// x0_in / nominal_in (nullable, one instance only): the state and the nominal
+// to use instead of the instance's staged copies.
 template <int G, int D>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_kernel(
-    const DevInst* __restrict__ insts, const int2* __restrict__ work, int group_stride, int table_floats) {
+    const DevInst* __restrict__ insts, const int2* __restrict__ work, int group_stride, int table_floats,
+    const float* __restrict__ x0_in, const float* __restrict__ nominal_in) {
   extern __shared__ float smem[];
   constexpr int R = 64 / G;
   const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
   const DevInst& I = insts[w.x];
-  rollout_item<G, D>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
+  rollout_item<G, D>(I, w.y, group_stride, table_floats, smem, I.H, nullptr, x0_in, nominal_in);
 }
 
 // State prediction: sample 0 of the instance (its knots read from samples) run
@@ -2499,11 +2506,6 @@ __global__ void reset_counters(unsigned int* __restrict__ c, int n) {
 // update_parts(N)); the workgroups beyond that return at once.
 // out (per call): the final nominal, best knots and info of the last iteration.
 // ---------------------------------------------------------------------------
-struct UpdateOut {
-  float* knots_out;   // nominal output of the last iteration
-  float* best_out;    // best knots or null
-  void* info_out;     // mppi_step_info or null
-};
 
 constexpr int kUpdWaves = kUpdThreads / 64;
 
@@ -2715,21 +2717,12 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
   if (t == 0) U.done[0] = 0u;  // ready for the next launch
   const UpdateOut* o = outs ? outs + blockIdx.y : &single;
   float* dst = (U.last_iter && o && o->knots_out) ? o->knots_out : U.nominal_out;
-  if ((E & 3) == 0)
-    rows_weighted_sum<4>(U.partial, parts, E, nullptr, s_part, [&](int e, float4 v) {
-      const float c[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) dst[4 * e + k] = nfin > 0 ? c[k] : U.nominal_in[4 * e + k];
-    });
-  else
-    rows_weighted_sum<1>(U.partial, parts, E, nullptr, s_part,
-                         [&](int e, float v) { dst[e] = nfin > 0 ? v : U.nominal_in[e]; });
-  __syncthreads();
-
-  // 5. best-sample tracking across the iterations of this call
+  const float* nom_in = (o && o->nominal_in) ? o->nominal_in : U.nominal_in;
+  // the call's running best starts from its input nominal, taken before the
+  // nominal output is written (the two may be the same buffer)
   float* bs = U.best_state;  // [E] knots, then S_best, best_iter, n_nonfinite, all_nonfinite, best_sample
   if (U.first_iter) {
-    for (int e = t; e < E; e += kUpdThreads) bs[e] = U.nominal_in[e];
+    for (int e = t; e < E; e += kUpdThreads) bs[e] = nom_in[e];
     if (t == 0) {
       bs[E] = INFINITY;
       reinterpret_cast<int*>(bs)[E + 1] = -1;
@@ -2738,6 +2731,18 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
       reinterpret_cast<int*>(bs)[E + 4] = -1;
     }
   }
+  __syncthreads();
+  if ((E & 3) == 0)
+    rows_weighted_sum<4>(U.partial, parts, E, nullptr, s_part, [&](int e, float4 v) {
+      const float c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dst[4 * e + k] = nfin > 0 ? c[k] : nom_in[4 * e + k];
+    });
+  else
+    rows_weighted_sum<1>(U.partial, parts, E, nullptr, s_part,
+                         [&](int e, float v) { dst[e] = nfin > 0 ? v : nom_in[e]; });
+
+  // 5. best-sample tracking across the iterations of this call
   __syncthreads();
   const bool improve = nfin > 0 && U.costs[nstar] < bs[E];
   __syncthreads();
@@ -2889,9 +2894,12 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
 
 // explicit instantiations
 #define MPPI_INST(G)                                                                                   \
-  template __global__ void rollout_kernel<G, 0>(const DevInst*, const int2*, int, int);                \
-  template __global__ void rollout_kernel<G, 3>(const DevInst*, const int2*, int, int);                \
-  template __global__ void rollout_kernel<G, 6>(const DevInst*, const int2*, int, int);                \
+  template __global__ void rollout_kernel<G, 0>(const DevInst*, const int2*, int, int, const float*,         \
+                                                const float*);                                            \
+  template __global__ void rollout_kernel<G, 3>(const DevInst*, const int2*, int, int, const float*,         \
+                                                const float*);                                            \
+  template __global__ void rollout_kernel<G, 6>(const DevInst*, const int2*, int, int, const float*,         \
+                                                const float*);                                            \
   template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int); \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \

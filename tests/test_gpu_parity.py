@@ -311,6 +311,26 @@ def test_lane_count_does_not_change_results(lanes):
     assert np.array_equal(a["costs"], b["costs"]) and np.array_equal(a["knots"], b["knots"])
 
 
+@pytest.mark.parametrize("name", ["quadruped_tp", "quadruped"])
+def test_step_in_place_equals_separate_buffers(name):
+    """mppi_step with the nominal output in the input buffer (allowed by the
+    interface) gives the bits of a step with separate buffers: knots, best knots
+    and step info (one iteration and three)."""
+    outs = []
+    for in_place in (False, True):
+        m, p, seed, model, c = _ctrl(name, n_samples=256)
+        E = c.E
+        st = _t(m["x0"])
+        ki = _t(synth.nominal_knots(m, p["n_knots"]))
+        ko = ki if in_place else torch.zeros(E, device="cuda")
+        best = torch.zeros(E, device="cuda")
+        info = torch.zeros(5, dtype=torch.int32, device="cuda")
+        c.step(st, ki, ko, best, info)
+        outs.append((_np(ko).copy(), _np(best).copy(), _np(info).copy()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
 def test_batched_step_equals_plain_steps():
     cfgs = [("chain", 32), ("quadruped", 48), ("humanoid", 40), ("quadruped", 16)]
     made = [_ctrl(nm, n_samples=k, seed=i) for i, (nm, k) in enumerate(cfgs)]
