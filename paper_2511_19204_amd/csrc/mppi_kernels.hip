@@ -2559,27 +2559,28 @@ __device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows
   const int t = threadIdx.x, EV = E / V;
   T* part = reinterpret_cast<T*>(s_part);
   const T* col = reinterpret_cast<const T*>(rows);
-  constexpr int kIn = 8;  // loads in flight per thread
+  constexpr int kIn = 24;  // loads in flight per thread (rows past cnt are not loaded)
   for (int e0 = 0; e0 < EV; e0 += kUpdThreads) {
     const int ec = min(kUpdThreads, EV - e0);
     const int G = kUpdThreads / ec;
     const int el = t % ec, g = t / ec, e = e0 + el;
     T acc = VT::zero();
     if (g < G) {
-      int n = g;
-      for (; n + (kIn - 1) * G < cnt; n += kIn * G) {
+      for (int n = g; n < cnt; n += kIn * G) {
         T a[kIn];
 #pragma unroll
-        for (int q = 0; q < kIn; ++q) a[q] = col[(size_t)(n + q * G) * EV + e];
+        for (int q = 0; q < kIn; ++q) {
+          const int r = n + q * G;
+          a[q] = r < cnt ? col[(size_t)r * EV + e] : VT::zero();
+        }
 #pragma unroll
         for (int q = 0; q < kIn; ++q) {
-          if (w) VT::fma(w[n + q * G], a[q], acc);
-          else VT::add(a[q], acc);
+          const int r = n + q * G;
+          if (r < cnt) {
+            if (w) VT::fma(w[r], a[q], acc);
+            else VT::add(a[q], acc);
+          }
         }
-      }
-      for (; n < cnt; n += G) {
-        if (w) VT::fma(w[n], col[(size_t)n * EV + e], acc);
-        else VT::add(col[(size_t)n * EV + e], acc);
       }
     }
     __syncthreads();
