@@ -36,6 +36,8 @@ template <int GC> __global__ void chain_persistent_kernel(const DevInst*, const 
 __global__ void reset_counters(unsigned int*, int);
 template <int G> __global__ void sample_kernel(const DevInst*, int);
 template <int G> __global__ void predict_kernel(const DevInst*, int, float*, int, int);
+template <int G> __global__ void predict_batch_kernel(const PredItem*, int, int);
+__global__ void shift_batch_kernel(const ShiftItem*);
 __global__ void shift_knots_kernel(const float*, float*, int, int, int, int, int, float, int);
 template <int G>
 __global__ void dynamics_kernel(const DevModel*, int, const float*, const float*, const float*, const float*, float,
@@ -1504,13 +1506,33 @@ extern "C" mppi_status mppi_profile_read(mppi_ctx* c, double* rollout_ms, int32_
 // ---------------------------------------------------------------------------
 struct BatchReq {
   mppi_ctx* ctx;
-  const float* state;     // nullptr: the instance's x0 and nominal are already in place (a tick)
-  const float* knots_in;
+  const float* state;     // a step: its state; a tick: the measured state
+  const float* knots_in;  // a step: its warm-start nominal (a tick starts from best_out)
   float* knots_out;       // outputs of the last iteration (each nullable)
-  float* best_out = nullptr;        // set for a tick (tau_best, in/out)
+  float* best_out = nullptr;        // a tick's tau_best (in/out)
   mppi_step_info* info_out = nullptr;
   int32_t n_delay = 0;              // a tick's prediction steps
+  bool tick = false;                // prediction and warm-start shift before the iterations
 };
+
+// Prediction groups of a batch's ticks by lane count: the launch shape covers the
+// largest instance of the group.
+static int pred_lanes(const mppi_ctx* c) {
+  const int g = next_pow2(c->m->host.nb);
+  return g < 4 ? 4 : (g > 64 ? 64 : g);
+}
+static hipError_t launch_predict_batch(int G, int n_items, const PredItem* items, int stride, int table,
+                                       hipStream_t s) {
+  const int lds = (table + (64 / G) * stride) * (int)sizeof(float);
+  switch (G) {
+    case 4: hipLaunchKernelGGL(predict_batch_kernel<4>, dim3(n_items), dim3(64), lds, s, items, stride, table); break;
+    case 8: hipLaunchKernelGGL(predict_batch_kernel<8>, dim3(n_items), dim3(64), lds, s, items, stride, table); break;
+    case 16: hipLaunchKernelGGL(predict_batch_kernel<16>, dim3(n_items), dim3(64), lds, s, items, stride, table); break;
+    case 32: hipLaunchKernelGGL(predict_batch_kernel<32>, dim3(n_items), dim3(64), lds, s, items, stride, table); break;
+    default: hipLaunchKernelGGL(predict_batch_kernel<64>, dim3(n_items), dim3(64), lds, s, items, stride, table); break;
+  }
+  return hipGetLastError();
+}
 
 static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsigned int* counters, int n_counters,
                                         bool persistent, hipStream_t s) {
@@ -1520,6 +1542,16 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   struct GroupDesc { int G; Dims dims; size_t work_off; int n_items; };
   struct IterDesc { size_t inst_off, up_off, out_off; int n_active; std::vector<GroupDesc> groups; };
   std::vector<IterDesc> iters(Imax);
+  // ticks: their prefixes (prediction by lane count, then the shifts) run after
+  // the staging copies and before the iterations
+  std::vector<int> ticks;
+  std::map<int, std::vector<int>> pred_groups;
+  for (int i = 0; i < n; ++i)
+    if (reqs[i].tick) {
+      ticks.push_back(i);
+      pred_groups[pred_lanes(reqs[i].ctx)].push_back(i);
+    }
+  const int nt = (int)ticks.size();
   // sizes
   size_t bytes = 2 * n * sizeof(StageItem);
   std::vector<std::vector<int>> active(Imax);
@@ -1528,6 +1560,10 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
       if (reqs[i].ctx->I > it) active[it].push_back(i);
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   bytes = align(bytes);
+  const size_t pred_off = bytes;
+  bytes = align(bytes + nt * sizeof(PredItem));
+  const size_t shift_off = bytes;
+  bytes = align(bytes + nt * sizeof(ShiftItem));
   for (int it = 0; it < Imax; ++it) {
     IterDesc& d = iters[it];
     d.n_active = (int)active[it].size();
@@ -1552,9 +1588,27 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   char* dv = reinterpret_cast<char*>(r->dev);
   auto* items = reinterpret_cast<StageItem*>(h);
   for (int i = 0; i < n; ++i) {
-    const bool staged = reqs[i].state == nullptr;
-    items[2 * i] = StageItem{reqs[i].state, reqs[i].ctx->x0, staged ? 0 : reqs[i].ctx->nq + reqs[i].ctx->nv};
-    items[2 * i + 1] = StageItem{reqs[i].knots_in, reqs[i].ctx->nom, staged ? 0 : reqs[i].ctx->E};
+    mppi_ctx* c = reqs[i].ctx;
+    if (reqs[i].tick) {  // measured state and tau_best into the prediction buffers
+      items[2 * i] = StageItem{reqs[i].state, c->x_meas, c->nq + c->nv};
+      items[2 * i + 1] = StageItem{reqs[i].best_out, c->pred_knots, c->E};
+    } else {
+      items[2 * i] = StageItem{reqs[i].state, c->x0, c->nq + c->nv};
+      items[2 * i + 1] = StageItem{reqs[i].knots_in, c->nom, c->E};
+    }
+  }
+  {
+    // predictions grouped by lane count (consecutive in the table), then the shifts
+    auto* hp = reinterpret_cast<PredItem*>(h + pred_off);
+    int k = 0;
+    for (auto& kv : pred_groups)
+      for (int i : kv.second) hp[k++] = PredItem{reqs[i].ctx->d_pred_inst, reqs[i].ctx->x0, reqs[i].n_delay};
+    auto* hs = reinterpret_cast<ShiftItem*>(h + shift_off);
+    for (int t = 0; t < nt; ++t) {
+      const mppi_ctx* c = reqs[ticks[t]].ctx;
+      hs[t] = ShiftItem{c->pred_knots, c->nom, c->K, c->nu, c->H * c->m->host.nsub, c->m->host.nsub,
+                        std::min(reqs[ticks[t]].n_delay, c->H), c->p.spline_mode, c->delta};
+    }
   }
   for (int it = 0; it < Imax; ++it) {
     IterDesc& d = iters[it];
@@ -1589,6 +1643,22 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   r->pending = true;  // event recorded after the last kernel reading the tables
   hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(256), 0, s, reinterpret_cast<StageItem*>(dv));
   HIP_TRY(hipGetLastError());
+  if (nt > 0) {
+    int k = 0;
+    for (auto& kv : pred_groups) {
+      int stride = 0, table = 0;
+      for (int i : kv.second) {
+        const mppi_ctx* c = reqs[i].ctx;
+        stride = std::max(stride, group_floats(kv.first, c->E));
+        table = std::max(table, body_sched_table_floats(c->m->host.nb, c->nc));
+      }
+      HIP_TRY(launch_predict_batch(kv.first, (int)kv.second.size(), reinterpret_cast<const PredItem*>(dv + pred_off) + k,
+                                   stride, table, s));
+      k += (int)kv.second.size();
+    }
+    hipLaunchKernelGGL(shift_batch_kernel, dim3(nt), dim3(256), 0, s, reinterpret_cast<const ShiftItem*>(dv + shift_off));
+    HIP_TRY(hipGetLastError());
+  }
   int ci = 0;
   for (int it = 0; it < Imax; ++it) {
     IterDesc& d = iters[it];
@@ -1684,7 +1754,7 @@ static void server_loop(mppi_server* S) {
           S->busy[r.ctx] = 1;
           r.status = 1;
           if (r.best)  // a tick: its prefix runs first, then the iterations read x0 and the nominal in place
-            batch.push_back(BatchReq{r.ctx, r.state, nullptr, r.knots_out, r.best, r.info, r.n_delay});
+            batch.push_back(BatchReq{r.ctx, r.state, nullptr, r.knots_out, r.best, r.info, r.n_delay, true});
           else
             batch.push_back(BatchReq{r.ctx, r.state, r.knots_in, r.knots_out});
           sl.tickets.push_back(*it);
@@ -1702,13 +1772,8 @@ static void server_loop(mppi_server* S) {
           if (st != MPPI_OK) break;
         }
       } else {
-        for (auto& b : batch) {
-          if (!b.best_out) continue;
-          st = tick_prefix(b.ctx, b.state, b.n_delay, b.best_out, nullptr, sl.stream);
-          if (st != MPPI_OK) break;
-          b.state = nullptr;
-          if (!b.knots_out) b.knots_out = b.ctx->pred_knots;  // as mppi_tick: consumed by the shift already
-        }
+        for (auto& b : batch)  // as mppi_tick: a tick without a nominal output writes it where the shift read
+          if (b.tick && !b.knots_out) b.knots_out = b.ctx->pred_knots;
         if (st == MPPI_OK) {
           std::lock_guard<std::mutex> lk(g_mu);
           st = launch_batch_dynamic(batch, sl.counters, 64 * 5, S->cfg.persistent != 0, sl.stream);

@@ -132,6 +132,22 @@ struct DevUpdate {
   float lambda;
 };
 
+// One tick prefix of a batch: the instance's state carried `steps` control steps
+// along its best trajectory (the prediction descriptor reads the measured state
+// and the trajectory from the instance's buffers), written to state_out.
+struct PredItem {
+  const DevInst* inst;
+  float* state_out;
+  int32_t steps;
+};
+// One warm-start shift of a batch (see the shift kernel): in -> out.
+struct ShiftItem {
+  const float* in;
+  float* out;
+  int32_t K, nu, F, nsub, n_steps, spline_mode;
+  float delta;
+};
+
 // Per-call outputs of an instance's update launch (null fields: not wanted).
 struct UpdateOut {
   float* knots_out;         // nominal output of the last iteration

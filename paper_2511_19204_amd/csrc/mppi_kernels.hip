@@ -1386,6 +1386,16 @@ __global__ __launch_bounds__(64) void predict_kernel(const DevInst* __restrict__
   rollout_item<G>(*inst, 0, group_stride, table_floats, smem, steps, state_out);
 }
 
+// The state predictions of a batch of ticks (instances whose trees take G
+// lanes), one workgroup per item; the LDS layout is sized for the largest.
+template <int G>
+__global__ __launch_bounds__(64) void predict_batch_kernel(const PredItem* __restrict__ items, int group_stride,
+                                                           int table_floats) {
+  extern __shared__ float smem[];
+  const PredItem it = items[blockIdx.x];
+  rollout_item<G>(*it.inst, 0, group_stride, table_floats, smem, it.steps, it.state_out);
+}
+
 // Persistent form: a grid sized to the resident wavefronts; each wavefront takes
 // work items from a device counter until the table is exhausted (every wavefront
 // reaches that exit).  Which wavefront runs an item does not change its result.
@@ -2783,11 +2793,9 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
 // variants then take the slopes of the spline through the shifted positions.
 // One workgroup; in and out must not alias.
 constexpr int kShiftThreads = 256;
-__global__ __launch_bounds__(kShiftThreads) void shift_knots_kernel(const float* __restrict__ in,
-                                                                    float* __restrict__ out, int K, int nu, int F,
-                                                                    int nsub, int n_steps, float delta,
-                                                                    int spline_mode) {
-  __shared__ float dg[kMaxKnots];
+__device__ __forceinline__ void shift_knots_block(const float* __restrict__ in, float* __restrict__ out, int K,
+                                                  int nu, int F, int nsub, int n_steps, float delta, int spline_mode,
+                                                  float* dg) {
   for (int i = threadIdx.x; i < K * nu; i += kShiftThreads) {
     const int k = i / nu, jj = i % nu;
     const long long m = (long long)k * F + (long long)n_steps * nsub * (K - 1);
@@ -2805,6 +2813,19 @@ __global__ __launch_bounds__(kShiftThreads) void shift_knots_kernel(const float*
   if (threadIdx.x == 0 && spline_mode == 1) natural_cubic_diagonal(K, dg);
   __syncthreads();
   for (int jj = threadIdx.x; jj < nu; jj += kShiftThreads) position_spline_slopes(spline_mode, K, nu, jj, delta, dg, out);
+}
+__global__ __launch_bounds__(kShiftThreads) void shift_knots_kernel(const float* __restrict__ in,
+                                                                    float* __restrict__ out, int K, int nu, int F,
+                                                                    int nsub, int n_steps, float delta,
+                                                                    int spline_mode) {
+  __shared__ float dg[kMaxKnots];
+  shift_knots_block(in, out, K, nu, F, nsub, n_steps, delta, spline_mode, dg);
+}
+// The warm-start shifts of a batch of ticks, one workgroup per item.
+__global__ __launch_bounds__(kShiftThreads) void shift_batch_kernel(const ShiftItem* __restrict__ items) {
+  __shared__ float dg[kMaxKnots];
+  const ShiftItem it = items[blockIdx.x];
+  shift_knots_block(it.in, it.out, it.K, it.nu, it.F, it.nsub, it.n_steps, it.delta, it.spline_mode, dg);
 }
 
 // Copy per-call inputs (state, warm-start knots) into instance buffers.
@@ -2904,6 +2925,7 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int); \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \
+  template __global__ void predict_batch_kernel<G>(const PredItem*, int, int);                         \
   template __global__ void dynamics_kernel<G>(const DevModel*, int, const float*, const float*,        \
                                               const float*, const float*, float, float*, int, int);  \
   template __global__ void team_kernel<G, 0>(const DevInst*, const int2*, int, int);                   \

@@ -311,14 +311,18 @@ def test_lane_count_does_not_change_results(lanes):
     assert np.array_equal(a["costs"], b["costs"]) and np.array_equal(a["knots"], b["knots"])
 
 
-@pytest.mark.parametrize("name", ["quadruped_tp", "quadruped"])
-def test_step_in_place_equals_separate_buffers(name):
+@pytest.mark.parametrize("name,schedule", [("quadruped_tp", "body"), ("quadruped", "body"),
+                                           ("quadruped", "chain"), ("quadruped", "team")])
+def test_step_in_place_equals_separate_buffers(name, schedule):
     """mppi_step with the nominal output in the input buffer (allowed by the
     interface) gives the bits of a step with separate buffers: knots, best knots
-    and step info (one iteration and three)."""
+    and step info (one iteration and three; the body schedule reads its inputs in
+    place, the others from staged copies)."""
     outs = []
     for in_place in (False, True):
-        m, p, seed, model, c = _ctrl(name, n_samples=256)
+        m, p, seed = synth.config(name, n_samples=256)
+        model = mppi.Model(m)
+        c = mppi.Controller(model, p, seed, schedule=schedule)
         E = c.E
         st = _t(m["x0"])
         ki = _t(synth.nominal_knots(m, p["n_knots"]))
