@@ -133,7 +133,6 @@ static int next_pow2(int x) {
 
 static bool valid_lanes(int G, const DevModel& M) { return (G == 4 || G == 8 || G == 16 || G == 32 || G == 64) && G >= M.nb; }
 
-static int lds_bytes(int G, int E) { return (64 / G) * group_floats(G, E) * (int)sizeof(float); }
 
 // ---------------------------------------------------------------------------
 // chain schedule tables: heavy-path decomposition and the per-body rows
