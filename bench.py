@@ -15,9 +15,10 @@ Also reported:
                    mppi_step_batch vs its captured hipGraph, rollout-steps/s and
                    per-robot tick latency;
   serving          the same robots ticking as Poisson processes at 50 Hz for a few
-                   seconds, served with continuous batching vs plain per-instance
-                   launches: throughput, p50/p99 latency from tick arrival, 20 ms
-                   deadline misses;
+                   seconds, served with request-level batches ("batched"),
+                   iteration-level rounds ("iteration") and plain per-instance
+                   launches ("plain"): throughput, p50/p99 latency from tick
+                   arrival, 20 ms deadline misses;
   roofline         the rollout kernel: algorithmic FP32 operations per launch
                    (flops.flops_per_rollout_step x K x H) / its mean duration,
                    against the FP32 vector peak (ALU-bound path);
@@ -293,8 +294,8 @@ def tasks(args, torch, mppi, synth):
 
 def serving(args, torch, mppi, synth, mode):
     """Poisson MPC ticks (50 Hz per robot) from the 64-robot mix, served by the
-    continuous-batching server (mode "batched") or by plain per-instance ticks
-    (mode "plain"); at most one outstanding tick per robot, so a tick that arrives
+    continuous-batching server (mode "batched": request-level batches; "iteration":
+    iteration-level rounds) or by plain per-instance ticks (mode "plain"); at most one outstanding tick per robot, so a tick that arrives
     while the robot's previous one runs waits, and its latency counts from arrival.
     Each tick is a full mppi_tick: the measured state (the robot's x0) is predicted
     forward by the robot's previous tick latency rounded up to control steps,
@@ -432,6 +433,7 @@ def main():
     srv = None
     if not args.no_serve:
         srv = {"batched": serving(args, torch, mppi, synth, "batched"),
+               "iteration": serving(args, torch, mppi, synth, "iteration"),
                "plain": serving(args, torch, mppi, synth, "plain"),
                "robots": args.robots, "rate_hz": 50.0, "deadline_ms": 20.0,
                "seconds": args.serve_seconds}

@@ -292,21 +292,28 @@ mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t);
 
 /* ---- Serving: continuous batching of MPC ticks --------------------------- */
 
-/* A server owns n_streams HIP streams and a worker thread.  Submitted ticks wait
- * in a FIFO; whenever a stream is free the worker forms a batch of up to
- * max_batch pending ticks whose instance is not already on the device (one
- * outstanding tick per instance) and launches it (mode 0: one fused batched
- * step; mode 1: plain per-instance steps, the baseline).  Ticks that arrive while
- * others run join the next batch, so work from several batches overlaps on the
- * device.  Each result equals the instance's own mppi_step (the instance's
+/* A server owns HIP streams and a worker thread.  Submitted ticks wait in a
+ * FIFO; one outstanding tick per instance is on the device at a time.
+ *  mode 0 (request-level batching): whenever one of the n_streams streams is
+ *    free the worker forms a batch of up to max_batch pending ticks and launches
+ *    all their iterations as one fused batched step; ticks that arrive while
+ *    others run join the next batch, so several batches overlap on the device.
+ *  mode 1: the same, with plain per-instance steps (the baseline).
+ *  mode 2 (iteration-level batching): each of the n_streams streams runs
+ *    rounds back to back; a round launches ONE iteration (Alg. 1) of every tick
+ *    admitted to that stream, after the prefixes of the ticks admitted at that
+ *    round.  Pending ticks join the first stream to finish a round (up to
+ *    max_batch admitted over all streams) and leave after their last iteration;
+ *    a tick stays on its stream.
+ * Each result equals the instance's own mppi_step / mppi_tick (the instance's
  * warm-start knots and noise tick stay on the device).  persistent selects the
  * persistent rollout launch (mppi_batch_opts).  Buffers passed to submit must
  * stay valid until the tick is reported done. */
 typedef struct {
   int32_t max_pending;   /* pending ticks beyond which submit returns MPPI_ENOSLOT */
-  int32_t n_streams;     /* 1..8 batches in flight                              */
-  int32_t max_batch;     /* ticks per batch                                     */
-  int32_t mode;          /* 0 batched, 1 plain per-instance launches            */
+  int32_t n_streams;     /* 1..8 batches (mode 2: rounds) in flight             */
+  int32_t max_batch;     /* ticks per batch (mode 2: admitted over all streams) */
+  int32_t mode;          /* 0 batched, 1 plain per-instance, 2 iteration-level  */
   int32_t persistent;    /* 1: persistent rollout launches                      */
 } mppi_server_cfg;
 typedef struct mppi_server mppi_server;
@@ -330,6 +337,7 @@ mppi_status mppi_server_submit_tick(mppi_server* s, mppi_ctx* c, const float* d_
 mppi_status mppi_server_poll(mppi_server* s, uint64_t ticket, int32_t* done, double* latency_s);
 /* Wait (up to timeout_s) until nothing is pending or in flight; MPPI_EBUSY on timeout. */
 mppi_status mppi_server_drain(mppi_server* s, double timeout_s);
+/* batches: launches so far (mode 2: rounds); requests: ticks they admitted. */
 mppi_status mppi_server_stats(mppi_server* s, int64_t* batches, int64_t* requests);
 mppi_status mppi_server_destroy(mppi_server* s);
 

@@ -1512,6 +1512,11 @@ struct BatchReq {
   mppi_step_info* info_out = nullptr;
   int32_t n_delay = 0;              // a tick's prediction steps
   bool tick = false;                // prediction and warm-start shift before the iterations
+  // the slice of the request's iterations this launch runs: it0 .. it0+n_it-1
+  // (n_it < 0: to the last).  The staging copies and a tick's prefix run with
+  // iteration 0; the outputs are written by the last iteration.
+  int32_t it0 = 0;
+  int32_t n_it = -1;
 };
 
 // Prediction groups of a batch's ticks by lane count: the launch shape covers the
@@ -1536,27 +1541,38 @@ static hipError_t launch_predict_batch(int G, int n_items, const PredItem* items
 static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsigned int* counters, int n_counters,
                                         bool persistent, hipStream_t s) {
   const int n = (int)reqs.size();
+  // iterations of request i in this launch: it0(i) .. it0(i)+n_iters[i]-1
+  std::vector<int> n_iters(n);
   int Imax = 0;
-  for (auto& r : reqs) Imax = std::max(Imax, r.ctx->I);
+  for (int i = 0; i < n; ++i) {
+    const int left = reqs[i].ctx->I - reqs[i].it0;
+    if (reqs[i].it0 < 0 || left < 1) return fail(MPPI_EINVAL, "iteration slice outside the instance's iterations");
+    n_iters[i] = reqs[i].n_it < 0 ? left : std::min(reqs[i].n_it, left);
+    Imax = std::max(Imax, n_iters[i]);
+  }
   struct GroupDesc { int G; Dims dims; size_t work_off; int n_items; };
   struct IterDesc { size_t inst_off, up_off, out_off; int n_active; std::vector<GroupDesc> groups; };
   std::vector<IterDesc> iters(Imax);
-  // ticks: their prefixes (prediction by lane count, then the shifts) run after
-  // the staging copies and before the iterations
-  std::vector<int> ticks;
+  // requests starting at iteration 0 stage their inputs; ticks among them run
+  // their prefixes (prediction by lane count, then the shifts) after the staging
+  // copies and before the iterations
+  std::vector<int> staged, ticks;
   std::map<int, std::vector<int>> pred_groups;
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
+    if (reqs[i].it0 != 0) continue;
+    staged.push_back(i);
     if (reqs[i].tick) {
       ticks.push_back(i);
       pred_groups[pred_lanes(reqs[i].ctx)].push_back(i);
     }
-  const int nt = (int)ticks.size();
+  }
+  const int ns = (int)staged.size(), nt = (int)ticks.size();
   // sizes
-  size_t bytes = 2 * n * sizeof(StageItem);
+  size_t bytes = 2 * ns * sizeof(StageItem);
   std::vector<std::vector<int>> active(Imax);
   for (int it = 0; it < Imax; ++it)
     for (int i = 0; i < n; ++i)
-      if (reqs[i].ctx->I > it) active[it].push_back(i);
+      if (n_iters[i] > it) active[it].push_back(i);
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   bytes = align(bytes);
   const size_t pred_off = bytes;
@@ -1586,14 +1602,15 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   char* h = reinterpret_cast<char*>(r->host);
   char* dv = reinterpret_cast<char*>(r->dev);
   auto* items = reinterpret_cast<StageItem*>(h);
-  for (int i = 0; i < n; ++i) {
-    mppi_ctx* c = reqs[i].ctx;
-    if (reqs[i].tick) {  // measured state and tau_best into the prediction buffers
-      items[2 * i] = StageItem{reqs[i].state, c->x_meas, c->nq + c->nv};
-      items[2 * i + 1] = StageItem{reqs[i].best_out, c->pred_knots, c->E};
+  for (int k = 0; k < ns; ++k) {
+    const BatchReq& q = reqs[staged[k]];
+    mppi_ctx* c = q.ctx;
+    if (q.tick) {  // measured state and tau_best into the prediction buffers
+      items[2 * k] = StageItem{q.state, c->x_meas, c->nq + c->nv};
+      items[2 * k + 1] = StageItem{q.best_out, c->pred_knots, c->E};
     } else {
-      items[2 * i] = StageItem{reqs[i].state, c->x0, c->nq + c->nv};
-      items[2 * i + 1] = StageItem{reqs[i].knots_in, c->nom, c->E};
+      items[2 * k] = StageItem{q.state, c->x0, c->nq + c->nv};
+      items[2 * k + 1] = StageItem{q.knots_in, c->nom, c->E};
     }
   }
   {
@@ -1616,9 +1633,10 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
     auto* ho = reinterpret_cast<UpdateOut*>(h + d.out_off);
     for (int a = 0; a < d.n_active; ++a) {
       const BatchReq& q = reqs[active[it][a]];
-      hi[a] = q.ctx->h_insts[it];
-      hu[a] = q.ctx->h_ups[it];
-      ho[a] = q.ctx->I - 1 == it ? UpdateOut{q.knots_out, q.best_out, q.info_out} : UpdateOut{nullptr, nullptr, nullptr};
+      const int ci = q.it0 + it;  // the instance's own iteration index
+      hi[a] = q.ctx->h_insts[ci];
+      hu[a] = q.ctx->h_ups[ci];
+      ho[a] = q.ctx->I - 1 == ci ? UpdateOut{q.knots_out, q.best_out, q.info_out} : UpdateOut{nullptr, nullptr, nullptr};
     }
     std::map<int, std::vector<int>> byG;
     for (int a = 0; a < d.n_active; ++a) byG[reqs[active[it][a]].ctx->lanes].push_back(a);
@@ -1640,8 +1658,10 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   }
   HIP_TRY(hipMemcpyAsync(r->dev, r->host, bytes, hipMemcpyHostToDevice, s));
   r->pending = true;  // event recorded after the last kernel reading the tables
-  hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(256), 0, s, reinterpret_cast<StageItem*>(dv));
-  HIP_TRY(hipGetLastError());
+  if (ns > 0) {
+    hipLaunchKernelGGL(stage_kernel, dim3(2 * ns), dim3(256), 0, s, reinterpret_cast<StageItem*>(dv));
+    HIP_TRY(hipGetLastError());
+  }
   if (nt > 0) {
     int k = 0;
     for (auto& kv : pred_groups) {
@@ -1696,12 +1716,18 @@ struct SrvReq {
   float* best = nullptr;
   mppi_step_info* info = nullptr;
 };
+// mode 2: an admitted request between its iterations
+struct SrvLive {
+  uint64_t ticket;
+  BatchReq req;  // req.it0: its next iteration
+};
 struct SrvSlot {
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
   bool busy = false;
-  std::vector<uint64_t> tickets;
+  std::vector<uint64_t> tickets;  // mode 2: the ticks whose last iteration the round runs
   unsigned int* counters = nullptr;
+  std::vector<SrvLive> live;      // mode 2: the requests admitted to this stream
 };
 }  // namespace
 
@@ -1719,7 +1745,109 @@ struct mppi_server {
   uint64_t next_ticket = 1;
   std::string error;
   int64_t launched_batches = 0, launched_requests = 0;
+  int live_n = 0;  // mode 2: admitted requests not yet complete
 };
+
+static void server_fail(mppi_server* S) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->error = g_err.empty() ? "launch failed" : g_err;
+  S->stop = true;
+}
+
+// Marks the tickets of a slot whose event has fired as done.
+static void server_retire(mppi_server* S, SrvSlot& sl) {
+  const auto now = Clock::now();
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (uint64_t t : sl.tickets) {
+    auto it = S->reqs.find(t);
+    if (it == S->reqs.end()) continue;
+    it->second.status = 2;
+    it->second.latency = std::chrono::duration<double>(now - it->second.t_submit).count();
+    S->busy.erase(it->second.ctx);
+  }
+  sl.tickets.clear();
+  sl.busy = false;
+}
+
+static BatchReq batch_req_of(const SrvReq& r) {
+  if (r.best)  // a tick: its prefix runs first, then the iterations read x0 and the nominal in place
+    return BatchReq{r.ctx, r.state, nullptr, r.knots_out, r.best, r.info, r.n_delay, true};
+  return BatchReq{r.ctx, r.state, r.knots_in, r.knots_out};
+}
+
+// Mode 2, iteration-level batching: each stream runs rounds back to back; a
+// round runs ONE iteration of every request admitted to that stream (the
+// prefixes of the requests admitted at that round first).  Pending requests join
+// whichever stream finishes a round first and leave after their last iteration,
+// so nothing waits for the rest of a batch to finish, while rounds on different
+// streams overlap and fill each other's tails.  A request stays on its stream,
+// which orders its iterations.
+static void server_loop_rounds(mppi_server* S) {
+  (void)hipSetDevice(S->device);
+  std::vector<BatchReq> batch;
+  while (!S->stop.load()) {
+    bool progressed = false;
+    for (auto& sl : S->slots) {
+      if (sl.busy) {
+        if (hipEventQuery(sl.ev) != hipSuccess) continue;
+        server_retire(S, sl);
+        progressed = true;
+      }
+      int admitted = 0;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (auto it = S->pending.begin(); it != S->pending.end() && S->live_n < S->cfg.max_batch;) {
+          SrvReq& r = S->reqs[*it];
+          if (S->busy.count(r.ctx)) { ++it; continue; }
+          S->busy[r.ctx] = 1;
+          r.status = 1;
+          BatchReq b = batch_req_of(r);
+          if (b.tick && !b.knots_out) b.knots_out = b.ctx->pred_knots;  // as mppi_tick
+          sl.live.push_back(SrvLive{*it, b});
+          ++admitted;
+          ++S->live_n;
+          it = S->pending.erase(it);
+        }
+      }
+      if (sl.live.empty()) continue;
+      batch.clear();
+      for (auto& l : sl.live) {
+        BatchReq b = l.req;
+        b.n_it = 1;
+        batch.push_back(b);
+      }
+      mppi_status st;
+      {
+        std::lock_guard<std::mutex> lk(g_mu);
+        st = launch_batch_dynamic(batch, sl.counters, 64 * 5, S->cfg.persistent != 0, sl.stream);
+      }
+      if (st == MPPI_OK && hipEventRecord(sl.ev, sl.stream) != hipSuccess) st = MPPI_EDEVICE;
+      if (st != MPPI_OK) {
+        server_fail(S);
+        return;
+      }
+      std::lock_guard<std::mutex> lk(S->mu);
+      size_t k = 0;
+      for (auto& l : sl.live) {
+        if (++l.req.it0 == l.req.ctx->I) {
+          sl.tickets.push_back(l.ticket);
+          --S->live_n;
+        } else {
+          sl.live[k++] = l;
+        }
+      }
+      sl.live.resize(k);
+      sl.busy = true;
+      S->launched_batches += 1;
+      S->launched_requests += admitted;
+      progressed = true;
+    }
+    if (!progressed) {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait_for(lk, std::chrono::microseconds(20));
+    }
+  }
+}
 
 static void server_loop(mppi_server* S) {
   (void)hipSetDevice(S->device);
@@ -1729,17 +1857,7 @@ static void server_loop(mppi_server* S) {
     for (auto& sl : S->slots) {
       if (!sl.busy) continue;
       if (hipEventQuery(sl.ev) != hipSuccess) continue;
-      const auto now = Clock::now();
-      std::lock_guard<std::mutex> lk(S->mu);
-      for (uint64_t t : sl.tickets) {
-        auto it = S->reqs.find(t);
-        if (it == S->reqs.end()) continue;
-        it->second.status = 2;
-        it->second.latency = std::chrono::duration<double>(now - it->second.t_submit).count();
-        S->busy.erase(it->second.ctx);
-      }
-      sl.tickets.clear();
-      sl.busy = false;
+      server_retire(S, sl);
       progressed = true;
     }
     for (auto& sl : S->slots) {
@@ -1752,10 +1870,7 @@ static void server_loop(mppi_server* S) {
           if (S->busy.count(r.ctx)) { ++it; continue; }
           S->busy[r.ctx] = 1;
           r.status = 1;
-          if (r.best)  // a tick: its prefix runs first, then the iterations read x0 and the nominal in place
-            batch.push_back(BatchReq{r.ctx, r.state, nullptr, r.knots_out, r.best, r.info, r.n_delay, true});
-          else
-            batch.push_back(BatchReq{r.ctx, r.state, r.knots_in, r.knots_out});
+          batch.push_back(batch_req_of(r));
           sl.tickets.push_back(*it);
           it = S->pending.erase(it);
         }
@@ -1780,9 +1895,7 @@ static void server_loop(mppi_server* S) {
       }
       if (st == MPPI_OK && hipEventRecord(sl.ev, sl.stream) != hipSuccess) st = MPPI_EDEVICE;
       if (st != MPPI_OK) {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->error = g_err.empty() ? "launch failed" : g_err;
-        S->stop = true;
+        server_fail(S);
         break;
       }
       sl.busy = true;
@@ -1801,7 +1914,8 @@ extern "C" mppi_status mppi_server_create(const mppi_server_cfg* cfg, mppi_serve
   if (!cfg || !out) return fail(MPPI_EINVAL, "null argument");
   if (cfg->n_streams < 1 || cfg->n_streams > 8) return fail(MPPI_EINVAL, "n_streams must be in 1..8");
   if (cfg->max_batch < 1 || cfg->max_pending < 1) return fail(MPPI_EINVAL, "max_batch and max_pending must be >= 1");
-  if (cfg->mode != 0 && cfg->mode != 1) return fail(MPPI_EINVAL, "mode must be 0 (batched) or 1 (plain)");
+  if (cfg->mode < 0 || cfg->mode > 2)
+    return fail(MPPI_EINVAL, "mode must be 0 (batched), 1 (plain) or 2 (iteration-level)");
   auto S = std::make_unique<mppi_server>();
   S->cfg = *cfg;
   HIP_TRY(hipGetDevice(&S->device));
@@ -1811,7 +1925,7 @@ extern "C" mppi_status mppi_server_create(const mppi_server_cfg* cfg, mppi_serve
     HIP_TRY(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
     HIP_TRY(hipMalloc(&sl.counters, 64 * 5 * sizeof(unsigned int)));
   }
-  S->worker = std::thread(server_loop, S.get());
+  S->worker = std::thread(cfg->mode == 2 ? server_loop_rounds : server_loop, S.get());
   *out = S.release();
   return MPPI_OK;
 }
@@ -1871,7 +1985,7 @@ extern "C" mppi_status mppi_server_drain(mppi_server* S, double timeout_s) {
     {
       std::lock_guard<std::mutex> lk(S->mu);
       if (S->stop && !S->error.empty()) return fail(MPPI_EDEVICE, "server stopped: " + S->error);
-      bool idle = S->pending.empty();
+      bool idle = S->pending.empty() && S->live_n == 0;
       for (auto& sl : S->slots) idle = idle && !sl.busy;
       if (idle) return MPPI_OK;
     }

@@ -432,10 +432,17 @@ def autotune(ctrl, state, knots, reps=3, stream=None):
 
 
 class Server:
-    """Continuous-batching server of MPC ticks (mode "batched" or "plain")."""
+    """Continuous-batching server of MPC ticks: mode "batched" (a batch runs all
+    iterations of the ticks it took), "plain" (per-instance launches) or
+    "iteration" (every round runs one iteration of each admitted tick; ticks join
+    at round boundaries)."""
 
-    def __init__(self, n_streams=2, max_batch=256, max_pending=100000, mode="batched", persistent=False):
-        cfg = ServerCfg(int(max_pending), int(n_streams), int(max_batch), 0 if mode == "batched" else 1,
+    MODES = {"batched": 0, "plain": 1, "iteration": 2}
+
+    def __init__(self, n_streams=3, max_batch=256, max_pending=100000, mode="iteration", persistent=False):
+        if mode not in self.MODES:
+            raise MppiError(f"unknown server mode {mode!r}; one of {sorted(self.MODES)}")
+        cfg = ServerCfg(int(max_pending), int(n_streams), int(max_batch), self.MODES[mode],
                         1 if persistent else 0)
         h = C.c_void_p()
         _check(lib().mppi_server_create(C.byref(cfg), C.byref(h)), "mppi_server_create")

@@ -69,3 +69,18 @@ def test_null_arguments_are_rejected():
     assert L.mppi_destroy(None) == -1
     assert L.mppi_debug_philox(None, None, None, -1, None) == -1
     assert L.mppi_debug_philox(None, None, None, 0, None) == 0
+
+
+@pytest.mark.parametrize("cfg", [dict(mode=3), dict(mode=-1), dict(n_streams=0), dict(n_streams=9),
+                                 dict(max_batch=0), dict(max_pending=0)])
+def test_server_config_is_checked_before_any_device_call(cfg):
+    """mppi_server_create rejects a config outside its documented ranges (modes
+    0..2, 1..8 streams, positive batch and queue sizes) with MPPI_EINVAL."""
+    base = dict(max_pending=16, n_streams=2, max_batch=4, mode=2, persistent=0)
+    base.update(cfg)
+    c = mppi.ServerCfg(base["max_pending"], base["n_streams"], base["max_batch"], base["mode"], base["persistent"])
+    h = C.c_void_p()
+    assert mppi.lib().mppi_server_create(C.byref(c), C.byref(h)) == -1
+    assert h.value is None
+    with pytest.raises(mppi.MppiError):
+        mppi.Server(mode="round-robin")

@@ -125,7 +125,7 @@ def test_autotune_picks_a_valid_lane_count_without_changing_results():
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain"])
+@pytest.mark.parametrize("mode", ["batched", "plain", "iteration"])
 def test_server_result_is_the_same_alone_and_in_the_mix(mix, mode):
     """Robot 0 served alone, then in a mix where the other robots' ticks arrive in
     between (continuous batching): its knots after every tick equal the plain
@@ -171,6 +171,9 @@ def test_server_result_is_the_same_alone_and_in_the_mix(mix, mode):
         assert requests == 3 + 3 * len(robots)
         if mode == "batched":
             assert batches < requests  # ticks were batched together
+        if mode == "iteration":  # a round per iteration, shared by the ticks in flight
+            n_it = sum(r[1]["n_iters"] for r in robots)
+            assert batches < 3 * (robots[0][1]["n_iters"] + n_it)
     finally:
         srv.close()
 
@@ -230,7 +233,7 @@ def _tick_reference(robots, ticks, delay):
     return refs
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain"])
+@pytest.mark.parametrize("mode", ["batched", "plain", "iteration"])
 def test_server_ticks_equal_the_instance_ticks(mode):
     """Served ticks (prediction by a per-tick delay, warm-start shift, iterations,
     tau_best carried on the device) of an uneven mix, submitted staggered with at
