@@ -141,7 +141,12 @@ class _Model:
 
 
 class _Params:
-    def __init__(self, p, nu):
+    def __init__(self, p, nu, nc=None):
+        # the C oracle reads f0z per contact point and q0_cost per joint
+        if nc is not None and "f0z" in p and len(p["f0z"]) != nc:
+            raise ValueError(f"f0z has {len(p['f0z'])} entries for {nc} contact points")
+        if nc is not None and "q0_cost" in p and len(p["q0_cost"]) != nu:
+            raise ValueError(f"q0_cost has {len(p['q0_cost'])} entries for {nu} joints")
         s = OrcParams()
         for name in ("n_samples", "horizon", "n_knots", "n_iters", "weight_mode", "noise_mode",
                      "cost_kind"):
@@ -238,7 +243,7 @@ def predict(model, params, x0, knots, n_steps):
 
 def predict_f32(model, params, x0, knots, n_steps):
     """predict() in the oracle's float instantiation (rounding reference only)."""
-    M = _Model(model); P = _Params(params, M.nu)
+    M = _Model(model); P = _Params(params, M.nu, M.nc)
     xa, xp = _d(x0); ka, kp = _d(knots)
     traj = np.zeros((params["horizon"] + 1, M.nq + M.nv))
     _check(lib().orc_rollout_f32_traj(C.c_void_p(M.ptr), C.c_void_p(P.ptr), xp, kp, traj.ctypes.data_as(_dp)),
@@ -247,7 +252,7 @@ def predict_f32(model, params, x0, knots, n_steps):
 
 
 def sample_knots(model, params, nominal, seed, tick, iota, n):
-    M = _Model(model); P = _Params(params, M.nu)
+    M = _Model(model); P = _Params(params, M.nu, M.nc)
     nom, npt = _d(nominal)
     out = np.zeros(2 * params["n_knots"] * M.nu)
     _check(lib().orc_sample_knots(M.ptr, P.ptr, npt, seed, tick, iota, n, out.ctypes.data_as(_dp)),
@@ -378,7 +383,7 @@ def contacts(model, q, v):
 
 
 def rollout(model, params, x0, knots, debug=False):
-    M = _Model(model); P = _Params(params, M.nu)
+    M = _Model(model); P = _Params(params, M.nu, M.nc)
     xa, xp = _d(x0); ka, kp = _d(knots)
     S = C.c_double()
     H = params["horizon"]
@@ -394,7 +399,7 @@ def rollout(model, params, x0, knots, debug=False):
 
 
 def rollout_f32(model, params, x0, knots):
-    M = _Model(model); P = _Params(params, M.nu)
+    M = _Model(model); P = _Params(params, M.nu, M.nc)
     xa, xp = _d(x0); ka, kp = _d(knots)
     S = C.c_double()
     masks = np.zeros(params["horizon"], np.uint32)
@@ -405,7 +410,7 @@ def rollout_f32(model, params, x0, knots):
 
 def rollouts(model, params, x0, nominal, seed, tick, iota, n0, count, threads=None, samples=False):
     """Costs of samples n0..n0+count-1 of iteration iota (and their knots)."""
-    M = _Model(model); P = _Params(params, M.nu)
+    M = _Model(model); P = _Params(params, M.nu, M.nc)
     xa, xp = _d(x0); na, npt = _d(nominal)
     S = np.zeros(count)
     E = 2 * params["n_knots"] * M.nu
@@ -452,7 +457,7 @@ def dense_route_update(w, samples, nk, nu, H, dt):
 def step(model, params, x0, knots_in, seed, tick, threads=None, f32=False):
     """Full MPC step; returns a dict with knots, best_knots, S_best, best_iter, costs, ...
     f32=True runs sampling and rollouts in float (FP32 divergence diagnosis only)."""
-    M = _Model(model); P = _Params(params, M.nu)
+    M = _Model(model); P = _Params(params, M.nu, M.nc)
     xa, xp = _d(x0); ka, kp = _d(knots_in)
     E = 2 * params["n_knots"] * M.nu
     out = np.zeros(E); best = np.zeros(E); sb = C.c_double(); bi = C.c_int32()

@@ -224,6 +224,15 @@ class Model:
                "mppi_debug_dynamics")
 
 
+def _check_param_lengths(p, nc, nu):
+    """The library reads f0z for every contact point and q0_cost for every joint
+    from the caller's arrays; shorter arrays would be read past their end."""
+    if len(p["f0z"]) != nc:
+        raise MppiError(f"f0z has {len(p['f0z'])} entries for {nc} contact points")
+    if len(p["q0_cost"]) != nu:
+        raise MppiError(f"q0_cost has {len(p['q0_cost'])} entries for {nu} joints")
+
+
 def make_params(p):
     s = Params()
     for name in ("n_samples", "horizon", "n_knots", "n_iters", "weight_mode", "noise_mode",
@@ -257,6 +266,7 @@ class Controller:
     def __init__(self, model, params, seed, lanes=0, schedule=None):
         self.model = model
         self.params = dict(params)
+        _check_param_lengths(params, model.nc, model.nu)
         s, self._keep = make_params(params)
         h = C.c_void_p()
         _check(lib().mppi_create(model.h, C.byref(s), C.c_uint64(seed), C.byref(h)), "mppi_create")

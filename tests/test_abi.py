@@ -84,3 +84,23 @@ def test_server_config_is_checked_before_any_device_call(cfg):
     assert h.value is None
     with pytest.raises(mppi.MppiError):
         mppi.Server(mode="round-robin")
+
+
+def test_per_contact_and_per_joint_arrays_must_match_the_model():
+    """f0z (one reference normal force per contact point) and q0_cost (one posture
+    target per joint) are read for every point and joint: the library binding and
+    the oracle both reject arrays of another length instead of reading past them."""
+    m, p, s = synth.config("quadruped", n_samples=8)
+    nc, nu = len(m["contact_body"]), m["n_u"]
+    mppi._check_param_lengths(p, nc, nu)
+    short = dict(p, f0z=np.asarray(p["f0z"])[:-1])
+    with pytest.raises(mppi.MppiError):
+        mppi._check_param_lengths(short, nc, nu)
+    with pytest.raises(mppi.MppiError):
+        mppi._check_param_lengths(dict(p, q0_cost=np.asarray(p["q0_cost"])[:-2]), nc, nu)
+    import oracle as O
+    x0 = np.asarray(m["x0"], dtype=np.float64)
+    knots = synth.nominal_knots(m, p["n_knots"])
+    O.rollout(m, dict(p, horizon=2), x0, knots)
+    with pytest.raises(ValueError):
+        O.rollout(m, dict(short, horizon=2), x0, knots)

@@ -164,6 +164,7 @@ def test_rollout_costs_contact_on_floating_base():
     m["contact_pos"] = np.concatenate([np.asarray(m["contact_pos"]),
                                        [[0.05, 0.02, -0.32], [-0.08, -0.03, -0.29]]]).astype(np.asarray(m["contact_pos"]).dtype)
     m["support"] = np.concatenate([np.asarray(m["support"]), [False, False]])
+    p["f0z"] = np.concatenate([np.asarray(p["f0z"]), [0.0, 0.0]]).astype(np.asarray(p["f0z"]).dtype)  # not support points
     model = mppi.Model(m)
     c = mppi.Controller(model, p, s)
     smp = _oracle_samples(m, p, s, 32)
