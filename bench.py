@@ -292,6 +292,12 @@ def tasks(args, torch, mppi, synth):
     return out
 
 
+# Server streams per mode, the best of a sweep over 1..6 on the 64-robot mix: the
+# batching modes run one stream whose launches fork their rollout groups onto
+# side streams; plain per-instance launches overlap best over three streams.
+SERVE_STREAMS = {"batched": 1, "iteration": 1, "plain": 3}
+
+
 def serving(args, torch, mppi, synth, mode):
     """Poisson MPC ticks (50 Hz per robot) from the 64-robot mix, served by the
     continuous-batching server (mode "batched": request-level batches; "iteration":
@@ -313,7 +319,8 @@ def serving(args, torch, mppi, synth, mode):
     dts = [p["dt"] for (m, p, seed) in robots]
     Hs = [p["horizon"] for (m, p, seed) in robots]
     delay = [1] * len(made)
-    srv = mppi.Server(n_streams=args.serve_streams, max_batch=len(made), mode=mode)
+    n_streams = args.serve_streams or SERVE_STREAMS[mode]
+    srv = mppi.Server(n_streams=n_streams, max_batch=len(made), mode=mode)
     # warm-up: one tick per robot
     tk = [srv.submit_tick(c, st, 1, k) for (_, c, st, k, _) in made]
     srv.drain()
@@ -349,7 +356,7 @@ def serving(args, torch, mppi, synth, mode):
     return {"rollout_steps_per_s": work_done / wall, "ticks": len(lat), "wall_s": wall,
             "tick_latency_p50_ms": _pct(lat_ms, 50), "tick_latency_p99_ms": _pct(lat_ms, 99),
             "deadline_miss_frac": float(np.mean(lat_ms > 20.0)), "batches": batches,
-            "ticks_per_batch": requests / max(batches, 1)}
+            "ticks_per_batch": requests / max(batches, 1), "streams": n_streams}
 
 
 def cpu_baseline(args, res):
@@ -406,7 +413,8 @@ def main():
     ap.add_argument("--task-ticks", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
-    ap.add_argument("--serve-streams", type=int, default=3)
+    ap.add_argument("--serve-streams", type=int, default=None,
+                    help="server streams for every serving mode (default: per mode, SERVE_STREAMS)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (reference for HBM byte counters)")

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -1538,8 +1539,20 @@ static hipError_t launch_predict_batch(int G, int n_items, const PredItem* items
   return hipGetLastError();
 }
 
+// Streams onto which an iteration's rollout groups fork: group 0 runs on the
+// launch stream, group k on aux[(k-1) % n_aux] after ev_fork recorded on the
+// launch stream; the launch stream waits for ev_join[j] recorded on aux[j] before
+// the iteration's update.  Groups of different lane counts then run side by side
+// instead of one after the other.
+struct ForkStreams {
+  const hipStream_t* aux = nullptr;
+  int n_aux = 0;
+  hipEvent_t ev_fork = nullptr;
+  const hipEvent_t* ev_join = nullptr;
+};
+
 static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsigned int* counters, int n_counters,
-                                        bool persistent, hipStream_t s) {
+                                        bool persistent, hipStream_t s, const ForkStreams* fork = nullptr) {
   const int n = (int)reqs.size();
   // iterations of request i in this launch: it0(i) .. it0(i)+n_iters[i]-1
   std::vector<int> n_iters(n);
@@ -1682,12 +1695,24 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   for (int it = 0; it < Imax; ++it) {
     IterDesc& d = iters[it];
     auto* di = reinterpret_cast<const DevInst*>(dv + d.inst_off);
-    for (auto& g : d.groups) {
+    const int n_groups = (int)d.groups.size();
+    const int n_fork = (fork && fork->n_aux > 0 && n_groups > 1) ? std::min(fork->n_aux, n_groups - 1) : 0;
+    if (n_fork > 0) {
+      HIP_TRY(hipEventRecord(fork->ev_fork, s));
+      for (int j = 0; j < n_fork; ++j) HIP_TRY(hipStreamWaitEvent(fork->aux[j], fork->ev_fork, 0));
+    }
+    for (int k = 0; k < n_groups; ++k) {
+      const GroupDesc& g = d.groups[k];
+      const hipStream_t gs = (n_fork > 0 && k > 0) ? fork->aux[(k - 1) % n_fork] : s;
       auto* w = reinterpret_cast<const int2*>(dv + g.work_off);
       if (persistent && counters && ci < n_counters)
-        HIP_TRY(launch_persistent(g.G, g.n_items, di, w, g.dims, counters + ci++, s));
+        HIP_TRY(launch_persistent(g.G, g.n_items, di, w, g.dims, counters + ci++, gs));
       else
-        HIP_TRY(launch_rollout(g.G, g.n_items, di, w, g.dims, s));
+        HIP_TRY(launch_rollout(g.G, g.n_items, di, w, g.dims, gs));
+    }
+    for (int j = 0; j < n_fork; ++j) {
+      HIP_TRY(hipEventRecord(fork->ev_join[j], fork->aux[j]));
+      HIP_TRY(hipStreamWaitEvent(s, fork->ev_join[j], 0));
     }
     hipLaunchKernelGGL(update_kernel, dim3(kUpdMaxParts, (unsigned)d.n_active), dim3(kUpdThreads), 0, s,
                        reinterpret_cast<const DevUpdate*>(dv + d.up_off), reinterpret_cast<const UpdateOut*>(dv + d.out_off),
@@ -1721,9 +1746,13 @@ struct SrvLive {
   uint64_t ticket;
   BatchReq req;  // req.it0: its next iteration
 };
+constexpr int kSrvAux = 3;  // most side streams per slot for a launch's rollout groups
 struct SrvSlot {
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
+  hipStream_t aux[kSrvAux] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kSrvAux] = {};
   bool busy = false;
   std::vector<uint64_t> tickets;  // mode 2: the ticks whose last iteration the round runs
   unsigned int* counters = nullptr;
@@ -1746,7 +1775,24 @@ struct mppi_server {
   std::string error;
   int64_t launched_batches = 0, launched_requests = 0;
   int live_n = 0;  // mode 2: admitted requests not yet complete
+  int n_aux = 0;   // side streams per slot
 };
+
+// Side streams per slot.  The runtime maps streams onto a few hardware queues
+// (GPU_MAX_HW_QUEUES, 4 by default) and two streams on one queue run in order.
+// A single slot forks its rollout groups onto the remaining queues.  With
+// several slots, side streams end up sharing queues with other slots' streams
+// and each slot's joins then wait behind the others' kernels (measured several
+// times slower), so they fork nothing.
+static int server_side_streams(int n_streams) {
+  if (n_streams != 1) return 0;
+  int hwq = 4;
+  if (const char* e = std::getenv("GPU_MAX_HW_QUEUES")) {
+    const int v = std::atoi(e);
+    if (v > 0) hwq = v;
+  }
+  return std::max(0, std::min(kSrvAux, hwq - 1));
+}
 
 static void server_fail(mppi_server* S) {
   std::lock_guard<std::mutex> lk(S->mu);
@@ -1769,6 +1815,21 @@ static void server_retire(mppi_server* S, SrvSlot& sl) {
   sl.busy = false;
 }
 
+// 1: the slot's launches have finished; 0: still running; -1: the device
+// reported an error (the server stops with it).
+static int slot_finished(mppi_server* S, SrvSlot& sl) {
+  const hipError_t e = hipEventQuery(sl.ev);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  fail(MPPI_EDEVICE, std::string("hipEventQuery: ") + hipGetErrorString(e));
+  server_fail(S);
+  return -1;
+}
+
+static ForkStreams fork_of(const mppi_server* S, const SrvSlot& sl) {
+  return ForkStreams{sl.aux, S->n_aux, sl.ev_fork, sl.ev_join};
+}
+
 static BatchReq batch_req_of(const SrvReq& r) {
   if (r.best)  // a tick: its prefix runs first, then the iterations read x0 and the nominal in place
     return BatchReq{r.ctx, r.state, nullptr, r.knots_out, r.best, r.info, r.n_delay, true};
@@ -1789,7 +1850,9 @@ static void server_loop_rounds(mppi_server* S) {
     bool progressed = false;
     for (auto& sl : S->slots) {
       if (sl.busy) {
-        if (hipEventQuery(sl.ev) != hipSuccess) continue;
+        const int f = slot_finished(S, sl);
+        if (f < 0) return;
+        if (f == 0) continue;
         server_retire(S, sl);
         progressed = true;
       }
@@ -1819,7 +1882,8 @@ static void server_loop_rounds(mppi_server* S) {
       mppi_status st;
       {
         std::lock_guard<std::mutex> lk(g_mu);
-        st = launch_batch_dynamic(batch, sl.counters, 64 * 5, S->cfg.persistent != 0, sl.stream);
+        const ForkStreams fk = fork_of(S, sl);
+        st = launch_batch_dynamic(batch, sl.counters, 64 * 5, S->cfg.persistent != 0, sl.stream, &fk);
       }
       if (st == MPPI_OK && hipEventRecord(sl.ev, sl.stream) != hipSuccess) st = MPPI_EDEVICE;
       if (st != MPPI_OK) {
@@ -1856,7 +1920,9 @@ static void server_loop(mppi_server* S) {
     bool progressed = false;
     for (auto& sl : S->slots) {
       if (!sl.busy) continue;
-      if (hipEventQuery(sl.ev) != hipSuccess) continue;
+      const int f = slot_finished(S, sl);
+      if (f < 0) return;
+      if (f == 0) continue;
       server_retire(S, sl);
       progressed = true;
     }
@@ -1890,7 +1956,8 @@ static void server_loop(mppi_server* S) {
           if (b.tick && !b.knots_out) b.knots_out = b.ctx->pred_knots;
         if (st == MPPI_OK) {
           std::lock_guard<std::mutex> lk(g_mu);
-          st = launch_batch_dynamic(batch, sl.counters, 64 * 5, S->cfg.persistent != 0, sl.stream);
+          const ForkStreams fk = fork_of(S, sl);
+          st = launch_batch_dynamic(batch, sl.counters, 64 * 5, S->cfg.persistent != 0, sl.stream, &fk);
         }
       }
       if (st == MPPI_OK && hipEventRecord(sl.ev, sl.stream) != hipSuccess) st = MPPI_EDEVICE;
@@ -1898,9 +1965,12 @@ static void server_loop(mppi_server* S) {
         server_fail(S);
         break;
       }
-      sl.busy = true;
-      S->launched_batches += 1;
-      S->launched_requests += (int64_t)batch.size();
+      {
+        std::lock_guard<std::mutex> lk(S->mu);  // drain and stats read these
+        sl.busy = true;
+        S->launched_batches += 1;
+        S->launched_requests += (int64_t)batch.size();
+      }
       progressed = true;
     }
     if (!progressed) {
@@ -1920,10 +1990,16 @@ extern "C" mppi_status mppi_server_create(const mppi_server_cfg* cfg, mppi_serve
   S->cfg = *cfg;
   HIP_TRY(hipGetDevice(&S->device));
   S->slots.resize(cfg->n_streams);
+  S->n_aux = cfg->mode == 1 ? 0 : server_side_streams(cfg->n_streams);
   for (auto& sl : S->slots) {
     HIP_TRY(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
     HIP_TRY(hipMalloc(&sl.counters, 64 * 5 * sizeof(unsigned int)));
+    HIP_TRY(hipEventCreateWithFlags(&sl.ev_fork, hipEventDisableTiming));
+    for (int j = 0; j < S->n_aux; ++j) {
+      HIP_TRY(hipStreamCreateWithFlags(&sl.aux[j], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&sl.ev_join[j], hipEventDisableTiming));
+    }
   }
   S->worker = std::thread(cfg->mode == 2 ? server_loop_rounds : server_loop, S.get());
   *out = S.release();
@@ -2008,9 +2084,16 @@ extern "C" mppi_status mppi_server_destroy(mppi_server* S) {
   S->cv.notify_all();
   if (S->worker.joinable()) S->worker.join();
   for (auto& sl : S->slots) {
-    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);  // the side streams join the slot's stream
+    for (int j = 0; j < kSrvAux; ++j)
+      if (sl.aux[j]) (void)hipStreamSynchronize(sl.aux[j]);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.ev_fork) (void)hipEventDestroy(sl.ev_fork);
     if (sl.counters) (void)hipFree(sl.counters);
+    for (int j = 0; j < kSrvAux; ++j) {
+      if (sl.ev_join[j]) (void)hipEventDestroy(sl.ev_join[j]);
+      if (sl.aux[j]) (void)hipStreamDestroy(sl.aux[j]);
+    }
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   delete S;

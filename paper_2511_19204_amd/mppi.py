@@ -449,7 +449,7 @@ class Server:
 
     MODES = {"batched": 0, "plain": 1, "iteration": 2}
 
-    def __init__(self, n_streams=3, max_batch=256, max_pending=100000, mode="iteration", persistent=False):
+    def __init__(self, n_streams=1, max_batch=256, max_pending=100000, mode="iteration", persistent=False):
         if mode not in self.MODES:
             raise MppiError(f"unknown server mode {mode!r}; one of {sorted(self.MODES)}")
         cfg = ServerCfg(int(max_pending), int(n_streams), int(max_batch), self.MODES[mode],

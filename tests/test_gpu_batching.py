@@ -125,13 +125,19 @@ def test_autotune_picks_a_valid_lane_count_without_changing_results():
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain", "iteration"])
-def test_server_result_is_the_same_alone_and_in_the_mix(mix, mode):
+# one stream: the launches fork their rollout groups (one per lane count) onto side
+# streams; several streams: no side streams
+SERVER_CASES = [("batched", 1), ("batched", 2), ("plain", 2), ("iteration", 1), ("iteration", 3)]
+
+
+@pytest.mark.parametrize("mode,n_streams", SERVER_CASES)
+def test_server_result_is_the_same_alone_and_in_the_mix(mix, mode, n_streams):
     """Robot 0 served alone, then in a mix where the other robots' ticks arrive in
     between (continuous batching): its knots after every tick equal the plain
     step's, and so do every other robot's."""
     robots, refs = mix
-    srv = mppi.Server(n_streams=2, max_batch=64, mode=mode)
+    assert len({c.lanes for (*_, c) in robots}) >= 2  # several rollout groups per launch
+    srv = mppi.Server(n_streams=n_streams, max_batch=64, mode=mode)
     try:
         # alone
         (m0, p0, s0, model0, c0) = robots[0]
@@ -233,8 +239,8 @@ def _tick_reference(robots, ticks, delay):
     return refs
 
 
-@pytest.mark.parametrize("mode", ["batched", "plain", "iteration"])
-def test_server_ticks_equal_the_instance_ticks(mode):
+@pytest.mark.parametrize("mode,n_streams", SERVER_CASES)
+def test_server_ticks_equal_the_instance_ticks(mode, n_streams):
     """Served ticks (prediction by a per-tick delay, warm-start shift, iterations,
     tau_best carried on the device) of an uneven mix, submitted staggered with at
     most one outstanding per robot: every robot's tau_best, nominal and step info
@@ -243,7 +249,7 @@ def test_server_ticks_equal_the_instance_ticks(mode):
     ticks = 3
     delay = lambda i, t, p: (i + 2 * t) % 5 if t != 1 else p["horizon"]  # includes 0 and the full horizon
     refs = _tick_reference(robots, ticks, delay)
-    srv = mppi.Server(n_streams=2, max_batch=6, mode=mode)
+    srv = mppi.Server(n_streams=n_streams, max_batch=6, mode=mode)
     try:
         for (*_, c) in robots:
             c.tick = 0
