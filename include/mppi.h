@@ -305,6 +305,11 @@ mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t);
  *    round.  Pending ticks join the first stream to finish a round (up to
  *    max_batch admitted over all streams) and leave after their last iteration;
  *    a tick stays on its stream.
+ * With n_streams = 1 in mode 0 or 2, each launch forks its rollout kernels (one
+ * per lane count) onto up to three side streams of the server, fewer when
+ * GPU_MAX_HW_QUEUES is below 4, so that kernels of different robot types run
+ * side by side; with several streams nothing forks (streams beyond the hardware
+ * queue count share queues and run in order).
  * Each result equals the instance's own mppi_step / mppi_tick (the instance's
  * warm-start knots and noise tick stay on the device).  persistent selects the
  * persistent rollout launch (mppi_batch_opts).  Buffers passed to submit must
