@@ -416,9 +416,14 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=None,
                     help="server streams for every serving mode (default: per mode, SERVE_STREAMS)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-modes", default="batched,iteration,plain",
+                    help="comma-separated server modes to serve the mix with")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    for mode in args.serve_modes.split(","):
+        if mode not in SERVE_STREAMS:
+            ap.error(f"unknown serving mode {mode!r}; one of {sorted(SERVE_STREAMS)}")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding is a design note, not a runnable path", file=sys.stderr)
@@ -440,11 +445,8 @@ def main():
     bvp = None if args.no_batch else batched_vs_plain(args, torch, mppi, synth)
     srv = None
     if not args.no_serve:
-        srv = {"batched": serving(args, torch, mppi, synth, "batched"),
-               "iteration": serving(args, torch, mppi, synth, "iteration"),
-               "plain": serving(args, torch, mppi, synth, "plain"),
-               "robots": args.robots, "rate_hz": 50.0, "deadline_ms": 20.0,
-               "seconds": args.serve_seconds}
+        srv = {mode: serving(args, torch, mppi, synth, mode) for mode in args.serve_modes.split(",")}
+        srv.update({"robots": args.robots, "rate_hz": 50.0, "deadline_ms": 20.0, "seconds": args.serve_seconds})
     loop = None if args.no_loop else closed_loop(args, torch, mppi, synth)
     task_res = None if args.no_tasks else tasks(args, torch, mppi, synth)
     cpu = None if args.no_cpu else cpu_baseline(args, res)
