@@ -292,10 +292,11 @@ def tasks(args, torch, mppi, synth):
     return out
 
 
-# Server streams per mode, the best of a sweep over 1..6 on the 64-robot mix: the
-# batching modes run one stream whose launches fork their rollout groups onto
-# side streams; plain per-instance launches overlap best over three streams.
-SERVE_STREAMS = {"batched": 1, "iteration": 1, "plain": 3}
+# Server streams per mode, the best of a sweep over 1..6 on the 64-robot mix:
+# iteration-level rounds run one stream per robot type (three); request-level
+# batches run one stream whose launches fork their rollout groups onto side
+# streams; plain per-instance launches overlap best over three streams.
+SERVE_STREAMS = {"batched": 1, "iteration": 3, "plain": 3}
 
 
 def serving(args, torch, mppi, synth, mode):

@@ -302,9 +302,11 @@ mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t);
  *  mode 2 (iteration-level batching): each of the n_streams streams runs
  *    rounds back to back; a round launches ONE iteration (Alg. 1) of every tick
  *    admitted to that stream, after the prefixes of the ticks admitted at that
- *    round.  Pending ticks join the first stream to finish a round (up to
- *    max_batch admitted over all streams) and leave after their last iteration;
- *    a tick stays on its stream.
+ *    round.  Pending ticks join their stream's next round (up to max_batch
+ *    admitted over all streams) and leave after their last iteration.  With
+ *    several streams all ticks of instances with the same lanes per rollout
+ *    (robot type) use one stream, types spread over the streams in order of
+ *    first appearance, so short rollouts never wait for a round of long ones.
  * With n_streams = 1 in mode 0 or 2, each launch forks its rollout kernels (one
  * per lane count) onto up to three side streams of the server, fewer when
  * GPU_MAX_HW_QUEUES is below 4, so that kernels of different robot types run

@@ -967,6 +967,7 @@ struct IterPlan {
   DevUpdate* ups = nullptr;     // device [n_active]
   std::vector<int> active;      // instance indices (into the batch) active in this iteration
   std::vector<GroupLaunch> groups;
+  int upd_parts = 1;            // update grid width: the most parts of an active instance
 };
 struct Plan {
   std::vector<const mppi_ctx*> ctxs;
@@ -1023,6 +1024,7 @@ static mppi_status build_plan(const std::vector<const mppi_ctx*>& ctxs, Plan** o
       ip.active.push_back(i);
       hi.push_back(ctxs[i]->h_insts[it]);
       hu.push_back(ctxs[i]->h_ups[it]);
+      ip.upd_parts = std::max(ip.upd_parts, hu.back().parts);
     }
     HIP_TRY(hipMalloc(&ip.insts, hi.size() * sizeof(DevInst)));
     HIP_TRY(hipMemcpy(ip.insts, hi.data(), hi.size() * sizeof(DevInst), hipMemcpyHostToDevice));
@@ -1147,7 +1149,7 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
       else
         HIP_TRY(launch_rollout(g.G, g.blocks, ip.insts, g.work, g.dims, s));
     }
-    hipLaunchKernelGGL(update_kernel, dim3(kUpdMaxParts, (unsigned)ip.active.size()), dim3(kUpdThreads), 0, s, ip.ups,
+    hipLaunchKernelGGL(update_kernel, dim3(ip.upd_parts, (unsigned)ip.active.size()), dim3(kUpdThreads), 0, s, ip.ups,
                        d_outs + out_off[it],
                        UpdateOut{nullptr, nullptr, nullptr});
     HIP_TRY(hipGetLastError());
@@ -1227,7 +1229,7 @@ extern "C" mppi_status mppi_graph_create(int32_t n, mppi_ctx* const* ctxs, const
                          : launch_rollout(gl.G, gl.blocks, ip.insts, gl.work, gl.dims, cs);
         if (e != hipSuccess) break;
       }
-      hipLaunchKernelGGL(update_kernel, dim3(kUpdMaxParts, (unsigned)ip.active.size()), dim3(kUpdThreads), 0, cs, ip.ups,
+      hipLaunchKernelGGL(update_kernel, dim3(ip.upd_parts, (unsigned)ip.active.size()), dim3(kUpdThreads), 0, cs, ip.ups,
                          d_outs + out_off[it], UpdateOut{nullptr, nullptr, nullptr});
     }
     hipGraph_t graph = nullptr;
@@ -1564,7 +1566,10 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
     Imax = std::max(Imax, n_iters[i]);
   }
   struct GroupDesc { int G; Dims dims; size_t work_off; int n_items; };
-  struct IterDesc { size_t inst_off, up_off, out_off; int n_active; std::vector<GroupDesc> groups; };
+  // upd_parts: the update grid's width, the most parts (blocks) of an active
+  // instance; blocks beyond an instance's own parts return at once but would
+  // still wait for a free slot on a busy device
+  struct IterDesc { size_t inst_off, up_off, out_off; int n_active, upd_parts = 1; std::vector<GroupDesc> groups; };
   std::vector<IterDesc> iters(Imax);
   // requests starting at iteration 0 stage their inputs; ticks among them run
   // their prefixes (prediction by lane count, then the shifts) after the staging
@@ -1649,6 +1654,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
       const int ci = q.it0 + it;  // the instance's own iteration index
       hi[a] = q.ctx->h_insts[ci];
       hu[a] = q.ctx->h_ups[ci];
+      d.upd_parts = std::max(d.upd_parts, hu[a].parts);
       ho[a] = q.ctx->I - 1 == ci ? UpdateOut{q.knots_out, q.best_out, q.info_out} : UpdateOut{nullptr, nullptr, nullptr};
     }
     std::map<int, std::vector<int>> byG;
@@ -1714,7 +1720,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
       HIP_TRY(hipEventRecord(fork->ev_join[j], fork->aux[j]));
       HIP_TRY(hipStreamWaitEvent(s, fork->ev_join[j], 0));
     }
-    hipLaunchKernelGGL(update_kernel, dim3(kUpdMaxParts, (unsigned)d.n_active), dim3(kUpdThreads), 0, s,
+    hipLaunchKernelGGL(update_kernel, dim3(d.upd_parts, (unsigned)d.n_active), dim3(kUpdThreads), 0, s,
                        reinterpret_cast<const DevUpdate*>(dv + d.up_off), reinterpret_cast<const UpdateOut*>(dv + d.out_off),
                        UpdateOut{nullptr, nullptr, nullptr});
     HIP_TRY(hipGetLastError());
@@ -1776,7 +1782,19 @@ struct mppi_server {
   int64_t launched_batches = 0, launched_requests = 0;
   int live_n = 0;  // mode 2: admitted requests not yet complete
   int n_aux = 0;   // side streams per slot
+  std::map<int, int> key_slot;  // mode 2, several slots: the slot of each rollout lane key (worker thread only)
 };
+
+// Mode 2 with several slots: every request of one rollout lane key (robot type)
+// goes to one slot, keys spread over the slots in order of first appearance, so
+// a slot's rounds never wait for a longer kind of rollout.
+static int slot_of(mppi_server* S, const mppi_ctx* c) {
+  const int n = (int)S->slots.size();
+  if (n == 1) return 0;
+  auto f = S->key_slot.find(c->lanes);
+  if (f == S->key_slot.end()) f = S->key_slot.emplace(c->lanes, (int)S->key_slot.size() % n).first;
+  return f->second;
+}
 
 // Side streams per slot.  The runtime maps streams onto a few hardware queues
 // (GPU_MAX_HW_QUEUES, 4 by default) and two streams on one queue run in order.
@@ -1839,16 +1857,17 @@ static BatchReq batch_req_of(const SrvReq& r) {
 // Mode 2, iteration-level batching: each stream runs rounds back to back; a
 // round runs ONE iteration of every request admitted to that stream (the
 // prefixes of the requests admitted at that round first).  Pending requests join
-// whichever stream finishes a round first and leave after their last iteration,
-// so nothing waits for the rest of a batch to finish, while rounds on different
-// streams overlap and fill each other's tails.  A request stays on its stream,
-// which orders its iterations.
+// their stream's next round (with several streams, the stream of their robot
+// type, slot_of) and leave after their last iteration, so nothing waits for the
+// rest of a batch to finish and short rollouts do not wait for long ones.  A
+// request stays on its stream, which orders its iterations.
 static void server_loop_rounds(mppi_server* S) {
   (void)hipSetDevice(S->device);
   std::vector<BatchReq> batch;
   while (!S->stop.load()) {
     bool progressed = false;
-    for (auto& sl : S->slots) {
+    for (int si = 0; si < (int)S->slots.size(); ++si) {
+      SrvSlot& sl = S->slots[si];
       if (sl.busy) {
         const int f = slot_finished(S, sl);
         if (f < 0) return;
@@ -1861,7 +1880,7 @@ static void server_loop_rounds(mppi_server* S) {
         std::lock_guard<std::mutex> lk(S->mu);
         for (auto it = S->pending.begin(); it != S->pending.end() && S->live_n < S->cfg.max_batch;) {
           SrvReq& r = S->reqs[*it];
-          if (S->busy.count(r.ctx)) { ++it; continue; }
+          if (S->busy.count(r.ctx) || slot_of(S, r.ctx) != si) { ++it; continue; }
           S->busy[r.ctx] = 1;
           r.status = 1;
           BatchReq b = batch_req_of(r);

@@ -445,11 +445,11 @@ class Server:
     """Continuous-batching server of MPC ticks: mode "batched" (a batch runs all
     iterations of the ticks it took), "plain" (per-instance launches) or
     "iteration" (every round runs one iteration of each admitted tick; ticks join
-    at round boundaries)."""
+    at round boundaries; with several streams each robot type has its own)."""
 
     MODES = {"batched": 0, "plain": 1, "iteration": 2}
 
-    def __init__(self, n_streams=1, max_batch=256, max_pending=100000, mode="iteration", persistent=False):
+    def __init__(self, n_streams=3, max_batch=256, max_pending=100000, mode="iteration", persistent=False):
         if mode not in self.MODES:
             raise MppiError(f"unknown server mode {mode!r}; one of {sorted(self.MODES)}")
         cfg = ServerCfg(int(max_pending), int(n_streams), int(max_batch), self.MODES[mode],
