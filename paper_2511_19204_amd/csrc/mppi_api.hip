@@ -13,6 +13,7 @@
 #include <memory>
 #include <atomic>
 #include <chrono>
+#include <climits>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -1782,18 +1783,33 @@ struct mppi_server {
   int64_t launched_batches = 0, launched_requests = 0;
   int live_n = 0;  // mode 2: admitted requests not yet complete
   int n_aux = 0;   // side streams per slot
-  std::map<int, int> key_slot;  // mode 2, several slots: the slot of each rollout lane key (worker thread only)
+  // mode 2, several slots (worker thread only): the slot of each rollout lane key
+  // (robot type) and the key owning each slot (kNoOwner: none; keys may be negative)
+  std::map<int, int> key_slot;
+  std::vector<int> slot_owner;
 };
 
-// Mode 2 with several slots: every request of one rollout lane key (robot type)
-// goes to one slot, keys spread over the slots in order of first appearance, so
-// a slot's rounds never wait for a longer kind of rollout.
-static int slot_of(mppi_server* S, const mppi_ctx* c) {
+// Mode 2 with several slots: each rollout lane key (robot type) claims a slot
+// that no type owns yet when it first appears (once every slot is owned, later
+// types share them in turn), and its requests go there, so a slot's rounds never
+// wait for a longer kind of rollout.  Slots that no type owns serve every type,
+// so fewer types than slots still use all streams.
+constexpr int kNoOwner = INT_MIN;
+static bool slot_takes(mppi_server* S, int si, const mppi_ctx* c) {
   const int n = (int)S->slots.size();
-  if (n == 1) return 0;
+  if (n == 1) return true;
   auto f = S->key_slot.find(c->lanes);
-  if (f == S->key_slot.end()) f = S->key_slot.emplace(c->lanes, (int)S->key_slot.size() % n).first;
-  return f->second;
+  if (f == S->key_slot.end()) {
+    int s = -1;
+    for (int i = 0; i < n && s < 0; ++i)
+      if (S->slot_owner[i] == kNoOwner) s = i;
+    if (s >= 0)
+      S->slot_owner[s] = c->lanes;
+    else
+      s = (int)S->key_slot.size() % n;
+    f = S->key_slot.emplace(c->lanes, s).first;
+  }
+  return f->second == si || S->slot_owner[si] == kNoOwner;
 }
 
 // Side streams per slot.  The runtime maps streams onto a few hardware queues
@@ -1858,7 +1874,7 @@ static BatchReq batch_req_of(const SrvReq& r) {
 // round runs ONE iteration of every request admitted to that stream (the
 // prefixes of the requests admitted at that round first).  Pending requests join
 // their stream's next round (with several streams, the stream of their robot
-// type, slot_of) and leave after their last iteration, so nothing waits for the
+// type, slot_takes) and leave after their last iteration, so nothing waits for the
 // rest of a batch to finish and short rollouts do not wait for long ones.  A
 // request stays on its stream, which orders its iterations.
 static void server_loop_rounds(mppi_server* S) {
@@ -1880,7 +1896,7 @@ static void server_loop_rounds(mppi_server* S) {
         std::lock_guard<std::mutex> lk(S->mu);
         for (auto it = S->pending.begin(); it != S->pending.end() && S->live_n < S->cfg.max_batch;) {
           SrvReq& r = S->reqs[*it];
-          if (S->busy.count(r.ctx) || slot_of(S, r.ctx) != si) { ++it; continue; }
+          if (S->busy.count(r.ctx) || !slot_takes(S, si, r.ctx)) { ++it; continue; }
           S->busy[r.ctx] = 1;
           r.status = 1;
           BatchReq b = batch_req_of(r);
@@ -2009,6 +2025,7 @@ extern "C" mppi_status mppi_server_create(const mppi_server_cfg* cfg, mppi_serve
   S->cfg = *cfg;
   HIP_TRY(hipGetDevice(&S->device));
   S->slots.resize(cfg->n_streams);
+  S->slot_owner.assign(cfg->n_streams, kNoOwner);
   S->n_aux = cfg->mode == 1 ? 0 : server_side_streams(cfg->n_streams);
   for (auto& sl : S->slots) {
     HIP_TRY(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
