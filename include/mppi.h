@@ -306,8 +306,9 @@ mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t);
  *    admitted over all streams) and leave after their last iteration.  With
  *    several streams each robot type (instances with the same lanes per
  *    rollout) claims a stream no type owns when it first appears and its ticks
- *    go there, so short rollouts never wait for a round of long ones; streams
- *    no type owns serve every type (once all are owned, later types share).
+ *    go there, so short rollouts never wait for a round of long ones; a stream
+ *    no type owns serves one type at a time (once all are owned, later types
+ *    share).
  * With n_streams = 1 in mode 0 or 2, each launch forks its rollout kernels (one
  * per lane count) onto up to three side streams of the server, fewer when
  * GPU_MAX_HW_QUEUES is below 4, so that kernels of different robot types run

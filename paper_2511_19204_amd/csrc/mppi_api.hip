@@ -1792,8 +1792,9 @@ struct mppi_server {
 // Mode 2 with several slots: each rollout lane key (robot type) claims a slot
 // that no type owns yet when it first appears (once every slot is owned, later
 // types share them in turn), and its requests go there, so a slot's rounds never
-// wait for a longer kind of rollout.  Slots that no type owns serve every type,
-// so fewer types than slots still use all streams.
+// wait for a longer kind of rollout.  Slots that no type owns take one type at a
+// time (that of their requests in flight, any type once empty), so fewer types
+// than slots still use all streams without mixing kinds of rollout in a round.
 constexpr int kNoOwner = INT_MIN;
 static bool slot_takes(mppi_server* S, int si, const mppi_ctx* c) {
   const int n = (int)S->slots.size();
@@ -1809,7 +1810,10 @@ static bool slot_takes(mppi_server* S, int si, const mppi_ctx* c) {
       s = (int)S->key_slot.size() % n;
     f = S->key_slot.emplace(c->lanes, s).first;
   }
-  return f->second == si || S->slot_owner[si] == kNoOwner;
+  if (f->second == si) return true;
+  if (S->slot_owner[si] != kNoOwner) return false;
+  const SrvSlot& sl = S->slots[si];
+  return sl.live.empty() || sl.live.front().req.ctx->lanes == c->lanes;
 }
 
 // Side streams per slot.  The runtime maps streams onto a few hardware queues
