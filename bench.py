@@ -18,7 +18,7 @@ Also reported:
                    seconds, served with request-level batches ("batched"),
                    iteration-level rounds ("iteration") and plain per-instance
                    launches ("plain"): throughput, p50/p99 latency from tick
-                   arrival, 20 ms deadline misses;
+                   arrival, 20 ms deadline misses, overall and per robot type;
   roofline         the rollout kernel: algorithmic FP32 operations per launch
                    (flops.flops_per_rollout_step x K x H) / its mean duration,
                    against the FP32 vector peak (ALU-bound path);
@@ -330,7 +330,7 @@ def serving(args, torch, mppi, synth, mode):
     torch.cuda.synchronize()
     nxt = [0] * len(made)
     live = {}
-    lat, work_done = [], 0
+    lat, lat_robot, work_done = [], [], 0
     t0 = time.perf_counter()
     while True:
         now = time.perf_counter() - t0
@@ -344,6 +344,7 @@ def serving(args, torch, mppi, synth, mode):
             srv_lat = srv.poll(ticket)
             if srv_lat is not None:
                 lat.append((sub - arrival) + srv_lat)
+                lat_robot.append(i)
                 delay[i] = min(Hs[i], max(1, int(np.ceil(srv_lat / dts[i]))))
                 work_done += w
                 del live[i]
@@ -354,7 +355,13 @@ def serving(args, torch, mppi, synth, mode):
     batches, requests = srv.stats()
     srv.close()
     lat_ms = np.asarray(lat) * 1e3
-    return {"rollout_steps_per_s": work_done / wall, "ticks": len(lat), "wall_s": wall,
+    kind = np.asarray([robots[i][0]["name"] for i in lat_robot])
+    per_model = {}
+    for name in sorted(set(kind.tolist())):
+        lm = lat_ms[kind == name]
+        per_model[name] = {"ticks": int(lm.size), "tick_latency_p50_ms": _pct(lm, 50),
+                           "tick_latency_p99_ms": _pct(lm, 99), "deadline_miss_frac": float(np.mean(lm > 20.0))}
+    return {"rollout_steps_per_s": work_done / wall, "ticks": len(lat), "wall_s": wall, "per_model": per_model,
             "tick_latency_p50_ms": _pct(lat_ms, 50), "tick_latency_p99_ms": _pct(lat_ms, 99),
             "deadline_miss_frac": float(np.mean(lat_ms > 20.0)), "batches": batches,
             "ticks_per_batch": requests / max(batches, 1), "streams": n_streams}
