@@ -126,8 +126,10 @@ def test_autotune_picks_a_valid_lane_count_without_changing_results():
 
 
 # one stream: the launches fork their rollout groups (one per lane count) onto side
-# streams; several streams: no side streams
-SERVER_CASES = [("batched", 1), ("batched", 2), ("plain", 2), ("iteration", 1), ("iteration", 3)]
+# streams; several streams: no side streams, and in iteration mode each robot type
+# owns a stream (with four streams and at most three types, one stream floats)
+SERVER_CASES = [("batched", 1), ("batched", 2), ("plain", 2), ("iteration", 1), ("iteration", 3),
+                ("iteration", 4)]
 
 
 @pytest.mark.parametrize("mode,n_streams", SERVER_CASES)
