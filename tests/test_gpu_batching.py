@@ -127,7 +127,8 @@ def test_autotune_picks_a_valid_lane_count_without_changing_results():
 
 # one stream: the launches fork their rollout groups (one per lane count) onto side
 # streams; several streams: no side streams, and in iteration mode each robot type
-# owns a stream (with four streams and at most three types, one stream floats)
+# owns a stream (with four streams and at most three types, at least one stream
+# is owned by none and takes ticks of one type at a time)
 SERVER_CASES = [("batched", 1), ("batched", 2), ("plain", 2), ("iteration", 1), ("iteration", 3),
                 ("iteration", 4)]
 
