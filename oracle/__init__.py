@@ -13,6 +13,7 @@ Each function names the part of Schramm et al. (arXiv 2511.19204) it follows:
   sample_knots ............ Alg. 1 sampling step + eq. vel-clamp
   forward_dynamics ........ articulated-body algorithm (the simulator's dynamics)
   rollout ................. Alg. 1 simulate step with the Sec. IV-A costs
+  forced_steps ............ one control step of that simulate step from given states
   weights ................. eq. omega-weights / eq. softmax_minmax
   weighted_average ........ eq. update-nominal carried to the knots
   step .................... Alg. 1 inner loop with Sec. III-D best tracking
@@ -87,6 +88,8 @@ def lib():
         _lib.orc_rk4.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, _dp]
         _lib.orc_dense_route_update.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                                                 _dp, _dp, _dp]
+        _lib.orc_forced_steps.argtypes = [C.c_void_p, C.c_void_p, _dp, C.c_int, _dp, _dp, _dp, _dp, _up,
+                                          _dp, _dp, C.c_int, C.c_int]
     return _lib
 
 
@@ -396,6 +399,37 @@ def rollout(model, params, x0, knots, debug=False):
     _check(lib().orc_rollout(C.c_void_p(M.ptr), C.c_void_p(P.ptr), xp, kp, C.byref(S), None, None,
                              None), "rollout")
     return S.value
+
+
+def forced_steps(model, params, x0, knots, traj, f32=False, threads=None):
+    """Trajectory-forced steps of the Alg. 1 simulate step: for rollout r (knots
+    [n, E], every rollout starting from x0) and each control step h < H, one
+    control step from the GIVEN state traj[r, h] (traj [n, H+1, nq+nv]).
+    Returns a dict of
+      qdd   [n, H, nv]      accelerations of the step's first physics substep
+      cost  [n, H+1]        running cost of step h; cost[:, H] = terminal cost at traj[:, H]
+      masks [n, H]          contact-activity mask (bit c: f_n > 0 at point c)
+      fn    [n, H, nc]      normal force of every contact point
+      next  [n, H, nq+nv]   the state the step reaches
+    f32=True evaluates in float (rounding reference only)."""
+    M = _Model(model); P = _Params(params, M.nu, M.nc)
+    H = int(params["horizon"])
+    kn = np.ascontiguousarray(knots, dtype=np.float64)
+    tr = np.ascontiguousarray(traj, dtype=np.float64)
+    n = kn.shape[0]
+    nx = M.nq + M.nv
+    if kn.shape != (n, 2 * params["n_knots"] * M.nu) or tr.shape != (n, H + 1, nx):
+        raise ValueError("knots must be [n, E] and traj [n, H+1, nq+nv]")
+    xa, xp = _d(x0)
+    out = {"qdd": np.zeros((n, H, M.nv)), "cost": np.zeros((n, H + 1)), "masks": np.zeros((n, H), np.uint32),
+           "next": np.zeros((n, H, nx)), "fn": np.zeros((n, H, max(M.nc, 1)))}
+    th = threads or os.cpu_count() or 1
+    _check(lib().orc_forced_steps(M.ptr, P.ptr, xp, n, kn.ctypes.data_as(_dp), tr.ctypes.data_as(_dp),
+                                  out["qdd"].ctypes.data_as(_dp), out["cost"].ctypes.data_as(_dp),
+                                  out["masks"].ctypes.data_as(_up), out["next"].ctypes.data_as(_dp),
+                                  out["fn"].ctypes.data_as(_dp), int(bool(f32)), th), "forced_steps")
+    out["fn"] = out["fn"][:, :, :M.nc]
+    return out
 
 
 def rollout_f32(model, params, x0, knots):

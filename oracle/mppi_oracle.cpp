@@ -900,37 +900,37 @@ static void integrate(const Model<T>& M, T dt, T* q, T* v, const std::vector<T>&
   }
 }
 
+// One control step h of a rollout, advancing (q, v) in place: n_sub physics
+// substeps of dt / n_sub (linearly implicit Euler: ABA with the implicit PD and
+// contact terms, then v += dt qdd, q += dt v), the PD law tracking the spline at
+// every substep time.  Returns the running cost of the step, taken on the state,
+// the clipped PD torques and the contact forces of its first substep.  Optional
+// outputs of that first substep: the contact-activity mask, the accelerations
+// qdd0 [nv] and the normal force of every contact point fn0 [nc].
 template <class T>
-static T rollout(const Model<T>& M, const orc_params* p, const T* x0, const T* knots, RolloutDebug<T> dbg) {
-  // Physics runs n_sub substeps of dt / n_sub per control step (linearly
-  // implicit Euler: ABA with the implicit PD and contact terms, then
-  // v += dt qdd, q += dt v).  The PD law tracks the spline evaluated at every
-  // substep time; the running cost is taken once per control step, on the
-  // state, the clipped PD torques and the contact forces of its first substep.
-  const int H = p->horizon, K = p->n_knots, nu = M.nu, nq = M.nq, nv = M.nv, ns = M.nsub;
+static T control_step(const Model<T>& M, const orc_params* p, const T* knots, int h, T* q, T* v,
+                      uint32_t* mask = nullptr, T* qdd0 = nullptr, T* fn0 = nullptr) {
+  const int H = p->horizon, K = p->n_knots, nu = M.nu, ns = M.nsub;
   const int F = H * ns;
   const T dtf = (T)(p->dt / ns), delta = (T)(p->horizon * p->dt / (K - 1));
   const int qo = M.fb ? 7 : 0;
-  std::vector<T> q(x0, x0 + nq), v(x0 + nq, x0 + nq + nv), tau(nu), qref(nu), vref(nu);
-  T S = 0;
+  std::vector<T> tau(nu), qref(nu), vref(nu);
   std::vector<V6<T>> fext;
   std::vector<M6<T>> Iadd;
-  for (int f = 0; f < F; ++f) {
-    const int h = f / ns;
-    const bool control = (f % ns) == 0;
-    if (dbg.traj && control)
-      for (int k = 0; k < nq + nv; ++k) dbg.traj[h * (nq + nv) + k] = k < nq ? q[k] : v[k - nq];
+  T c = 0;
+  for (int sub = 0; sub < ns; ++sub) {
+    const int f = h * ns + sub;
+    const bool control = sub == 0;
     for (int j = 0; j < nu; ++j) {
       hermite_eval(knots, K, nu, F, delta, f, j, &qref[j], &vref[j]);
       if (p->spline_mode != 0) vref[j] = 0;  // position-only variants: zero velocity targets
     }
-    PDOut<T> pd = pd_law(M, q.data(), v.data(), qref.data(), vref.data(), dtf);
+    PDOut<T> pd = pd_law(M, q, v, qref.data(), vref.data(), dtf);
     tau = pd.tau;
-    Kin<T> Kn = kinematics(M, q.data(), v.data());
+    Kin<T> Kn = kinematics(M, q, v);
     ContactOut<T> C = contacts(M, Kn, fext, dtf, &Iadd);
     std::vector<T> qdd = aba(M, Kn, tau.data(), fext, &Iadd, pd.g.data());
     if (control) {
-      T c = 0;
       T eff = 0;
       for (int j = 0; j < nu; ++j) eff += tau[j] * tau[j];
       if (p->cost_kind == 0) {
@@ -938,7 +938,7 @@ static T rollout(const Model<T>& M, const orc_params* p, const T* x0, const T* k
         T dz = ee[2] - (T)p->z_des;
         c = (T)p->w_ee * dz * dz + (T)p->w_tau * eff;
       } else {
-        T phi = orientation_error(q.data() + 3, p->q_des);
+        T phi = orientation_error(q + 3, p->q_des);
         T dq2 = 0;
         for (int j = 0; j < nu; ++j) {
           T e = q[qo + j] - (T)p->q0_cost[j];
@@ -952,17 +952,24 @@ static T rollout(const Model<T>& M, const orc_params* p, const T* x0, const T* k
         c = (T)p->w_h * std::fabs(q[2] - (T)p->z_des) + (T)p->w_or * phi * phi + (T)p->w_q * dq2 +
             (T)p->w_cv * cv + (T)p->w_cf * cf + (T)p->w_eff * eff;
       }
-      if (dbg.masks) dbg.masks[h] = C.mask;
-      if (dbg.stage) dbg.stage[h] = c;
-      S += c;
+      if (mask) *mask = C.mask;
+      if (qdd0) std::copy(qdd.begin(), qdd.end(), qdd0);
+      if (fn0)
+        for (int ci = 0; ci < M.nc; ++ci) fn0[ci] = C.force[ci][2];
     }
-    integrate(M, dtf, q.data(), v.data(), qdd);
+    integrate(M, dtf, q, v, qdd);
   }
-  if (dbg.traj)
-    for (int k = 0; k < nq + nv; ++k) dbg.traj[H * (nq + nv) + k] = k < nq ? q[k] : v[k - nq];
+  return c;
+}
+
+// Terminal cost on x_H (Sec. IV-A): the L1 distance of the base position to
+// p(x0) + v_des H dt (its height z_terminal instead when terminal_z_abs), or
+// for the end-effector task w_ee (z_ee - z_des)^2.
+template <class T>
+static T terminal_cost(const Model<T>& M, const orc_params* p, const T* x0, const T* q, const T* v) {
   T cT = 0;
   if (p->cost_kind == 0) {
-    Kin<T> Kn = kinematics(M, q.data(), v.data());
+    Kin<T> Kn = kinematics(M, q, v);
     V3<T> ee = point_world(Kn, M.ee_body, M.ee_pos);
     T dz = ee[2] - (T)p->z_des;
     cT = (T)p->w_ee * dz * dz;
@@ -974,6 +981,29 @@ static T rollout(const Model<T>& M, const orc_params* p, const T* x0, const T* k
     }
     cT *= (T)p->w_H;
   }
+  return cT;
+}
+
+// One rollout (Alg. 1 simulate step): H control steps from x0, the running
+// costs summed as they come (no dt factor), then the terminal cost; a
+// non-finite total becomes +inf.
+template <class T>
+static T rollout(const Model<T>& M, const orc_params* p, const T* x0, const T* knots, RolloutDebug<T> dbg) {
+  const int H = p->horizon, nq = M.nq, nv = M.nv;
+  std::vector<T> q(x0, x0 + nq), v(x0 + nq, x0 + nq + nv);
+  T S = 0;
+  for (int h = 0; h < H; ++h) {
+    if (dbg.traj)
+      for (int k = 0; k < nq + nv; ++k) dbg.traj[h * (nq + nv) + k] = k < nq ? q[k] : v[k - nq];
+    uint32_t mk = 0;
+    const T c = control_step(M, p, knots, h, q.data(), v.data(), &mk);
+    if (dbg.masks) dbg.masks[h] = mk;
+    if (dbg.stage) dbg.stage[h] = c;
+    S += c;
+  }
+  if (dbg.traj)
+    for (int k = 0; k < nq + nv; ++k) dbg.traj[H * (nq + nv) + k] = k < nq ? q[k] : v[k - nq];
+  const T cT = terminal_cost(M, p, x0, q.data(), v.data());
   if (dbg.stage) dbg.stage[H] = cT;
   S += cT;
   if (!std::isfinite((double)S)) S = std::numeric_limits<T>::infinity();
@@ -1378,6 +1408,67 @@ int orc_rollout_f32_traj(const orc_model* m, const orc_params* p, const double* 
   std::vector<float> x(x0, x0 + nx), th(knots, knots + E), tr((size_t)(p->horizon + 1) * nx);
   (void)rollout<float>(M, p, x.data(), th.data(), RolloutDebug<float>{tr.data(), nullptr, nullptr});
   for (size_t i = 0; i < tr.size(); ++i) traj[i] = (double)tr[i];
+  return 0;
+}
+
+}  // extern "C"
+
+// Trajectory-forced steps (see orc_forced_steps), in T.
+template <class T>
+static void forced_steps(const Model<T>& M, const orc_params* p, const double* x0d, int n, const double* knots,
+                         const double* traj, double* qdd, double* cost, uint32_t* masks, double* next, double* fn,
+                         int threads) {
+  const int H = p->horizon, nq = M.nq, nv = M.nv, nx = nq + nv, nc = M.nc, E = 2 * p->n_knots * M.nu;
+  const std::vector<T> x0(x0d, x0d + nx);
+#pragma omp parallel for schedule(dynamic) num_threads(threads)
+  for (int r = 0; r < n; ++r) {
+    const std::vector<T> th(knots + (size_t)r * E, knots + (size_t)(r + 1) * E);
+    std::vector<T> q(nq), v(nv), a(nv), f(std::max(nc, 1));
+    for (int h = 0; h <= H; ++h) {
+      const double* xs = traj + ((size_t)r * (H + 1) + h) * nx;
+      for (int k = 0; k < nq; ++k) q[k] = (T)xs[k];
+      for (int k = 0; k < nv; ++k) v[k] = (T)xs[nq + k];
+      if (h == H) {
+        cost[(size_t)r * (H + 1) + H] = (double)terminal_cost(M, p, x0.data(), q.data(), v.data());
+        break;
+      }
+      uint32_t mk = 0;
+      const T c = control_step(M, p, th.data(), h, q.data(), v.data(), &mk, a.data(), f.data());
+      const size_t rh = (size_t)r * H + h;
+      cost[(size_t)r * (H + 1) + h] = (double)c;
+      if (masks) masks[rh] = mk;
+      if (qdd)
+        for (int k = 0; k < nv; ++k) qdd[rh * nv + k] = (double)a[k];
+      if (next)
+        for (int k = 0; k < nx; ++k) next[rh * nx + k] = (double)(k < nq ? q[k] : v[k - nq]);
+      if (fn)
+        for (int k = 0; k < nc; ++k) fn[rh * nc + k] = (double)f[k];
+    }
+  }
+}
+
+extern "C" {
+
+// Trajectory-forced rollout steps: for rollout r of n (knots [n][E], all from
+// the initial state x0 [nq+nv]) and each control step h < H, one control step
+// of the rollout from the given state traj[r][h] (traj [n][H+1][nq+nv], e.g.
+// states recorded by another implementation): the accelerations of its first
+// substep qdd [n][H][nv], its running cost cost[n][H+1], its contact mask
+// masks [n][H], the normal force of every contact point fn [n][H][nc] and the
+// state it reaches next [n][H][nq+nv]; cost[r][H] = the terminal cost at
+// traj[r][H].  f32 != 0 evaluates in float.  Outputs other than cost are nullable.
+int orc_forced_steps(const orc_model* m, const orc_params* p, const double* x0, int n, const double* knots,
+                     const double* traj, double* qdd, double* cost, uint32_t* masks, double* next, double* fn,
+                     int f32, int threads) {
+  if (!model_ok(m) || !params_ok(m, p) || n < 0 || !cost) return -1;
+  threads = threads < 1 ? 1 : threads;
+  if (f32) {
+    Model<float> M = load_model<float>(m);
+    forced_steps<float>(M, p, x0, n, knots, traj, qdd, cost, masks, next, fn, threads);
+  } else {
+    Model<double> M = load_model<double>(m);
+    forced_steps<double>(M, p, x0, n, knots, traj, qdd, cost, masks, next, fn, threads);
+  }
   return 0;
 }
 

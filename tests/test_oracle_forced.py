@@ -1,0 +1,54 @@
+"""The oracle's trajectory-forced steps (one control step of the Alg. 1 simulate
+step from a given state), which the GPU's per-step parity checks use: fed the
+oracle's own trajectory they reproduce it, its stage costs and masks exactly,
+and their accelerations equal the separately exposed step dynamics at that
+state with the Hermite reference of that step."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2511_19204_amd import synth
+
+
+@pytest.mark.parametrize("kind", ["chain", "quadruped", "humanoid"])
+def test_forced_steps_reproduce_the_rollout(kind):
+    m, p, seed = synth.config(kind, n_samples=4)
+    p = dict(p)
+    p["horizon"] = 30
+    H, K, nu = p["horizon"], p["n_knots"], m["n_u"]
+    kn = synth.nominal_knots(m, K)
+    samples = np.stack([O.sample_knots(m, p, kn, seed, 0, 0, n) for n in range(3)])
+    trajs, stages, masks = [], [], []
+    for s in samples:
+        S, traj, mk, st = O.rollout(m, p, m["x0"], s, debug=True)
+        trajs.append(traj); stages.append(st); masks.append(mk)
+    trajs = np.stack(trajs)
+    out = O.forced_steps(m, p, m["x0"], samples, trajs)
+    assert np.array_equal(out["next"], trajs[:, 1:])
+    assert np.array_equal(out["cost"], np.stack(stages))
+    assert np.array_equal(out["masks"], np.stack(masks))
+    nq = m["n_q"]
+    for r in range(3):
+        for h in (0, 7, H - 1):
+            qr = np.zeros(nu); vr = np.zeros(nu)
+            for j in range(nu):
+                qr[j], vr[j] = O.hermite(samples[r], K, nu, H, p["dt"], h, j)
+            x = trajs[r, h]
+            qdd, _, _, cf = O.step_dynamics(m, x[:nq], x[nq:], qr, vr, p["dt"])
+            assert np.allclose(out["qdd"][r, h], qdd, rtol=0, atol=1e-9 * max(1.0, np.abs(qdd).max()))
+            if m["contact_body"].size:
+                assert np.allclose(out["fn"][r, h], cf[:, 2], rtol=0, atol=1e-9)
+
+
+def test_forced_steps_float_evaluation_is_close_to_fp64():
+    m, p, seed = synth.config("quadruped", n_samples=4)
+    p = dict(p)
+    p["horizon"] = 20
+    kn = synth.nominal_knots(m, p["n_knots"])
+    s = O.sample_knots(m, p, kn, seed, 0, 0, 1)[None]
+    _, traj, _, _ = O.rollout(m, p, m["x0"], s[0], debug=True)
+    a = O.forced_steps(m, p, m["x0"], s, traj[None])
+    b = O.forced_steps(m, p, m["x0"], s, traj[None], f32=True)
+    scale = np.maximum(1.0, np.abs(a["qdd"]).max(axis=2, keepdims=True))
+    assert np.max(np.abs(a["qdd"] - b["qdd"]) / scale) < 1e-3
+    assert not np.array_equal(a["qdd"], b["qdd"])
