@@ -373,6 +373,21 @@ mppi_status mppi_debug_dynamics(const mppi_model* m, int32_t n, const float* d_q
 mppi_status mppi_debug_rollouts(mppi_ctx* c, const float* d_state, const float* d_samples, float* d_costs,
                                 uint32_t* d_masks, void* stream);
 
+/* Step-by-step record of iteration `iter` of mppi_step at noise tick `tick`,
+ * from d_state and the nominal d_knots_in, with mppi_step's own rollout kernel
+ * and launch shape (the simulate step of Alg. 1 with the Sec. IV-A costs):
+ *   d_trace_map [N] device int32, record slot of sample n or -1 (not recorded)
+ *   d_trace     [slots][H + 1][nq + 2 nv + 2] device float: record h < H holds
+ *               the state (q, v) at the start of control step h, the
+ *               accelerations of its first physics substep (nv), its running
+ *               cost and its contact mask (uint32 bits); record H holds the
+ *               final state, zero accelerations, the terminal cost and 0
+ *   d_samples   [N][2][K][n_u], d_costs [N], d_masks [N][H] device outputs
+ * Body schedule only (MPPI_EINVAL otherwise).  Blocks until done. */
+mppi_status mppi_debug_trace(mppi_ctx* c, const float* d_state, const float* d_knots_in, int32_t iter, uint32_t tick,
+                             const int32_t* d_trace_map, float* d_trace, float* d_samples, float* d_costs,
+                             uint32_t* d_masks, void* stream);
+
 /* Weights and update from given costs d_costs [N] and samples d_samples
  * [N][2][K][n_u]: d_knots_out = sum_n w_n sample_n (unchanged d_knots_in if no
  * cost is finite), d_weights [N] (nullable). */

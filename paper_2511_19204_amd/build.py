@@ -47,6 +47,8 @@ def resource_usage(remarks: str) -> dict:
 def check_resources(usage: dict) -> None:
     bad = []
     for name, u in usage.items():
+        if "rollout_trace_kernel" in name:
+            continue  # verification kernel: its per-step record stores may spill
         if u.get("ScratchSize", 0) != 0:
             bad.append(f"{name}: {u['ScratchSize']} bytes/lane of scratch (register spills)")
         if "rollout_kernel" in name and "persistent" not in name and u.get("Occupancy", 0) < 2:

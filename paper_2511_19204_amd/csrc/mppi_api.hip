@@ -30,6 +30,7 @@ namespace mppi {
 // kernels (mppi_kernels.hip)
 template <int G, int D>
 __global__ void rollout_kernel(const DevInst*, const int2*, int, int, const float*, const float*);
+template <int G, int D> __global__ void rollout_trace_kernel(const DevInst*, const int2*, int, int);
 template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
 template <int G, int D> __global__ void team_kernel(const DevInst*, const int2*, int, int);
@@ -1440,6 +1441,58 @@ extern "C" mppi_status mppi_debug_rollouts(mppi_ctx* c, const float* d_state, co
   if (st != MPPI_OK) return st;
   const int R = rollouts_per_block(c->lanes, dims_of(c));
   HIP_TRY(launch_rollout(c->lanes, (c->N + R - 1) / R, d, nullptr, dims_of(c), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipFree(d));
+  return MPPI_OK;
+}
+
+// The traced twin of launch_rollout for one instance of the body schedule: the
+// same grid, block, LDS layout and depth specialisation as mppi_step's launch.
+template <int G>
+static hipError_t launch_trace_G(const DevInst* inst, int N, const LaunchShape& sh, int depth, hipStream_t s) {
+  const int blocks = (N + sh.groups - 1) / sh.groups;
+  if (depth <= 3)
+    hipLaunchKernelGGL((rollout_trace_kernel<G, 3>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
+  else if (depth <= 6)
+    hipLaunchKernelGGL((rollout_trace_kernel<G, 6>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
+  else
+    hipLaunchKernelGGL((rollout_trace_kernel<G, 0>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
+  return hipGetLastError();
+}
+static hipError_t launch_trace(int key, const DevInst* inst, int N, const Dims& dm, hipStream_t s) {
+  const LaunchShape sh = launch_shape(key, dm);
+  switch (key) {
+    case 4: return launch_trace_G<4>(inst, N, sh, dm.depth, s);
+    case 8: return launch_trace_G<8>(inst, N, sh, dm.depth, s);
+    case 16: return launch_trace_G<16>(inst, N, sh, dm.depth, s);
+    case 32: return launch_trace_G<32>(inst, N, sh, dm.depth, s);
+    case 64: return launch_trace_G<64>(inst, N, sh, dm.depth, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+extern "C" mppi_status mppi_debug_trace(mppi_ctx* c, const float* d_state, const float* d_knots_in, int32_t iter,
+                                        uint32_t tick, const int32_t* d_trace_map, float* d_trace, float* d_samples,
+                                        float* d_costs, uint32_t* d_masks, void* stream) {
+  if (!c || !d_state || !d_knots_in || !d_trace_map || !d_trace || !d_samples || !d_costs || !d_masks)
+    return fail(MPPI_EINVAL, "null argument");
+  if (iter < 0 || iter >= c->I) return fail(MPPI_EINVAL, "iter must be in 0..n_iters-1");
+  if (!(c->lanes > 0 && c->lanes < kTeamKey)) return fail(MPPI_EINVAL, "tracing needs the body schedule");
+  hipStream_t s = (hipStream_t)stream;
+  DevInst h = c->h_insts[iter];
+  h.x0 = d_state;
+  h.nominal = d_knots_in;
+  h.samples = d_samples;
+  h.costs = d_costs;
+  h.masks = d_masks;
+  h.use_tick_value = 1;
+  h.tick_value = tick;
+  h.trace = d_trace;
+  h.trace_map = d_trace_map;
+  DevInst* d = nullptr;
+  mppi_status st = debug_inst(h, s, &d);
+  if (st != MPPI_OK) return st;
+  HIP_TRY(launch_trace(c->lanes, d, c->N, dims_of(c), s));
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipFree(d));
   return MPPI_OK;

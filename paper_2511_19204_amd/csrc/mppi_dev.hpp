@@ -113,6 +113,10 @@ struct DevInst {
   int32_t or_target;     // 0: identity target (the orientation term uses q_base directly)
   int32_t terminal_z_abs;  // 1: terminal target height z_terminal
   float z_terminal;
+  // verification only (read when masks is set): per-step records of the
+  // rollouts with trace_map[n] >= 0, see trace_record
+  float* trace;              // [traced][H + 1][nq + 2 nv + 2], or null
+  const int32_t* trace_map;  // [N] record slot of sample n, or -1
 };
 
 // Per-instance state of the weighting/update stage.

@@ -1237,8 +1237,41 @@ __device__ __forceinline__ void integrate_base(float* bq, float* bv, const float
 // steps control steps are simulated (the horizon for a rollout).  With state_out
 // set (state prediction, one sample) the state reached is written there and
 // no cost is formed.
-template <int G, int D = 0>
+// Per-step record of a traced rollout (verification of the simulate step of
+// Alg. 1, step by step): record h < H holds the state (q, v) at the start of
+// control step h, the accelerations of its first physics substep, its running
+// cost and its contact mask (bits); record H the final state, zero
+// accelerations, the terminal cost and 0.  Layout [q | v | qdd | cost | mask].
+template <int G>
+__device__ __forceinline__ void trace_record(const DevInst& I, int n, bool valid, int h, int fb, int nq, int nv,
+                                             bool is_joint, int j, int b, int l, const StepIO& io, bool with_acc,
+                                             float cost, uint32_t mk) {
+  if (!valid) return;
+  const int slot = I.trace_map[n];
+  if (slot < 0) return;
+  const int rec = nq + 2 * nv + 2;
+  float* r = I.trace + ((size_t)slot * (I.H + 1) + h) * rec;
+  if (is_joint) {
+    r[(fb ? 7 : 0) + j] = io.q;
+    r[nq + (fb ? 6 : 0) + j] = io.v;
+    r[nq + nv + (fb ? 6 : 0) + j] = with_acc ? io.qdd : 0.f;
+  }
+  if (fb && b == 0) {
+    for (int k = 0; k < 7; ++k) r[k] = io.bq[k];
+    for (int k = 0; k < 6; ++k) {
+      r[nq + k] = io.bv[k];
+      r[nq + nv + k] = with_acc ? io.ba[k] : 0.f;
+    }
+  }
+  if (l == 0) {
+    r[nq + 2 * nv] = cost;
+    r[nq + 2 * nv + 1] = __uint_as_float(mk);
+  }
+}
+
 // x0_in / nominal_in (nullable) replace the instance's staged state and nominal.
+// TR: also write the per-step records of traced rollouts (verification kernel).
+template <int G, int D = 0, bool TR = false>
 __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride,
                                                             int table_floats, float* smem, int steps,
                                                             float* state_out, const float* x0_in = nullptr,
@@ -1311,6 +1344,10 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
       if (masks) {
         const uint32_t mk = group_or<G>(io.mask, red, l);
         if (l == 0 && valid) masks[(size_t)n * H + clk.h] = mk;
+        if (TR && I.trace) {
+          const float c = group_sum<G>(io.cost, red, l);
+          trace_record<G>(I, n, valid, clk.h, fb, nq, nq - fb, is_joint, j, b, l, io, true, c, mk);
+        }
       }
     }
     // joints (other lanes hold q = qd = qdd = 0)
@@ -1336,6 +1373,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   }
 
   // terminal cost
+  float term_e = 0.f;
   if (sc.cost_kind == 1) {
     if (fb && b == 0) {
       const float T = (float)H * I.dt;
@@ -1346,11 +1384,16 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
         e += fabsf(io.bq[k] - target);
       }
       acc += I.w_H * e;
+      term_e = e;
     }
   } else {
     // end-effector height at x_H
     physics_step<G, D>(sc, bc, tab, gs, b, body_lane, io, false, true);
     acc += io.cost;
+  }
+  if (TR && masks && I.trace) {
+    const float ct = group_sum<G>(sc.cost_kind == 1 ? I.w_H * term_e : io.cost, red, l);
+    trace_record<G>(I, n, valid, H, fb, nq, nq - fb, is_joint, j, b, l, io, false, ct, 0u);
   }
   float S = group_sum<G>(acc, red, l);
   if (l == 0 && valid) {
@@ -1374,6 +1417,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ro
   const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
   const DevInst& I = insts[w.x];
   rollout_item<G, D>(I, w.y, group_stride, table_floats, smem, I.H, nullptr, x0_in, nominal_in);
+}
+
+// The rollout kernel with per-step records of the traced rollouts (same launch
+// shape and arithmetic; verification only).
+template <int G, int D>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_trace_kernel(
+    const DevInst* __restrict__ insts, const int2* __restrict__ work, int group_stride, int table_floats) {
+  extern __shared__ float smem[];
+  constexpr int R = 64 / G;
+  const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
+  const DevInst& I = insts[w.x];
+  rollout_item<G, D, true>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
 }
 
 // State prediction: sample 0 of the instance (its knots read from samples) run
@@ -2922,6 +2977,9 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
                                                 const float*);                                            \
   template __global__ void rollout_kernel<G, 6>(const DevInst*, const int2*, int, int, const float*,         \
                                                 const float*);                                            \
+  template __global__ void rollout_trace_kernel<G, 0>(const DevInst*, const int2*, int, int);            \
+  template __global__ void rollout_trace_kernel<G, 3>(const DevInst*, const int2*, int, int);            \
+  template __global__ void rollout_trace_kernel<G, 6>(const DevInst*, const int2*, int, int);            \
   template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int); \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \

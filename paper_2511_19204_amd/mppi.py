@@ -71,7 +71,7 @@ EXPORTS = [
     "mppi_get_tick", "mppi_set_schedule", "mppi_get_schedule", "mppi_set_lanes_per_rollout",
     "mppi_get_lanes_per_rollout", "mppi_set_targets", "mppi_step", "mppi_predict", "mppi_shift_knots", "mppi_tick",
     "mppi_step_batch", "mppi_debug_philox", "mppi_debug_samples", "mppi_debug_dynamics",
-    "mppi_debug_rollouts", "mppi_debug_update", "mppi_profile_enable", "mppi_profile_read",
+    "mppi_debug_rollouts", "mppi_debug_trace", "mppi_debug_update", "mppi_profile_enable", "mppi_profile_read",
     "mppi_set_batch_options", "mppi_graph_create", "mppi_graph_launch", "mppi_graph_destroy",
     "mppi_autotune", "mppi_server_create", "mppi_server_submit", "mppi_server_submit_tick", "mppi_server_poll",
     "mppi_server_drain", "mppi_server_stats", "mppi_server_destroy",
@@ -115,6 +115,7 @@ def lib():
         L.mppi_debug_samples.argtypes = [vp, vp, i32, u32, vp, vp]
         L.mppi_debug_dynamics.argtypes = [vp, i32, vp, vp, vp, vp, C.c_float, vp, vp]
         L.mppi_debug_rollouts.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mppi_debug_trace.argtypes = [vp, vp, vp, i32, u32, vp, vp, vp, vp, vp, vp]
         L.mppi_debug_update.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.mppi_profile_enable.argtypes = [vp, i32]
         L.mppi_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i32),
@@ -375,6 +376,13 @@ class Controller:
     def rollouts(self, state, samples, costs, masks=None, stream=None):
         _check(lib().mppi_debug_rollouts(self.h, _ptr(state), _ptr(samples), _ptr(costs),
                                          _ptr(masks), _stream(stream)), "mppi_debug_rollouts")
+
+    def trace(self, state, knots_in, iteration, tick, trace_map, trace, samples, costs, masks, stream=None):
+        """mppi_debug_trace: iteration `iteration` of a step at `tick`, with per-step
+        records [slots][H+1][nq + 2 nv + 2] of the samples whose trace_map entry >= 0."""
+        _check(lib().mppi_debug_trace(self.h, _ptr(state), _ptr(knots_in), int(iteration), C.c_uint32(tick),
+                                      _ptr(trace_map), _ptr(trace), _ptr(samples), _ptr(costs), _ptr(masks),
+                                      _stream(stream)), "mppi_debug_trace")
 
     def update(self, costs, samples, knots_in, knots_out, weights=None, stream=None):
         _check(lib().mppi_debug_update(self.h, _ptr(costs), _ptr(samples), _ptr(knots_in),
