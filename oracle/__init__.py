@@ -88,6 +88,7 @@ def lib():
         _lib.orc_rk4.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, _dp]
         _lib.orc_dense_route_update.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                                                 _dp, _dp, _dp]
+        _lib.orc_integrate_batch.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, _dp]
         _lib.orc_forced_steps.argtypes = [C.c_void_p, C.c_void_p, _dp, C.c_int, _dp, _dp, _dp, _dp, _up,
                                           _dp, _dp, C.c_int, C.c_int]
     return _lib
@@ -429,6 +430,19 @@ def forced_steps(model, params, x0, knots, traj, f32=False, threads=None):
                                   out["masks"].ctypes.data_as(_up), out["next"].ctypes.data_as(_dp),
                                   out["fn"].ctypes.data_as(_dp), int(bool(f32)), th), "forced_steps")
     out["fn"] = out["fn"][:, :, :M.nc]
+    return out
+
+
+def integrate(model, dt, X, A):
+    """The rollout's integration step alone: states X [n, nq+nv] advanced by dt
+    with accelerations A [n, nv] (joints and base twist: v += dt a; joints
+    q += dt v; base p += dt R v_lin, quaternion times exp(dt w / 2))."""
+    M = _Model(model)
+    Xa = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, M.nq + M.nv)
+    Aa = np.ascontiguousarray(A, dtype=np.float64).reshape(-1, M.nv)
+    out = np.zeros_like(Xa)
+    _check(lib().orc_integrate_batch(M.ptr, float(dt), Xa.shape[0], Xa.ctypes.data_as(_dp), Aa.ctypes.data_as(_dp),
+                                     out.ctypes.data_as(_dp)), "integrate")
     return out
 
 

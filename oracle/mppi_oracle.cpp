@@ -1472,6 +1472,23 @@ int orc_forced_steps(const orc_model* m, const orc_params* p, const double* x0, 
   return 0;
 }
 
+// The integration step of a rollout alone (semi-implicit Euler with the base
+// quaternion advanced by the exponential of the body angular velocity) for n
+// states X [n][nq+nv] and accelerations A [n][nv], step dt: out [n][nq+nv].
+int orc_integrate_batch(const orc_model* m, double dt, int n, const double* X, const double* A, double* out) {
+  if (!model_ok(m) || n < 0 || !(dt >= 0)) return -1;
+  Model<double> M = load_model<double>(m);
+  const int nq = M.nq, nv = M.nv, nx = nq + nv;
+  std::vector<double> qdd(nv);
+  for (int r = 0; r < n; ++r) {
+    double* q = out + (size_t)r * nx;
+    std::copy(X + (size_t)r * nx, X + (size_t)(r + 1) * nx, q);
+    std::copy(A + (size_t)r * nv, A + (size_t)(r + 1) * nv, qdd.begin());
+    integrate(M, dt, q, q + nq, qdd);
+  }
+  return 0;
+}
+
 // Samples n0 .. n0+count-1 of iteration iota: knots generated from the
 // counter-based stream and rolled out (OpenMP over samples).  Used for sampled
 // parity at full problem sizes and for the CPU baseline timing.

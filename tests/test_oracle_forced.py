@@ -52,3 +52,37 @@ def test_forced_steps_float_evaluation_is_close_to_fp64():
     scale = np.maximum(1.0, np.abs(a["qdd"]).max(axis=2, keepdims=True))
     assert np.max(np.abs(a["qdd"] - b["qdd"]) / scale) < 1e-3
     assert not np.array_equal(a["qdd"], b["qdd"])
+
+
+@pytest.mark.parametrize("kind", ["chain", "quadruped"])
+def test_integrate_alone_reproduces_the_step(kind):
+    """The integration step applied to the step's own accelerations gives the
+    next state of the rollout bit for bit (one physics substep per control step)."""
+    m, p, seed = synth.config(kind, n_samples=4)
+    p = dict(p)
+    p["horizon"] = 12
+    kn = synth.nominal_knots(m, p["n_knots"])
+    s = O.sample_knots(m, p, kn, seed, 0, 0, 2)
+    _, traj, _, _ = O.rollout(m, p, m["x0"], s, debug=True)
+    out = O.forced_steps(m, p, m["x0"], s[None], traj[None])
+    nxt = O.integrate(m, p["dt"], traj[:-1], out["qdd"][0])
+    assert np.array_equal(nxt, traj[1:])
+
+
+def test_integrate_free_flight_closed_form():
+    """Zero acceleration: joints and base position move by dt v (base linear
+    velocity rotated to the world); a base spinning about z at rate w turns its
+    quaternion by dt w."""
+    m, p, seed = synth.config("quadruped", n_samples=4)
+    nq, nv = m["n_q"], m["n_v"]
+    x = np.array(m["x0"], float)
+    x[nq + 2] = 1.5                 # yaw rate
+    x[nq + 3:nq + 6] = [0.2, -0.1, 0.3]
+    x[nq + 6:] = np.linspace(-1, 1, m["n_u"])
+    dt = 0.01
+    out = O.integrate(m, dt, x[None], np.zeros((1, nv)))[0]
+    assert np.allclose(out[7:nq], x[7:nq] + dt * x[nq + 6:], rtol=0, atol=1e-15)
+    assert np.allclose(out[:3], x[:3] + dt * x[nq + 3:nq + 6], rtol=0, atol=1e-15)  # identity orientation
+    half = 0.5 * 1.5 * dt
+    assert np.allclose(out[3:7], [np.cos(half), 0, 0, np.sin(half)], rtol=0, atol=1e-15)
+    assert np.array_equal(out[nq:], x[nq:])
