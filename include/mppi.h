@@ -394,6 +394,30 @@ mppi_status mppi_debug_trace(mppi_ctx* c, const float* d_state, const float* d_k
 mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, const float* d_samples,
                               const float* d_knots_in, float* d_knots_out, float* d_weights, void* stream);
 
+/* ---- Without allocation -------------------------------------------------- */
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the weights
+ * and weighted knot update of mppi_debug_update, with the instance's settings
+ * passed directly instead of a context, and the update's scratch (per-slice
+ * weighted sums, the finished-slice counter, a running-best record) in a fixed
+ * device array of the library instead of per-context buffers.
+ *   n_samples    N, 1..65536; n_elems E = 2 K n_u, 1..8192
+ *   lambda > 0, weight_mode 0 (min-max normalised) or 1 (raw), as in mppi_params
+ *   d_costs [N], d_samples [N][E] (16-byte aligned when E is a multiple of 4),
+ *   d_knots_in [E]: device inputs; d_knots_out [E] = sum_n w_n sample_n
+ *   (d_knots_in unchanged if no cost is finite), d_weights [N] or NULL
+ * The array holds 64 x 8192 + 8264 floats (about 2.03 MiB) per device that
+ * calls it, kept until the process ends; its address is looked up once per
+ * device.  The call allocates nothing and launches two kernels on the stream
+ * (a counter reset and the update).  Every call on one device shares that
+ * device's array, so calls that overlap on one device race: order them on one
+ * stream (or with events).  Errors: MPPI_EINVAL for sizes beyond the maximum,
+ * null or misaligned pointers; MPPI_EDEVICE. */
+mppi_status mppi_update_noalloc(int32_t n_samples, int32_t n_elems, float lambda, int32_t weight_mode,
+                                const float* d_costs, const float* d_samples, const float* d_knots_in,
+                                float* d_knots_out, float* d_weights, void* stream);
+
 /* ---- Kernel timing ------------------------------------------------------- */
 
 /* When enabled, mppi_step records three HIP events per iteration on its stream:

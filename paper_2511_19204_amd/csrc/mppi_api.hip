@@ -46,6 +46,7 @@ template <int G>
 __global__ void dynamics_kernel(const DevModel*, int, const float*, const float*, const float*, const float*, float,
                                 float*, int, int);
 __global__ void update_kernel(const DevUpdate*, const UpdateOut*, UpdateOut);
+__global__ void update_single_kernel(DevUpdate);
 struct StageItem {
   const float* src;
   float* dst;
@@ -1519,6 +1520,81 @@ extern "C" mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, cons
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipFree(d));
+  return MPPI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the update without allocation: its scratch in a fixed device array
+// ---------------------------------------------------------------------------
+// Layout (floats): [kNaParts][kNaMaxE] per-slice weighted sums, then the
+// running-best record [kNaMaxE + 5], then the finished-slice counter (as bits).
+constexpr int kNaMaxE = 8192;
+constexpr int kNaMaxN = 65536;
+constexpr size_t kNaPartial = (size_t)kUpdMaxParts * kNaMaxE;
+constexpr size_t kNaBest = kNaPartial;
+constexpr size_t kNaCounter = kNaBest + kNaMaxE + 8;
+constexpr size_t kNaFloats = kNaCounter + 64;
+static __device__ __align__(256) float scratch[kNaFloats];
+
+// The scratch's device address per device (the array's host-side name is not a
+// device address), looked up once per device with that device current.
+static std::mutex g_na_mu;
+static std::unordered_map<int, float*> g_na_ptr;
+
+static mppi_status noalloc_scratch(float** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  auto it = g_na_ptr.find(dev);
+  if (it != g_na_ptr.end()) {
+    *out = it->second;
+    return MPPI_OK;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(MPPI_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_na_ptr[dev] = static_cast<float*>(ptr);
+  *out = static_cast<float*>(ptr);
+  return MPPI_OK;
+}
+
+extern "C" mppi_status mppi_update_noalloc(int32_t n_samples, int32_t n_elems, float lambda, int32_t weight_mode,
+                                           const float* d_costs, const float* d_samples, const float* d_knots_in,
+                                           float* d_knots_out, float* d_weights, void* stream) {
+  if (!d_costs || !d_samples || !d_knots_in || !d_knots_out) return fail(MPPI_EINVAL, "null argument");
+  if (n_samples < 1 || n_samples > kNaMaxN) return fail(MPPI_EINVAL, "n_samples must be in 1..65536");
+  if (n_elems < 1 || n_elems > kNaMaxE) return fail(MPPI_EINVAL, "n_elems must be in 1..8192");
+  if (!(lambda > 0.f)) return fail(MPPI_EINVAL, "lambda must be positive");
+  if (weight_mode != 0 && weight_mode != 1) return fail(MPPI_EINVAL, "weight_mode must be 0 or 1");
+  if ((n_elems & 3) == 0 && (reinterpret_cast<uintptr_t>(d_samples) & 15) != 0)
+    return fail(MPPI_EINVAL, "d_samples must be 16-byte aligned when n_elems is a multiple of 4");
+  float* base = nullptr;
+  mppi_status st = noalloc_scratch(&base);
+  if (st != MPPI_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  DevUpdate u{};
+  u.costs = d_costs;
+  u.samples = d_samples;
+  u.nominal_in = d_knots_in;
+  u.nominal_out = d_knots_out;
+  u.weights = d_weights;
+  u.best_state = base + kNaBest;
+  u.partial = base;
+  u.done = reinterpret_cast<uint32_t*>(base + kNaCounter);
+  u.N = n_samples;
+  u.E = n_elems;
+  u.weight_mode = weight_mode;
+  u.first_iter = 1;
+  u.parts = update_parts(n_samples);
+  u.lambda = lambda;
+  // the counter is left at zero by every complete launch; cleared here too (a
+  // fill kernel, so the call can be captured in a graph) in case an earlier
+  // launch on this device never finished
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, u.done, 1);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(update_single_kernel, dim3(u.parts), dim3(kUpdThreads), 0, s, u);
+  HIP_TRY(hipGetLastError());
   return MPPI_OK;
 }
 

@@ -2659,9 +2659,9 @@ __device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows
   }
 }
 
-__global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __restrict__ ups,
-                                                             const UpdateOut* __restrict__ outs, UpdateOut single) {
-  const DevUpdate& U = ups[blockIdx.y];
+// The update of one instance by one workgroup (its part blockIdx.x); o: the
+// call's outputs (null fields: not wanted).
+__device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut o) {
   const int part = blockIdx.x, parts = U.parts;
   if (part >= parts) return;
   const int t = threadIdx.x, N = U.N, E = U.E;
@@ -2781,9 +2781,8 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
   if (!s_last) return;
   __threadfence();
   if (t == 0) U.done[0] = 0u;  // ready for the next launch
-  const UpdateOut* o = outs ? outs + blockIdx.y : &single;
-  float* dst = (U.last_iter && o && o->knots_out) ? o->knots_out : U.nominal_out;
-  const float* nom_in = (o && o->nominal_in) ? o->nominal_in : U.nominal_in;
+  float* dst = (U.last_iter && o.knots_out) ? o.knots_out : U.nominal_out;
+  const float* nom_in = o.nominal_in ? o.nominal_in : U.nominal_in;
   // the call's running best starts from its input nominal, taken before the
   // nominal output is written (the two may be the same buffer)
   float* bs = U.best_state;  // [E] knots, then S_best, best_iter, n_nonfinite, all_nonfinite, best_sample
@@ -2825,11 +2824,11 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
     reinterpret_cast<int*>(bs)[E + 3] += nfin == 0 ? 1 : 0;
   }
   __syncthreads();
-  if (U.last_iter && o) {
-    if (o->best_out)
-      for (int e = t; e < E; e += kUpdThreads) o->best_out[e] = bs[e];
-    if (t == 0 && o->info_out) {
-      float* inf = reinterpret_cast<float*>(o->info_out);
+  if (U.last_iter) {
+    if (o.best_out)
+      for (int e = t; e < E; e += kUpdThreads) o.best_out[e] = bs[e];
+    if (t == 0 && o.info_out) {
+      float* inf = reinterpret_cast<float*>(o.info_out);
       inf[0] = bs[E];
       reinterpret_cast<int*>(inf)[1] = reinterpret_cast<int*>(bs)[E + 1];
       reinterpret_cast<int*>(inf)[2] = reinterpret_cast<int*>(bs)[E + 2];
@@ -2838,6 +2837,17 @@ __global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __
     }
   }
   if (U.last_iter && t == 0 && U.tick) U.tick[0] += 1u;
+}
+
+__global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __restrict__ ups,
+                                                             const UpdateOut* __restrict__ outs, UpdateOut single) {
+  update_body(ups[blockIdx.y], outs ? outs[blockIdx.y] : single);
+}
+
+// One instance whose descriptor arrives as a kernel argument (no device copy of
+// it), with no per-call outputs besides the nominal and the weights.
+__global__ __launch_bounds__(kUpdThreads) void update_single_kernel(DevUpdate U) {
+  update_body(U, UpdateOut{nullptr, nullptr, nullptr, nullptr});
 }
 
 // Warm start (Sec. III-E): the knots of a trajectory shifted forward by n_steps

@@ -74,7 +74,7 @@ EXPORTS = [
     "mppi_debug_rollouts", "mppi_debug_trace", "mppi_debug_update", "mppi_profile_enable", "mppi_profile_read",
     "mppi_set_batch_options", "mppi_graph_create", "mppi_graph_launch", "mppi_graph_destroy",
     "mppi_autotune", "mppi_server_create", "mppi_server_submit", "mppi_server_submit_tick", "mppi_server_poll",
-    "mppi_server_drain", "mppi_server_stats", "mppi_server_destroy",
+    "mppi_server_drain", "mppi_server_stats", "mppi_server_destroy", "mppi_update_noalloc",
     "mppi_last_error", "mppi_version",
 ]
 
@@ -132,6 +132,7 @@ def lib():
         L.mppi_server_drain.argtypes = [vp, C.c_double]
         L.mppi_server_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.mppi_server_destroy.argtypes = [vp]
+        L.mppi_update_noalloc.argtypes = [i32, i32, C.c_float, i32, vp, vp, vp, vp, vp, vp]
         L.mppi_last_error.restype = C.c_char_p
         L.mppi_version.restype = C.c_char_p
         for name in EXPORTS[:-2]:
@@ -388,6 +389,15 @@ class Controller:
         _check(lib().mppi_debug_update(self.h, _ptr(costs), _ptr(samples), _ptr(knots_in),
                                        _ptr(knots_out), _ptr(weights), _stream(stream)),
                "mppi_debug_update")
+
+
+def update_noalloc(n_samples, n_elems, lam, weight_mode, costs, samples, knots_in, knots_out, weights=None,
+                   stream=None):
+    """mppi_update_noalloc: weights and weighted knot update with the library's
+    fixed scratch (no device allocation)."""
+    _check(lib().mppi_update_noalloc(int(n_samples), int(n_elems), float(lam), int(weight_mode), _ptr(costs),
+                                     _ptr(samples), _ptr(knots_in), _ptr(knots_out), _ptr(weights),
+                                     _stream(stream)), "mppi_update_noalloc")
 
 
 def step_batch(ctrls, states, knots_in, knots_out, best_knots=None, infos=None, stream=None):

@@ -104,3 +104,20 @@ def test_per_contact_and_per_joint_arrays_must_match_the_model():
     O.rollout(m, dict(p, horizon=2), x0, knots)
     with pytest.raises(ValueError):
         O.rollout(m, dict(short, horizon=2), x0, knots)
+
+
+@pytest.mark.parametrize("n,e,lam,mode,ptr", [
+    (0, 8, 1.0, 0, 256), (65537, 8, 1.0, 0, 256), (8, 0, 1.0, 0, 256), (8, 8193, 1.0, 0, 256),
+    (8, 8, 0.0, 0, 256), (8, 8, 1.0, 2, 256), (8, 8, 1.0, 0, 260),
+])
+def test_noalloc_update_rejects_sizes_beyond_its_scratch(n, e, lam, mode, ptr):
+    """mppi_update_noalloc checks its arguments on the host before any device
+    call: sample and knot counts within its fixed scratch (65536 samples, 8192
+    floats per knot vector), a positive temperature, a known weight mode, and
+    16-byte aligned samples when the rows are read as 128-bit words."""
+    L = mppi.lib()
+    fake = C.c_void_p(256)  # never dereferenced: the call fails on the host first
+    rc = L.mppi_update_noalloc(n, e, lam, mode, fake, C.c_void_p(ptr), fake, fake, None, None)
+    assert rc == -1
+    assert len(L.mppi_last_error()) > 0
+    assert L.mppi_update_noalloc(8, 8, 1.0, 0, None, fake, fake, fake, None, None) == -1
