@@ -64,7 +64,8 @@ class OrcParams(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        # ORACLE_LIB: another build of the same source (the sanitizer build)
+        path = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
         if not os.path.exists(path):
             _build.build()
         _lib = C.CDLL(path)

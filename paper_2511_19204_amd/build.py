@@ -21,6 +21,7 @@ ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("mppi_kernels.hip", "mppi_api.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "mppi_dev.hpp"), os.path.join(ROOT, "include", "mppi.h")]
 LIB = os.path.join(HERE, "libmppi.so")
+LIB_SAN = os.path.join(HERE, "libmppi_san.so")
 ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
@@ -59,13 +60,33 @@ def check_resources(usage: dict) -> None:
         raise RuntimeError("kernel resource check failed:\n" + "\n".join(bad))
 
 
-def build(force: bool = True, verbose: bool = False) -> str:
-    if not force and os.path.exists(LIB):
-        mt = os.path.getmtime(LIB)
+# Host code only (the runtime: validation, tables, batching, the server's worker
+# thread) under AddressSanitizer and UndefinedBehaviorSanitizer; device code is
+# built as in the product library.  Load it with MPPI_LIB and clang's ASan
+# runtime preloaded (sanitizer_runtime()).
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g", "-shared-libsan"]
+
+
+def sanitizer_runtime() -> str:
+    """clang's shared ASan runtime that the host-sanitizer build links against."""
+    res = subprocess.run(["hipcc", "--print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = res.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        rd = subprocess.run(["hipcc", "--print-resource-dir"], capture_output=True, text=True).stdout.strip()
+        path = os.path.join(rd, "lib", "linux", "libclang_rt.asan-x86_64.so")
+    return path
+
+
+def build(force: bool = True, verbose: bool = False, sanitize: bool = False) -> str:
+    lib = LIB_SAN if sanitize else LIB
+    if not force and os.path.exists(lib):
+        mt = os.path.getmtime(lib)
         if all(os.path.getmtime(f) <= mt for f in SOURCES + HEADERS):
-            return LIB
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-Rpass-analysis=kernel-resource-usage", *SOURCES, "-o", tmp]
+            return lib
+    tmp = lib + ".tmp"
+    extra = SAN_HOST if sanitize else []
+    cmd = ["hipcc", *FLAGS, *extra, "-Rpass-analysis=kernel-resource-usage", *SOURCES, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = ("packed-fp32-ops", "kernel-resource-usage")
     msgs = [ln for ln in (res.stdout + res.stderr).splitlines()
@@ -75,8 +96,8 @@ def build(force: bool = True, verbose: bool = False) -> str:
     if verbose and msgs:
         print("\n".join(msgs))
     check_resources(resource_usage(res.stderr))
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmppi.so")
+# MPPI_LIB: another build of the same sources (the host-sanitizer build)
+LIB_PATH = os.environ.get("MPPI_LIB") or os.path.join(_HERE, "libmppi.so")
 _lib = None
 
 MPPI_OK = 0
