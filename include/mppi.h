@@ -190,9 +190,9 @@ mppi_status mppi_get_tick(const mppi_ctx* c, uint32_t* tick);
  * The body and chain schedules and every lane count give bit-identical
  * results; the team schedule evaluates the same formulas with sums taken in
  * another order, so its results differ from theirs by rounding (its own results
- * are deterministic and independent of batching).  A new context uses the team
- * schedule where the tree allows it, else the body schedule with the smallest
- * lane count that holds the tree; mppi_autotune times all of them.
+ * are deterministic and independent of batching).  A new context uses the body
+ * schedule with the smallest lane count that holds the tree; mppi_autotune
+ * times all of them.
  * mppi_set_lanes_per_rollout selects the body schedule with `lanes` lanes (0 =
  * the smallest valid count); mppi_get_lanes_per_rollout reports the lane count
  * of the current schedule. */
@@ -275,20 +275,26 @@ mppi_status mppi_graph_launch(mppi_graph* g, void* stream);
 mppi_status mppi_graph_destroy(mppi_graph* g);
 
 /* Autotuner: times `reps` steps of the instance from (d_state, d_knots) for the
- * body schedule at each valid lane count and for the chain schedule, and keeps
- * the fastest; results are cached per (model, N, H, K) for the process.  The
+ * body schedule at each valid lane count, for the chain schedule and for the
+ * team schedule (where the tree allows them), and keeps the fastest; results
+ * are cached per (model, N, H, K) for the process.  The
  * instance's tick is restored.  Blocks until the timing steps finish.  Writes
  * the chosen lane count to *best_lanes (nullable); mppi_get_schedule tells the
  * schedule. */
 mppi_status mppi_autotune(mppi_ctx* c, const float* d_state, const float* d_knots, int32_t reps, void* stream,
                           int32_t* best_lanes);
 
-/* Replace the instance's task targets (cost definition of Sec. IV-A) for the
- * calls issued after this one.  Waits until the device is idle (kernels of
- * earlier calls may still read the instance's tables), then updates them.
- * Graphs captured before the call keep the old targets.  MPPI_EINVAL for a
- * non-unit orientation target. */
-mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t);
+/* Replace the instance's task targets (cost definition of Sec. IV-A).  The
+ * change is one small kernel on `stream` (hipStream_t, NULL = the null stream)
+ * that writes the instance's device target block, which the kernels read when
+ * they run: work enqueued on `stream` after this call sees the new targets,
+ * work before it the old ones, and nothing else waits (no device-wide
+ * synchronisation).  Work of the instance on other streams -- a server's
+ * streams, graphs launched elsewhere -- is not ordered with the change: order
+ * it with events, or change targets while none of the instance's work is in
+ * flight.  Launch plans and graphs stay valid and use the targets current when
+ * they run.  MPPI_EINVAL for a non-unit orientation target. */
+mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t, void* stream);
 
 /* ---- Serving: continuous batching of MPC ticks --------------------------- */
 

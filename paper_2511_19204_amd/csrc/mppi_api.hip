@@ -47,6 +47,7 @@ __global__ void dynamics_kernel(const DevModel*, int, const float*, const float*
                                 float*, int, int);
 __global__ void update_kernel(const DevUpdate*, const UpdateOut*, UpdateOut);
 __global__ void update_single_kernel(DevUpdate);
+__global__ void set_targets_kernel(DevTargets*, DevTargets);
 struct StageItem {
   const float* src;
   float* dst;
@@ -102,6 +103,7 @@ struct mppi_ctx {
   // device buffers
   float *sigma = nullptr, *x0 = nullptr, *nom = nullptr, *samples = nullptr, *costs = nullptr;
   float *best_state = nullptr, *f0z = nullptr, *q0 = nullptr;
+  DevTargets* d_targets = nullptr;  // task targets, read by the kernels when they run
   // state prediction: measured state, trajectory knots, a cost slot, its descriptor
   float *x_meas = nullptr, *pred_knots = nullptr, *pred_cost = nullptr;
   DevInst* d_pred_inst = nullptr;
@@ -417,7 +419,7 @@ static void free_ctx_events(mppi_ctx* c) {
 static void free_ctx_buffers(mppi_ctx* c) {
   void* ptrs[] = {c->sigma, c->x0, c->nom, c->samples, c->costs, c->best_state, c->f0z, c->q0,
                   c->tick, c->d_insts, c->d_ups, c->x_meas, c->pred_knots, c->pred_cost, c->d_pred_inst,
-                  c->upd_partial, c->upd_done};
+                  c->upd_partial, c->upd_done, c->d_targets};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -425,6 +427,22 @@ static void free_ctx_buffers(mppi_ctx* c) {
 static bool valid_target(const float* q) {
   const double n2 = (double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3];
   return n2 == 0.0 || std::fabs(n2 - 1.0) <= 1e-4;
+}
+
+// The device form of the task targets (an all-zero orientation target stands
+// for the identity).
+static DevTargets targets_of(const mppi_params& p) {
+  DevTargets t{};
+  t.z_des = p.z_des;
+  for (int k = 0; k < 3; ++k) t.v_des[k] = p.v_des[k];
+  const float* qd = p.q_des;
+  const bool zero = qd[0] == 0.f && qd[1] == 0.f && qd[2] == 0.f && qd[3] == 0.f;
+  const bool ident = zero || (qd[0] == 1.f && qd[1] == 0.f && qd[2] == 0.f && qd[3] == 0.f);
+  t.or_target = ident ? 0 : 1;
+  for (int k = 0; k < 4; ++k) t.q_des[k] = zero ? (k == 0 ? 1.f : 0.f) : qd[k];
+  t.terminal_z_abs = p.terminal_z_abs ? 1 : 0;
+  t.z_terminal = p.z_terminal;
+  return t;
 }
 
 static void build_tables(mppi_ctx* c) {
@@ -448,17 +466,10 @@ static void build_tables(mppi_ctx* c) {
     d.seed_lo = (uint32_t)(c->seed & 0xffffffffu); d.seed_hi = (uint32_t)(c->seed >> 32);
     d.dt = c->p.dt; d.delta = c->delta; d.lambda = c->p.lambda;
     d.w_h = c->p.w_h; d.w_or = c->p.w_or; d.w_q = c->p.w_q; d.w_cv = c->p.w_cv; d.w_cf = c->p.w_cf;
-    d.w_eff = c->p.w_eff; d.w_H = c->p.w_H; d.w_ee = c->p.w_ee; d.w_tau = c->p.w_tau; d.z_des = c->p.z_des;
-    for (int k = 0; k < 3; ++k) d.v_des[k] = c->p.v_des[k];
+    d.w_eff = c->p.w_eff; d.w_H = c->p.w_H; d.w_ee = c->p.w_ee; d.w_tau = c->p.w_tau;
+    d.targets = c->d_targets;
     d.generate = 1;
     d.spline_mode = c->p.spline_mode;
-    const float* qd = c->p.q_des;
-    const bool zero = qd[0] == 0.f && qd[1] == 0.f && qd[2] == 0.f && qd[3] == 0.f;
-    const bool ident = zero || (qd[0] == 1.f && qd[1] == 0.f && qd[2] == 0.f && qd[3] == 0.f);
-    d.or_target = ident ? 0 : 1;
-    for (int k = 0; k < 4; ++k) d.q_des[k] = zero ? (k == 0 ? 1.f : 0.f) : qd[k];
-    d.terminal_z_abs = c->p.terminal_z_abs ? 1 : 0;
-    d.z_terminal = c->p.z_terminal;
     (void)M;
     DevUpdate& u = c->h_ups[it];
     u.costs = d.costs;
@@ -537,6 +548,12 @@ extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, ui
   if ((e = hipMalloc(&c->upd_done, sizeof(uint32_t))) != hipSuccess) return bail(e, "hipMalloc update counter");
   if ((e = hipMalloc(&c->d_insts, c->I * sizeof(DevInst))) != hipSuccess) return bail(e, "hipMalloc insts");
   if ((e = hipMalloc(&c->d_ups, c->I * sizeof(DevUpdate))) != hipSuccess) return bail(e, "hipMalloc ups");
+  if ((e = hipMalloc(&c->d_targets, sizeof(DevTargets))) != hipSuccess) return bail(e, "hipMalloc targets");
+  {
+    const DevTargets tg = targets_of(c->p);
+    if ((e = hipMemcpy(c->d_targets, &tg, sizeof(DevTargets), hipMemcpyHostToDevice)) != hipSuccess)
+      return bail(e, "upload targets");
+  }
   std::vector<float> f0(std::max(M.nc, 1), 0.f), q0(c->nu, 0.f);
   if (p->f0z)
     for (int i = 0; i < M.nc; ++i) f0[i] = p->f0z[i];
@@ -594,19 +611,16 @@ extern "C" mppi_status mppi_get_tick(const mppi_ctx* c, uint32_t* tick) {
   return MPPI_OK;
 }
 
-extern "C" mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t) {
+extern "C" mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t, void* stream) {
   if (!c || !t) return fail(MPPI_EINVAL, "null argument");
   if (!valid_target(t->q_des)) return fail(MPPI_EINVAL, "q_des must be a unit quaternion or all zero");
-  HIP_TRY(hipDeviceSynchronize());
   c->p.z_des = t->z_des;
   for (int k = 0; k < 3; ++k) c->p.v_des[k] = t->v_des[k];
   for (int k = 0; k < 4; ++k) c->p.q_des[k] = t->q_des[k];
   c->p.terminal_z_abs = t->terminal_z_abs;
   c->p.z_terminal = t->z_terminal;
-  build_tables(c);
-  HIP_TRY(hipMemcpy(c->d_insts, c->h_insts.data(), c->I * sizeof(DevInst), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(c->d_ups, c->h_ups.data(), c->I * sizeof(DevUpdate), hipMemcpyHostToDevice));
-  purge_plans(c);
+  hipLaunchKernelGGL(set_targets_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, c->d_targets, targets_of(c->p));
+  HIP_TRY(hipGetLastError());
   return MPPI_OK;
 }
 
@@ -1911,6 +1925,7 @@ struct mppi_server {
   std::string error;
   int64_t launched_batches = 0, launched_requests = 0;
   int live_n = 0;  // mode 2: admitted requests not yet complete
+  int in_launch = 0;  // modes 0 and 1: requests taken from the queue, their stream not yet marked busy
   int n_aux = 0;   // side streams per slot
   // mode 2, several slots (worker thread only): the slot of each rollout lane key
   // (robot type) and the key owning each slot (kNoOwner: none; keys may be negative)
@@ -2108,6 +2123,7 @@ static void server_loop(mppi_server* S) {
           sl.tickets.push_back(*it);
           it = S->pending.erase(it);
         }
+        S->in_launch += (int)batch.size();  // seen by drain until the slot is marked busy
       }
       if (batch.empty()) continue;
       mppi_status st = MPPI_OK;
@@ -2135,6 +2151,7 @@ static void server_loop(mppi_server* S) {
       }
       {
         std::lock_guard<std::mutex> lk(S->mu);  // drain and stats read these
+        S->in_launch -= (int)batch.size();
         sl.busy = true;
         S->launched_batches += 1;
         S->launched_requests += (int64_t)batch.size();
@@ -2230,7 +2247,7 @@ extern "C" mppi_status mppi_server_drain(mppi_server* S, double timeout_s) {
     {
       std::lock_guard<std::mutex> lk(S->mu);
       if (S->stop && !S->error.empty()) return fail(MPPI_EDEVICE, "server stopped: " + S->error);
-      bool idle = S->pending.empty() && S->live_n == 0;
+      bool idle = S->pending.empty() && S->live_n == 0 && S->in_launch == 0;
       for (auto& sl : S->slots) idle = idle && !sl.busy;
       if (idle) return MPPI_OK;
     }

@@ -88,6 +88,18 @@ struct DevModel {
   alignas(16) float team_rows[kMaxBodies][kTeamRow];
 };
 
+// Task targets of an instance's costs (Sec. IV-A), in a block of their own that
+// the kernels read when they run, so a change between calls is one small
+// stream-ordered write and cached launch tables stay valid.
+struct DevTargets {
+  float z_des;
+  float v_des[3];
+  float q_des[4];         // base orientation target (w, x, y, z)
+  int32_t or_target;      // 0: identity target (the orientation term uses q_base directly)
+  int32_t terminal_z_abs; // 1: terminal target height z_terminal
+  float z_terminal;
+};
+
 // One MPC instance's view for one planning iteration.
 struct DevInst {
   const DevModel* model;
@@ -105,14 +117,10 @@ struct DevInst {
   int32_t use_tick_value;
   uint32_t seed_lo, seed_hi;
   float dt, delta, lambda;
-  float w_h, w_or, w_q, w_cv, w_cf, w_eff, w_H, w_ee, w_tau, z_des;
-  float v_des[3];
+  float w_h, w_or, w_q, w_cv, w_cf, w_eff, w_H, w_ee, w_tau;
+  const DevTargets* targets;  // the instance's task targets
   int32_t generate;      // 1: sample knots from the counter-based stream; 0: read samples
   int32_t spline_mode;   // 0 cubic Hermite, 1 natural cubic, 2 quadratic (position knots, zero velocity targets)
-  float q_des[4];        // base orientation target (w, x, y, z)
-  int32_t or_target;     // 0: identity target (the orientation term uses q_base directly)
-  int32_t terminal_z_abs;  // 1: terminal target height z_terminal
-  float z_terminal;
   // verification only (read when masks is set): per-step records of the
   // rollouts with trace_map[n] >= 0, see trace_record
   float* trace;              // [traced][H + 1][nq + 2 nv + 2], or null

@@ -517,9 +517,10 @@ __device__ __forceinline__ StepConst load_step_const(const DevModel& M, const De
     c.dt = I->dt / (float)M.nsub;
     c.delta = I->delta; c.inv_delta = 1.f / I->delta; c.inv_F = 1.f / (float)c.F;
     c.w_h = I->w_h; c.w_or = I->w_or; c.w_q = I->w_q; c.w_cv = I->w_cv; c.w_cf = I->w_cf; c.w_eff = I->w_eff;
-    c.w_ee = I->w_ee; c.w_tau = I->w_tau; c.z_des = I->z_des;
-    c.or_target = I->or_target;
-    c.q_des[0] = I->q_des[0]; c.q_des[1] = I->q_des[1]; c.q_des[2] = I->q_des[2]; c.q_des[3] = I->q_des[3];
+    const DevTargets& tg = *I->targets;
+    c.w_ee = I->w_ee; c.w_tau = I->w_tau; c.z_des = tg.z_des;
+    c.or_target = tg.or_target;
+    c.q_des[0] = tg.q_des[0]; c.q_des[1] = tg.q_des[1]; c.q_des[2] = tg.q_des[2]; c.q_des[3] = tg.q_des[3];
   } else {
     c.cost_kind = -1; c.K = 2; c.nu = M.nu; c.F = 1; c.spline_mode = 0;
     c.dt = dt_override;
@@ -1380,7 +1381,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
       float e = 0.f;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const float target = (k == 2 && I.terminal_z_abs) ? I.z_terminal : x0[k] + I.v_des[k] * T;
+        const float target = (k == 2 && I.targets->terminal_z_abs) ? I.targets->z_terminal : x0[k] + I.targets->v_des[k] * T;
         e += fabsf(io.bq[k] - target);
       }
       acc += I.w_H * e;
@@ -2079,7 +2080,7 @@ __device__ __attribute__((always_inline)) void team_item(const DevInst& I, int f
       float e = 0.f;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const float target = (q == 2 && I.terminal_z_abs) ? I.z_terminal : I.x0[q] + I.v_des[q] * T;
+        const float target = (q == 2 && I.targets->terminal_z_abs) ? I.targets->z_terminal : I.x0[q] + I.targets->v_des[q] * T;
         e += fabsf(io.bq[q] - target);
       }
       acc += I.w_H * e;
@@ -2506,7 +2507,7 @@ __device__ __attribute__((always_inline)) void chain_item(const DevInst& I, int 
       float e = 0.f;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const float target = (k == 2 && I.terminal_z_abs) ? I.z_terminal : I.x0[k] + I.v_des[k] * T;
+        const float target = (k == 2 && I.targets->terminal_z_abs) ? I.targets->z_terminal : I.x0[k] + I.targets->v_des[k] * T;
         e += fabsf(bq[k] - target);
       }
       rec[34] += I.w_H * e;
@@ -2558,6 +2559,11 @@ __global__ __launch_bounds__(64) void chain_persistent_kernel(const DevInst* __r
     chain_item<GC>(insts[w.x], w.y, group_stride, table_floats, groups, smem);
     wave_sync();
   }
+}
+
+// A new set of task targets for an instance, ordered on the launch stream.
+__global__ void set_targets_kernel(DevTargets* __restrict__ dst, DevTargets v) {
+  if (threadIdx.x == 0) *dst = v;
 }
 
 __global__ void reset_counters(unsigned int* __restrict__ c, int n) {

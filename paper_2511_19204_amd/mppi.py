@@ -107,7 +107,7 @@ def lib():
         L.mppi_set_lanes_per_rollout.argtypes = [vp, i32]
         L.mppi_get_lanes_per_rollout.argtypes = [vp, C.POINTER(i32)]
         L.mppi_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
-        L.mppi_set_targets.argtypes = [vp, C.POINTER(Targets)]
+        L.mppi_set_targets.argtypes = [vp, C.POINTER(Targets), vp]
         L.mppi_predict.argtypes = [vp, vp, vp, i32, vp, vp]
         L.mppi_shift_knots.argtypes = [vp, vp, i32, vp, vp]
         L.mppi_tick.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
@@ -309,8 +309,9 @@ class Controller:
         _check(lib().mppi_get_lanes_per_rollout(self.h, C.byref(g)), "mppi_get_lanes_per_rollout")
         return g.value
 
-    def set_targets(self, z_des=None, v_des=None, q_des=None, terminal_z_abs=None, z_terminal=None):
-        """mppi_set_targets: change the task targets (fields left None keep their values)."""
+    def set_targets(self, z_des=None, v_des=None, q_des=None, terminal_z_abs=None, z_terminal=None, stream=None):
+        """mppi_set_targets: change the task targets (fields left None keep their
+        values), ordered on `stream` (torch's current stream by default)."""
         for k, v in (("z_des", z_des), ("v_des", v_des), ("q_des", q_des), ("terminal_z_abs", terminal_z_abs),
                      ("z_terminal", z_terminal)):
             if v is not None:
@@ -324,7 +325,7 @@ class Controller:
             t.q_des[k] = float(qd[k])
         t.terminal_z_abs = int(self.params.get("terminal_z_abs", 0))
         t.z_terminal = float(self.params.get("z_terminal", 0.0))
-        _check(lib().mppi_set_targets(self.h, C.byref(t)), "mppi_set_targets")
+        _check(lib().mppi_set_targets(self.h, C.byref(t), _stream(stream)), "mppi_set_targets")
 
     def set_lanes(self, lanes):
         """Body schedule with `lanes` lanes per rollout."""

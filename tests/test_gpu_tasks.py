@@ -5,7 +5,8 @@ and changing targets between calls.
 Bars as for the other rollouts: over oracle-made samples, at least 90 % of the
 rollouts with contact sequences identical to the oracle's, and on those the
 relative cost error at most 1e-3; mppi_set_targets equals an instance created
-with the same targets bit for bit."""
+with the same targets bit for bit, is ordered on its stream, and cached plans
+and graphs use the targets current when they run."""
 import numpy as np
 import pytest
 
@@ -97,6 +98,58 @@ def test_set_targets_equals_creating_with_them():
         p = synth.task_params(m, p0, "walking")
         p["q_des"] = [0.5, 0.0, 0.0, 0.0]
         mppi.Controller(model, p, s)
+
+
+def test_set_targets_is_stream_ordered_and_plans_and_graphs_follow():
+    """mppi_set_targets is one kernel on the stream: a step enqueued before it
+    scores the old targets and one enqueued after it the new ones, with no
+    synchronisation in between; a cached batch plan and a captured graph made
+    before the change score the targets current when they run."""
+    m, p0, s = _task("walking", 64)
+    model = mppi.Model(m)
+    kn = _t(synth.nominal_knots(m, p0["n_knots"]))
+    x = _t(m["x0"])
+    ph = synth.task_params(m, p0, "handstand")
+    pw = dict(ph)
+    pw.update(q_des=[0.0] * 4, terminal_z_abs=0, z_terminal=0.0, v_des=list(p0["v_des"]))
+
+    def fresh(p, tick):
+        c = mppi.Controller(model, p, s)
+        c.tick = tick
+        o = torch.zeros_like(kn)
+        c.step(x, kn, o)
+        return _np(o)
+
+    ref_w, ref_h, ref_h6 = fresh(pw, 5), fresh(ph, 5), fresh(ph, 6)
+    assert not np.array_equal(ref_w, ref_h)
+    c = mppi.Controller(model, pw, s)
+    stream = torch.cuda.Stream()
+    a, b = torch.zeros_like(kn), torch.zeros_like(kn)
+    torch.cuda.synchronize()
+    c.tick = 5
+    with torch.cuda.stream(stream):
+        c.step(x, kn, a, stream=stream)             # tick 5, then the tick advances to 6 on the device
+        c.set_targets(q_des=ph["q_des"], stream=stream)
+        c.step(x, kn, b, stream=stream)             # tick 6
+    stream.synchronize()
+    assert np.array_equal(_np(a), ref_w) and np.array_equal(_np(b), ref_h6)
+    # a cached plan (batched step) and a graph made under the handstand targets
+    c.tick = 5
+    o = torch.zeros_like(kn)
+    mppi.step_batch([c], [x], [kn], [o])
+    assert np.array_equal(_np(o), ref_h)
+    g = mppi.Graph([c], [x], [kn], [o])
+    c.set_targets(q_des=[0.0] * 4)
+    c.tick = 5
+    mppi.step_batch([c], [x], [kn], [o])
+    assert np.array_equal(_np(o), ref_w)
+    c.tick = 5
+    g.launch()
+    assert np.array_equal(_np(o), ref_w)
+    c.set_targets(q_des=ph["q_des"])
+    c.tick = 5
+    g.launch()
+    assert np.array_equal(_np(o), ref_h)
 
 
 def test_batch_of_different_tasks_equals_plain_steps():

@@ -184,23 +184,56 @@ def test_tick_against_oracle_smooth_arm():
     assert inf[4] == int(np.argmin(r["costs"][r["best_iter"]]))
 
 
-def test_failed_to_improve_statistic_over_ticks():
-    """A sequence of ticks of the arm task with the best trajectory carried on the
-    device and the robot following the plan: every tick reports a valid best
-    (iteration, sample), and the fraction where no sample beat the shifted
-    previous best (the diagnostic of the best-trajectory ablation) is printed."""
+def _oracle_tick(m, p, s, tick, x_meas, best, delay):
+    """One control step of Alg. 1 with Sec. III-E's prediction and warm start:
+    x_t = predict(x_meas, best, delay), tau_0 = best shifted by delay, then the
+    I iterations; returns the predicted state and the step's results."""
+    xpred = O.predict(m, p, x_meas, best, delay)
+    k0 = O.shift_knots(best, p["n_knots"], m["n_u"], p["horizon"], p["dt"], delay)
+    r = O.step(m, p, xpred, k0, s, tick)
+    r["best_sample"] = int(np.argmin(r["costs"][r["best_iter"]])) if r["best_iter"] >= 0 else -1
+    return xpred, r
+
+
+def test_best_trajectory_carried_across_ticks_against_oracle():
+    """Twelve chained ticks of the arm task (Sec. III-D/III-E: tau_best carried
+    from tick to tick, predicted, shifted, refined; the robot follows the plan,
+    so the next measurement is this tick's prediction), on the GPU with the best
+    trajectory kept on the device and in the oracle, each side running its own
+    chain.  After every tick: tau_best, the nominal and the predicted state
+    within 1e-4 max(1, |x|) (the two chains run free, so the float rounding of
+    earlier ticks carries into the state; a tick's own prediction is held to
+    the per-step bars of the trajectory-forced tests), the same best iteration
+    and sample, and so
+    the same "failed to improve" flag (the best is sample 0 of iteration 0, the
+    shifted previous solution) and the same count over the run."""
     m, p, s, model, c = _ctrl("chain", n_samples=32)
-    best = _t(synth.nominal_knots(m, p["n_knots"]))
-    x = _t(m["x0"])
-    failed = 0
-    ticks = 12
+    delay, ticks = 2, 12
+    best_o = synth.nominal_knots(m, p["n_knots"]).astype(np.float64)
+    x_o = np.asarray(m["x0"], np.float64)
+    best = _t(best_o)
+    x = _t(x_o)
+    c.tick = 0
+    failed_gpu = failed_orc = 0
     for t in range(ticks):
         info = torch.zeros(mppi.INFO_INTS, dtype=torch.int32, device="cuda")
         xp = torch.zeros_like(x)
-        c.run_tick(x, 2, best, None, info, xp)
+        ko = torch.zeros(c.E, device="cuda")
+        c.run_tick(x, delay, best, ko, info, xp)
+        x_o, r = _oracle_tick(m, p, s, t, x_o, best_o, delay)
+        best_o = r["best_knots"]
         inf = _np(info)
-        assert 0 <= inf[1] < p["n_iters"] and 0 <= inf[4] < p["n_samples"]
-        failed += int(inf[1] == 0 and inf[4] == 0)
-        x = xp  # the robot follows the plan: next measurement = this prediction
-    print(f"failed to improve: {failed}/{ticks}")
-    assert 0 <= failed <= ticks
+        eb = np.max(np.abs(_np(best) - best_o) / np.maximum(1.0, np.abs(best_o)))
+        ek = np.max(np.abs(_np(ko) - r["knots"]) / np.maximum(1.0, np.abs(r["knots"])))
+        ex = np.max(np.abs(_np(xp) - x_o) / np.maximum(1.0, np.abs(x_o)))
+        print(f"tick {t}: best err {eb:.2e}, nominal err {ek:.2e}, state err {ex:.2e}, "
+              f"best (iter, sample) gpu ({inf[1]}, {inf[4]}) oracle ({r['best_iter']}, {r['best_sample']})")
+        assert eb <= 1e-4 and ek <= 1e-4 and ex <= 1e-4, t
+        assert (int(inf[1]), int(inf[4])) == (r["best_iter"], r["best_sample"]), t
+        assert abs(inf[:1].view(np.float32)[0] - r["S_best"]) <= 1e-3 * abs(r["S_best"])
+        failed_gpu += int(inf[1] == 0 and inf[4] == 0)
+        failed_orc += int(r["best_iter"] == 0 and r["best_sample"] == 0)
+        x = xp
+    print(f"failed to improve: gpu {failed_gpu}/{ticks}, oracle {failed_orc}/{ticks}")
+    assert failed_gpu == failed_orc
+    assert c.tick == ticks
