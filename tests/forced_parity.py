@@ -1,0 +1,190 @@
+"""Trajectory-forced parity of the Alg. 1 simulate step against the FP64 oracle
+(shared by the GPU tests of single steps, batches and graphs).  The protocol and
+its bars are stated in tests/test_gpu_trace.py."""
+import numpy as np
+import torch
+
+import oracle as O
+
+from paper_2511_19204_amd import mppi
+
+
+def _t(x, dtype=torch.float32):
+    return torch.tensor(np.asarray(x), dtype=dtype, device="cuda")
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+ACC_TOL, X_TOL, COST_TOL, KNOT_TOL, FN_FLIP = 1e-5, 1e-5, 1e-3, 1e-4, 0.05
+SENS_FACTOR, SENS_DRAWS = 10.0, 8
+
+
+def traced_iterations(c, m, p, tick, x0, kn_in, select):
+    """The step's iterations one at a time: mppi_debug_trace of iteration it
+    around the current nominal, then the update kernel on its costs and samples.
+    select[it] = indices of the rollouts recorded in iteration it."""
+    N, H, E = p["n_samples"], p["horizon"], c.E
+    nq, nv = m["n_q"], m["n_v"]
+    rec = nq + 2 * nv + 2
+    st = _t(x0)
+    nom = _t(kn_in)
+    out = []
+    for it in range(p["n_iters"]):
+        idx = np.asarray(select[it], dtype=np.int64)
+        tmap = np.full(N, -1, np.int32)
+        tmap[idx] = np.arange(len(idx), dtype=np.int32)
+        trace = torch.full((max(len(idx), 1), H + 1, rec), float("nan"), device="cuda")
+        samples = torch.zeros((N, E), device="cuda")
+        costs = torch.zeros(N, device="cuda")
+        masks = torch.zeros((N, H), dtype=torch.int32, device="cuda")
+        c.trace(st, nom, it, tick, _t(tmap, torch.int32), trace, samples, costs, masks)
+        nxt = torch.zeros(E, device="cuda")
+        w = torch.zeros(N, device="cuda")
+        c.update(costs, samples, nom, nxt, w)
+        out.append({"idx": idx, "trace": _np(trace)[:len(idx)], "samples": _np(samples),
+                    "costs": _np(costs), "masks": _np(masks).view(np.uint32), "nominal": _np(nom),
+                    "next": _np(nxt), "weights": _np(w)})
+        nom = nxt
+    return out
+
+
+def fused_step(c, m, p, tick, x0, kn_in):
+    E = c.E
+    ko = torch.zeros(E, device="cuda")
+    best = torch.zeros(E, device="cuda")
+    info = torch.zeros(5, dtype=torch.int32, device="cuda")
+    costs = torch.zeros((p["n_iters"], p["n_samples"]), device="cuda")
+    c.tick = tick
+    c.step(_t(x0), _t(kn_in), ko, best, info, costs)
+    inf = _np(info)
+    return {"knots": _np(ko), "best": _np(best), "costs": _np(costs), "S_best": inf[:1].view(np.float32)[0],
+            "best_iter": int(inf[1]), "n_nonfinite": int(inf[2]), "best_sample": int(inf[4])}
+
+
+# model constants the device path stores in derived, float-rounded forms (joint
+# rotation constants, inertias about joint origins, contact rows)
+MODEL_CONSTANTS = ("axis", "R_tree", "p_tree", "mass", "com", "inertia", "contact_pos", "armature", "kp", "kd")
+
+
+def _rounding_perturbed(a, rng):
+    """a with every entry scaled by 1 + e, |e| <= 2^-24 (float rounding)."""
+    a = np.asarray(a, dtype=np.float64)
+    return a * (1 + rng.uniform(-1, 1, a.shape) * 2.0**-24)
+
+
+def check_forced(m, p, x0, knots, trace, S_gpu, label):
+    """Per-step parity of recorded rollouts (see the module docstring); returns
+    the counts it prints."""
+    H, nq, nv = p["horizon"], m["n_q"], m["n_v"]
+    nx = nq + nv
+    assert m.get("n_substeps", 1) == 1
+    assert trace.dtype == np.float32
+    MK = trace[:, :H, nx + nv + 1].view(np.uint32)
+    X = trace[:, :, :nx].astype(np.float64)
+    A = trace[:, :H, nx:nx + nv].astype(np.float64)
+    C = trace[:, :, nx + nv].astype(np.float64)
+    assert np.all(np.isfinite(X)) and np.all(np.isfinite(S_gpu)), label
+    ref = O.forced_steps(m, p, x0, knots, X)
+    r32 = O.forced_steps(m, p, x0, knots, X, f32=True)
+    n_roll = X.shape[0]
+    steps = n_roll * H
+
+    # contact masks: differences only on points at the threshold
+    flip = MK != ref["masks"]
+    for r, h in np.argwhere(flip):
+        bits = int(MK[r, h]) ^ int(ref["masks"][r, h])
+        pts = [k for k in range(32) if bits >> k & 1]
+        assert np.all(np.abs(ref["fn"][r, h, pts]) <= FN_FLIP), (label, "mask flip", r, h, ref["fn"][r, h, pts])
+
+    # float evaluations and exact evaluations at rounding-level perturbations of
+    # the inputs (state and knots), for the ill-conditioned steps
+    scale = np.maximum(np.abs(ref["qdd"]).max(axis=2), 1.0)
+    ea = np.abs(A - ref["qdd"]).max(axis=2) / scale
+    e32 = np.abs(r32["qdd"] - ref["qdd"]).max(axis=2) / scale
+    cr = ref["cost"]
+    dc = np.abs(C[:, :H] - cr[:, :H])
+    sens_a, sens_c = np.zeros_like(ea), np.zeros_like(dc)
+    if ((ea > ACC_TOL) | (dc > COST_TOL * np.abs(cr[:, :H]))).any():
+        rng = np.random.default_rng(0)
+        for _ in range(SENS_DRAWS):
+            Xp = _rounding_perturbed(X, rng)
+            Kp = _rounding_perturbed(knots, rng)
+            mp = {k: (_rounding_perturbed(v, rng) if k in MODEL_CONSTANTS else v) for k, v in m.items()}
+            rp = O.forced_steps(mp, p, x0, Kp, Xp)
+            sens_a = np.maximum(sens_a, np.abs(rp["qdd"] - ref["qdd"]).max(axis=2) / scale)
+            sens_c = np.maximum(sens_c, np.abs(rp["cost"][:, :H] - cr[:, :H]))
+            rq = O.forced_steps(mp, p, x0, Kp, Xp, f32=True)
+            e32 = np.maximum(e32, np.abs(rq["qdd"] - ref["qdd"]).max(axis=2) / scale)
+
+    # accelerations
+    ok = (ea <= ACC_TOL) | flip
+    esc32 = ~ok & (ea <= 2 * e32)
+    escS = ~ok & ~esc32 & (ea <= SENS_FACTOR * sens_a)
+    bad = ~ok & ~esc32 & ~escS
+    assert not bad.any(), (label, "acceleration", np.argwhere(bad)[:5], ea[bad][:5], e32[bad][:5], sens_a[bad][:5])
+
+    # integration from x_h with the GPU's own accelerations
+    xi = O.integrate(m, p["dt"], X[:, :H].reshape(-1, nx), A.reshape(-1, nv)).reshape(n_roll, H, nx)
+    ex = np.abs(X[:, 1:] - xi).max(axis=2) / np.maximum(np.abs(xi).max(axis=2), 1.0)
+    assert ex.max() <= X_TOL, (label, "integration", ex.max())
+
+    # running and terminal costs
+    okc = (dc <= COST_TOL * np.abs(cr[:, :H])) | flip
+    escC = ~okc & (dc <= SENS_FACTOR * sens_c)
+    rc = dc / np.maximum(np.abs(cr[:, :H]), 1e-30)
+    assert (okc | escC).all(), (label, "running cost", np.argwhere(~okc & ~escC)[:5], dc[~okc & ~escC][:5],
+                                cr[:, :H][~okc & ~escC][:5], sens_c[~okc & ~escC][:5])
+    et = np.abs(C[:, H] - cr[:, H]) / np.maximum(np.abs(cr[:, H]), 1e-6)
+    assert et.max() <= COST_TOL, (label, "terminal cost", et.max())
+
+    # rollout cost against the oracle's costs along the GPU's trajectory
+    clean = ~flip.any(axis=1)
+    S_forced = cr.sum(axis=1)
+    es = np.abs(S_gpu - S_forced) / np.abs(S_forced)
+    assert es[clean].max() <= COST_TOL, (label, "rollout cost", es[clean].max())
+    stats = {"rollouts": n_roll, "steps": steps, "acc_within_1e-5": int(((ea <= ACC_TOL) & ~flip).sum()),
+             "acc_esc_f32": int(esc32.sum()), "acc_esc_sens": int(escS.sum()), "acc_max": float(np.max(ea[~flip], initial=0.0)),
+             "x_max": float(ex.max()), "mask_flips": int(flip.sum()), "cost_max": float(np.max(rc[okc & ~flip], initial=0.0)),
+             "cost_esc_sens": int(escC.sum()),
+             "esc_ratio_f32": float(np.max((ea / np.maximum(e32, 1e-30))[esc32 | escS], initial=0.0)),
+             "esc_ratio_sens": float(np.max((ea / np.maximum(sens_a, 1e-30))[esc32 | escS], initial=0.0)),
+             "S_max": float(es[clean].max()), "S_checked": int(clean.sum())}
+    print(f"{label}: {stats}")
+    return stats
+
+
+def check_iterations(c, m, p, seed, tick, x0, kn, its, fused, label, n_sample_check=32):
+    """The iteration-by-iteration run equals the fused step bit for bit, and each
+    iteration's sampling, update and the best tracking follow the oracle."""
+    N, E, K, nu = p["n_samples"], c.E, p["n_knots"], m["n_u"]
+    for it, d in enumerate(its):
+        assert np.array_equal(d["costs"], fused["costs"][it]), (label, it, "costs differ from mppi_step")
+    assert np.array_equal(its[-1]["next"], fused["knots"]), (label, "nominal differs from mppi_step")
+    delta = p["horizon"] * p["dt"] / (K - 1)
+    qb = np.tile(np.maximum(np.abs(m["q_min"]), np.abs(m["q_max"])), K)
+    extra = np.concatenate([np.zeros(K * nu), 8 * 2.0**-24 * qb * 2 / delta])
+    best_S, best_it, best_n = np.inf, -1, -1
+    for it, d in enumerate(its):
+        # sampled knots (Alg. 1 sampling step, eq. vel-clamp) around the GPU's nominal
+        nom = d["nominal"].astype(np.float64)
+        for n in np.unique(np.r_[np.linspace(0, N - 1, min(N, n_sample_check)).astype(int), N - 1]):
+            ref = O.sample_knots(m, p, nom, seed, tick, it, int(n))
+            tol = 2e-6 * np.maximum(1.0, np.abs(ref)) + extra
+            assert np.all(np.abs(d["samples"][n] - ref) <= tol), (label, it, n)
+        # update (eq. softmax_minmax, eq. update-nominal) from the GPU's costs and samples
+        S = d["costs"].astype(np.float64)
+        w, nstar, nf = O.weights(S, p["lambda"], p["weight_mode"])
+        assert np.max(np.abs(d["weights"] - w)) <= 1e-6, (label, it)
+        ref = O.weighted_average(w, d["samples"].astype(np.float64)) if nf else nom
+        assert np.max(np.abs(d["next"] - ref) / np.maximum(1.0, np.abs(ref))) <= KNOT_TOL, (label, it)
+        # best tracking (Sec. III-D): strict improvement, lowest index among equal minima
+        if nf and S[nstar] < best_S:
+            best_S, best_it, best_n = S[nstar], it, nstar
+    assert fused["best_iter"] == best_it and fused["best_sample"] == best_n, (label, fused["best_iter"], best_it)
+    assert fused["S_best"] == np.float32(best_S)
+    assert np.array_equal(fused["best"], its[best_it]["samples"][best_n])
+
+
