@@ -20,8 +20,16 @@ Also reported:
                    launches ("plain"): throughput, p50/p99 latency from tick
                    arrival, 20 ms deadline misses, overall and per robot type;
   roofline         the rollout kernel: algorithmic FP32 operations per launch
-                   (flops.flops_per_rollout_step x K x H) / its mean duration,
-                   against the FP32 vector peak (ALU-bound path);
+                   (the oracle's non-trivial operation count per rollout step,
+                   profiles/flops_per_rollout_step.txt, x K x H) / its mean
+                   duration from HIP events, against the FP32 vector peak
+                   (ALU-bound path); the kernel's own formula count
+                   (flops.py) and the oracle's raw count beside it;
+  sizes            the same workload at K = 256, 1024, 8192 and 16384;
+  ticks            single-instance MPC tick latency (mppi_tick: prediction,
+                   warm start, all iterations) of the chain (K=32, H=50, I=10)
+                   and the humanoid (K=256, H=150, I=3) configurations;
+  autotune         the autotuner's choice of schedule for the primary workload;
   cpu_baseline     the CPU oracle (FP64, OpenMP over samples) on a bounded sample
                    of the same workload.
 Prints one JSON line.
@@ -90,13 +98,31 @@ def kernel_label(m, schedule, lanes):
     return f"{name}<{lanes}, {spec}>"
 
 
-def primary(args, torch, mppi, synth, flops):
-    m, p, seed = synth.config("quadruped_tp", n_samples=args.samples)
+def oracle_flops(name):
+    """(non-trivial, raw) operations per rollout step of a workload, as the
+    committed summary written by oracle/count_flops.py states them."""
+    vals = {}
+    for line in open(os.path.join(ROOT, "profiles", "flops_per_rollout_step.txt")):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    return float(vals[f"{name}.nontrivial_per_step"]), float(vals[f"{name}.raw_per_step"])
+
+
+def primary(args, torch, mppi, synth, flops, samples=None, steps=None, tune=False):
+    m, p, seed = synth.config("quadruped_tp", n_samples=samples or args.samples)
     model = mppi.Model(m)
     ctrl = mppi.Controller(model, p, seed, lanes=args.lanes, schedule=args.schedule)
     st = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
     k0 = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
+    tuned = None
+    if tune and not args.lanes and not args.schedule:
+        # the autotuner times every schedule and lane count for this (model, K, H)
+        # and keeps the fastest; ticks are restored
+        lanes = mppi.autotune(ctrl, st, k0, reps=3)
+        tuned = {"schedule": ctrl.schedule, "lanes_per_rollout": lanes}
     ka, kb = k0.clone(), torch.zeros_like(k0)
+    steps = steps or args.steps
     for _ in range(args.warmup):
         ctrl.step(st, ka, kb)
         ka, kb = kb, ka
@@ -106,11 +132,11 @@ def primary(args, torch, mppi, synth, flops):
     stream = torch.cuda.current_stream()
     # step boundaries: step i runs between marks i and i + 1 (one event per step,
     # since the end of a step is the start of the next on the stream)
-    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     marks[0].record(stream)
-    for i in range(args.steps):
+    for i in range(steps):
         ctrl.step(st, ka, kb)
         marks[i + 1].record(stream)
         ka, kb = kb, ka
@@ -118,20 +144,67 @@ def primary(args, torch, mppi, synth, flops):
     wall = time.perf_counter() - t0
     roll_ms, n_roll, upd_ms, n_upd = ctrl.profile_read()
     ctrl.profile(False)
-    lat = [marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)]
+    lat = [marks[i].elapsed_time(marks[i + 1]) for i in range(steps)]
     N, H, I = p["n_samples"], p["horizon"], p["n_iters"]
     steps_rollout = N * H * I
-    fl = flops.flops_per_rollout_step(m)
+    fl_nt, fl_raw = oracle_flops("quadruped_tp")
+    fl_kernel = flops.flops_per_rollout_step(m)
     avg_roll_s = roll_ms / max(n_roll, 1) / 1e3
-    achieved = fl * N * H / avg_roll_s / 1e12
+    achieved = fl_nt * N * H / avg_roll_s / 1e12
     res = {
         "model": m, "params": p, "ctrl": ctrl, "model_h": model,
-        "wall": wall, "value": steps_rollout * args.steps / wall, "lat": lat,
+        "wall": wall, "value": steps_rollout * steps / wall, "lat": lat,
         "kernel_ms": roll_ms / max(n_roll, 1), "update_ms": upd_ms / max(n_upd, 1),
-        "achieved_tflops": achieved, "flops_per_rollout_step": fl, "lanes": ctrl.lanes,
-        "schedule": ctrl.schedule,
+        "achieved_tflops": achieved, "lanes": ctrl.lanes, "schedule": ctrl.schedule, "autotune": tuned,
+        "flops_per_rollout_step": {"oracle_nontrivial": fl_nt, "oracle_raw": fl_raw, "kernel_formulas": fl_kernel},
+        "achieved_tflops_kernel_formulas": fl_kernel * N * H / avg_roll_s / 1e12,
     }
     return res
+
+
+def sizes(args, torch, mppi, synth, flops):
+    """The primary workload at other sample counts (K = 256 and 1024 of the
+    throughput configuration; 8192 and 16384, two wavefronts per SIMD)."""
+    out = {}
+    for K in (256, 1024, 8192, 16384):
+        r = primary(args, torch, mppi, synth, flops, samples=K, steps=max(5, args.steps // 2))
+        out[f"K{K}"] = {"rollout_steps_per_s": r["value"], "ms_per_step": 1e3 * r["wall"] / max(5, args.steps // 2),
+                        "rollout_kernel_ms": r["kernel_ms"], "update_kernel_ms": r["update_ms"],
+                        "achieved_tflops": r["achieved_tflops"], "step_latency_p50_ms": _pct(r["lat"], 50),
+                        "step_latency_p99_ms": _pct(r["lat"], 99)}
+        r["ctrl"].close()
+    return out
+
+
+def single_ticks(args, torch, mppi, synth):
+    """Tick latency of one instance alone (mppi_tick: prediction by one control
+    step, warm-start shift, all iterations), from HIP events around each tick on
+    its stream: the chain (K=32, H=50, I=10) and humanoid (K=256, H=150, I=3)
+    configurations."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name in ("chain", "humanoid"):
+        m, p, seed = synth.config(name)
+        model = mppi.Model(m)
+        c = mppi.Controller(model, p, seed)
+        x = torch.tensor(m["x0"], dtype=torch.float32, device="cuda")
+        best = torch.tensor(synth.nominal_knots(m, p["n_knots"]), dtype=torch.float32, device="cuda")
+        for _ in range(5):
+            c.run_tick(x, 1, best)
+        n = args.tick_runs
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * n)]
+        torch.cuda.synchronize()
+        for i in range(n):
+            ev[2 * i].record(stream)
+            c.run_tick(x, 1, best)
+            ev[2 * i + 1].record(stream)
+        torch.cuda.synchronize()
+        lat = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(n)]
+        out[name] = {"K": p["n_samples"], "H": p["horizon"], "I": p["n_iters"], "ticks": n,
+                     "tick_latency_p50_ms": _pct(lat, 50), "tick_latency_p99_ms": _pct(lat, 99),
+                     "rollout_steps_per_s": p["n_samples"] * p["horizon"] * p["n_iters"] / (np.mean(lat) / 1e3)}
+        c.close()
+    return out
 
 
 def batched_vs_plain(args, torch, mppi, synth):
@@ -170,6 +243,13 @@ def batched_vs_plain(args, torch, mppi, synth):
         end.record(stream)
         return start, [end] * len(made)
 
+    def persistent_round():
+        mppi.set_batch_options(persistent=True)
+        try:
+            return batched_round()
+        finally:
+            mppi.set_batch_options(persistent=False)
+
     graph = mppi.Graph(ctrls, states, kins, kouts)
 
     def graph_round():
@@ -181,7 +261,8 @@ def batched_vs_plain(args, torch, mppi, synth):
         return start, [end] * len(made)
 
     out = {}
-    for name, fn in (("plain", plain_round), ("batched", batched_round), ("graph", graph_round)):
+    for name, fn in (("plain", plain_round), ("batched", batched_round), ("batched_persistent", persistent_round),
+                     ("graph", graph_round)):
         fn()  # warm-up (builds the batched launch plan once)
         torch.cuda.synchronize()
         lat = []
@@ -197,6 +278,8 @@ def batched_vs_plain(args, torch, mppi, synth):
     out["robots"] = len(made)
     out["rollout_steps_per_round"] = work
     out["speedup"] = out["batched"]["rollout_steps_per_s"] / out["plain"]["rollout_steps_per_s"]
+    out["persistent_vs_launch_per_item"] = (out["batched_persistent"]["rollout_steps_per_s"]
+                                            / out["batched"]["rollout_steps_per_s"])
     return out
 
 
@@ -368,16 +451,20 @@ def serving(args, torch, mppi, synth, mode):
 
 
 def cpu_baseline(args, res):
-    """The FP64 oracle on the host cores: median of 5 timed runs over all cores
-    (OpenMP over samples) and, on a smaller sample, over one thread."""
+    """The FP64 oracle on the host cores: median of 5 timed runs over every core
+    the process may use (OpenMP over samples) and, on a smaller sample, over one
+    thread.  The cores are those of the affinity mask, limited only by the
+    environment's OMP_NUM_THREADS when it is set (a machine's CPU share for one
+    GPU); nproc is recorded beside the count used."""
     import oracle as O
     from paper_2511_19204_amd import synth
     m, p = res["model"], res["params"]
     try:
-        cores = len(os.sched_getaffinity(0))
+        affinity = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+        affinity = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    cores = max(1, min(affinity, int(omp))) if omp.isdigit() and int(omp) > 0 else affinity
     kn = synth.nominal_knots(m, p["n_knots"])
     H = p["horizon"]
 
@@ -395,7 +482,8 @@ def cpu_baseline(args, res):
     one_rate, _ = rate(args.cpu_sample_1t, 1)
     wall = time.perf_counter() - t0
     return {"value": all_rate, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
-            "value_1thread": one_rate,
+            "value_1thread": one_rate, "nproc": os.cpu_count(), "affinity_cores": affinity,
+            "omp_num_threads": omp or None,
             "sample": f"median of 5 runs of {args.cpu_sample} of the {p['n_samples']} rollouts (H={H}) on "
                       f"{cores} threads and of {args.cpu_sample_1t} rollouts on 1 thread; FP64, OpenMP over "
                       f"samples; {wall:.1f} s wall in total"}
@@ -420,6 +508,10 @@ def main():
     ap.add_argument("--no-tasks", action="store_true", help="skip the task presets in closed loop")
     ap.add_argument("--task-ticks", type=int, default=200)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sizes", action="store_true", help="skip the runs at K = 256, 1024, 8192, 16384")
+    ap.add_argument("--no-ticks", action="store_true", help="skip the single-instance tick latencies")
+    ap.add_argument("--tick-runs", type=int, default=100)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default schedule")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-streams", type=int, default=None,
                     help="server streams for every serving mode (default: per mode, SERVE_STREAMS)")
@@ -449,7 +541,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    res = primary(args, torch, mppi, synth, flops)
+    res = primary(args, torch, mppi, synth, flops, tune=not args.no_autotune)
+    size_res = None if args.no_sizes else sizes(args, torch, mppi, synth, flops)
+    tick_res = None if args.no_ticks else single_ticks(args, torch, mppi, synth)
     bvp = None if args.no_batch else batched_vs_plain(args, torch, mppi, synth)
     srv = None
     if not args.no_serve:
@@ -498,8 +592,12 @@ def main():
             "kernel_ms": res["kernel_ms"],
             "update_kernel_ms": res["update_ms"],
             "flops_per_rollout_step": res["flops_per_rollout_step"],
+            "achieved_with_kernel_formula_count": res["achieved_tflops_kernel_formulas"],
             "kernel_source_digest": digest,
         },
+        "autotune": res["autotune"],
+        "sizes": size_res,
+        "ticks": tick_res,
         "cpu_baseline": cpu,
         "batched_vs_plain": bvp,
         "serving": srv,

@@ -89,6 +89,8 @@ def lib():
         _lib.orc_rk4.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, _dp]
         _lib.orc_dense_route_update.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                                                 _dp, _dp, _dp]
+        _lib.orc_count_selftest.argtypes = [_dp]
+        _lib.orc_count_ops.argtypes = [C.c_void_p, C.c_void_p, _dp, _dp, C.c_uint64, C.c_int, _dp]
         _lib.orc_integrate_batch.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, _dp]
         _lib.orc_forced_steps.argtypes = [C.c_void_p, C.c_void_p, _dp, C.c_int, _dp, _dp, _dp, _dp, _up,
                                           _dp, _dp, C.c_int, C.c_int]
@@ -445,6 +447,30 @@ def integrate(model, dt, X, A):
     _check(lib().orc_integrate_batch(M.ptr, float(dt), Xa.shape[0], Xa.ctypes.data_as(_dp), Aa.ctypes.data_as(_dp),
                                      out.ctypes.data_as(_dp)), "integrate")
     return out
+
+
+OP_KINDS = ("add", "mul", "div", "sqrt", "trans", "cmp", "nt_add", "nt_mul", "nt_div")
+
+
+def count_ops(model, params, x0, nominal, seed, n=1):
+    """Arithmetic of one rollout (sample n drawn around `nominal`, H control steps
+    from x0, terminal cost) counted by the oracle's operation-counting scalar:
+    {"rollout": {kind: count}, "sampling": {kind: count}} with kinds add (incl.
+    subtraction), mul, div, sqrt, trans (sin, cos, exp, log, atan2), cmp
+    (comparisons, fabs, floor) and the non-trivial nt_add, nt_mul, nt_div
+    (operations not involving an exact 0, or 1 for products and divisors)."""
+    M = _Model(model); P = _Params(params, M.nu, M.nc)
+    xa, xp = _d(x0); na, npt = _d(nominal)
+    out = np.zeros(18)
+    _check(lib().orc_count_ops(M.ptr, P.ptr, xp, npt, seed, int(n), out.ctypes.data_as(_dp)), "count_ops")
+    return {"rollout": dict(zip(OP_KINDS, out[:9])), "sampling": dict(zip(OP_KINDS, out[9:]))}
+
+
+def count_selftest():
+    """Counts of y = A x (3x3) with the counting scalar: (general A, identity A)."""
+    out = np.zeros(18)
+    lib().orc_count_selftest(out.ctypes.data_as(_dp))
+    return dict(zip(OP_KINDS, out[:9])), dict(zip(OP_KINDS, out[9:]))
 
 
 def rollout_f32(model, params, x0, knots):

@@ -31,6 +31,8 @@
 #include <vector>
 #ifdef _OPENMP
 #include <omp.h>
+
+#include "opcount.hpp"
 #endif
 
 extern "C" {
@@ -1486,6 +1488,62 @@ int orc_integrate_batch(const orc_model* m, double dt, int n, const double* X, c
     std::copy(A + (size_t)r * nv, A + (size_t)(r + 1) * nv, qdd.begin());
     integrate(M, dt, q, q + nq, qdd);
   }
+  return 0;
+}
+
+// Counts of two 3x3 matrix-vector products with the Flop scalar, y = A x,
+// for the pin of the counting rules: out[0..8] for a general A, out[9..17] for
+// the identity (kinds as in orc_count_ops).
+int orc_count_selftest(double* out) {
+  auto run = [](const double* A, double* o) {
+    Flop x[3] = {0.5, -2.0, 3.0}, y[3];
+    g_tally = OpTally{};
+    for (int i = 0; i < 3; ++i) {
+      Flop acc = 0;
+      for (int j = 0; j < 3; ++j) acc += Flop(A[i * 3 + j]) * x[j];
+      y[i] = acc;
+    }
+    (void)y;
+    const OpTally& t = g_tally;
+    o[0] = (double)t.add; o[1] = (double)t.mul; o[2] = (double)t.div; o[3] = (double)t.sqrt;
+    o[4] = (double)t.trans; o[5] = (double)t.cmp; o[6] = (double)t.nt_add; o[7] = (double)t.nt_mul;
+    o[8] = (double)t.nt_div;
+  };
+  const double G[9] = {1.5, 2, -3, 4, 5, 6, 7, 8, 9}, I[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  run(G, out);
+  run(I, out + 9);
+  return 0;
+}
+
+// The arithmetic of one rollout of the Alg. 1 simulate step, counted with the
+// Flop scalar (see opcount.hpp): sample n's knots drawn around `nominal` and
+// clipped (iteration 0, tick 0; the Box-Muller normals themselves are formed in
+// double and not counted), its H control steps from x0 and its terminal cost.
+// out[0..8]: the rollout's raw add/sub, mul, div, sqrt, transcendental and
+// comparison counts, then its non-trivial add/sub, mul and div counts;
+// out[9..17]: the same for the sampling alone.  Model set-up is not counted.
+int orc_count_ops(const orc_model* m, const orc_params* p, const double* x0, const double* nominal, uint64_t seed,
+                  int n, double* out) {
+  if (!model_ok(m) || !params_ok(m, p) || n < 0 || !out) return -1;
+  Model<Flop> M = load_model<Flop>(m);
+  const int E = 2 * p->n_knots * M.nu, nq = M.nq, nv = M.nv, H = p->horizon;
+  std::vector<double> sig(p->n_iters * p->n_knots);
+  sigma_table(p, sig.data());
+  std::vector<Flop> nom(nominal, nominal + E), th(E), x(x0, x0 + nq + nv);
+  std::vector<Flop> q(x.begin(), x.begin() + nq), v(x.begin() + nq, x.end());
+  auto put = [](const OpTally& t, double* o) {
+    o[0] = (double)t.add; o[1] = (double)t.mul; o[2] = (double)t.div; o[3] = (double)t.sqrt;
+    o[4] = (double)t.trans; o[5] = (double)t.cmp; o[6] = (double)t.nt_add; o[7] = (double)t.nt_mul;
+    o[8] = (double)t.nt_div;
+  };
+  g_tally = OpTally{};
+  sample_knots<Flop>(M, p, nom.data(), sig.data(), seed, 0, 0, n, th.data());
+  put(g_tally, out + 9);
+  g_tally = OpTally{};
+  sample_knots<Flop>(M, p, nom.data(), sig.data(), seed, 0, 0, n, th.data());
+  for (int h = 0; h < H; ++h) (void)control_step<Flop>(M, p, th.data(), h, q.data(), v.data());
+  (void)terminal_cost<Flop>(M, p, x.data(), q.data(), v.data());
+  put(g_tally, out);
   return 0;
 }
 
