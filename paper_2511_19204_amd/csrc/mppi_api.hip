@@ -1012,8 +1012,8 @@ struct RingSlot {
 };
 std::mutex g_mu;
 std::vector<std::unique_ptr<Plan>> g_plans;
-std::vector<RingSlot> g_ring;
-int g_ring_next = 0;
+// launch-table buffers of batched launches (a deque: entries never move)
+std::deque<RingSlot> g_ring;
 }  // namespace
 
 static void purge_plans(const mppi_ctx* c) {
@@ -1079,15 +1079,28 @@ static mppi_status build_plan(const std::vector<const mppi_ctx*>& ctxs, Plan** o
   return MPPI_OK;
 }
 
+// A launch-table buffer that no kernel reads any more: the first entry whose
+// last reader has finished (its event, recorded after that kernel on whichever
+// stream ran it, has completed), or a new entry when every one is still in use.
+// Never waits: a batch on one stream must not stall behind another stream's
+// longer work (the pool grows to the number of batches in flight at once).
 static mppi_status ring_slot(size_t bytes, RingSlot** out) {
-  if (g_ring.empty()) g_ring.resize(8);
-  RingSlot& r = g_ring[g_ring_next];
-  g_ring_next = (g_ring_next + 1) % (int)g_ring.size();
-  if (r.pending) {
-    // waits for the last kernel that read this slot's tables (any stream)
-    HIP_TRY(hipEventSynchronize(r.ev));
-    r.pending = false;
+  RingSlot* found = nullptr;
+  for (RingSlot& e : g_ring) {
+    if (e.pending) {
+      const hipError_t q = hipEventQuery(e.ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return fail(MPPI_EDEVICE, std::string("hipEventQuery: ") + hipGetErrorString(q));
+      e.pending = false;
+    }
+    found = &e;
+    break;
   }
+  if (!found) {
+    g_ring.emplace_back();
+    found = &g_ring.back();
+  }
+  RingSlot& r = *found;
   if (r.cap < bytes) {
     if (r.host) (void)hipHostFree(r.host);
     if (r.dev) (void)hipFree(r.dev);

@@ -67,20 +67,19 @@ def test_queue_full_returns_enoslot_and_recovers():
     srv.drain(120.0)
     for t, _ in accepted:
         assert srv.poll(t) is not None
-    # the queue accepts again once drained
-    t = srv.submit_tick(c, x, 0, bests[-1])
+    # the queue accepts again once drained (a buffer of its own: the accepted
+    # ticks' results are compared below)
+    t = srv.submit_tick(c, x, 0, _t(synth.nominal_knots(m, p["n_knots"])))
     srv.drain(120.0)
     assert srv.poll(t) is not None
     srv.close()
     # the accepted ticks followed one another on the instance: replaying them as
     # plain ticks from the same start gives the same best trajectories
     c2 = mppi.Controller(model, p, s)
-    ref = _t(synth.nominal_knots(m, p["n_knots"]))
     for i, (_, b) in enumerate(accepted):
         r = _t(synth.nominal_knots(m, p["n_knots"]))
         c2.run_tick(x, 0, r)
         assert np.array_equal(_np(r), _np(b)), i
-    del ref
 
 
 def test_late_tick_latency_includes_the_wait_for_the_previous_tick():
