@@ -310,9 +310,13 @@ def closed_loop(args, torch, mppi, synth):
         x, xp = xp, x
         delay = max(1, int(np.ceil(dt_ms / 1e3 / p["dt"])))
     lat = np.array(lat)
+    frac = failed / len(lat)
+    note = ("latency record; the controller itself is degenerate at these settings: no sample improved on "
+            "the shifted plan in any tick (64 samples of the 0.4 rad kernel knock the synthetic robot off "
+            "balance), so failed_to_improve_frac says nothing about the paper's statistic") if frac == 1.0 else None
     return {"robot": "quadruped18, K=64, H=100, I=3", "ticks": len(lat),
             "tick_latency_p50_ms": float(np.percentile(lat, 50)), "tick_latency_p99_ms": float(np.percentile(lat, 99)),
-            "delay_steps_mean": float(np.mean(delays)), "failed_to_improve_frac": failed / len(lat)}
+            "delay_steps_mean": float(np.mean(delays)), "failed_to_improve_frac": frac, "note": note}
 
 
 def _angle(q1, q2):
