@@ -27,6 +27,12 @@ step.  The bars, per step:
                  discontinuous there (the implicit damping switches on at
                  f_n > 0), so such steps skip the acceleration and cost bars
                  and are counted
+  torque clip    a step beyond the acceleration bar with a joint whose
+                 unclipped PD torque lies within its float rounding of the
+                 actuator limit passes if its accelerations match the FP64 step
+                 on the other branch of the clip within 1e-5 (the implicit PD
+                 gain exists only below the limit, so the branches differ by a
+                 finite step); counted
   running cost   1e-3 relative, unless the cost is ill-conditioned the same
                  way (a term like |f - f0| cancels at a settled stance): then
                  within 10x of its rounding sensitivity

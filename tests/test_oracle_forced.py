@@ -86,3 +86,50 @@ def test_integrate_free_flight_closed_form():
     half = 0.5 * 1.5 * dt
     assert np.allclose(out[3:7], [np.cos(half), 0, 0, np.sin(half)], rtol=0, atol=1e-15)
     assert np.array_equal(out[nq:], x[nq:])
+
+
+def test_clip_flip_classifier():
+    """The torque-clip flip classification of the GPU per-step check: a step
+    whose joint torque sits at its limit within rounding is accepted when its
+    accelerations are those of the other clip branch, and only then."""
+    from forced_parity import ACC_TOL, _clip_flips
+    m, p, seed = synth.config("quadruped", n_samples=4)
+    p = dict(p)
+    p["horizon"] = 20
+    H, K, nu, nq, dt = p["horizon"], p["n_knots"], m["n_u"], m["n_q"], p["dt"]
+    kn = synth.nominal_knots(m, K)
+    s = O.sample_knots(m, p, kn, seed, 0, 0, 1)
+    _, traj, _, _ = O.rollout(m, p, m["x0"], s, debug=True)
+    h, j = 9, 4
+    qr = np.array([O.hermite(s, K, nu, H, dt, h, i)[0] for i in range(nu)])
+    vr = np.array([O.hermite(s, K, nu, H, dt, h, i)[1] for i in range(nu)])
+    kp, kd, tm = m["kp"][j], m["kd"][j], m["tau_max"][j]
+
+    def at(frac):
+        """Trajectory copy whose joint-j torque at step h is frac * tau_max."""
+        X = traj.copy()
+        t = kp * (qr[j] - X[h, 7 + j]) + kd * (vr[j] - X[h, nq + 6 + j])
+        X[h, 7 + j] -= (frac * tm - t) / kp
+        return X
+
+    X = at(1 + 1e-9)                      # FP64 saturates, at the limit within rounding
+    a_sat = O.step_dynamics(m, X[h, :nq], X[h, nq:], qr, vr, dt)[0]
+    qr_in = qr.copy()
+    qr_in[j] -= 2e-9 * tm / kp            # the same step below the limit
+    a_lin = O.step_dynamics(m, X[h, :nq], X[h, nq:], qr_in, vr, dt)[0]
+    scale = max(np.abs(a_sat).max(), 1.0)
+    assert np.abs(a_sat - a_lin).max() / scale > 100 * ACC_TOL  # the branches differ by a finite step
+    cand = np.zeros((1, H), dtype=bool)
+    cand[0, h] = True
+
+    def classify(X, a):
+        A = np.zeros((1, H, m["n_v"]))
+        A[0, h] = a
+        return bool(_clip_flips(m, p, s[None], X[None], A, cand)[0, h])
+
+    assert classify(X, a_lin)                 # other branch: a clip flip
+    assert not classify(X, a_lin * (1 + 1e-3))  # other branch, wrong values
+    assert not classify(X, a_sat * (1 + 1e-3))  # own branch, wrong values
+    Xf = at(0.9)                               # far from the limit: never a flip
+    a_far = O.step_dynamics(m, Xf[h, :nq], Xf[h, nq:], qr, vr, dt)[0]
+    assert not classify(Xf, a_far * (1 + 1e-3))
