@@ -94,8 +94,14 @@ def kernel_label(m, schedule, lanes):
     spec = 3 if d <= 3 else 6 if d <= 6 else 0
     if schedule == "chain":
         return f"chain_kernel<{lanes}>"
-    name = "team_kernel" if schedule == "team" else "rollout_kernel"
-    return f"{name}<{lanes}, {spec}>"
+    if schedule == "team":
+        return f"team_kernel<{lanes}, {spec}>"
+    # legged trees (a floating base with serial chains, depth first) up to three
+    # levels deep take the kernel with the chains' LDS paths compiled out
+    nch = [sum(1 for q in par if q == b) for b in range(len(par))]
+    leg = (bool(m["floating_base"]) and len(par) > 1 and spec == 3 and 8 <= lanes <= 32
+           and all(par[b] in (b - 1, 0) and nch[b] <= 1 for b in range(1, len(par))))
+    return f"rollout_kernel<{lanes}, {spec}, {'true' if leg else 'false'}>"
 
 
 def oracle_flops(name):

@@ -28,9 +28,9 @@
 
 namespace mppi {
 // kernels (mppi_kernels.hip)
-template <int G, int D>
+template <int G, int D, bool LEG>
 __global__ void rollout_kernel(const DevInst*, const int2*, int, int, const float*, const float*);
-template <int G, int D> __global__ void rollout_trace_kernel(const DevInst*, const int2*, int, int);
+template <int G, int D, bool LEG> __global__ void rollout_trace_kernel(const DevInst*, const int2*, int, int);
 template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
 template <int G, int D> __global__ void team_kernel(const DevInst*, const int2*, int, int);
@@ -100,6 +100,7 @@ struct mppi_ctx {
   int lanes = 0;
   int device = 0;
   float delta = 0.f;
+  bool regen = false;  // the update draws the samples again (samples stays unallocated)
   // device buffers
   float *sigma = nullptr, *x0 = nullptr, *nom = nullptr, *samples = nullptr, *costs = nullptr;
   float *best_state = nullptr, *f0z = nullptr, *q0 = nullptr;
@@ -469,11 +470,13 @@ static void build_tables(mppi_ctx* c) {
     d.w_eff = c->p.w_eff; d.w_H = c->p.w_H; d.w_ee = c->p.w_ee; d.w_tau = c->p.w_tau;
     d.targets = c->d_targets;
     d.generate = 1;
+    d.store_samples = c->regen ? 0 : 1;
     d.spline_mode = c->p.spline_mode;
     (void)M;
     DevUpdate& u = c->h_ups[it];
     u.costs = d.costs;
     u.samples = c->samples;
+    u.regen = c->regen ? c->d_insts + it : nullptr;
     u.nominal_in = d.nominal;
     u.nominal_out = c->nom + (size_t)(1 + ((it + 1) % 2)) * c->E;
     u.weights = nullptr;
@@ -537,7 +540,12 @@ extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, ui
   if ((e = hipMalloc(&c->sigma, sig.size() * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc sigma");
   if ((e = hipMalloc(&c->x0, (c->nq + c->nv) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc x0");
   if ((e = hipMalloc(&c->nom, 3 * E * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc nominal");
-  if ((e = hipMalloc(&c->samples, (size_t)c->N * E * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc samples");
+  // the update draws the samples' knots again from the counter-based stream when
+  // they are the cubic Hermite knots in whole blocks (K n_u even); otherwise the
+  // rollouts store them for it
+  c->regen = (c->K * c->nu) % 2 == 0 && p->spline_mode == 0;
+  if (!c->regen && (e = hipMalloc(&c->samples, (size_t)c->N * E * sizeof(float))) != hipSuccess)
+    return bail(e, "hipMalloc samples");
   if ((e = hipMalloc(&c->costs, (size_t)c->I * c->N * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc costs");
   if ((e = hipMalloc(&c->best_state, (E + 5) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc best");
   if ((e = hipMalloc(&c->f0z, std::max(M.nc, 1) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc f0z");
@@ -672,10 +680,24 @@ extern "C" mppi_status mppi_get_schedule(const mppi_ctx* c, int32_t* schedule) {
 
 
 // Largest per-instance sizes of one launch (they size the LDS regions).
+// A legged tree: a floating base with serial chains hanging off it, numbered
+// depth first (every joint body's parent is the previous body, or the base for
+// a chain's first body, and no body but the base has more than one child).
+static bool legged(const DevModel& M) {
+  if (!M.fb || M.nb < 2) return false;
+  for (int b = 1; b < M.nb; ++b) {
+    if (M.parent[b] != b - 1 && M.parent[b] != 0) return false;
+    if (M.n_child[b] > 1) return false;
+  }
+  return true;
+}
+
 struct Dims {
   int E = 0, nb = 0, nc = 0, nch = 0, natt = 0, ns = 0, depth = 0;
+  bool leg = true;  // every instance added is a legged tree
   void add(const mppi_ctx* c) {
     const DevModel& M = c->m->host;
+    leg = leg && legged(M);
     E = std::max(E, c->E);
     nb = std::max(nb, M.nb);
     nc = std::max(nc, M.nc);
@@ -726,15 +748,22 @@ static int rollouts_per_block(int key, const Dims& dm) { return launch_shape(key
 // loops unrolled; deeper trees take the general one
 template <int G>
 static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
-                                   int depth, hipStream_t s, const float* x0_in, const float* nominal_in) {
+                                   int depth, bool leg, hipStream_t s, const float* x0_in, const float* nominal_in) {
+  if constexpr (G >= 8 && G <= 32) {
+    if (depth <= 3 && leg) {
+      hipLaunchKernelGGL((rollout_kernel<G, 3, true>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride,
+                         sh.table, x0_in, nominal_in);
+      return hipGetLastError();
+    }
+  }
   if (depth <= 3)
-    hipLaunchKernelGGL((rollout_kernel<G, 3>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
+    hipLaunchKernelGGL((rollout_kernel<G, 3, false>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
                        x0_in, nominal_in);
   else if (depth <= 6)
-    hipLaunchKernelGGL((rollout_kernel<G, 6>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
+    hipLaunchKernelGGL((rollout_kernel<G, 6, false>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
                        x0_in, nominal_in);
   else
-    hipLaunchKernelGGL((rollout_kernel<G, 0>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
+    hipLaunchKernelGGL((rollout_kernel<G, 0, false>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
                        x0_in, nominal_in);
   return hipGetLastError();
 }
@@ -763,11 +792,11 @@ static hipError_t launch_rollout(int key, int blocks, const DevInst* insts, cons
   if ((x0_in || nominal_in) && !(key > 0 && key < kTeamKey)) return hipErrorInvalidValue;
   const LaunchShape sh = launch_shape(key, dm);
   switch (key) {
-    case 4: return launch_rollout_G<4>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
-    case 8: return launch_rollout_G<8>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
-    case 16: return launch_rollout_G<16>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
-    case 32: return launch_rollout_G<32>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
-    case 64: return launch_rollout_G<64>(blocks, insts, work, sh, dm.depth, s, x0_in, nominal_in);
+    case 4: return launch_rollout_G<4>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
+    case 8: return launch_rollout_G<8>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
+    case 16: return launch_rollout_G<16>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
+    case 32: return launch_rollout_G<32>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
+    case 64: return launch_rollout_G<64>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
     case kTeamKey + 4: return launch_team_G<4>(blocks, insts, work, sh, dm.depth, s);
     case kTeamKey + 8: return launch_team_G<8>(blocks, insts, work, sh, dm.depth, s);
     case kTeamKey + 16: return launch_team_G<16>(blocks, insts, work, sh, dm.depth, s);
@@ -855,7 +884,7 @@ static mppi_status run_iterations(mppi_ctx* c, float* d_knots_out, float* d_best
     if (c->profile) HIP_TRY(hipEventRecord(mk[1], s));
     UpdateOut o{nullptr, nullptr, nullptr, nom0};
     if (it == c->I - 1) o = UpdateOut{d_knots_out, d_best_knots, d_info, nom0};
-    hipLaunchKernelGGL(update_kernel, dim3(update_parts(c->N), 1), dim3(kUpdThreads), 0, s, c->d_ups + it, nullptr, o);
+    hipLaunchKernelGGL(update_kernel, dim3(c->h_ups[it].parts, 1), dim3(kUpdThreads), 0, s, c->d_ups + it, nullptr, o);
     HIP_TRY(hipGetLastError());
     if (c->profile) {
       HIP_TRY(hipEventRecord(mk[2], s));
@@ -1404,6 +1433,7 @@ extern "C" mppi_status mppi_debug_samples(mppi_ctx* c, const float* d_knots_in, 
   DevInst h = c->h_insts[iter];
   h.nominal = d_knots_in;
   h.samples = d_samples;
+  h.store_samples = 1;
   h.use_tick_value = 1;
   h.tick_value = tick;
   DevInst* d = nullptr;
@@ -1477,24 +1507,32 @@ extern "C" mppi_status mppi_debug_rollouts(mppi_ctx* c, const float* d_state, co
 // The traced twin of launch_rollout for one instance of the body schedule: the
 // same grid, block, LDS layout and depth specialisation as mppi_step's launch.
 template <int G>
-static hipError_t launch_trace_G(const DevInst* inst, int N, const LaunchShape& sh, int depth, hipStream_t s) {
+static hipError_t launch_trace_G(const DevInst* inst, int N, const LaunchShape& sh, int depth, bool leg,
+                                 hipStream_t s) {
   const int blocks = (N + sh.groups - 1) / sh.groups;
+  if constexpr (G >= 8 && G <= 32) {
+    if (depth <= 3 && leg) {
+      hipLaunchKernelGGL((rollout_trace_kernel<G, 3, true>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr,
+                         sh.stride, sh.table);
+      return hipGetLastError();
+    }
+  }
   if (depth <= 3)
-    hipLaunchKernelGGL((rollout_trace_kernel<G, 3>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
+    hipLaunchKernelGGL((rollout_trace_kernel<G, 3, false>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
   else if (depth <= 6)
-    hipLaunchKernelGGL((rollout_trace_kernel<G, 6>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
+    hipLaunchKernelGGL((rollout_trace_kernel<G, 6, false>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
   else
-    hipLaunchKernelGGL((rollout_trace_kernel<G, 0>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
+    hipLaunchKernelGGL((rollout_trace_kernel<G, 0, false>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
   return hipGetLastError();
 }
 static hipError_t launch_trace(int key, const DevInst* inst, int N, const Dims& dm, hipStream_t s) {
   const LaunchShape sh = launch_shape(key, dm);
   switch (key) {
-    case 4: return launch_trace_G<4>(inst, N, sh, dm.depth, s);
-    case 8: return launch_trace_G<8>(inst, N, sh, dm.depth, s);
-    case 16: return launch_trace_G<16>(inst, N, sh, dm.depth, s);
-    case 32: return launch_trace_G<32>(inst, N, sh, dm.depth, s);
-    case 64: return launch_trace_G<64>(inst, N, sh, dm.depth, s);
+    case 4: return launch_trace_G<4>(inst, N, sh, dm.depth, dm.leg, s);
+    case 8: return launch_trace_G<8>(inst, N, sh, dm.depth, dm.leg, s);
+    case 16: return launch_trace_G<16>(inst, N, sh, dm.depth, dm.leg, s);
+    case 32: return launch_trace_G<32>(inst, N, sh, dm.depth, dm.leg, s);
+    case 64: return launch_trace_G<64>(inst, N, sh, dm.depth, dm.leg, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1511,6 +1549,7 @@ extern "C" mppi_status mppi_debug_trace(mppi_ctx* c, const float* d_state, const
   h.x0 = d_state;
   h.nominal = d_knots_in;
   h.samples = d_samples;
+  h.store_samples = 1;
   h.costs = d_costs;
   h.masks = d_masks;
   h.use_tick_value = 1;
@@ -1533,6 +1572,7 @@ extern "C" mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, cons
   DevUpdate h = c->h_ups[0];
   h.costs = d_costs;
   h.samples = d_samples;
+  h.regen = nullptr;  // the same parts as the context's own update, so the same sums
   h.nominal_in = d_knots_in;
   h.nominal_out = d_knots_out;
   h.weights = d_weights;
@@ -1542,7 +1582,7 @@ extern "C" mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, cons
   DevUpdate* d = nullptr;
   HIP_TRY(hipMalloc(&d, sizeof(DevUpdate)));
   HIP_TRY(hipMemcpyAsync(d, &h, sizeof(DevUpdate), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(update_kernel, dim3(update_parts(c->N), 1), dim3(kUpdThreads), 0, s, d, nullptr,
+  hipLaunchKernelGGL(update_kernel, dim3(h.parts, 1), dim3(kUpdThreads), 0, s, d, nullptr,
                      UpdateOut{nullptr, nullptr, nullptr});
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));

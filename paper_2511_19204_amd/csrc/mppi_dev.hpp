@@ -120,6 +120,8 @@ struct DevInst {
   float w_h, w_or, w_q, w_cv, w_cf, w_eff, w_H, w_ee, w_tau;
   const DevTargets* targets;  // the instance's task targets
   int32_t generate;      // 1: sample knots from the counter-based stream; 0: read samples
+  int32_t store_samples; // with generate: 1 writes the sampled knots to samples (the
+                         // update reads them); 0 leaves them to the update to regenerate
   int32_t spline_mode;   // 0 cubic Hermite, 1 natural cubic, 2 quadratic (position knots, zero velocity targets)
   // verification only (read when masks is set): per-step records of the
   // rollouts with trace_map[n] >= 0, see trace_record
@@ -130,7 +132,10 @@ struct DevInst {
 // Per-instance state of the weighting/update stage.
 struct DevUpdate {
   const float* costs;    // [N]
-  const float* samples;  // [N][E]
+  const float* samples;  // [N][E] (read when regen is null)
+  const DevInst* regen;  // the iteration's sampling descriptor: the update draws the
+                         // samples' knots again from the counter-based stream (null:
+                         // reads samples)
   const float* nominal_in;  // [E]
   float* nominal_out;    // [E]
   float* weights;        // [N] or null

@@ -38,8 +38,10 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
       k.x += 0x9E3779B9u;
       k.y += 0xBB67AE85u;
     }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    // the 64-bit products give high and low words in one multiply each
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
   }
   return c;
@@ -820,7 +822,14 @@ __device__ __forceinline__ float forward_joint(const float* al, const float* e, 
 template <int D> constexpr int kLevelUnroll = D > 0 ? D : 1;
 template <int D> constexpr int kLevelUnrollRoot = D > 0 ? D + 1 : 1;
 
-template <int G, int D = 0>
+// LEG: the tree is a floating base with serial chains hanging off it (every
+// joint body's parent is the previous lane, or the base for a chain's first
+// body; no body but the base has more than one child), so a frame, an
+// acceleration or a carried inertia always comes from the neighbouring lane
+// except the base's, which gathers the chains through LDS.  The same
+// arithmetic as the general form, with its LDS paths and their branches
+// compiled out.
+template <int G, int D = 0, bool LEG = false>
 __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const float* tab, float* __restrict__ gs,
                              int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
   const int maxd = D > 0 ? D : sc.max_depth;
@@ -892,7 +901,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
         fk_base_child(io.bv, C, bc.p_tree, bc.axis_p, io.v, R, p, e, ax, v, c, beta);
       } else {
         float Rl[9], pl[3], vl[6], bl[6];
-        if (bc.flags & kAdjParent) {
+        if (LEG || (bc.flags & kAdjParent)) {
 #pragma unroll
           for (int k = 0; k < 9; ++k) Rl[k] = sR[k];
 #pragma unroll
@@ -911,7 +920,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
         }
         fk_joint(Rl, pl, vl, bl, C, bc.p_tree, bc.axis_p, io.v, R, p, e, ax, v, c, beta);
       }
-      if (bc.flags & kFrameOut) put_frame(slots + b * kSlot, R, p, v, beta);
+      if (!LEG && (bc.flags & kFrameOut)) put_frame(slots + b * kSlot, R, p, v, beta);
     }
     wave_sync();
   }
@@ -976,7 +985,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
     float Ip[21], pp[6];
     if (body_lane && depth == d) {
       const int nch = bc.n_child;
-      if (nch > 0) {
+      if ((!LEG || d == 0) && nch > 0) {
         // children reached through LDS: the first kFold records are read together
         // (a missing child reads this lane's own slot and is not added), then
         // added in child order; more children follow one by one
@@ -1004,7 +1013,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
       }
       if (is_joint) {
         backward_joint(IA, pA, ax, c, e, tau, bc.arm, gain, U, invD, u, Ip, pp);
-        if (bc.flags & kArtOut) put_art(slots + b * kSlot, Ip, pp);
+        if ((!LEG || d == 1) && (bc.flags & kArtOut)) put_art(slots + b * kSlot, Ip, pp);
       }
     }
     wave_sync();
@@ -1045,7 +1054,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
       if (fb && d == 1) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) al[k] = a0[k];
-      } else if (bc.flags & kAdjParent) {
+      } else if (LEG || (bc.flags & kAdjParent)) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) al[k] = sa[k];
       } else if (lam >= 0) {
@@ -1055,7 +1064,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
         al[0] = al[1] = al[2] = 0.f; al[3] = 0.f; al[4] = 0.f; al[5] = g;
       }
       qdd = forward_joint(al, e, c, U, u, invD, ax, a);
-      if (bc.flags & kFrameOut) put_acc(slots + b * kSlot, a);
+      if (!LEG && (bc.flags & kFrameOut)) put_acc(slots + b * kSlot, a);
     }
     wave_sync();
     if (d < maxd) {
@@ -1070,44 +1079,77 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
 // Knot sampling for one rollout group: counter-based normals, perturbation,
 // position clip and bound-aware velocity clamp.
 // ---------------------------------------------------------------------------
+// Sample n's position and velocity knot of one element (Alg. 1 sampling step:
+// the nominal (nq, nv) perturbed by the iteration's std sq at the element's
+// knot, the position clipped to the joint range [lo, hi], the velocity clamped
+// by eq. vel-clamp) from the uniform words (xa, xb) of its counter-based block,
+// by Box-Muller.  Sample 0 is the nominal itself (clipped and clamped the same
+// way).  The rollout's sampler and the update's regeneration both call this, so
+// they give the same bits.
+struct ElemConst {
+  float sq, lo, hi;  // std at the element's knot, joint range
+  int m;             // element index k nu + jj
+};
+__device__ __forceinline__ ElemConst elem_const(const DevModel& M, const DevInst& I, const float* sig, int m) {
+  const int k = m / I.nu, jj = m % I.nu;
+  return ElemConst{sig[k], M.qmin[jj], M.qmax[jj], m};
+}
+__device__ __forceinline__ void perturb_element(const ElemConst& ec, float delta, float nq, float nv, int n,
+                                                uint32_t xa, uint32_t xb, bool with_velocity, float& tq,
+                                                float& tv) {
+  float zq = 0.f, zv = 0.f;
+  if (n > 0) {
+    const float ua = u01(xa), ub = u01(xb);
+    const float r = sqrtf(-2.f * logf(ua));
+    zq = r * cospif(2.f * ub);
+    zv = r * sinpif(2.f * ub);
+  }
+  tq = fminf(fmaxf(fmaf(ec.sq, zq, nq), ec.lo), ec.hi);
+  tv = 0.f;
+  if (with_velocity) {
+    const float sv = ec.sq / delta;
+    const float lim = 2.f * fminf(ec.hi - tq, tq - ec.lo) / delta;
+    tv = fminf(fmaxf(fmaf(sv, zv, nv), -lim), lim);
+  }
+}
+
+// The counter-based block blk of sample n in iteration I.iter at tick `tick`
+// (key = seed; counter = (blk, n, iter, tick)); sample 0 draws none.
+__device__ __forceinline__ uint4 sample_words(const DevInst& I, int n, int blk, uint32_t tick) {
+  if (n == 0) return make_uint4(0u, 0u, 0u, 0u);
+  return philox(make_uint4((uint32_t)blk, (uint32_t)n, (uint32_t)I.iter, tick), make_uint2(I.seed_lo, I.seed_hi));
+}
+__device__ __forceinline__ uint32_t sample_tick(const DevInst& I) {
+  return I.use_tick_value ? I.tick_value : *I.tick_ptr;
+}
+
+// Knot sampling for one rollout group: block blk gives elements 2 blk and
+// 2 blk + 1 (its words x, y and z, w); the lanes of the group take the blocks
+// in turn.
 template <int G>
 __device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, float* knots, bool valid,
                              const float* tab, const float* nominal = nullptr) {
   const float* nom = nominal ? nominal : I.nominal;
   const int K = I.K, nu = I.nu, KU = K * nu;
   const int nblk = (KU + 1) / 2;
-  const uint2 key = make_uint2(I.seed_lo, I.seed_hi);
   const float* sig = I.sigma + I.iter * K;
-  const uint32_t tick = I.use_tick_value ? I.tick_value : *I.tick_ptr;
+  const uint32_t tick = sample_tick(I);
+  const bool store = valid && I.store_samples;
+  const bool with_v = I.spline_mode == 0;
   for (int blk = l; blk < nblk; blk += G) {
-    uint4 x = make_uint4(0u, 0u, 0u, 0u);
-    if (n > 0) x = philox(make_uint4((uint32_t)blk, (uint32_t)n, (uint32_t)I.iter, tick), key);
+    const uint4 x = sample_words(I, n, blk, tick);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const int m = 2 * blk + half;
       if (m >= KU) break;
-      const int k = m / nu, jj = m % nu;
-      float zq = 0.f, zv = 0.f;
-      if (n > 0) {
-        const uint32_t xa = half ? x.z : x.x, xb = half ? x.w : x.y;
-        const float ua = u01(xa), ub = u01(xb);
-        const float r = sqrtf(-2.f * logf(ua));
-        zq = r * cospif(2.f * ub);
-        zv = r * sinpif(2.f * ub);
-      }
-      const float sq = sig[k];
-      const float lo = M.qmin[jj], hi = M.qmax[jj];
-      float tq = fmaf(sq, zq, nom[m]);
-      tq = fminf(fmaxf(tq, lo), hi);
+      float tq, tv;
+      perturb_element(elem_const(M, I, sig, m), I.delta, nom[m], with_v ? nom[KU + m] : 0.f, n,
+                      half ? x.z : x.x, half ? x.w : x.y, with_v, tq, tv);
       knots[m] = tq;
-      if (valid) I.samples[(size_t)n * I.E + m] = tq;
-      if (I.spline_mode == 0) {
-        const float sv = sq / I.delta;
-        const float lim = 2.f * fminf(hi - tq, tq - lo) / I.delta;
-        float tv = fmaf(sv, zv, nom[KU + m]);
-        tv = fminf(fmaxf(tv, -lim), lim);
+      if (store) I.samples[(size_t)n * I.E + m] = tq;
+      if (with_v) {
         knots[KU + m] = tv;
-        if (valid) I.samples[(size_t)n * I.E + KU + m] = tv;
+        if (store) I.samples[(size_t)n * I.E + KU + m] = tv;
       }
     }
   }
@@ -1116,7 +1158,7 @@ __device__ void sample_group(const DevModel& M, const DevInst& I, int n, int l, 
     wave_sync();
     for (int jj = l; jj < nu; jj += G) {
       position_spline_slopes(I.spline_mode, K, nu, jj, I.delta, tab + kTabSpline, knots);
-      if (valid)
+      if (store)
         for (int k = 0; k < K; ++k) I.samples[(size_t)n * I.E + KU + k * nu + jj] = knots[KU + k * nu + jj];
     }
   }
@@ -1272,7 +1314,7 @@ __device__ __forceinline__ void trace_record(const DevInst& I, int n, bool valid
 
 // x0_in / nominal_in (nullable) replace the instance's staged state and nominal.
 // TR: also write the per-step records of traced rollouts (verification kernel).
-template <int G, int D = 0, bool TR = false>
+template <int G, int D = 0, bool TR = false, bool LEG = false>
 __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride,
                                                             int table_floats, float* smem, int steps,
                                                             float* state_out, const float* x0_in = nullptr,
@@ -1339,7 +1381,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     // (lanes without a joint evaluate zero knots and never use the result)
     hermite_eval(hs, (float)clk.rem * sc.inv_F, sc.inv_delta, &io.qref, &io.vref);
     if (sc.spline_mode != 0) io.vref = 0.f;  // position-only variants: zero velocity targets
-    physics_step<G, D>(sc, bc, tab, gs, b, body_lane, io, control);
+    physics_step<G, D, LEG>(sc, bc, tab, gs, b, body_lane, io, control);
     if (control) {
       acc += io.cost;
       if (masks) {
@@ -1389,7 +1431,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     }
   } else {
     // end-effector height at x_H
-    physics_step<G, D>(sc, bc, tab, gs, b, body_lane, io, false, true);
+    physics_step<G, D, LEG>(sc, bc, tab, gs, b, body_lane, io, false, true);
     acc += io.cost;
   }
   if (TR && masks && I.trace) {
@@ -1409,7 +1451,8 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 // D > 0: every instance of the launch is at most D levels deep.
 // x0_in / nominal_in (nullable, one instance only): the state and the nominal
 // to use instead of the instance's staged copies.
-template <int G, int D>
+// LEG: every instance of the launch is a legged tree (see physics_step).
+template <int G, int D, bool LEG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_kernel(
     const DevInst* __restrict__ insts, const int2* __restrict__ work, int group_stride, int table_floats,
     const float* __restrict__ x0_in, const float* __restrict__ nominal_in) {
@@ -1417,19 +1460,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ro
   constexpr int R = 64 / G;
   const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
   const DevInst& I = insts[w.x];
-  rollout_item<G, D>(I, w.y, group_stride, table_floats, smem, I.H, nullptr, x0_in, nominal_in);
+  rollout_item<G, D, false, LEG>(I, w.y, group_stride, table_floats, smem, I.H, nullptr, x0_in, nominal_in);
 }
 
 // The rollout kernel with per-step records of the traced rollouts (same launch
 // shape and arithmetic; verification only).
-template <int G, int D>
+template <int G, int D, bool LEG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_trace_kernel(
     const DevInst* __restrict__ insts, const int2* __restrict__ work, int group_stride, int table_floats) {
   extern __shared__ float smem[];
   constexpr int R = 64 / G;
   const int2 w = work ? work[blockIdx.x] : make_int2(0, (int)blockIdx.x * R);
   const DevInst& I = insts[w.x];
-  rollout_item<G, D, true>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
+  rollout_item<G, D, true, LEG>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
 }
 
 // State prediction: sample 0 of the instance (its knots read from samples) run
@@ -2572,9 +2615,10 @@ __global__ void reset_counters(unsigned int* __restrict__ c, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Weighting, update and best tracking.  Grid (kUpdMaxParts, instances): the
-// workgroups of an instance each take one slice of its samples (parts of
-// update_parts(N)); the workgroups beyond that return at once.
+// Weighting, update and best tracking.  Grid (the most parts of the launch's
+// instances, instances): the workgroups of an instance each take one slice of
+// its samples (U.parts of them, update_parts(N)); the workgroups beyond that
+// return at once.
 // out (per call): the final nominal, best knots and info of the last iteration.
 // ---------------------------------------------------------------------------
 
@@ -2665,12 +2709,93 @@ __device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows
   }
 }
 
+// The same sum as rows_weighted_sum<4> over the samples rows n0 .. n0 + cnt - 1,
+// with each sample's knots drawn again from the counter-based stream instead of
+// read (the rollout kernel then stores none).  Element block b holds positions
+// 2b, 2b + 1 and velocities 2b, 2b + 1 (one counter-based block); there are
+// E / 4 of them, as many as rows_weighted_sum<4> has, so the threads form the
+// same groups, every element is accumulated over the same rows in the same
+// order and the two forms give the same bits.  Needs K nu even and the cubic
+// Hermite knots (velocities sampled, not derived).
+__device__ __forceinline__ void regen_weighted_sum(const DevInst& I, const float* nom, uint32_t tick, int n0, int cnt,
+                                                   const float* w, float* s_part, float* mine) {
+  const DevModel& M = *I.model;
+  const int t = threadIdx.x, KU = I.K * I.nu, EV = KU / 2;
+  const float* sig = I.sigma + I.iter * I.K;
+  float4* part = reinterpret_cast<float4*>(s_part);
+  for (int e0 = 0; e0 < EV; e0 += kUpdThreads) {
+    const int ec = min(kUpdThreads, EV - e0);
+    const int G = kUpdThreads / ec;
+    const int el = t % ec, g = t / ec, b = e0 + el;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (g < G) {
+      const ElemConst c0 = elem_const(M, I, sig, 2 * b), c1 = elem_const(M, I, sig, 2 * b + 1);
+      const float nq0 = nom[2 * b], nq1 = nom[2 * b + 1], nv0 = nom[KU + 2 * b], nv1 = nom[KU + 2 * b + 1];
+      // kRow rows are drawn together (independent chains the scheduler can
+      // interleave), then added in row order
+      constexpr int kRow = 4;
+      for (int r0 = g; r0 < cnt; r0 += kRow * G) {
+        float4 th[kRow];
+#pragma unroll
+        for (int q = 0; q < kRow; ++q) {
+          const int n = n0 + min(r0 + q * G, cnt - 1);  // rows past the slice are drawn, not added
+          const uint4 x = sample_words(I, n, b, tick);
+          perturb_element(c0, I.delta, nq0, nv0, n, x.x, x.y, true, th[q].x, th[q].z);
+          perturb_element(c1, I.delta, nq1, nv1, n, x.z, x.w, true, th[q].y, th[q].w);
+        }
+#pragma unroll
+        for (int q = 0; q < kRow; ++q) {
+          const int r = r0 + q * G;
+          if (r < cnt) {
+            const float wr = w[r];
+            acc.x = fmaf(wr, th[q].x, acc.x); acc.y = fmaf(wr, th[q].y, acc.y);
+            acc.z = fmaf(wr, th[q].z, acc.z); acc.w = fmaf(wr, th[q].w, acc.w);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (g < G) part[g * ec + el] = acc;
+    __syncthreads();
+    if (t < ec) {
+      float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int k = 0; k < G; ++k) {
+        const float4 a = part[k * ec + t];
+        sum.x += a.x; sum.y += a.y; sum.z += a.z; sum.w += a.w;
+      }
+      const int m = 2 * (e0 + t);
+      mine[m] = sum.x; mine[m + 1] = sum.y;
+      mine[KU + m] = sum.z; mine[KU + m + 1] = sum.w;
+    }
+  }
+}
+
+// Knots of sample n (drawn again, as above) into dst [E].
+__device__ __forceinline__ void regen_sample(const DevInst& I, const float* nom, uint32_t tick, int n, float* dst) {
+  const DevModel& M = *I.model;
+  const int KU = I.K * I.nu;
+  const float* sig = I.sigma + I.iter * I.K;
+  for (int b = threadIdx.x; b < KU / 2; b += kUpdThreads) {
+    const uint4 x = sample_words(I, n, b, tick);
+    float q0, v0, q1, v1;
+    perturb_element(elem_const(M, I, sig, 2 * b), I.delta, nom[2 * b], nom[KU + 2 * b], n, x.x, x.y, true, q0, v0);
+    perturb_element(elem_const(M, I, sig, 2 * b + 1), I.delta, nom[2 * b + 1], nom[KU + 2 * b + 1], n, x.z, x.w,
+                    true, q1, v1);
+    dst[2 * b] = q0; dst[2 * b + 1] = q1;
+    dst[KU + 2 * b] = v0; dst[KU + 2 * b + 1] = v1;
+  }
+}
+
 // The update of one instance by one workgroup (its part blockIdx.x); o: the
 // call's outputs (null fields: not wanted).
 __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut o) {
   const int part = blockIdx.x, parts = U.parts;
   if (part >= parts) return;
   const int t = threadIdx.x, N = U.N, E = U.E;
+  // the nominal the iteration's samples perturbed (the call's input on its first
+  // iteration when the caller's buffer is read in place)
+  const float* nom_in = o.nominal_in ? o.nominal_in : U.nominal_in;
+  const uint32_t tick = U.regen ? sample_tick(*U.regen) : 0u;  // read before the last part advances it
   __shared__ float s_v[kUpdThreads];
   __shared__ int s_i[kUpdThreads];
   __shared__ float s_x[kUpdThreads];
@@ -2773,7 +2898,9 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
   }
   __syncthreads();
   float* mine = U.partial + (size_t)part * E;
-  if ((E & 3) == 0)
+  if (U.regen)
+    regen_weighted_sum(*U.regen, nom_in, tick, n0, cnt, s_w, s_part, mine);
+  else if ((E & 3) == 0)
     rows_weighted_sum<4>(U.samples + (size_t)n0 * E, cnt, E, s_w, s_part,
                          [&](int e, float4 v) { reinterpret_cast<float4*>(mine)[e] = v; });
   else
@@ -2788,9 +2915,9 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
   __threadfence();
   if (t == 0) U.done[0] = 0u;  // ready for the next launch
   float* dst = (U.last_iter && o.knots_out) ? o.knots_out : U.nominal_out;
-  const float* nom_in = o.nominal_in ? o.nominal_in : U.nominal_in;
-  // the call's running best starts from its input nominal, taken before the
-  // nominal output is written (the two may be the same buffer)
+  // the call's running best starts from its input nominal; the best tracking
+  // runs before the nominal output is written, since the two may be the same
+  // buffer and a drawn-again best sample reads the input nominal
   float* bs = U.best_state;  // [E] knots, then S_best, best_iter, n_nonfinite, all_nonfinite, best_sample
   if (U.first_iter) {
     for (int e = t; e < E; e += kUpdThreads) bs[e] = nom_in[e];
@@ -2803,22 +2930,15 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
     }
   }
   __syncthreads();
-  if ((E & 3) == 0)
-    rows_weighted_sum<4>(U.partial, parts, E, nullptr, s_part, [&](int e, float4 v) {
-      const float c[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) dst[4 * e + k] = nfin > 0 ? c[k] : nom_in[4 * e + k];
-    });
-  else
-    rows_weighted_sum<1>(U.partial, parts, E, nullptr, s_part,
-                         [&](int e, float v) { dst[e] = nfin > 0 ? v : nom_in[e]; });
 
   // 5. best-sample tracking across the iterations of this call
-  __syncthreads();
   const bool improve = nfin > 0 && U.costs[nstar] < bs[E];
   __syncthreads();
-  if (improve)
-    for (int e = t; e < E; e += kUpdThreads) bs[e] = U.samples[(size_t)nstar * E + e];
+  if (improve) {
+    if (U.regen) regen_sample(*U.regen, nom_in, tick, nstar, bs);
+    else
+      for (int e = t; e < E; e += kUpdThreads) bs[e] = U.samples[(size_t)nstar * E + e];
+  }
   __syncthreads();
   if (t == 0) {
     if (improve) {
@@ -2829,6 +2949,18 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
     reinterpret_cast<int*>(bs)[E + 2] += N - nfin;
     reinterpret_cast<int*>(bs)[E + 3] += nfin == 0 ? 1 : 0;
   }
+  __syncthreads();
+
+  // 6. the nominal: the slices added in part order
+  if ((E & 3) == 0)
+    rows_weighted_sum<4>(U.partial, parts, E, nullptr, s_part, [&](int e, float4 v) {
+      const float c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dst[4 * e + k] = nfin > 0 ? c[k] : nom_in[4 * e + k];
+    });
+  else
+    rows_weighted_sum<1>(U.partial, parts, E, nullptr, s_part,
+                         [&](int e, float v) { dst[e] = nfin > 0 ? v : nom_in[e]; });
   __syncthreads();
   if (U.last_iter) {
     if (o.best_out)
@@ -2987,15 +3119,15 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
 
 // explicit instantiations
 #define MPPI_INST(G)                                                                                   \
-  template __global__ void rollout_kernel<G, 0>(const DevInst*, const int2*, int, int, const float*,         \
-                                                const float*);                                            \
-  template __global__ void rollout_kernel<G, 3>(const DevInst*, const int2*, int, int, const float*,         \
-                                                const float*);                                            \
-  template __global__ void rollout_kernel<G, 6>(const DevInst*, const int2*, int, int, const float*,         \
-                                                const float*);                                            \
-  template __global__ void rollout_trace_kernel<G, 0>(const DevInst*, const int2*, int, int);            \
-  template __global__ void rollout_trace_kernel<G, 3>(const DevInst*, const int2*, int, int);            \
-  template __global__ void rollout_trace_kernel<G, 6>(const DevInst*, const int2*, int, int);            \
+  template __global__ void rollout_kernel<G, 0, false>(const DevInst*, const int2*, int, int, const float*,  \
+                                                       const float*);                                     \
+  template __global__ void rollout_kernel<G, 3, false>(const DevInst*, const int2*, int, int, const float*,  \
+                                                       const float*);                                     \
+  template __global__ void rollout_kernel<G, 6, false>(const DevInst*, const int2*, int, int, const float*,  \
+                                                       const float*);                                     \
+  template __global__ void rollout_trace_kernel<G, 0, false>(const DevInst*, const int2*, int, int);     \
+  template __global__ void rollout_trace_kernel<G, 3, false>(const DevInst*, const int2*, int, int);     \
+  template __global__ void rollout_trace_kernel<G, 6, false>(const DevInst*, const int2*, int, int);     \
   template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int); \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \
@@ -3006,6 +3138,15 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   template __global__ void team_kernel<G, 3>(const DevInst*, const int2*, int, int);                   \
   template __global__ void team_kernel<G, 6>(const DevInst*, const int2*, int, int);                   \
   template __global__ void team_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int);
+// legged trees up to 3 levels deep (a base and 2..10 chains of up to three bodies)
+#define MPPI_LEG_INST(G)                                                                               \
+  template __global__ void rollout_kernel<G, 3, true>(const DevInst*, const int2*, int, int, const float*,   \
+                                                      const float*);                                      \
+  template __global__ void rollout_trace_kernel<G, 3, true>(const DevInst*, const int2*, int, int);
+MPPI_LEG_INST(8)
+MPPI_LEG_INST(16)
+MPPI_LEG_INST(32)
+#undef MPPI_LEG_INST
 MPPI_INST(4)
 MPPI_INST(8)
 MPPI_INST(16)
