@@ -101,7 +101,8 @@ def kernel_label(m, schedule, lanes):
     nch = [sum(1 for q in par if q == b) for b in range(len(par))]
     leg = (bool(m["floating_base"]) and len(par) > 1 and spec == 3 and 8 <= lanes <= 32
            and all(par[b] in (b - 1, 0) and nch[b] <= 1 for b in range(1, len(par))))
-    return f"rollout_kernel<{lanes}, {spec}, {'true' if leg else 'false'}>"
+    quad = leg and lanes == 16 and par == [-1, 0, 1, 2, 0, 4, 5, 0, 7, 8, 0, 10, 11]
+    return f"rollout_kernel<{lanes}, {spec}, {2 if quad else 1 if leg else 0}>"
 
 
 def oracle_flops(name):

@@ -28,9 +28,9 @@
 
 namespace mppi {
 // kernels (mppi_kernels.hip)
-template <int G, int D, bool LEG>
+template <int G, int D, int LEG>
 __global__ void rollout_kernel(const DevInst*, const int2*, int, int, const float*, const float*);
-template <int G, int D, bool LEG> __global__ void rollout_trace_kernel(const DevInst*, const int2*, int, int);
+template <int G, int D, int LEG> __global__ void rollout_trace_kernel(const DevInst*, const int2*, int, int);
 template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
 template <int G, int D> __global__ void team_kernel(const DevInst*, const int2*, int, int);
@@ -691,13 +691,21 @@ static bool legged(const DevModel& M) {
   }
   return true;
 }
+// A legged tree of four chains of three bodies (the quadruped's shape).
+static bool legged_4x3(const DevModel& M) {
+  if (!legged(M) || M.nb != 13) return false;
+  for (int k = 0; k < 4; ++k)
+    if (M.parent[1 + 3 * k] != 0 || M.parent[2 + 3 * k] != 1 + 3 * k || M.parent[3 + 3 * k] != 2 + 3 * k) return false;
+  return true;
+}
 
 struct Dims {
   int E = 0, nb = 0, nc = 0, nch = 0, natt = 0, ns = 0, depth = 0;
-  bool leg = true;  // every instance added is a legged tree
+  bool leg = true, quad = true;  // every instance added is a legged tree / of four chains of three
   void add(const mppi_ctx* c) {
     const DevModel& M = c->m->host;
     leg = leg && legged(M);
+    quad = quad && legged_4x3(M);
     E = std::max(E, c->E);
     nb = std::max(nb, M.nb);
     nc = std::max(nc, M.nc);
@@ -748,22 +756,30 @@ static int rollouts_per_block(int key, const Dims& dm) { return launch_shape(key
 // loops unrolled; deeper trees take the general one
 template <int G>
 static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2* work, const LaunchShape& sh,
-                                   int depth, bool leg, hipStream_t s, const float* x0_in, const float* nominal_in) {
+                                   const Dims& dm, hipStream_t s, const float* x0_in, const float* nominal_in) {
+  const int depth = dm.depth;
+  if constexpr (G == 16) {
+    if (depth <= 3 && dm.quad) {
+      hipLaunchKernelGGL((rollout_kernel<16, 3, 2>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride,
+                         sh.table, x0_in, nominal_in);
+      return hipGetLastError();
+    }
+  }
   if constexpr (G >= 8 && G <= 32) {
-    if (depth <= 3 && leg) {
-      hipLaunchKernelGGL((rollout_kernel<G, 3, true>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride,
+    if (depth <= 3 && dm.leg) {
+      hipLaunchKernelGGL((rollout_kernel<G, 3, 1>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride,
                          sh.table, x0_in, nominal_in);
       return hipGetLastError();
     }
   }
   if (depth <= 3)
-    hipLaunchKernelGGL((rollout_kernel<G, 3, false>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
+    hipLaunchKernelGGL((rollout_kernel<G, 3, 0>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
                        x0_in, nominal_in);
   else if (depth <= 6)
-    hipLaunchKernelGGL((rollout_kernel<G, 6, false>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
+    hipLaunchKernelGGL((rollout_kernel<G, 6, 0>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
                        x0_in, nominal_in);
   else
-    hipLaunchKernelGGL((rollout_kernel<G, 0, false>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
+    hipLaunchKernelGGL((rollout_kernel<G, 0, 0>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride, sh.table,
                        x0_in, nominal_in);
   return hipGetLastError();
 }
@@ -792,11 +808,11 @@ static hipError_t launch_rollout(int key, int blocks, const DevInst* insts, cons
   if ((x0_in || nominal_in) && !(key > 0 && key < kTeamKey)) return hipErrorInvalidValue;
   const LaunchShape sh = launch_shape(key, dm);
   switch (key) {
-    case 4: return launch_rollout_G<4>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
-    case 8: return launch_rollout_G<8>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
-    case 16: return launch_rollout_G<16>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
-    case 32: return launch_rollout_G<32>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
-    case 64: return launch_rollout_G<64>(blocks, insts, work, sh, dm.depth, dm.leg, s, x0_in, nominal_in);
+    case 4: return launch_rollout_G<4>(blocks, insts, work, sh, dm, s, x0_in, nominal_in);
+    case 8: return launch_rollout_G<8>(blocks, insts, work, sh, dm, s, x0_in, nominal_in);
+    case 16: return launch_rollout_G<16>(blocks, insts, work, sh, dm, s, x0_in, nominal_in);
+    case 32: return launch_rollout_G<32>(blocks, insts, work, sh, dm, s, x0_in, nominal_in);
+    case 64: return launch_rollout_G<64>(blocks, insts, work, sh, dm, s, x0_in, nominal_in);
     case kTeamKey + 4: return launch_team_G<4>(blocks, insts, work, sh, dm.depth, s);
     case kTeamKey + 8: return launch_team_G<8>(blocks, insts, work, sh, dm.depth, s);
     case kTeamKey + 16: return launch_team_G<16>(blocks, insts, work, sh, dm.depth, s);
@@ -1507,32 +1523,39 @@ extern "C" mppi_status mppi_debug_rollouts(mppi_ctx* c, const float* d_state, co
 // The traced twin of launch_rollout for one instance of the body schedule: the
 // same grid, block, LDS layout and depth specialisation as mppi_step's launch.
 template <int G>
-static hipError_t launch_trace_G(const DevInst* inst, int N, const LaunchShape& sh, int depth, bool leg,
-                                 hipStream_t s) {
+static hipError_t launch_trace_G(const DevInst* inst, int N, const LaunchShape& sh, const Dims& dm, hipStream_t s) {
   const int blocks = (N + sh.groups - 1) / sh.groups;
+  const int depth = dm.depth;
+  if constexpr (G == 16) {
+    if (depth <= 3 && dm.quad) {
+      hipLaunchKernelGGL((rollout_trace_kernel<16, 3, 2>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr,
+                         sh.stride, sh.table);
+      return hipGetLastError();
+    }
+  }
   if constexpr (G >= 8 && G <= 32) {
-    if (depth <= 3 && leg) {
-      hipLaunchKernelGGL((rollout_trace_kernel<G, 3, true>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr,
+    if (depth <= 3 && dm.leg) {
+      hipLaunchKernelGGL((rollout_trace_kernel<G, 3, 1>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr,
                          sh.stride, sh.table);
       return hipGetLastError();
     }
   }
   if (depth <= 3)
-    hipLaunchKernelGGL((rollout_trace_kernel<G, 3, false>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
+    hipLaunchKernelGGL((rollout_trace_kernel<G, 3, 0>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
   else if (depth <= 6)
-    hipLaunchKernelGGL((rollout_trace_kernel<G, 6, false>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
+    hipLaunchKernelGGL((rollout_trace_kernel<G, 6, 0>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
   else
-    hipLaunchKernelGGL((rollout_trace_kernel<G, 0, false>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
+    hipLaunchKernelGGL((rollout_trace_kernel<G, 0, 0>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr, sh.stride, sh.table);
   return hipGetLastError();
 }
 static hipError_t launch_trace(int key, const DevInst* inst, int N, const Dims& dm, hipStream_t s) {
   const LaunchShape sh = launch_shape(key, dm);
   switch (key) {
-    case 4: return launch_trace_G<4>(inst, N, sh, dm.depth, dm.leg, s);
-    case 8: return launch_trace_G<8>(inst, N, sh, dm.depth, dm.leg, s);
-    case 16: return launch_trace_G<16>(inst, N, sh, dm.depth, dm.leg, s);
-    case 32: return launch_trace_G<32>(inst, N, sh, dm.depth, dm.leg, s);
-    case 64: return launch_trace_G<64>(inst, N, sh, dm.depth, dm.leg, s);
+    case 4: return launch_trace_G<4>(inst, N, sh, dm, s);
+    case 8: return launch_trace_G<8>(inst, N, sh, dm, s);
+    case 16: return launch_trace_G<16>(inst, N, sh, dm, s);
+    case 32: return launch_trace_G<32>(inst, N, sh, dm, s);
+    case 64: return launch_trace_G<64>(inst, N, sh, dm, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -243,6 +243,12 @@ __device__ __forceinline__ float from_prev_lane(float x) {
 __device__ __forceinline__ float from_next_lane(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x130, 0xf, 0xf, true));
 }
+// value held by lane l + N of this lane's row of 16 lanes (DPP row shift;
+// every lane must be active; lanes past the row's end read 0)
+template <int N>
+__device__ __forceinline__ float from_row_lane(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x100 + N, 0xf, 0xf, true));
+}
 // value held by the first lane of this lane's rollout group of G lanes (groups
 // are aligned): a swizzle in bit-mask mode that clears the low lane-index bits
 // within each 32-lane half, or the first lane for a whole wavefront; every lane
@@ -822,14 +828,16 @@ __device__ __forceinline__ float forward_joint(const float* al, const float* e, 
 template <int D> constexpr int kLevelUnroll = D > 0 ? D : 1;
 template <int D> constexpr int kLevelUnrollRoot = D > 0 ? D + 1 : 1;
 
-// LEG: the tree is a floating base with serial chains hanging off it (every
-// joint body's parent is the previous lane, or the base for a chain's first
-// body; no body but the base has more than one child), so a frame, an
+// LEG = 1: the tree is a floating base with serial chains hanging off it
+// (every joint body's parent is the previous lane, or the base for a chain's
+// first body; no body but the base has more than one child), so a frame, an
 // acceleration or a carried inertia always comes from the neighbouring lane
-// except the base's, which gathers the chains through LDS.  The same
-// arithmetic as the general form, with its LDS paths and their branches
-// compiled out.
-template <int G, int D = 0, bool LEG = false>
+// except the base's, which gathers the chains through LDS.  LEG = 2: such a
+// tree with four chains of three bodies in groups of 16 lanes (the chains'
+// first bodies at lanes 1, 4, 7 and 10), whose base gathers the chains by row
+// shifts instead.  The same arithmetic as the general form (children added in
+// the same order), with its LDS paths and their branches compiled out.
+template <int G, int D = 0, int LEG = 0>
 __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const float* tab, float* __restrict__ gs,
                              int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
   const int maxd = D > 0 ? D : sc.max_depth;
@@ -901,7 +909,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
         fk_base_child(io.bv, C, bc.p_tree, bc.axis_p, io.v, R, p, e, ax, v, c, beta);
       } else {
         float Rl[9], pl[3], vl[6], bl[6];
-        if (LEG || (bc.flags & kAdjParent)) {
+        if (LEG != 0 || (bc.flags & kAdjParent)) {
 #pragma unroll
           for (int k = 0; k < 9; ++k) Rl[k] = sR[k];
 #pragma unroll
@@ -920,7 +928,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
         }
         fk_joint(Rl, pl, vl, bl, C, bc.p_tree, bc.axis_p, io.v, R, p, e, ax, v, c, beta);
       }
-      if (!LEG && (bc.flags & kFrameOut)) put_frame(slots + b * kSlot, R, p, v, beta);
+      if (LEG == 0 && (bc.flags & kFrameOut)) put_frame(slots + b * kSlot, R, p, v, beta);
     }
     wave_sync();
   }
@@ -977,15 +985,43 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // ---- backward sweep, leaves to root: each joint lane publishes its
   //      articulated inertia and bias already carried to its parent's origin
   float U[6], invD = 0.f, u = 0.f;
+  // kFoldAll (trees at most three levels deep): the inertia and bias carried to
+  // the parent are zero until the lane's own level, then its body's (kept for
+  // the rest of the sweep), and every lane adds its next lane's after each
+  // level.  Deeper trees keep them per level (unset on lanes of other levels)
+  // and add them on the parents only, which needs fewer registers.
+  constexpr bool kFoldAll = D > 0 && D <= 3;
+  float Ip[21], pp[6];
+  if constexpr (kFoldAll) {
+#pragma unroll
+    for (int q = 0; q < 21; ++q) Ip[q] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) pp[q] = 0.f;
+  }
 #pragma unroll kLevelUnrollRoot<D>
   for (int d = maxd; d >= 0; --d) {
-    // inertia and bias carried to the parent by the lanes of level d; other lanes
-    // leave them unset (their values are never read: a parent takes them only
-    // from a child of level d)
-    float Ip[21], pp[6];
+    if constexpr (LEG == 2) {
+      if (d == 0) {
+        // the base adds chains 2, 3 and 4 (lanes 4, 7 and 10 of the group) in
+        // child order; every lane adds, only the base's sums are used (the
+        // joint lanes' articulated inertias are no longer needed)
+#pragma unroll
+        for (int q = 0; q < 21; ++q) IA[q] += from_row_lane<4>(Ip[q]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) pA[q] += from_row_lane<4>(pp[q]);
+#pragma unroll
+        for (int q = 0; q < 21; ++q) IA[q] += from_row_lane<7>(Ip[q]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) pA[q] += from_row_lane<7>(pp[q]);
+#pragma unroll
+        for (int q = 0; q < 21; ++q) IA[q] += from_row_lane<10>(Ip[q]);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) pA[q] += from_row_lane<10>(pp[q]);
+      }
+    }
     if (body_lane && depth == d) {
       const int nch = bc.n_child;
-      if ((!LEG || d == 0) && nch > 0) {
+      if (LEG != 2 && (LEG == 0 || d == 0) && nch > 0) {
         // children reached through LDS: the first kFold records are read together
         // (a missing child reads this lane's own slot and is not added), then
         // added in child order; more children follow one by one
@@ -1013,22 +1049,35 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
       }
       if (is_joint) {
         backward_joint(IA, pA, ax, c, e, tau, bc.arm, gain, U, invD, u, Ip, pp);
-        if ((!LEG || d == 1) && (bc.flags & kArtOut)) put_art(slots + b * kSlot, Ip, pp);
+        if (LEG != 2 && (LEG == 0 || d == 1) && (bc.flags & kArtOut)) put_art(slots + b * kSlot, Ip, pp);
       }
     }
     wave_sync();
     if (d > 0) {
-      // a parent at level d - 1 adds its first child's contribution first, then the others'
-      float sI[21], spp[6];
+      // a parent at level d - 1 adds its first child's contribution first, then
+      // the others'
+      if constexpr (kFoldAll) {
+        // every lane adds its next lane's carried inertia (one DPP add): in a
+        // depth-first numbering the next body is this body's child iff it is
+        // one level deeper, so a lane of level d - 1 takes its first child's; a
+        // lane not yet swept takes a zero (its next lane is not swept yet
+        // either); a lane already swept no longer needs its sums
 #pragma unroll
-      for (int q = 0; q < 21; ++q) sI[q] = from_next_lane(Ip[q]);
+        for (int q = 0; q < 21; ++q) IA[q] += from_next_lane(Ip[q]);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) spp[q] = from_next_lane(pp[q]);
-      if (body_lane && depth == d - 1 && (bc.flags & kAdjChild)) {
+        for (int q = 0; q < 6; ++q) pA[q] += from_next_lane(pp[q]);
+      } else {
+        float sI[21], spp[6];
 #pragma unroll
-        for (int q = 0; q < 21; ++q) IA[q] += sI[q];
+        for (int q = 0; q < 21; ++q) sI[q] = from_next_lane(Ip[q]);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) pA[q] += spp[q];
+        for (int q = 0; q < 6; ++q) spp[q] = from_next_lane(pp[q]);
+        if (body_lane && depth == d - 1 && (bc.flags & kAdjChild)) {
+#pragma unroll
+          for (int q = 0; q < 21; ++q) IA[q] += sI[q];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) pA[q] += spp[q];
+        }
       }
     }
   }
@@ -1054,7 +1103,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
       if (fb && d == 1) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) al[k] = a0[k];
-      } else if (LEG || (bc.flags & kAdjParent)) {
+      } else if (LEG != 0 || (bc.flags & kAdjParent)) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) al[k] = sa[k];
       } else if (lam >= 0) {
@@ -1064,7 +1113,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
         al[0] = al[1] = al[2] = 0.f; al[3] = 0.f; al[4] = 0.f; al[5] = g;
       }
       qdd = forward_joint(al, e, c, U, u, invD, ax, a);
-      if (!LEG && (bc.flags & kFrameOut)) put_acc(slots + b * kSlot, a);
+      if (LEG == 0 && (bc.flags & kFrameOut)) put_acc(slots + b * kSlot, a);
     }
     wave_sync();
     if (d < maxd) {
@@ -1314,7 +1363,7 @@ __device__ __forceinline__ void trace_record(const DevInst& I, int n, bool valid
 
 // x0_in / nominal_in (nullable) replace the instance's staged state and nominal.
 // TR: also write the per-step records of traced rollouts (verification kernel).
-template <int G, int D = 0, bool TR = false, bool LEG = false>
+template <int G, int D = 0, bool TR = false, int LEG = 0>
 __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride,
                                                             int table_floats, float* smem, int steps,
                                                             float* state_out, const float* x0_in = nullptr,
@@ -1451,8 +1500,8 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 // D > 0: every instance of the launch is at most D levels deep.
 // x0_in / nominal_in (nullable, one instance only): the state and the nominal
 // to use instead of the instance's staged copies.
-// LEG: every instance of the launch is a legged tree (see physics_step).
-template <int G, int D, bool LEG>
+// LEG: every instance of the launch is a legged tree of that kind (see physics_step).
+template <int G, int D, int LEG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_kernel(
     const DevInst* __restrict__ insts, const int2* __restrict__ work, int group_stride, int table_floats,
     const float* __restrict__ x0_in, const float* __restrict__ nominal_in) {
@@ -1465,7 +1514,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ro
 
 // The rollout kernel with per-step records of the traced rollouts (same launch
 // shape and arithmetic; verification only).
-template <int G, int D, bool LEG>
+template <int G, int D, int LEG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_trace_kernel(
     const DevInst* __restrict__ insts, const int2* __restrict__ work, int group_stride, int table_floats) {
   extern __shared__ float smem[];
@@ -3119,15 +3168,15 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
 
 // explicit instantiations
 #define MPPI_INST(G)                                                                                   \
-  template __global__ void rollout_kernel<G, 0, false>(const DevInst*, const int2*, int, int, const float*,  \
+  template __global__ void rollout_kernel<G, 0, 0>(const DevInst*, const int2*, int, int, const float*,  \
                                                        const float*);                                     \
-  template __global__ void rollout_kernel<G, 3, false>(const DevInst*, const int2*, int, int, const float*,  \
+  template __global__ void rollout_kernel<G, 3, 0>(const DevInst*, const int2*, int, int, const float*,  \
                                                        const float*);                                     \
-  template __global__ void rollout_kernel<G, 6, false>(const DevInst*, const int2*, int, int, const float*,  \
+  template __global__ void rollout_kernel<G, 6, 0>(const DevInst*, const int2*, int, int, const float*,  \
                                                        const float*);                                     \
-  template __global__ void rollout_trace_kernel<G, 0, false>(const DevInst*, const int2*, int, int);     \
-  template __global__ void rollout_trace_kernel<G, 3, false>(const DevInst*, const int2*, int, int);     \
-  template __global__ void rollout_trace_kernel<G, 6, false>(const DevInst*, const int2*, int, int);     \
+  template __global__ void rollout_trace_kernel<G, 0, 0>(const DevInst*, const int2*, int, int);     \
+  template __global__ void rollout_trace_kernel<G, 3, 0>(const DevInst*, const int2*, int, int);     \
+  template __global__ void rollout_trace_kernel<G, 6, 0>(const DevInst*, const int2*, int, int);     \
   template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int); \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \
@@ -3140,13 +3189,16 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   template __global__ void team_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int);
 // legged trees up to 3 levels deep (a base and 2..10 chains of up to three bodies)
 #define MPPI_LEG_INST(G)                                                                               \
-  template __global__ void rollout_kernel<G, 3, true>(const DevInst*, const int2*, int, int, const float*,   \
+  template __global__ void rollout_kernel<G, 3, 1>(const DevInst*, const int2*, int, int, const float*,   \
                                                       const float*);                                      \
-  template __global__ void rollout_trace_kernel<G, 3, true>(const DevInst*, const int2*, int, int);
+  template __global__ void rollout_trace_kernel<G, 3, 1>(const DevInst*, const int2*, int, int);
 MPPI_LEG_INST(8)
 MPPI_LEG_INST(16)
 MPPI_LEG_INST(32)
 #undef MPPI_LEG_INST
+// four chains of three bodies on 16 lanes (the quadruped's shape)
+template __global__ void rollout_kernel<16, 3, 2>(const DevInst*, const int2*, int, int, const float*, const float*);
+template __global__ void rollout_trace_kernel<16, 3, 2>(const DevInst*, const int2*, int, int);
 MPPI_INST(4)
 MPPI_INST(8)
 MPPI_INST(16)
