@@ -250,13 +250,18 @@ __device__ __forceinline__ float from_row_lane(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x100 + N, 0xf, 0xf, true));
 }
 // value held by the first lane of this lane's rollout group of G lanes (groups
-// are aligned): a swizzle in bit-mask mode that clears the low lane-index bits
-// within each 32-lane half, or the first lane for a whole wavefront; every lane
-// must be active
+// are aligned): for G = 16 a DPP broadcast of each row's lane 0
+// (row_newbcast:0), for G = 4 a quad permutation (0, 0, 0, 0), else a swizzle
+// in bit-mask mode that clears the low lane-index bits within each 32-lane
+// half, or the first lane for a whole wavefront; every lane must be active
 template <int G>
 __device__ __forceinline__ float from_group_lane0(float x) {
   if constexpr (G == 64) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+  } else if constexpr (G == 16) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x150, 0xf, 0xf, false));
+  } else if constexpr (G == 4) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x00, 0xf, 0xf, false));
   } else {
     constexpr int and_mask = 0x1f & ~(G - 1);
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), and_mask));
@@ -825,6 +830,34 @@ __device__ __forceinline__ float forward_joint(const float* al, const float* e, 
 // D > 0: the tree is at most D levels deep, fixed at compile time so the level
 // loops unroll (levels below the tree have no body and cost only their shifts).
 // Unroll counts of the loops over levels 1..D and D..0 (1: a run-time loop).
+// A body's kinematics in a physics step (base axes, about the body origin):
+// rotation R, origin p, lever arm e from the parent origin, joint axis ax,
+// twist v, velocity product c and bias acceleration beta.  The base's R, p and
+// beta are the identity frame and zero (base_frame).  The legged-tree kernels
+// keep it across steps (set once by init_kin): a lane whose frame a neighbour
+// reads before the lane's own level then hands over its previous step's
+// values, which the neighbour does not use (the compiler would otherwise
+// materialise the not-yet-computed values); the other kernels, with less
+// register room, take it fresh every step.
+struct BodyKin {
+  float R[9], p[3], e[3], ax[3], v[6], c[6], beta[6];
+};
+__device__ __forceinline__ void base_frame(BodyKin& k) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) k.R[i] = (i % 4 == 0) ? 1.f : 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k.p[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) k.beta[i] = 0.f;
+}
+__device__ __forceinline__ void init_kin(BodyKin& k) {
+  base_frame(k);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k.e[i] = k.ax[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) k.v[i] = k.c[i] = 0.f;
+}
+
 template <int D> constexpr int kLevelUnroll = D > 0 ? D : 1;
 template <int D> constexpr int kLevelUnrollRoot = D > 0 ? D + 1 : 1;
 
@@ -839,7 +872,8 @@ template <int D> constexpr int kLevelUnrollRoot = D > 0 ? D + 1 : 1;
 // the same order), with its LDS paths and their branches compiled out.
 template <int G, int D = 0, int LEG = 0>
 __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const float* tab, float* __restrict__ gs,
-                             int b, bool body_lane, StepIO& io, bool want_cost, bool terminal = false) {
+                             int b, bool body_lane, StepIO& io, BodyKin& kin_kept, bool want_cost,
+                             bool terminal = false) {
   const int maxd = D > 0 ? D : sc.max_depth;
   // the joint-rotation constants are read first so the LDS latency passes
   // under the PD law, the base cost and frame B
@@ -852,7 +886,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
     Ib[4 * k] = x.x; Ib[4 * k + 1] = x.y; Ib[4 * k + 2] = x.z; Ib[4 * k + 3] = x.w;
   }
   float* slots = gs;
-  const int fb = sc.fb;
+  const int fb = LEG != 0 ? 1 : sc.fb;  // legged trees have a floating base
   const bool is_base = body_lane && fb && b == 0;
   const bool is_joint = body_lane && !is_base;
 
@@ -876,15 +910,20 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   }
 
   // ---- forward kinematics, level by level (slot: R, p, v, beta about the body origin)
-  float R[9], p[3], e[3], ax[3], v[6], c[6], beta[6];
+  BodyKin kin_step;  // the other kernels: fresh every step
+  BodyKin& kin = LEG != 0 ? kin_kept : kin_step;
+  float(&R)[9] = kin.R;
+  float(&p)[3] = kin.p;
+  float(&e)[3] = kin.e;
+  float(&ax)[3] = kin.ax;
+  float(&v)[6] = kin.v;
+  float(&c)[6] = kin.c;
+  float(&beta)[6] = kin.beta;
   const int depth = bc.depth;
   if (is_base) {  // (lever arm, axis and velocity product are never read for the base)
+    if constexpr (LEG == 0) base_frame(kin);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.f : 0.f;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) p[k] = 0.f;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) { v[k] = io.bv[k]; beta[k] = 0.f; }
+    for (int k = 0; k < 6; ++k) v[k] = io.bv[k];
   }
   float C[9];
   if (is_joint) {
@@ -1390,7 +1429,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   wave_sync();
 
   const StepConst sc = load_step_const(M, &I, 0.f);
-  const int fb = sc.fb, nb = M.nb, nq = fb ? 7 + M.nu : M.nu;
+  const int fb = LEG != 0 ? 1 : sc.fb, nb = M.nb, nq = fb ? 7 + M.nu : M.nu;
   const bool body_lane = l < nb;
   const int b = l;
   const bool is_joint = body_lane && !(fb && b == 0);
@@ -1412,6 +1451,8 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
 
   BodyConst bc;
   load_body(M, &I, b, body_lane, tab, bc);
+  BodyKin kin_kept;  // legged trees: kept across the steps (see BodyKin)
+  if constexpr (LEG != 0) init_kin(kin_kept);
   uint32_t* const masks = I.masks;
   const int H = I.H, F = sc.F, F_run = steps * sc.nsub;
   float acc = 0.f;
@@ -1430,7 +1471,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     // (lanes without a joint evaluate zero knots and never use the result)
     hermite_eval(hs, (float)clk.rem * sc.inv_F, sc.inv_delta, &io.qref, &io.vref);
     if (sc.spline_mode != 0) io.vref = 0.f;  // position-only variants: zero velocity targets
-    physics_step<G, D, LEG>(sc, bc, tab, gs, b, body_lane, io, control);
+    physics_step<G, D, LEG>(sc, bc, tab, gs, b, body_lane, io, kin_kept, control);
     if (control) {
       acc += io.cost;
       if (masks) {
@@ -1480,7 +1521,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     }
   } else {
     // end-effector height at x_H
-    physics_step<G, D, LEG>(sc, bc, tab, gs, b, body_lane, io, false, true);
+    physics_step<G, D, LEG>(sc, bc, tab, gs, b, body_lane, io, kin_kept, false, true);
     acc += io.cost;
   }
   if (TR && masks && I.trace) {
@@ -3159,7 +3200,8 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   io.dt = dt;
   BodyConst bc;
   load_body(M, nullptr, l, body_lane, tab, bc);
-  physics_step<G>(sc, bc, tab, gs, l, body_lane, io, false);
+  BodyKin kin;  // (unused: the general kernel takes its kinematics fresh)
+  physics_step<G>(sc, bc, tab, gs, l, body_lane, io, kin, false);
   if (!valid) return;
   if (is_joint) qdd[(size_t)s * nv + (fb ? 6 : 0) + j] = io.qdd;
   if (fb && l == 0)
