@@ -30,6 +30,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Branch-weight hint for a rare path when H holds (a compile-time constant),
+// else the condition as is.  With one wavefront per SIMD every taken branch
+// costs that wavefront an instruction refetch, so the legged kernels ask for
+// their rare paths to be laid out of line; the general kernels keep the default
+// layout (with the hints their register allocation spills).  A macro: the hint
+// has to sit in the branch's own condition.
+#define MPPI_RARE(H, c) ((H) ? __builtin_expect(!!(c), 0) : !!(c))
+
 // Philox4x32-10 (Salmon et al., SC'11).
 __device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
 #pragma unroll
@@ -1288,9 +1296,10 @@ __device__ __forceinline__ void hermite(const float* knots, int K, int nu, float
 // control-step index.
 struct StepClock {
   int seg = 0, rem = 0, sub = 0, h = 0;
+  template <bool H = false>
   __device__ __forceinline__ void advance(int K, int F, int nsub) {
     rem += K - 1;
-    while (rem >= F) {
+    while (MPPI_RARE(H, rem >= F)) {
       rem -= F;
       ++seg;
     }
@@ -1326,6 +1335,7 @@ __device__ __forceinline__ uint32_t group_or(uint32_t x, float* red, int l) {
 
 // semi-implicit Euler on the base: v += dt a, p += dt R(quat) v_lin, quat <- quat (x) exp(dt w)
 // (R: the rotation of the quaternion bq[3..6], as quat_R gives it)
+template <bool H = false>
 __device__ __forceinline__ void integrate_base_R(float* bq, float* bv, const float* ba, float dt, const float* R) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) bv[k] = fmaf(dt, ba[k], bv[k]);
@@ -1339,7 +1349,7 @@ __device__ __forceinline__ void integrate_base_R(float* bq, float* bv, const flo
   const float t2 = (hdt * hdt) * wn2;
   float e0 = 1.f + t2 * (-0.5f + t2 * (1.f / 24.f + t2 * (-1.f / 720.f)));
   float k = hdt * (1.f + t2 * (-1.f / 6.f + t2 * (1.f / 120.f + t2 * (-1.f / 5040.f))));
-  if (!(t2 < 0.0625f)) {
+  if (MPPI_RARE(H, !(t2 < 0.0625f))) {
     const float wn = sqrtf(wn2);
     float sn, cs;
     sincosf(hdt * wn, &sn, &cs);
@@ -1464,7 +1474,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   int hseg = -1;
   for (int f = 0; f < F_run; ++f) {
     const bool control = clk.sub == 0;
-    if (D == 0 || clk.seg != hseg) {
+    if (D == 0 || MPPI_RARE(LEG != 0, clk.seg != hseg)) {
       hseg = clk.seg;
       if (is_joint) hs = hermite_segment(knots, sc.K, sc.nu, hseg, j, sc.delta);
     }
@@ -1474,7 +1484,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     physics_step<G, D, LEG>(sc, bc, tab, gs, b, body_lane, io, kin_kept, control);
     if (control) {
       acc += io.cost;
-      if (masks) {
+      if (MPPI_RARE(LEG != 0, masks != nullptr)) {
         const uint32_t mk = group_or<G>(io.mask, red, l);
         if (l == 0 && valid) masks[(size_t)n * H + clk.h] = mk;
         if (TR && I.trace) {
@@ -1486,8 +1496,8 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     // joints (other lanes hold q = qd = qdd = 0)
     io.v = fmaf(io.dt, io.qdd, io.v);
     io.q = fmaf(io.dt, io.v, io.q);
-    if (fb) integrate_base_R(io.bq, io.bv, io.ba, io.dt, io.Rb);  // every lane: the same base state
-    clk.advance(sc.K, F, sc.nsub);
+    if (fb) integrate_base_R<LEG != 0>(io.bq, io.bv, io.ba, io.dt, io.Rb);  // every lane: the same base state
+    clk.advance<LEG != 0>(sc.K, F, sc.nsub);
   }
   if (state_out) {
     if (valid) {
