@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -31,7 +32,8 @@ namespace mppi {
 template <int G, int D, int LEG>
 __global__ void rollout_kernel(const DevInst*, const int2*, int, int, const float*, const float*);
 template <int G, int D, int LEG> __global__ void rollout_trace_kernel(const DevInst*, const int2*, int, int);
-template <int G> __global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
+template <int G, int D, int LEG>
+__global__ void rollout_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
 template <int GC> __global__ void chain_kernel(const DevInst*, const int2*, int, int, int);
 template <int G, int D> __global__ void team_kernel(const DevInst*, const int2*, int, int);
 template <int G> __global__ void team_persistent_kernel(const DevInst*, const int2*, int, unsigned int*, int, int);
@@ -45,7 +47,7 @@ __global__ void shift_knots_kernel(const float*, float*, int, int, int, int, int
 template <int G>
 __global__ void dynamics_kernel(const DevModel*, int, const float*, const float*, const float*, const float*, float,
                                 float*, int, int);
-__global__ void update_kernel(const DevUpdate*, const UpdateOut*, UpdateOut);
+template <int T> __global__ void update_kernel(const DevUpdate*, const UpdateOut*, UpdateOut);
 __global__ void update_single_kernel(DevUpdate);
 __global__ void set_targets_kernel(DevTargets*, DevTargets);
 struct StageItem {
@@ -109,7 +111,7 @@ struct mppi_ctx {
   float *x_meas = nullptr, *pred_knots = nullptr, *pred_cost = nullptr;
   DevInst* d_pred_inst = nullptr;
   uint32_t* tick = nullptr;
-  float* upd_partial = nullptr;  // [update_parts(N)][E] update scratch
+  float* upd_partial = nullptr;  // [update_shape(N).parts][E] update scratch
   uint32_t* upd_done = nullptr;  // update parts finished (0 between launches)
   DevInst* d_insts = nullptr;   // [I]
   DevUpdate* d_ups = nullptr;   // [I]
@@ -488,7 +490,8 @@ static void build_tables(mppi_ctx* c) {
     u.done = c->upd_done;
     u.N = c->N; u.E = c->E; u.iter = it; u.weight_mode = c->p.weight_mode;
     u.first_iter = it == 0; u.last_iter = it == c->I - 1;
-    u.parts = update_parts(c->N);
+    u.parts = update_shape(c->N).parts;
+    u.threads = update_shape(c->N).threads;
     u.lambda = c->p.lambda;
   }
 }
@@ -551,7 +554,7 @@ extern "C" mppi_status mppi_create(const mppi_model* m, const mppi_params* p, ui
   if ((e = hipMalloc(&c->f0z, std::max(M.nc, 1) * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc f0z");
   if ((e = hipMalloc(&c->q0, c->nu * sizeof(float))) != hipSuccess) return bail(e, "hipMalloc q0");
   if ((e = hipMalloc(&c->tick, sizeof(uint32_t))) != hipSuccess) return bail(e, "hipMalloc tick");
-  if ((e = hipMalloc(&c->upd_partial, (size_t)update_parts(c->N) * E * sizeof(float))) != hipSuccess)
+  if ((e = hipMalloc(&c->upd_partial, (size_t)update_shape(c->N).parts * E * sizeof(float))) != hipSuccess)
     return bail(e, "hipMalloc update scratch");
   if ((e = hipMalloc(&c->upd_done, sizeof(uint32_t))) != hipSuccess) return bail(e, "hipMalloc update counter");
   if ((e = hipMalloc(&c->d_insts, c->I * sizeof(DevInst))) != hipSuccess) return bail(e, "hipMalloc insts");
@@ -839,10 +842,25 @@ static hipError_t launch_persistent_k(Kern kern, int n_items, const LaunchShape&
   return hipGetLastError();
 }
 
+// the persistent body-schedule kernel with the specialisation launch_rollout_G would take
+template <int G>
+static hipError_t launch_persistent_body(int n_items, const LaunchShape& sh, const Dims& dm, unsigned int* counter,
+                                         hipStream_t s, const DevInst* insts, const int2* work) {
+#define P_ARGS n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table
+  if constexpr (G == 16)
+    if (dm.depth <= 3 && dm.quad) return launch_persistent_k(rollout_persistent_kernel<16, 3, 2>, P_ARGS);
+  if constexpr (G >= 8 && G <= 32)
+    if (dm.depth <= 3 && dm.leg) return launch_persistent_k(rollout_persistent_kernel<G, 3, 1>, P_ARGS);
+  if (dm.depth <= 3) return launch_persistent_k(rollout_persistent_kernel<G, 3, 0>, P_ARGS);
+  if (dm.depth <= 6) return launch_persistent_k(rollout_persistent_kernel<G, 6, 0>, P_ARGS);
+  return launch_persistent_k(rollout_persistent_kernel<G, 0, 0>, P_ARGS);
+#undef P_ARGS
+}
+
 static hipError_t launch_persistent(int key, int n_items, const DevInst* insts, const int2* work, const Dims& dm,
                                     unsigned int* counter, hipStream_t s) {
   const LaunchShape sh = launch_shape(key, dm);
-#define BODY_P(G) launch_persistent_k(rollout_persistent_kernel<G>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table)
+#define BODY_P(G) launch_persistent_body<G>(n_items, sh, dm, counter, s, insts, work)
 #define CHAIN_P(GC) launch_persistent_k(chain_persistent_kernel<GC>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table, sh.groups)
 #define TEAM_P(G) launch_persistent_k(team_persistent_kernel<G>, n_items, sh, counter, s, insts, work, n_items, counter, sh.stride, sh.table)
   switch (key) {
@@ -868,6 +886,40 @@ static hipError_t launch_persistent(int key, int n_items, const DevInst* insts, 
 }
 
 static std::atomic<int> g_persistent{0};
+
+// Grid of an iteration's update launches over a table of instances ordered with
+// the 64-thread updates first (update_shape): n64 instances of at most parts64
+// parts, then n256 of at most parts256.
+struct UpdGrid {
+  int n64 = 0, parts64 = 1, n256 = 0, parts256 = 1;
+  void add(const DevUpdate& u) {
+    if (u.threads == 64) {
+      ++n64;
+      parts64 = std::max(parts64, u.parts);
+    } else {
+      ++n256;
+      parts256 = std::max(parts256, u.parts);
+    }
+  }
+};
+// instance order for such a table: the 64-thread updates first, otherwise as given
+static void order_by_update_shape(std::vector<int>& idx, const std::function<int(int)>& n_of) {
+  std::stable_partition(idx.begin(), idx.end(), [&](int i) { return update_shape(n_of(i)).threads == 64; });
+}
+static hipError_t launch_updates(const DevUpdate* ups, const UpdateOut* outs, const UpdGrid& g, hipStream_t s) {
+  const UpdateOut none{nullptr, nullptr, nullptr, nullptr};
+  if (g.n64 > 0) hipLaunchKernelGGL(update_kernel<64>, dim3(g.parts64, g.n64), dim3(64), 0, s, ups, outs, none);
+  if (g.n256 > 0)
+    hipLaunchKernelGGL(update_kernel<kUpdThreads>, dim3(g.parts256, g.n256), dim3(kUpdThreads), 0, s, ups + g.n64,
+                       outs ? outs + g.n64 : nullptr, none);
+  return hipGetLastError();
+}
+// one instance's update (its shape), with the call's outputs o
+static hipError_t launch_update1(const DevUpdate* u, const DevUpdate& h, const UpdateOut& o, hipStream_t s) {
+  if (h.threads == 64) hipLaunchKernelGGL(update_kernel<64>, dim3(h.parts, 1), dim3(64), 0, s, u, nullptr, o);
+  else hipLaunchKernelGGL(update_kernel<kUpdThreads>, dim3(h.parts, 1), dim3(kUpdThreads), 0, s, u, nullptr, o);
+  return hipGetLastError();
+}
 
 extern "C" mppi_status mppi_set_batch_options(const mppi_batch_opts* o) {
   if (!o) return fail(MPPI_EINVAL, "null options");
@@ -900,8 +952,7 @@ static mppi_status run_iterations(mppi_ctx* c, float* d_knots_out, float* d_best
     if (c->profile) HIP_TRY(hipEventRecord(mk[1], s));
     UpdateOut o{nullptr, nullptr, nullptr, nom0};
     if (it == c->I - 1) o = UpdateOut{d_knots_out, d_best_knots, d_info, nom0};
-    hipLaunchKernelGGL(update_kernel, dim3(c->h_ups[it].parts, 1), dim3(kUpdThreads), 0, s, c->d_ups + it, nullptr, o);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_update1(c->d_ups + it, c->h_ups[it], o, s));
     if (c->profile) {
       HIP_TRY(hipEventRecord(mk[2], s));
       c->ev_marks.push_back(mk);
@@ -1029,7 +1080,7 @@ struct IterPlan {
   DevUpdate* ups = nullptr;     // device [n_active]
   std::vector<int> active;      // instance indices (into the batch) active in this iteration
   std::vector<GroupLaunch> groups;
-  int upd_parts = 1;            // update grid width: the most parts of an active instance
+  UpdGrid upd;                  // update launches (active holds the 64-thread updates first)
 };
 struct Plan {
   std::vector<const mppi_ctx*> ctxs;
@@ -1081,12 +1132,13 @@ static mppi_status build_plan(const std::vector<const mppi_ctx*>& ctxs, Plan** o
     IterPlan& ip = plan->iters[it];
     std::vector<DevInst> hi;
     std::vector<DevUpdate> hu;
-    for (int i = 0; i < (int)ctxs.size(); ++i) {
-      if (ctxs[i]->I <= it) continue;
-      ip.active.push_back(i);
+    for (int i = 0; i < (int)ctxs.size(); ++i)
+      if (ctxs[i]->I > it) ip.active.push_back(i);
+    order_by_update_shape(ip.active, [&](int i) { return ctxs[i]->N; });
+    for (int i : ip.active) {
       hi.push_back(ctxs[i]->h_insts[it]);
       hu.push_back(ctxs[i]->h_ups[it]);
-      ip.upd_parts = std::max(ip.upd_parts, hu.back().parts);
+      ip.upd.add(hu.back());
     }
     HIP_TRY(hipMalloc(&ip.insts, hi.size() * sizeof(DevInst)));
     HIP_TRY(hipMemcpy(ip.insts, hi.data(), hi.size() * sizeof(DevInst), hipMemcpyHostToDevice));
@@ -1224,10 +1276,7 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
       else
         HIP_TRY(launch_rollout(g.G, g.blocks, ip.insts, g.work, g.dims, s));
     }
-    hipLaunchKernelGGL(update_kernel, dim3(ip.upd_parts, (unsigned)ip.active.size()), dim3(kUpdThreads), 0, s, ip.ups,
-                       d_outs + out_off[it],
-                       UpdateOut{nullptr, nullptr, nullptr});
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_updates(ip.ups, d_outs + out_off[it], ip.upd, s));
   }
   HIP_TRY(hipEventRecord(r->ev, s));
   return MPPI_OK;
@@ -1304,8 +1353,7 @@ extern "C" mppi_status mppi_graph_create(int32_t n, mppi_ctx* const* ctxs, const
                          : launch_rollout(gl.G, gl.blocks, ip.insts, gl.work, gl.dims, cs);
         if (e != hipSuccess) break;
       }
-      hipLaunchKernelGGL(update_kernel, dim3(ip.upd_parts, (unsigned)ip.active.size()), dim3(kUpdThreads), 0, cs, ip.ups,
-                         d_outs + out_off[it], UpdateOut{nullptr, nullptr, nullptr});
+      if (e == hipSuccess) e = launch_updates(ip.ups, d_outs + out_off[it], ip.upd, cs);
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
@@ -1605,9 +1653,7 @@ extern "C" mppi_status mppi_debug_update(mppi_ctx* c, const float* d_costs, cons
   DevUpdate* d = nullptr;
   HIP_TRY(hipMalloc(&d, sizeof(DevUpdate)));
   HIP_TRY(hipMemcpyAsync(d, &h, sizeof(DevUpdate), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(update_kernel, dim3(h.parts, 1), dim3(kUpdThreads), 0, s, d, nullptr,
-                     UpdateOut{nullptr, nullptr, nullptr});
-  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_update1(d, h, UpdateOut{nullptr, nullptr, nullptr, nullptr}, s));
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipFree(d));
   return MPPI_OK;
@@ -1677,6 +1723,7 @@ extern "C" mppi_status mppi_update_noalloc(int32_t n_samples, int32_t n_elems, f
   u.weight_mode = weight_mode;
   u.first_iter = 1;
   u.parts = update_parts(n_samples);
+  u.threads = kUpdThreads;
   u.lambda = lambda;
   // the counter is left at zero by every complete launch; cleared here too (a
   // fill kernel, so the call can be captured in a graph) in case an earlier
@@ -1786,10 +1833,10 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
     Imax = std::max(Imax, n_iters[i]);
   }
   struct GroupDesc { int G; Dims dims; size_t work_off; int n_items; };
-  // upd_parts: the update grid's width, the most parts (blocks) of an active
-  // instance; blocks beyond an instance's own parts return at once but would
-  // still wait for a free slot on a busy device
-  struct IterDesc { size_t inst_off, up_off, out_off; int n_active, upd_parts = 1; std::vector<GroupDesc> groups; };
+  // upd: the update launches' grids (the active list holds the 64-thread
+  // updates first); blocks beyond an instance's own parts return at once but
+  // would still wait for a free slot on a busy device
+  struct IterDesc { size_t inst_off, up_off, out_off; int n_active; UpdGrid upd; std::vector<GroupDesc> groups; };
   std::vector<IterDesc> iters(Imax);
   // requests starting at iteration 0 stage their inputs; ticks among them run
   // their prefixes (prediction by lane count, then the shifts) after the staging
@@ -1808,9 +1855,11 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   // sizes
   size_t bytes = 2 * ns * sizeof(StageItem);
   std::vector<std::vector<int>> active(Imax);
-  for (int it = 0; it < Imax; ++it)
+  for (int it = 0; it < Imax; ++it) {
     for (int i = 0; i < n; ++i)
       if (n_iters[i] > it) active[it].push_back(i);
+    order_by_update_shape(active[it], [&](int i) { return reqs[i].ctx->N; });
+  }
   auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
   bytes = align(bytes);
   const size_t pred_off = bytes;
@@ -1874,7 +1923,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
       const int ci = q.it0 + it;  // the instance's own iteration index
       hi[a] = q.ctx->h_insts[ci];
       hu[a] = q.ctx->h_ups[ci];
-      d.upd_parts = std::max(d.upd_parts, hu[a].parts);
+      d.upd.add(hu[a]);
       ho[a] = q.ctx->I - 1 == ci ? UpdateOut{q.knots_out, q.best_out, q.info_out} : UpdateOut{nullptr, nullptr, nullptr};
     }
     std::map<int, std::vector<int>> byG;
@@ -1940,10 +1989,8 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
       HIP_TRY(hipEventRecord(fork->ev_join[j], fork->aux[j]));
       HIP_TRY(hipStreamWaitEvent(s, fork->ev_join[j], 0));
     }
-    hipLaunchKernelGGL(update_kernel, dim3(d.upd_parts, (unsigned)d.n_active), dim3(kUpdThreads), 0, s,
-                       reinterpret_cast<const DevUpdate*>(dv + d.up_off), reinterpret_cast<const UpdateOut*>(dv + d.out_off),
-                       UpdateOut{nullptr, nullptr, nullptr});
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_updates(reinterpret_cast<const DevUpdate*>(dv + d.up_off),
+                           reinterpret_cast<const UpdateOut*>(dv + d.out_off), d.upd, s));
   }
   HIP_TRY(hipEventRecord(r->ev, s));
   return MPPI_OK;

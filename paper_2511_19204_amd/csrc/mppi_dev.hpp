@@ -146,6 +146,7 @@ struct DevUpdate {
   float* partial;        // [update_parts(N)][E] per-part weighted sums (scratch)
   uint32_t* done;        // parts finished in the current launch (0 between launches)
   int32_t N, E, iter, weight_mode, first_iter, last_iter, parts;
+  int32_t threads;       // workgroup size of the instance's update launches (update_shape)
   float lambda;
 };
 
@@ -181,6 +182,23 @@ constexpr int kUpdMinSlice = 64;  // samples per part at least
 __host__ __device__ inline int update_parts(int N) {
   const int p = (N + kUpdMinSlice - 1) / kUpdMinSlice;
   return p < 1 ? 1 : (p > kUpdMaxParts ? kUpdMaxParts : p);
+}
+// Workgroup size and parts of an instance's update.  Up to 1024 samples (the
+// sizes served together with other instances' rollouts) the workgroups are one
+// wavefront of 64 threads over slices of 16 samples: a wavefront needs the
+// registers of one SIMD where a rollout wavefront has ended, while a 256-thread
+// workgroup needs four of them on one compute unit, which a device full of
+// rollouts rarely has.  Larger instances take 256 threads over slices of 64.
+// The shape depends on N only, so an instance's sums are the same in every path.
+struct UpdShape {
+  int threads, parts;
+};
+__host__ __device__ inline UpdShape update_shape(int N) {
+  if (N <= 1024) {
+    const int p = (N + 15) / 16;
+    return UpdShape{64, p < 1 ? 1 : (p > kUpdMaxParts ? kUpdMaxParts : p)};
+  }
+  return UpdShape{kUpdThreads, update_parts(N)};
 }
 
 

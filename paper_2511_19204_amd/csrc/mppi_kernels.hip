@@ -1598,7 +1598,10 @@ __global__ __launch_bounds__(64) void predict_batch_kernel(const PredItem* __res
 // Persistent form: a grid sized to the resident wavefronts; each wavefront takes
 // work items from a device counter until the table is exhausted (every wavefront
 // reaches that exit).  Which wavefront runs an item does not change its result.
-template <int G>
+// The same depth and legged-tree specialisations as rollout_kernel.  Its item
+// loop costs it the two-wavefront register budget (held to 256 registers it
+// spills), so it runs one wavefront per SIMD.
+template <int G, int D, int LEG>
 __global__ __launch_bounds__(64) void rollout_persistent_kernel(const DevInst* __restrict__ insts,
                                                                 const int2* __restrict__ work, int n_items,
                                                                 unsigned int* __restrict__ counter, int group_stride,
@@ -1611,7 +1614,7 @@ __global__ __launch_bounds__(64) void rollout_persistent_kernel(const DevInst* _
     if (item >= n_items) break;
     const int2 w = work[item];
     const DevInst& I = insts[w.x];
-    rollout_item<G>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
+    rollout_item<G, D, false, LEG>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
   }
 }
 
@@ -2722,14 +2725,15 @@ __global__ void reset_counters(unsigned int* __restrict__ c, int n) {
 // out (per call): the final nominal, best knots and info of the last iteration.
 // ---------------------------------------------------------------------------
 
-constexpr int kUpdWaves = kUpdThreads / 64;
+// The update's workgroups have T threads (64 or 256, update_shape).
 
 // Block-wide sum in a fixed order (tree over threads), deterministic.
+template <int T>
 __device__ __forceinline__ float block_sum(float x, float* buf) {
   const int t = threadIdx.x;
   buf[t] = x;
   __syncthreads();
-  for (int off = kUpdThreads / 2; off > 0; off >>= 1) {
+  for (int off = T / 2; off > 0; off >>= 1) {
     if (t < off) buf[t] += buf[t + off];
     __syncthreads();
   }
@@ -2739,9 +2743,9 @@ __device__ __forceinline__ float block_sum(float x, float* buf) {
 }
 
 // Sums over one index range of a row-major [*, E] array, V consecutive floats
-// (V = 4 or 1) per element block.  The workgroup covers up to kUpdThreads
-// element blocks at a time; the G = kUpdThreads / (blocks in the chunk) thread
-// groups take the rows in turn (group g: rows g, g + G, ...), each in index
+// (V = 4 or 1) per element block.  The workgroup covers up to T element blocks
+// at a time; the G = T / (blocks in the chunk) thread groups take the rows in
+// turn (group g: rows g, g + G, ...), each in index
 // order, and their sums are added in group order.
 template <int V>
 struct VecT;
@@ -2766,7 +2770,7 @@ struct VecT<1> {
 
 // sum_{n < cnt} w[n] rows[n][:] (w null: weight 1); the result goes to
 // emit(element block, value) on threads t < blocks in the chunk.
-template <int V, typename Emit>
+template <int V, int NT, typename Emit>
 __device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows, int cnt, int E, const float* w,
                                                   float* s_part, Emit emit) {
   using VT = VecT<V>;
@@ -2775,9 +2779,9 @@ __device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows
   T* part = reinterpret_cast<T*>(s_part);
   const T* col = reinterpret_cast<const T*>(rows);
   constexpr int kIn = 24;  // loads in flight per thread (rows past cnt are not loaded)
-  for (int e0 = 0; e0 < EV; e0 += kUpdThreads) {
-    const int ec = min(kUpdThreads, EV - e0);
-    const int G = kUpdThreads / ec;
+  for (int e0 = 0; e0 < EV; e0 += NT) {
+    const int ec = min(NT, EV - e0);
+    const int G = NT / ec;
     const int el = t % ec, g = t / ec, e = e0 + el;
     T acc = VT::zero();
     if (g < G) {
@@ -2817,15 +2821,16 @@ __device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows
 // same groups, every element is accumulated over the same rows in the same
 // order and the two forms give the same bits.  Needs K nu even and the cubic
 // Hermite knots (velocities sampled, not derived).
+template <int T>
 __device__ __forceinline__ void regen_weighted_sum(const DevInst& I, const float* nom, uint32_t tick, int n0, int cnt,
                                                    const float* w, float* s_part, float* mine) {
   const DevModel& M = *I.model;
   const int t = threadIdx.x, KU = I.K * I.nu, EV = KU / 2;
   const float* sig = I.sigma + I.iter * I.K;
   float4* part = reinterpret_cast<float4*>(s_part);
-  for (int e0 = 0; e0 < EV; e0 += kUpdThreads) {
-    const int ec = min(kUpdThreads, EV - e0);
-    const int G = kUpdThreads / ec;
+  for (int e0 = 0; e0 < EV; e0 += T) {
+    const int ec = min(T, EV - e0);
+    const int G = T / ec;
     const int el = t % ec, g = t / ec, b = e0 + el;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (g < G) {
@@ -2871,11 +2876,12 @@ __device__ __forceinline__ void regen_weighted_sum(const DevInst& I, const float
 }
 
 // Knots of sample n (drawn again, as above) into dst [E].
+template <int T>
 __device__ __forceinline__ void regen_sample(const DevInst& I, const float* nom, uint32_t tick, int n, float* dst) {
   const DevModel& M = *I.model;
   const int KU = I.K * I.nu;
   const float* sig = I.sigma + I.iter * I.K;
-  for (int b = threadIdx.x; b < KU / 2; b += kUpdThreads) {
+  for (int b = threadIdx.x; b < KU / 2; b += T) {
     const uint4 x = sample_words(I, n, b, tick);
     float q0, v0, q1, v1;
     perturb_element(elem_const(M, I, sig, 2 * b), I.delta, nom[2 * b], nom[KU + 2 * b], n, x.x, x.y, true, q0, v0);
@@ -2888,6 +2894,7 @@ __device__ __forceinline__ void regen_sample(const DevInst& I, const float* nom,
 
 // The update of one instance by one workgroup (its part blockIdx.x); o: the
 // call's outputs (null fields: not wanted).
+template <int T>
 __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut o) {
   const int part = blockIdx.x, parts = U.parts;
   if (part >= parts) return;
@@ -2896,10 +2903,10 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
   // iteration when the caller's buffer is read in place)
   const float* nom_in = o.nominal_in ? o.nominal_in : U.nominal_in;
   const uint32_t tick = U.regen ? sample_tick(*U.regen) : 0u;  // read before the last part advances it
-  __shared__ float s_v[kUpdThreads];
-  __shared__ int s_i[kUpdThreads];
-  __shared__ float s_x[kUpdThreads];
-  __shared__ __align__(16) float s_part[kUpdWaves * 64 * 4];
+  __shared__ float s_v[T];
+  __shared__ int s_i[T];
+  __shared__ float s_x[T];
+  __shared__ __align__(16) float s_part[T * 4];
   __shared__ int s_last;
   __shared__ float s_w[(65536 + kUpdMaxParts - 1) / kUpdMaxParts];  // this part's normalised weights (N <= 65536)
 
@@ -2909,10 +2916,10 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
 
   // 1. over all samples (every part the same way, so every part gets the same
   //    values): finite minimum (lowest index), maximum and count.  Each thread
-  //    takes samples t, t + kUpdThreads, ... in order; up to kReg of them stay in
+  //    takes samples t, t + T, ... in order; up to kReg of them stay in
   //    registers for the weight sum, and the slice's costs go to s_w.
   constexpr int kIn = 8, kReg = 16;
-  const bool in_regs = N <= kReg * kUpdThreads;
+  const bool in_regs = N <= kReg * T;
   const float* costs = U.costs;
   float Sv[kReg];
   float mn = INFINITY, mx = -INFINITY;
@@ -2928,26 +2935,26 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
   if (in_regs) {
 #pragma unroll
     for (int q = 0; q < kReg; ++q) {
-      const int n = t + q * kUpdThreads;
+      const int n = t + q * T;
       Sv[q] = n < N ? costs[n] : INFINITY;
     }
 #pragma unroll
-    for (int q = 0; q < kReg; ++q) visit(Sv[q], t + q * kUpdThreads);
+    for (int q = 0; q < kReg; ++q) visit(Sv[q], t + q * T);
   } else {
-    for (int m0 = t; m0 < N; m0 += kIn * kUpdThreads) {
+    for (int m0 = t; m0 < N; m0 += kIn * T) {
       float Sq[kIn];
 #pragma unroll
       for (int q = 0; q < kIn; ++q) {
-        const int n = m0 + q * kUpdThreads;
+        const int n = m0 + q * T;
         Sq[q] = n < N ? costs[n] : INFINITY;
       }
 #pragma unroll
-      for (int q = 0; q < kIn; ++q) visit(Sq[q], m0 + q * kUpdThreads);
+      for (int q = 0; q < kIn; ++q) visit(Sq[q], m0 + q * T);
     }
   }
   s_v[t] = mn; s_i[t] = arg; s_x[t] = mx;
   __syncthreads();
-  for (int off = kUpdThreads / 2; off > 0; off >>= 1) {
+  for (int off = T / 2; off > 0; off >>= 1) {
     if (t < off) {
       const float om = s_v[t + off];
       const int oi = s_i[t + off];
@@ -2959,7 +2966,7 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
   const float smin = s_v[0], smax = s_x[0];
   const int nstar = s_i[0];
   __syncthreads();
-  const int nfin = (int)block_sum((float)nf, s_x);
+  const int nfin = (int)block_sum<T>((float)nf, s_x);
 
   // 2. unnormalised weights e_n = exp(-S_hat / lambda) and their sum
   const float range = smax - smin;
@@ -2975,23 +2982,23 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
 #pragma unroll
     for (int q = 0; q < kReg; ++q) zs += weight(Sv[q]);
   } else {
-    for (int m0 = t; m0 < N; m0 += kIn * kUpdThreads) {
+    for (int m0 = t; m0 < N; m0 += kIn * T) {
       float Sq[kIn];
 #pragma unroll
       for (int q = 0; q < kIn; ++q) {
-        const int n = m0 + q * kUpdThreads;
+        const int n = m0 + q * T;
         Sq[q] = n < N ? costs[n] : INFINITY;
       }
 #pragma unroll
       for (int q = 0; q < kIn; ++q) zs += weight(Sq[q]);
     }
   }
-  const float Z = block_sum(zs, s_x);
+  const float Z = block_sum<T>(zs, s_x);
   const float invZ = nfin > 0 ? 1.f / Z : 0.f;
 
   // 3. this part's slice: normalised weights (from the costs in s_w), then its
   //    weighted knot sum
-  for (int i = t; i < cnt; i += kUpdThreads) {
+  for (int i = t; i < cnt; i += T) {
     const float w = weight(s_w[i]) * invZ;
     s_w[i] = w;
     if (U.weights) U.weights[n0 + i] = w;
@@ -2999,12 +3006,12 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
   __syncthreads();
   float* mine = U.partial + (size_t)part * E;
   if (U.regen)
-    regen_weighted_sum(*U.regen, nom_in, tick, n0, cnt, s_w, s_part, mine);
+    regen_weighted_sum<T>(*U.regen, nom_in, tick, n0, cnt, s_w, s_part, mine);
   else if ((E & 3) == 0)
-    rows_weighted_sum<4>(U.samples + (size_t)n0 * E, cnt, E, s_w, s_part,
+    rows_weighted_sum<4, T>(U.samples + (size_t)n0 * E, cnt, E, s_w, s_part,
                          [&](int e, float4 v) { reinterpret_cast<float4*>(mine)[e] = v; });
   else
-    rows_weighted_sum<1>(U.samples + (size_t)n0 * E, cnt, E, s_w, s_part, [&](int e, float v) { mine[e] = v; });
+    rows_weighted_sum<1, T>(U.samples + (size_t)n0 * E, cnt, E, s_w, s_part, [&](int e, float v) { mine[e] = v; });
 
   // 4. the last part to finish adds the slices in part order
   __threadfence();
@@ -3020,7 +3027,7 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
   // buffer and a drawn-again best sample reads the input nominal
   float* bs = U.best_state;  // [E] knots, then S_best, best_iter, n_nonfinite, all_nonfinite, best_sample
   if (U.first_iter) {
-    for (int e = t; e < E; e += kUpdThreads) bs[e] = nom_in[e];
+    for (int e = t; e < E; e += T) bs[e] = nom_in[e];
     if (t == 0) {
       bs[E] = INFINITY;
       reinterpret_cast<int*>(bs)[E + 1] = -1;
@@ -3035,9 +3042,9 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
   const bool improve = nfin > 0 && U.costs[nstar] < bs[E];
   __syncthreads();
   if (improve) {
-    if (U.regen) regen_sample(*U.regen, nom_in, tick, nstar, bs);
+    if (U.regen) regen_sample<T>(*U.regen, nom_in, tick, nstar, bs);
     else
-      for (int e = t; e < E; e += kUpdThreads) bs[e] = U.samples[(size_t)nstar * E + e];
+      for (int e = t; e < E; e += T) bs[e] = U.samples[(size_t)nstar * E + e];
   }
   __syncthreads();
   if (t == 0) {
@@ -3053,18 +3060,18 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
 
   // 6. the nominal: the slices added in part order
   if ((E & 3) == 0)
-    rows_weighted_sum<4>(U.partial, parts, E, nullptr, s_part, [&](int e, float4 v) {
+    rows_weighted_sum<4, T>(U.partial, parts, E, nullptr, s_part, [&](int e, float4 v) {
       const float c[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int k = 0; k < 4; ++k) dst[4 * e + k] = nfin > 0 ? c[k] : nom_in[4 * e + k];
     });
   else
-    rows_weighted_sum<1>(U.partial, parts, E, nullptr, s_part,
+    rows_weighted_sum<1, T>(U.partial, parts, E, nullptr, s_part,
                          [&](int e, float v) { dst[e] = nfin > 0 ? v : nom_in[e]; });
   __syncthreads();
   if (U.last_iter) {
     if (o.best_out)
-      for (int e = t; e < E; e += kUpdThreads) o.best_out[e] = bs[e];
+      for (int e = t; e < E; e += T) o.best_out[e] = bs[e];
     if (t == 0 && o.info_out) {
       float* inf = reinterpret_cast<float*>(o.info_out);
       inf[0] = bs[E];
@@ -3077,16 +3084,19 @@ __device__ __forceinline__ void update_body(const DevUpdate& U, const UpdateOut 
   if (U.last_iter && t == 0 && U.tick) U.tick[0] += 1u;
 }
 
-__global__ __launch_bounds__(kUpdThreads) void update_kernel(const DevUpdate* __restrict__ ups,
-                                                             const UpdateOut* __restrict__ outs, UpdateOut single) {
-  update_body(ups[blockIdx.y], outs ? outs[blockIdx.y] : single);
+template <int T>
+__global__ __launch_bounds__(T) void update_kernel(const DevUpdate* __restrict__ ups,
+                                                   const UpdateOut* __restrict__ outs, UpdateOut single) {
+  update_body<T>(ups[blockIdx.y], outs ? outs[blockIdx.y] : single);
 }
 
 // One instance whose descriptor arrives as a kernel argument (no device copy of
 // it), with no per-call outputs besides the nominal and the weights.
 __global__ __launch_bounds__(kUpdThreads) void update_single_kernel(DevUpdate U) {
-  update_body(U, UpdateOut{nullptr, nullptr, nullptr, nullptr});
+  update_body<kUpdThreads>(U, UpdateOut{nullptr, nullptr, nullptr, nullptr});
 }
+template __global__ void update_kernel<64>(const DevUpdate*, const UpdateOut*, UpdateOut);
+template __global__ void update_kernel<256>(const DevUpdate*, const UpdateOut*, UpdateOut);
 
 // Warm start (Sec. III-E): the knots of a trajectory shifted forward by n_steps
 // control steps, i.e. its spline at t_k + n_steps dt clamped to the horizon end
@@ -3229,7 +3239,12 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
   template __global__ void rollout_trace_kernel<G, 0, 0>(const DevInst*, const int2*, int, int);     \
   template __global__ void rollout_trace_kernel<G, 3, 0>(const DevInst*, const int2*, int, int);     \
   template __global__ void rollout_trace_kernel<G, 6, 0>(const DevInst*, const int2*, int, int);     \
-  template __global__ void rollout_persistent_kernel<G>(const DevInst*, const int2*, int, unsigned int*, int, int); \
+  template __global__ void rollout_persistent_kernel<G, 0, 0>(const DevInst*, const int2*, int, unsigned int*, int,  \
+                                                             int);                                                \
+  template __global__ void rollout_persistent_kernel<G, 3, 0>(const DevInst*, const int2*, int, unsigned int*, int,  \
+                                                             int);                                                \
+  template __global__ void rollout_persistent_kernel<G, 6, 0>(const DevInst*, const int2*, int, unsigned int*, int,  \
+                                                             int);                                                \
   template __global__ void sample_kernel<G>(const DevInst*, int);                                      \
   template __global__ void predict_kernel<G>(const DevInst*, int, float*, int, int);                   \
   template __global__ void predict_batch_kernel<G>(const PredItem*, int, int);                         \
@@ -3243,7 +3258,9 @@ __global__ __launch_bounds__(64) void dynamics_kernel(const DevModel* __restrict
 #define MPPI_LEG_INST(G)                                                                               \
   template __global__ void rollout_kernel<G, 3, 1>(const DevInst*, const int2*, int, int, const float*,   \
                                                       const float*);                                      \
-  template __global__ void rollout_trace_kernel<G, 3, 1>(const DevInst*, const int2*, int, int);
+  template __global__ void rollout_trace_kernel<G, 3, 1>(const DevInst*, const int2*, int, int);                \
+  template __global__ void rollout_persistent_kernel<G, 3, 1>(const DevInst*, const int2*, int, unsigned int*, int,  \
+                                                             int);
 MPPI_LEG_INST(8)
 MPPI_LEG_INST(16)
 MPPI_LEG_INST(32)
@@ -3251,6 +3268,7 @@ MPPI_LEG_INST(32)
 // four chains of three bodies on 16 lanes (the quadruped's shape)
 template __global__ void rollout_kernel<16, 3, 2>(const DevInst*, const int2*, int, int, const float*, const float*);
 template __global__ void rollout_trace_kernel<16, 3, 2>(const DevInst*, const int2*, int, int);
+template __global__ void rollout_persistent_kernel<16, 3, 2>(const DevInst*, const int2*, int, unsigned int*, int, int);
 MPPI_INST(4)
 MPPI_INST(8)
 MPPI_INST(16)
