@@ -1098,10 +1098,11 @@ struct Plan {
     }
   }
 };
-// per-call argument block uploaded through a pinned ring
+// per-call argument block in a pool of pinned host buffers that the kernels read
+// in place
 struct RingSlot {
   void* host = nullptr;
-  void* dev = nullptr;
+  void* dev = nullptr;  // the same memory's device address
   size_t cap = 0;
   hipEvent_t ev = nullptr;
   bool pending = false;
@@ -1200,11 +1201,12 @@ static mppi_status ring_slot(size_t bytes, RingSlot** out) {
   RingSlot& r = *found;
   if (r.cap < bytes) {
     if (r.host) (void)hipHostFree(r.host);
-    if (r.dev) (void)hipFree(r.dev);
     r.host = r.dev = nullptr;
     size_t cap = std::max<size_t>(bytes, 4096);
+    // pinned host memory that the kernels read in place (no upload copy: a copy
+    // is a blit kernel, which on a device full of rollouts waits for a free slot)
     HIP_TRY(hipHostMalloc(&r.host, cap));
-    HIP_TRY(hipMalloc(&r.dev, cap));
+    HIP_TRY(hipHostGetDevicePointer(&r.dev, r.host, 0));
     r.cap = cap;
   }
   if (!r.ev) HIP_TRY(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
@@ -1259,7 +1261,6 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
                          : UpdateOut{nullptr, nullptr, nullptr};
     }
   }
-  HIP_TRY(hipMemcpyAsync(r->dev, r->host, bytes, hipMemcpyHostToDevice, s));
   // the slot is reusable only once every kernel reading its tables has finished:
   // its event is recorded after the last of them (below), since another call may
   // run on another stream
@@ -1771,7 +1772,7 @@ extern "C" mppi_status mppi_profile_read(mppi_ctx* c, double* rollout_ms, int32_
 
 // ---------------------------------------------------------------------------
 // batches of arbitrary composition without device allocation: launch tables
-// built on the host and uploaded in one async copy from the pinned ring
+// built on the host in a pinned buffer of the pool, which the kernels read in place
 // ---------------------------------------------------------------------------
 struct BatchReq {
   mppi_ctx* ctx;
@@ -1922,6 +1923,10 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
       const BatchReq& q = reqs[active[it][a]];
       const int ci = q.it0 + it;  // the instance's own iteration index
       hi[a] = q.ctx->h_insts[ci];
+      // served rounds: trees deeper than three levels (the longest per-step
+      // chains, on the critical path of their rounds) issue first where their
+      // wavefronts share a SIMD with others
+      hi[a].wave_prio = q.ctx->m->host.max_depth > 3 ? 3 : 0;
       hu[a] = q.ctx->h_ups[ci];
       d.upd.add(hu[a]);
       ho[a] = q.ctx->I - 1 == ci ? UpdateOut{q.knots_out, q.best_out, q.info_out} : UpdateOut{nullptr, nullptr, nullptr};
@@ -1944,7 +1949,6 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
         for (int n0 = 0; n0 < reqs[active[it][a]].ctx->N; n0 += R) w[k++] = make_int2(a, n0);
     }
   }
-  HIP_TRY(hipMemcpyAsync(r->dev, r->host, bytes, hipMemcpyHostToDevice, s));
   r->pending = true;  // event recorded after the last kernel reading the tables
   if (ns > 0) {
     hipLaunchKernelGGL(stage_kernel, dim3(2 * ns), dim3(256), 0, s, reinterpret_cast<StageItem*>(dv));

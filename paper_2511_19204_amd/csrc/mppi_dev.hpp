@@ -123,6 +123,7 @@ struct DevInst {
   int32_t store_samples; // with generate: 1 writes the sampled knots to samples (the
                          // update reads them); 0 leaves them to the update to regenerate
   int32_t spline_mode;   // 0 cubic Hermite, 1 natural cubic, 2 quadratic (position knots, zero velocity targets)
+  int32_t wave_prio;     // issue priority (0..3) of the rollout wavefronts among those sharing a SIMD
   // verification only (read when masks is set): per-step records of the
   // rollouts with trace_map[n] >= 0, see trace_record
   float* trace;              // [traced][H + 1][nq + 2 nv + 2], or null

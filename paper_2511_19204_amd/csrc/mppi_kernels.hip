@@ -1418,6 +1418,14 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
                                                             float* state_out, const float* x0_in = nullptr,
                                                             const float* nominal_in = nullptr) {
   const float* x0 = x0_in ? x0_in : I.x0;
+  // issue priority among the wavefronts sharing a SIMD (the server raises it for
+  // the trees with the longest per-step chains)
+  switch (I.wave_prio) {
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    case 3: __builtin_amdgcn_s_setprio(3); break;
+    default: break;
+  }
   const int lane = threadIdx.x;
   const int grp = lane / G, l = lane % G;
   const DevModel& M = *I.model;
