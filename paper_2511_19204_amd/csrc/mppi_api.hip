@@ -970,7 +970,7 @@ extern "C" mppi_status mppi_step(mppi_ctx* c, const float* d_state, const float*
   // others take copies in the instance's buffers (one launch)
   if (c->lanes > 0 && c->lanes < kTeamKey)
     return run_iterations(c, d_knots_out, d_best_knots, d_info, d_costs, s, d_state, d_knots_in);
-  hipLaunchKernelGGL(copy2_kernel, dim3(2), dim3(256), 0, s, d_state, c->x0, c->nq + c->nv, d_knots_in, c->nom, c->E);
+  hipLaunchKernelGGL(copy2_kernel, dim3(2), dim3(64), 0, s, d_state, c->x0, c->nq + c->nv, d_knots_in, c->nom, c->E);
   HIP_TRY(hipGetLastError());
   return run_iterations(c, d_knots_out, d_best_knots, d_info, d_costs, s);
 }
@@ -1002,7 +1002,7 @@ static mppi_status launch_predict(const mppi_ctx* c, int steps, float* out, hipS
 }
 
 static mppi_status launch_shift(const mppi_ctx* c, const float* in, int steps, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(shift_knots_kernel, dim3(1), dim3(256), 0, s, in, out, c->K, c->nu, c->H * c->m->host.nsub,
+  hipLaunchKernelGGL(shift_knots_kernel, dim3(1), dim3(kShiftThreads), 0, s, in, out, c->K, c->nu, c->H * c->m->host.nsub,
                      c->m->host.nsub, std::min(steps, c->H), c->delta, c->p.spline_mode);
   HIP_TRY(hipGetLastError());
   return MPPI_OK;
@@ -1039,7 +1039,7 @@ static mppi_status tick_prefix(mppi_ctx* c, const float* d_state_meas, int32_t n
                                float* d_state_pred, hipStream_t s) {
   const size_t nx = (size_t)(c->nq + c->nv) * sizeof(float);
   // x_t: the measured state carried n_delay control steps along tau_best
-  hipLaunchKernelGGL(copy2_kernel, dim3(2), dim3(256), 0, s, d_state_meas, c->x_meas, c->nq + c->nv, d_best,
+  hipLaunchKernelGGL(copy2_kernel, dim3(2), dim3(64), 0, s, d_state_meas, c->x_meas, c->nq + c->nv, d_best,
                      c->pred_knots, c->E);
   HIP_TRY(hipGetLastError());
   if (n_delay == 0) {
@@ -1267,7 +1267,7 @@ extern "C" mppi_status mppi_step_batch(int32_t n, mppi_ctx* const* ctxs, const f
   r->pending = true;
   auto* d_items = reinterpret_cast<StageItem*>(r->dev);
   auto* d_outs = reinterpret_cast<UpdateOut*>(d_items + 2 * n);
-  hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(256), 0, s, d_items);
+  hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(64), 0, s, d_items);
   HIP_TRY(hipGetLastError());
   for (int it = 0; it < Imax; ++it) {
     IterPlan& ip = plan->iters[it];
@@ -1346,7 +1346,7 @@ extern "C" mppi_status mppi_graph_create(int32_t n, mppi_ctx* const* ctxs, const
   HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(256), 0, cs, d_items);
+    hipLaunchKernelGGL(stage_kernel, dim3(2 * n), dim3(64), 0, cs, d_items);
     for (int it = 0; it < Imax && e == hipSuccess; ++it) {
       IterPlan& ip = plan->iters[it];
       for (auto& gl : ip.groups) {
@@ -1951,7 +1951,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
   }
   r->pending = true;  // event recorded after the last kernel reading the tables
   if (ns > 0) {
-    hipLaunchKernelGGL(stage_kernel, dim3(2 * ns), dim3(256), 0, s, reinterpret_cast<StageItem*>(dv));
+    hipLaunchKernelGGL(stage_kernel, dim3(2 * ns), dim3(64), 0, s, reinterpret_cast<StageItem*>(dv));
     HIP_TRY(hipGetLastError());
   }
   if (nt > 0) {
@@ -1967,7 +1967,7 @@ static mppi_status launch_batch_dynamic(const std::vector<BatchReq>& reqs, unsig
                                    stride, table, s));
       k += (int)kv.second.size();
     }
-    hipLaunchKernelGGL(shift_batch_kernel, dim3(nt), dim3(256), 0, s, reinterpret_cast<const ShiftItem*>(dv + shift_off));
+    hipLaunchKernelGGL(shift_batch_kernel, dim3(nt), dim3(kShiftThreads), 0, s, reinterpret_cast<const ShiftItem*>(dv + shift_off));
     HIP_TRY(hipGetLastError());
   }
   int ci = 0;

@@ -177,6 +177,10 @@ struct UpdateOut {
 
 // The update splits an instance's samples into `parts` consecutive slices, one
 // workgroup each; the last workgroup to finish sums the slices in order.
+// Workgroup size of the small per-call kernels (staging copies, warm-start
+// shifts): one wavefront, which finds room wherever one rollout wavefront has
+// ended on a device full of rollouts.
+constexpr int kShiftThreads = 64;
 constexpr int kUpdThreads = 256;
 constexpr int kUpdMaxParts = 64;
 constexpr int kUpdMinSlice = 64;  // samples per part at least

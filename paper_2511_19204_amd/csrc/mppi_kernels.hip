@@ -3113,7 +3113,7 @@ template __global__ void update_kernel<256>(const DevUpdate*, const UpdateOut*, 
 // integer m = k F + n_steps n_sub (K - 1) = seg F + rem.  Position-only spline
 // variants then take the slopes of the spline through the shifted positions.
 // One workgroup; in and out must not alias.
-constexpr int kShiftThreads = 256;
+
 __device__ __forceinline__ void shift_knots_block(const float* __restrict__ in, float* __restrict__ out, int K,
                                                   int nu, int F, int nsub, int n_steps, float delta, int spline_mode,
                                                   float* dg) {
