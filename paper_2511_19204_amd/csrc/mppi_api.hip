@@ -371,24 +371,6 @@ extern "C" mppi_status mppi_model_create(const mppi_model_desc* d, mppi_model** 
     M.c_count[b] = ci - M.c_begin[b];
   }
   build_chain_tables(M);
-  // base spatial inertia about its own origin (packed symmetric 6x6)
-  if (fb) {
-    const double mm = d->mass[0];
-    const double c[3] = {d->com[0], d->com[1], d->com[2]};
-    const float* in = d->inertia;
-    const double Ic[9] = {in[0], in[3], in[4], in[3], in[1], in[5], in[4], in[5], in[2]};
-    const double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-    double full[6][6] = {};
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) full[r][q] = Ic[r * 3 + q] + mm * ((r == q ? c2 : 0) - c[r] * c[q]);
-    const double cx[9] = {0, -c[2], c[1], c[2], 0, -c[0], -c[1], c[0], 0};
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) { full[r][q + 3] = mm * cx[r * 3 + q]; full[q + 3][r] = full[r][q + 3]; }
-    for (int r = 0; r < 3; ++r) full[r + 3][r + 3] = mm;
-    int e = 0;
-    for (int r = 0; r < 6; ++r)
-      for (int q = r; q < 6; ++q) M.base_I[e++] = (float)full[r][q];
-  }
   m->nq = fb ? 7 + nu : nu;
   m->nv = fb ? 6 + nu : nu;
   hipError_t e1 = hipGetDevice(&m->device);

@@ -45,13 +45,11 @@ constexpr int kFrSlot = 28;
 // contacts sorted by body.  Precomputed on the host from mppi_model_desc:
 //  * the joint rotation C(q) = R_tree Rot(axis, q) is stored as
 //    C = P0 + cos(q) P1 + sin(q) P2 (Rodrigues' formula distributed over R_tree);
-//  * axis_p = R_tree axis, the joint axis in the parent frame;
-//  * base_I = spatial inertia of the base about its own origin (packed 6x6).
+//  * axis_p = R_tree axis, the joint axis in the parent frame.
 struct DevModel {
   int32_t nb, fb, nu, nc, nsub, ee_body, n_levels, max_depth;
   float k, d, mu, eps, g, mtot;
   float ee_pos[3];
-  float base_I[21];
   int32_t parent[kMaxBodies];
   int32_t depth[kMaxBodies];
   int32_t n_child[kMaxBodies];
@@ -229,7 +227,7 @@ __host__ __device__ inline int group_floats(int G, int E) {
 }
 
 // Model table, staged once per work item at the start of a block's LDS:
-//   [0,24)            base spatial inertia (21, packed) and padding
+//   [0,24)            unused (keeps the layout's LDS bank alignment)
 //   [24,88)           modified diagonal of the natural cubic spline's slope
 //                     system (K entries; spline mode 1)
 //   [88,88+nc*kCt)    contact rows (position, nominal normal force, index)

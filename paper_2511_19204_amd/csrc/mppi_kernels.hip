@@ -553,11 +553,10 @@ __device__ __forceinline__ StepConst load_step_const(const DevModel& M, const De
   return c;
 }
 
-// Stage the model table (base inertia, contact rows with the instance's nominal
+// Stage the model table (contact rows with the instance's nominal
 // normal forces) into LDS with all 64 lanes of the wavefront.
 __device__ __forceinline__ void stage_model_table(const DevModel& M, const DevInst* I, float* tab, int lane,
                                                   bool joint_rows = false) {
-  if (lane < 21) tab[lane] = M.base_I[lane];
   const float* cs = &M.ctab[0][0];
   for (int i = lane; i < M.nc * kCt; i += 64) tab[kTabContacts + i] = cs[i];
   if (joint_rows) {
@@ -887,12 +886,6 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // under the PD law, the base cost and frame B
   float Pt[28];
   load_rotation_constants(bc.P, Pt);
-  float Ib[24];  // the base's rigid inertia (packed), for the same reason
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const float4 x = get4(tab + 4 * k);
-    Ib[4 * k] = x.x; Ib[4 * k + 1] = x.y; Ib[4 * k + 2] = x.z; Ib[4 * k + 3] = x.w;
-  }
   float* slots = gs;
   const int fb = LEG != 0 ? 1 : sc.fb;  // legged trees have a floating base
   const bool is_base = body_lane && fb && b == 0;
@@ -998,12 +991,9 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // gravity as a spatial acceleration in B axes: (0, Rb^T (0, 0, -g)), the same about any origin
   const float agl[3] = {-g * Rb[6], -g * Rb[7], -g * Rb[8]};
   if (body_lane) {
-    if (is_base) {
-#pragma unroll
-      for (int k = 0; k < 21; ++k) IA[k] = Ib[k];
-    } else {
-      body_inertia(R, bc.com, bc.Ic, bc.mass, IA);
-    }
+    // every body's rigid inertia about its origin, the base's too (its frame is
+    // the identity: every schedule forms it from the same constants the same way)
+    body_inertia(R, bc.com, bc.Ic, bc.mass, IA);
     bias_force(IA, v, pA);
 
     // contacts carried by this body (point x relative to the body origin); the
@@ -1982,8 +1972,8 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
   if (r.body_lane) {
     float IA[21], pA[6];
     if (is_base) {
-#pragma unroll
-      for (int q = 0; q < 21; ++q) IA[q] = tab[q];
+      const float eye[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+      body_inertia(eye, tb.com, tb.Ic, tb.mass, IA);
     } else {
       body_inertia(R, tb.com, tb.Ic, tb.mass, IA);
     }
@@ -2440,8 +2430,8 @@ __device__ __forceinline__ uint32_t chain_backward(const StepConst& sc, const fl
       const float tau = r[30], gain = r[31];
       float IA[21], pA[6];
       if (is_base) {
-#pragma unroll
-        for (int k = 0; k < 21; ++k) IA[k] = tab[k];
+        const float eye[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+        body_inertia(eye, rw + row::com, rw + row::Ic, rw[row::mass], IA);
       } else {
         body_inertia(R, rw + row::com, rw + row::Ic, rw[row::mass], IA);
       }
