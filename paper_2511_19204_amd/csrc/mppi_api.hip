@@ -676,9 +676,12 @@ static bool legged(const DevModel& M) {
   }
   return true;
 }
-// A legged tree of four chains of three bodies (the quadruped's shape).
+// A legged tree of four chains of three bodies (the quadruped's shape) with at
+// most one contact point per body.
 static bool legged_4x3(const DevModel& M) {
   if (!legged(M) || M.nb != 13) return false;
+  for (int b = 0; b < M.nb; ++b)
+    if (M.c_count[b] > 1) return false;
   for (int k = 0; k < 4; ++k)
     if (M.parent[1 + 3 * k] != 0 || M.parent[2 + 3 * k] != 1 + 3 * k || M.parent[3 + 3 * k] != 2 + 3 * k) return false;
   return true;

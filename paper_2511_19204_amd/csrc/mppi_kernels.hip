@@ -998,7 +998,8 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
 
     // contacts carried by this body (point x relative to the body origin); the
     // first one's row is held in registers, further ones are read from the table
-    const int c0 = bc.c_begin, cn = bc.c_count;
+    // (LEG = 2: at most one contact per body, so no loop)
+    const int c0 = bc.c_begin, cn = LEG == 2 ? min(bc.c_count, 1) : bc.c_count;
     for (int ci = c0; ci < c0 + cn; ++ci) {
       float ct[5];
       if (ci == c0) {
