@@ -149,13 +149,22 @@ def _check(rc, what):
         raise MppiError(f"{what} failed ({rc}): {lib().mppi_last_error().decode()}")
 
 
+def _addr(t):
+    """Address of a torch tensor's data after the checks every buffer of the C ABI
+    needs: contiguous, of a 32-bit element type (float32 values, int32 words)."""
+    import torch
+    if t.dtype not in (torch.float32, torch.int32):
+        raise TypeError(f"tensors passed to the library must be float32 or int32, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the library must be contiguous")
+    return t.data_ptr()
+
+
 def _ptr(t):
     """Device pointer of a torch tensor (None -> NULL)."""
     if t is None:
         return None
-    if not t.is_contiguous():
-        raise ValueError("tensors passed to the library must be contiguous")
-    return C.c_void_p(t.data_ptr())
+    return C.c_void_p(_addr(t))
 
 
 def _stream(stream):
@@ -405,7 +414,7 @@ def update_noalloc(n_samples, n_elems, lam, weight_mode, costs, samples, knots_i
 def step_batch(ctrls, states, knots_in, knots_out, best_knots=None, infos=None, stream=None):
     """Fused step of several controllers (lists of equal length)."""
     n = len(ctrls)
-    arr = lambda xs: (C.c_void_p * n)(*[x.h if isinstance(x, Controller) else (x.data_ptr() if x is not None else None) for x in xs])  # noqa: E731
+    arr = lambda xs: (C.c_void_p * n)(*[x.h if isinstance(x, Controller) else (_addr(x) if x is not None else None) for x in xs])  # noqa: E731
     hs = arr(ctrls)
     st = arr(states)
     ki = arr(knots_in)
@@ -417,7 +426,7 @@ def step_batch(ctrls, states, knots_in, knots_out, best_knots=None, infos=None, 
 
 def _ptr_array(xs):
     n = len(xs)
-    return (C.c_void_p * n)(*[(x.h if isinstance(x, Controller) else x.data_ptr()) if x is not None else None
+    return (C.c_void_p * n)(*[(x.h if isinstance(x, Controller) else _addr(x)) if x is not None else None
                               for x in xs])
 
 

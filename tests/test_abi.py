@@ -121,3 +121,21 @@ def test_noalloc_update_rejects_sizes_beyond_its_scratch(n, e, lam, mode, ptr):
     assert rc == -1
     assert len(L.mppi_last_error()) > 0
     assert L.mppi_update_noalloc(8, 8, 1.0, 0, None, fake, fake, fake, None, None) == -1
+
+
+def test_buffers_must_be_contiguous_32_bit_tensors():
+    """Every buffer of the C ABI holds float32 values or int32 words; the binding
+    refuses any other tensor before a call (a float64 tensor would be read as
+    twice as many garbage floats)."""
+    torch = pytest.importorskip("torch")
+    assert mppi._ptr(None) is None
+    x = torch.zeros(4)
+    assert mppi._ptr(x).value == x.data_ptr()
+    with pytest.raises(TypeError):
+        mppi._ptr(torch.zeros(4, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        mppi._ptr(torch.zeros(4, dtype=torch.int64))
+    with pytest.raises(ValueError):
+        mppi._ptr(torch.zeros((4, 4)).t())
+    with pytest.raises(TypeError):
+        mppi._ptr_array([torch.zeros(3, dtype=torch.float16)])
