@@ -2768,7 +2768,11 @@ struct VecT<1> {
 };
 
 // sum_{n < cnt} w[n] rows[n][:] (w null: weight 1); the result goes to
-// emit(element block, value) on threads t < blocks in the chunk.
+// emit(element block, value) on threads t < blocks in the chunk.  The element
+// blocks are taken NT at a time; each block's rows are split over G threads
+// (rows g, g + G, ...), whose sums are then added in g order.  G depends on the
+// number of blocks only (NT / EV, at least 1), not on the chunk, so every element
+// is added in the same order whichever chunk holds it.
 template <int V, int NT, typename Emit>
 __device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows, int cnt, int E, const float* w,
                                                   float* s_part, Emit emit) {
@@ -2778,9 +2782,9 @@ __device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows
   T* part = reinterpret_cast<T*>(s_part);
   const T* col = reinterpret_cast<const T*>(rows);
   constexpr int kIn = 24;  // loads in flight per thread (rows past cnt are not loaded)
+  const int G = NT / min(NT, EV);
   for (int e0 = 0; e0 < EV; e0 += NT) {
     const int ec = min(NT, EV - e0);
-    const int G = NT / ec;
     const int el = t % ec, g = t / ec, e = e0 + el;
     T acc = VT::zero();
     if (g < G) {
@@ -2816,10 +2820,12 @@ __device__ __forceinline__ void rows_weighted_sum(const float* __restrict__ rows
 // with each sample's knots drawn again from the counter-based stream instead of
 // read (the rollout kernel then stores none).  Element block b holds positions
 // 2b, 2b + 1 and velocities 2b, 2b + 1 (one counter-based block); there are
-// E / 4 of them, as many as rows_weighted_sum<4> has, so the threads form the
-// same groups, every element is accumulated over the same rows in the same
-// order and the two forms give the same bits.  Needs K nu even and the cubic
-// Hermite knots (velocities sampled, not derived).
+// E / 4 of them, as many as rows_weighted_sum<4> has, so the rows of every block
+// are split over as many threads (G), every element is accumulated over the same
+// rows in the same order and the two forms give the same bits (a block may sit
+// in another chunk of T blocks than in the stored form; G is the same for every
+// chunk).  Needs K nu even and the cubic Hermite knots (velocities sampled, not
+// derived).
 template <int T>
 __device__ __forceinline__ void regen_weighted_sum(const DevInst& I, const float* nom, uint32_t tick, int n0, int cnt,
                                                    const float* w, float* s_part, float* mine) {
@@ -2827,9 +2833,9 @@ __device__ __forceinline__ void regen_weighted_sum(const DevInst& I, const float
   const int t = threadIdx.x, KU = I.K * I.nu, EV = KU / 2;
   const float* sig = I.sigma + I.iter * I.K;
   float4* part = reinterpret_cast<float4*>(s_part);
+  const int G = T / min(T, EV);
   for (int e0 = 0; e0 < EV; e0 += T) {
     const int ec = min(T, EV - e0);
-    const int G = T / ec;
     const int el = t % ec, g = t / ec, b = e0 + el;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (g < G) {

@@ -157,6 +157,45 @@ def quadruped_model(seed=0):
     return m
 
 
+def hexapod_model(seed=0):
+    """Free base + 6 legs of (abduction about x, hip about y, knee about y), point feet:
+    a legged tree of six three-body chains (19 bodies), built like the quadruped.
+
+    Base 8-20 kg, every link 0.2-1.0 kg (drawn per link type, shared by the legs).
+    The initial state stands on the six feet with the static spring compression.
+    """
+    rng = np.random.default_rng(seed)
+    jit = lambda v: v * (1 + rng.uniform(-0.1, 0.1))  # noqa: E731
+    m_base = rng.uniform(8.0, 20.0)
+    m_abd, m_thigh, m_shank = rng.uniform(0.2, 1.0, 3)
+    bx, by, bz = jit(0.60), jit(0.30), jit(0.10)
+    hx, hy, off = jit(0.25), jit(0.12), jit(0.06)
+    L = jit(0.18)
+    hip0, knee0 = 0.8, -1.6
+    t = _Tree()
+    t.body(-1, (0, 0, 1), (0, 0, 0), m_base, (0, 0, 0), (bx, by, bz))
+    feet = []
+    for sx, sy in ((1, 1), (1, -1), (0, 1), (0, -1), (-1, 1), (-1, -1)):
+        a = t.body(0, (1, 0, 0), (sx * hx, sy * hy, 0), m_abd, (0, sy * 0.03, 0), (0.07, 0.05, 0.05),
+                   joint=(-0.8, 0.8, 20.0, 120.0, 2.5, 0.0))
+        h = t.body(a, (0, 1, 0), (0, sy * off, 0), m_thigh, (0, 0, -L / 2), (0.04, 0.04, L),
+                   joint=(-1.0, 2.6, 20.0, 120.0, 2.5, hip0))
+        k = t.body(h, (0, 1, 0), (0, 0, -L), m_shank, (0, 0, -L / 2), (0.03, 0.03, L),
+                   joint=(-2.7, -0.5, 35.0, 120.0, 2.5, knee0))
+        feet.append(k)
+    cpos = [(0.0, 0.0, -L)] * 6
+    m = t.finish("hexapod24", True, feet, cpos)
+    m["n_substeps"] = 1
+    m["armature"] = f32(np.full(m["n_u"], 0.01))
+    m_tot = float(np.sum(m["mass"]))
+    sink = m_tot * GRAVITY / (6 * m["k_contact"])
+    z0 = 2 * L * np.cos(hip0) - sink
+    q = np.concatenate([[0.0, 0.0, z0, 1.0, 0.0, 0.0, 0.0], np.tile([0.0, hip0, knee0], 6)])
+    m["x0"] = f32(np.concatenate([q, np.zeros(m["n_v"])]))
+    m["support"] = np.ones(6, bool)
+    return m
+
+
 def humanoid_model(seed=0):
     """Free pelvis + 2 legs x 6 + torso yaw + 2 arms x 4 (27 DoF), 10 contact points.
 
@@ -345,6 +384,7 @@ def config(name, n_samples=None, seed=0):
     quadruped_tp 18 DoF at throughput scale, K in {256,1024,4096}, H=200, 1 iteration,
                  linear std 0.05->0.4
     humanoid     27 DoF, K=256, H=150, dt=0.004, 10 knots, 3 iterations, exp kernel 0.4
+    hexapod      24 DoF (six three-joint legs), K=64, H=100, as quadruped
     """
     if name == "chain":
         m = chain_model(seed)
@@ -358,6 +398,9 @@ def config(name, n_samples=None, seed=0):
     elif name == "humanoid":
         m = humanoid_model(seed)
         p = params(m, n_samples or 256, 150, 0.004, 10, 3, ("exp", 0.4, 1.0, 1.0), "bipedal")
+    elif name == "hexapod":
+        m = hexapod_model(seed)
+        p = params(m, n_samples or 64, 100, 0.005, 8, 3, ("exp", 0.4, 1.0, 1.0), "walking")
     else:
         raise KeyError(name)
     return m, p, 1000 + seed
