@@ -105,3 +105,35 @@ def test_legged_kernel_forced_parity(name):
     assert seen == (1 << nc) - 1, "every contact point, the second shank points included, was exercised"
     assert tot["mask_flips"] <= 1e-3 * tot["steps"]
     assert fused["n_nonfinite"] == 0
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batches_that_widen_the_kernel_equal_plain_steps(persistent):
+    """A batched launch takes the most general kernel its instances share: a
+    hexapod beside a humanoid (32 lanes each) runs the general kernel, the
+    two-contact quadruped beside the plain one (16 lanes) the legged-tree kernel
+    instead of the four-by-three one.  Every instance must still equal its plain
+    step bit for bit."""
+    made = []
+    for i, (name, n) in enumerate([("hexapod", 40), ("humanoid", 24), ("hexapod", 7),
+                                   ("quadruped2c", 33), ("quadruped", 48)]):
+        m, p, s = _cfg(name, n)
+        model = mppi.Model(m)
+        c = mppi.Controller(model, p, s + i, schedule="body")
+        made.append((m, p, c))
+    assert [c.lanes for (_, _, c) in made] == [32, 32, 32, 16, 16]
+    plain = [_step(c, m, p, synth.nominal_knots(m, p["n_knots"]), 2) for (m, p, c) in made]
+    states = [torch.tensor(np.asarray(m["x0"], np.float32), device="cuda") for (m, p, c) in made]
+    kin = [torch.tensor(synth.nominal_knots(m, p["n_knots"]).astype(np.float32), device="cuda")
+           for (m, p, c) in made]
+    kout = [torch.zeros(c.E, device="cuda") for (m, p, c) in made]
+    for (m, p, c) in made:
+        c.tick = 2
+    mppi.set_batch_options(persistent)
+    try:
+        mppi.step_batch([c for (m, p, c) in made], states, kin, kout)
+    finally:
+        mppi.set_batch_options(False)
+    torch.cuda.synchronize()
+    for i in range(len(made)):
+        assert np.array_equal(kout[i].cpu().numpy(), plain[i]["knots"]), i
