@@ -47,7 +47,7 @@ def _cfg(name, n, **over):
 
 
 @pytest.mark.parametrize("name,count,H", [("chain", 32, 50), ("quadruped", 48, 20), ("humanoid", 32, 40),
-                                          ("ytree", 40, 50), ("quadruped", 21, 20)])
+                                          ("ytree", 40, 50), ("quadruped", 21, 20), ("hexapod", 40, 20)])
 def test_team_rollout_costs_match_oracle(name, count, H):
     m, p, s = _cfg(name, count, horizon=H)
     model = mppi.Model(m)
@@ -99,7 +99,8 @@ def test_team_close_to_body_on_the_smooth_arm():
     assert rel.max() <= 1e-5, rel.max()
 
 
-@pytest.mark.parametrize("name,n", [("quadruped", 64), ("humanoid", 40), ("ytree", 45), ("quadruped", 37)])
+@pytest.mark.parametrize("name,n", [("quadruped", 64), ("humanoid", 40), ("ytree", 45), ("quadruped", 37),
+                                    ("hexapod", 33)])
 def test_team_is_deterministic_and_batches_bit_identically(name, n):
     m, p, s = _cfg(name, n)
     model = mppi.Model(m)
