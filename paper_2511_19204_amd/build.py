@@ -7,10 +7,10 @@ expression only (-ffp-contract=on), so an inlined helper rounds the same way
 in every kernel that uses it.
 
 The compiler's per-kernel resource remarks are checked: no kernel may use
-scratch memory (register spills), and the body-schedule rollout kernel must fit
-two wavefronts per SIMD (at most 256 VGPRs), which launches of more than one
-wavefront per SIMD rely on (the persistent form sizes its grid to the occupancy
-it gets).
+scratch memory (register spills), and the body-schedule rollout kernel and every
+persistent kernel must fit two wavefronts per SIMD (at most 256 VGPRs), which
+launches of more than one wavefront per SIMD rely on (the persistent forms size
+their grids to the occupancy they get).
 """
 import os
 import re
@@ -52,7 +52,7 @@ def check_resources(usage: dict) -> None:
             continue  # verification kernel: its per-step record stores may spill
         if u.get("ScratchSize", 0) != 0:
             bad.append(f"{name}: {u['ScratchSize']} bytes/lane of scratch (register spills)")
-        if "rollout_kernel" in name and "persistent" not in name and u.get("Occupancy", 0) < 2:
+        if ("rollout_kernel" in name or "persistent_kernel" in name) and u.get("Occupancy", 0) < 2:
             bad.append(f"{name}: {u.get('VGPRs')} VGPRs + {u.get('AGPRs')} AGPRs, occupancy {u.get('Occupancy')} < 2")
     if not usage:
         bad.append("no kernel resource remarks were produced")

@@ -1403,11 +1403,16 @@ __device__ __forceinline__ void trace_record(const DevInst& I, int n, bool valid
 
 // x0_in / nominal_in (nullable) replace the instance's staged state and nominal.
 // TR: also write the per-step records of traced rollouts (verification kernel).
+// per_item: called once per work item in a loop (the persistent form): the lane
+// index is passed through an empty asm statement that claims to change it, so
+// what derives from it (group, body, LDS addresses) is formed again for each
+// item instead of being held live across the loop, which would take the kernel
+// past the two-wavefront register budget.
 template <int G, int D = 0, bool TR = false, int LEG = 0>
 __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, int first, int group_stride,
                                                             int table_floats, float* smem, int steps,
                                                             float* state_out, const float* x0_in = nullptr,
-                                                            const float* nominal_in = nullptr) {
+                                                            const float* nominal_in = nullptr, bool per_item = false) {
   const float* x0 = x0_in ? x0_in : I.x0;
   // issue priority among the wavefronts sharing a SIMD (the server raises it for
   // the trees with the longest per-step chains)
@@ -1417,7 +1422,8 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     case 3: __builtin_amdgcn_s_setprio(3); break;
     default: break;
   }
-  const int lane = threadIdx.x;
+  int lane = threadIdx.x;
+  if (per_item) asm volatile("" : "+v"(lane));
   const int grp = lane / G, l = lane % G;
   const DevModel& M = *I.model;
   float* tab = smem;
@@ -1597,23 +1603,24 @@ __global__ __launch_bounds__(64) void predict_batch_kernel(const PredItem* __res
 // Persistent form: a grid sized to the resident wavefronts; each wavefront takes
 // work items from a device counter until the table is exhausted (every wavefront
 // reaches that exit).  Which wavefront runs an item does not change its result.
-// The same depth and legged-tree specialisations as rollout_kernel.  Its item
-// loop costs it the two-wavefront register budget (held to 256 registers it
-// spills), so it runs one wavefront per SIMD.
+// The same depth and legged-tree specialisations as rollout_kernel, and the same
+// two wavefronts per SIMD: the lane index is made opaque once per item (see
+// rollout_item's per_item), so nothing derived from it stays live across items.
 template <int G, int D, int LEG>
-__global__ __launch_bounds__(64) void rollout_persistent_kernel(const DevInst* __restrict__ insts,
-                                                                const int2* __restrict__ work, int n_items,
-                                                                unsigned int* __restrict__ counter, int group_stride,
-                                                                int table_floats) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void rollout_persistent_kernel(
+    const DevInst* __restrict__ insts, const int2* __restrict__ work, int n_items, unsigned int* __restrict__ counter,
+    int group_stride, int table_floats) {
   extern __shared__ float smem[];
   for (;;) {
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
     int item = 0;
-    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    if (lane == 0) item = (int)atomicAdd(counter, 1u);
     item = __builtin_amdgcn_readfirstlane(item);
     if (item >= n_items) break;
     const int2 w = work[item];
     const DevInst& I = insts[w.x];
-    rollout_item<G, D, false, LEG>(I, w.y, group_stride, table_floats, smem, I.H, nullptr);
+    rollout_item<G, D, false, LEG>(I, w.y, group_stride, table_floats, smem, I.H, nullptr, nullptr, nullptr, true);
   }
 }
 
@@ -2124,11 +2131,13 @@ __device__ __attribute__((always_inline)) void team_step(const StepConst& sc, co
   io.qdd = is_joint ? br[sl * 8 + 5] : 0.f;
 }
 
-// Fused rollout of one work item on the team schedule (as rollout_item).
+// Fused rollout of one work item on the team schedule (as rollout_item, per_item
+// included).
 template <int G, int D = 0>
 __device__ __attribute__((always_inline)) void team_item(const DevInst& I, int first, int group_stride,
-                                                         int table_floats, float* smem) {
-  const int lane = threadIdx.x;
+                                                         int table_floats, float* smem, bool per_item = false) {
+  int lane = threadIdx.x;
+  if (per_item) asm volatile("" : "+v"(lane));
   const int grp = lane / G, l = lane % G;
   const DevModel& M = *I.model;
   float* tab = smem;
@@ -2256,19 +2265,20 @@ __global__ __launch_bounds__(64) void team_kernel(const DevInst* __restrict__ in
 
 // Persistent form (as rollout_persistent_kernel).
 template <int G>
-__global__ __launch_bounds__(64) void team_persistent_kernel(const DevInst* __restrict__ insts,
-                                                             const int2* __restrict__ work, int n_items,
-                                                             unsigned int* __restrict__ counter, int group_stride,
-                                                             int table_floats) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void team_persistent_kernel(
+    const DevInst* __restrict__ insts, const int2* __restrict__ work, int n_items, unsigned int* __restrict__ counter,
+    int group_stride, int table_floats) {
   extern __shared__ float smem[];
   for (;;) {
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
     int item = 0;
-    if (threadIdx.x == 0) item = (int)atomicAdd(counter, 1u);
+    if (lane == 0) item = (int)atomicAdd(counter, 1u);
     item = __builtin_amdgcn_readfirstlane(item);
     if (item >= n_items) break;
     const int2 w = work[item];
     const DevInst& I = insts[w.x];
-    team_item<G>(I, w.y, group_stride, table_floats, smem);
+    team_item<G>(I, w.y, group_stride, table_floats, smem, true);
   }
 }
 
