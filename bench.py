@@ -415,7 +415,7 @@ def serving(args, torch, mppi, synth, mode):
     Hs = [p["horizon"] for (m, p, seed) in robots]
     delay = [1] * len(made)
     n_streams = args.serve_streams or SERVE_STREAMS[mode]
-    srv = mppi.Server(n_streams=n_streams, max_batch=len(made), mode=mode)
+    srv = mppi.Server(n_streams=n_streams, max_batch=len(made), mode=mode, persistent=args.serve_persistent)
     # warm-up: one tick per robot
     tk = [srv.submit_tick(c, st, 1, k) for (_, c, st, k, _) in made]
     srv.drain()
@@ -458,7 +458,8 @@ def serving(args, torch, mppi, synth, mode):
     return {"rollout_steps_per_s": work_done / wall, "ticks": len(lat), "wall_s": wall, "per_model": per_model,
             "tick_latency_p50_ms": _pct(lat_ms, 50), "tick_latency_p99_ms": _pct(lat_ms, 99),
             "deadline_miss_frac": float(np.mean(lat_ms > 20.0)), "batches": batches,
-            "ticks_per_batch": requests / max(batches, 1), "streams": n_streams}
+            "ticks_per_batch": requests / max(batches, 1), "streams": n_streams,
+            "persistent": bool(args.serve_persistent)}
 
 
 def cpu_baseline(args, res):
@@ -524,6 +525,8 @@ def main():
     ap.add_argument("--tick-runs", type=int, default=100)
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default schedule")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-persistent", action="store_true",
+                    help="served rounds launch the persistent rollout kernels")
     ap.add_argument("--serve-streams", type=int, default=None,
                     help="server streams for every serving mode (default: per mode, SERVE_STREAMS)")
     ap.add_argument("--no-serve", action="store_true")
