@@ -1023,12 +1023,12 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   // ---- backward sweep, leaves to root: each joint lane publishes its
   //      articulated inertia and bias already carried to its parent's origin
   float U[6], invD = 0.f, u = 0.f;
-  // kFoldAll (trees at most three levels deep): the inertia and bias carried to
-  // the parent are zero until the lane's own level, then its body's (kept for
-  // the rest of the sweep), and every lane adds its next lane's after each
-  // level.  Deeper trees keep them per level (unset on lanes of other levels)
-  // and add them on the parents only, which needs fewer registers.
-  constexpr bool kFoldAll = D > 0 && D <= 3;
+  // kFoldAll (depth-specialised kernels): the inertia and bias carried to the
+  // parent are zero until the lane's own level, then its body's (kept for the
+  // rest of the sweep), and every lane adds its next lane's after each level.
+  // The run-time-depth kernel keeps them per level (unset on lanes of other
+  // levels) and adds them on the parents only.
+  constexpr bool kFoldAll = D > 0;
   float Ip[21], pp[6];
   if constexpr (kFoldAll) {
 #pragma unroll
