@@ -32,9 +32,9 @@ __device__ __forceinline__ void wave_sync() {
 
 // Branch-weight hint for a rare path when H holds (a compile-time constant),
 // else the condition as is.  With one wavefront per SIMD every taken branch
-// costs that wavefront an instruction refetch, so the legged kernels ask for
-// their rare paths to be laid out of line; the general kernels keep the default
-// layout (with the hints their register allocation spills).  A macro: the hint
+// costs that wavefront an instruction refetch, so the legged and depth-6
+// kernels ask for their rare paths to be laid out of line; the other kernels
+// keep the default layout (with the hints their register allocation spills).  A macro: the hint
 // has to sit in the branch's own condition.
 #define MPPI_RARE(H, c) ((H) ? __builtin_expect(!!(c), 0) : !!(c))
 
@@ -998,11 +998,13 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
 
     // contacts carried by this body (point x relative to the body origin); the
     // first one's row is held in registers, further ones are read from the table
-    // (LEG = 2: at most one contact per body, so no loop)
+    // (LEG = 2: at most one contact per body, so no loop; the depth-6 kernels read
+    // the first row from the table too, and spend the registers on the layout
+    // hints of rollout_item)
     const int c0 = bc.c_begin, cn = LEG == 2 ? min(bc.c_count, 1) : bc.c_count;
     for (int ci = c0; ci < c0 + cn; ++ci) {
       float ct[5];
-      if (ci == c0) {
+      if (ci == c0 && D != 6) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) ct[k] = bc.ct0[k];
       } else {
@@ -1477,9 +1479,11 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   // every step (the same values)
   HermiteSeg hs{0.f, 0.f, 0.f, 0.f};
   int hseg = -1;
+  // rare paths laid out of line (MPPI_RARE) where the registers allow it
+  constexpr bool kHints = LEG != 0 || D == 6;
   for (int f = 0; f < F_run; ++f) {
     const bool control = clk.sub == 0;
-    if (D == 0 || MPPI_RARE(LEG != 0, clk.seg != hseg)) {
+    if (D == 0 || MPPI_RARE(kHints, clk.seg != hseg)) {
       hseg = clk.seg;
       if (is_joint) hs = hermite_segment(knots, sc.K, sc.nu, hseg, j, sc.delta);
     }
@@ -1489,7 +1493,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     physics_step<G, D, LEG>(sc, bc, tab, gs, b, body_lane, io, kin_kept, control);
     if (control) {
       acc += io.cost;
-      if (MPPI_RARE(LEG != 0, masks != nullptr)) {
+      if (MPPI_RARE(kHints, masks != nullptr)) {
         const uint32_t mk = group_or<G>(io.mask, red, l);
         if (l == 0 && valid) masks[(size_t)n * H + clk.h] = mk;
         if (TR && I.trace) {
@@ -1501,8 +1505,8 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
     // joints (other lanes hold q = qd = qdd = 0)
     io.v = fmaf(io.dt, io.qdd, io.v);
     io.q = fmaf(io.dt, io.v, io.q);
-    if (fb) integrate_base_R<LEG != 0>(io.bq, io.bv, io.ba, io.dt, io.Rb);  // every lane: the same base state
-    clk.advance<LEG != 0>(sc.K, F, sc.nsub);
+    if (fb) integrate_base_R<kHints>(io.bq, io.bv, io.ba, io.dt, io.Rb);  // every lane: the same base state
+    clk.advance<kHints>(sc.K, F, sc.nsub);
   }
   if (state_out) {
     if (valid) {
