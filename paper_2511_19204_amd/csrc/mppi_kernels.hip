@@ -1065,7 +1065,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
         // children reached through LDS: the first kFold records are read together
         // (a missing child reads this lane's own slot and is not added), then
         // added in child order; more children follow one by one
-        constexpr int kFold = D > 0 ? 3 : 2;  // (the generic kernels have fewer registers to spare)
+        constexpr int kFold = (D > 0 && D != 6) ? 3 : 2;  // (the generic and depth-6 kernels have fewer registers to spare)
         float t[kFold][28];
 #pragma unroll
         for (int k = 0; k < kFold; ++k) {
