@@ -43,6 +43,15 @@ import time
 
 import numpy as np
 
+# Hardware queues per process.  HIP maps streams onto GPU_MAX_HW_QUEUES hardware
+# queues (four by default); more busy streams than that share queues, whose
+# time-slicing adds milliseconds to the served tail.  The serving run uses six
+# server streams besides torch's, so it asks for at least eight.  Read when the
+# process first touches the GPU, so it is set here, before torch is imported; a
+# larger value already in the environment is kept.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -386,11 +395,12 @@ def tasks(args, torch, mppi, synth):
     return out
 
 
-# Server streams per mode, the best of a sweep over 1..6 on the 64-robot mix:
-# iteration-level rounds run one stream per robot type (three); request-level
-# batches run one stream whose launches fork their rollout groups onto side
-# streams; plain per-instance launches overlap best over three streams.
-SERVE_STREAMS = {"batched": 1, "iteration": 3, "plain": 3}
+# Server streams per mode, the best of sweeps on the 64-robot mix: iteration-level
+# rounds run six streams (one per robot type, the other three taking one type at
+# a time), with a hardware queue each; request-level batches run one stream whose
+# launches fork their rollout groups onto side streams; plain per-instance
+# launches overlap best over three streams.
+SERVE_STREAMS = {"batched": 1, "iteration": 6, "plain": 3}
 
 
 def serving(args, torch, mppi, synth, mode):
@@ -459,7 +469,7 @@ def serving(args, torch, mppi, synth, mode):
             "tick_latency_p50_ms": _pct(lat_ms, 50), "tick_latency_p99_ms": _pct(lat_ms, 99),
             "deadline_miss_frac": float(np.mean(lat_ms > 20.0)), "batches": batches,
             "ticks_per_batch": requests / max(batches, 1), "streams": n_streams,
-            "persistent": bool(args.serve_persistent)}
+            "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")), "persistent": bool(args.serve_persistent)}
 
 
 def cpu_baseline(args, res):

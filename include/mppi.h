@@ -318,8 +318,11 @@ mppi_status mppi_set_targets(mppi_ctx* c, const mppi_targets* t, void* stream);
  * With n_streams = 1 in mode 0 or 2, each launch forks its rollout kernels (one
  * per lane count) onto up to three side streams of the server, fewer when
  * GPU_MAX_HW_QUEUES is below 4, so that kernels of different robot types run
- * side by side; with several streams nothing forks (streams beyond the hardware
- * queue count share queues and run in order).
+ * side by side; with several streams nothing forks.  Streams beyond the
+ * process's hardware queue count (GPU_MAX_HW_QUEUES, four unless set before the
+ * process first touches the GPU) share queues, whose time-slicing delays every
+ * round on them: give each server stream a queue of its own (n_streams plus the
+ * caller's busy streams at most GPU_MAX_HW_QUEUES).
  * Each result equals the instance's own mppi_step / mppi_tick (the instance's
  * warm-start knots and noise tick stay on the device).  persistent selects the
  * persistent rollout launch (mppi_batch_opts).  Buffers passed to submit must

@@ -474,7 +474,10 @@ class Server:
     """Continuous-batching server of MPC ticks: mode "batched" (a batch runs all
     iterations of the ticks it took), "plain" (per-instance launches) or
     "iteration" (every round runs one iteration of each admitted tick; ticks join
-    at round boundaries; with several streams each robot type has its own)."""
+    at round boundaries; with several streams each robot type has its own).
+    Each stream should have a hardware queue of its own: GPU_MAX_HW_QUEUES (four
+    by default) must be set before the process first touches the GPU to at least
+    n_streams plus the caller's busy streams."""
 
     MODES = {"batched": 0, "plain": 1, "iteration": 2}
 
