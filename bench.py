@@ -395,12 +395,13 @@ def tasks(args, torch, mppi, synth):
     return out
 
 
-# Server streams per mode, the best of sweeps on the 64-robot mix: iteration-level
-# rounds run six streams (one per robot type, the other three taking one type at
-# a time), with a hardware queue each; request-level batches run one stream whose
-# launches fork their rollout groups onto side streams; plain per-instance
-# launches overlap best over three streams.
-SERVE_STREAMS = {"batched": 1, "iteration": 6, "plain": 3}
+# Server streams per mode, the best of sweeps on the 64-robot mix with a hardware
+# queue per stream: iteration-level rounds run six streams (one per robot type,
+# the other three taking one type at a time; five to seven measure the same);
+# request-level batches run one stream whose launches fork their rollout groups
+# onto side streams (two to six streams measure worse); plain per-instance
+# launches overlap best over six streams.
+SERVE_STREAMS = {"batched": 1, "iteration": 6, "plain": 6}
 
 
 def serving(args, torch, mppi, synth, mode):
