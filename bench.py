@@ -43,15 +43,6 @@ import time
 
 import numpy as np
 
-# Hardware queues per process.  HIP maps streams onto GPU_MAX_HW_QUEUES hardware
-# queues (four by default); more busy streams than that share queues, whose
-# time-slicing adds milliseconds to the served tail.  The serving run uses six
-# server streams besides torch's, so it asks for at least eight.  Read when the
-# process first touches the GPU, so it is set here, before torch is imported; a
-# larger value already in the environment is kept.
-if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
-    os.environ["GPU_MAX_HW_QUEUES"] = "8"
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -554,6 +545,14 @@ def main():
               "sharding is a design note, not a runnable path", file=sys.stderr)
         sys.exit(2)
 
+    # Hardware queues per process.  HIP maps streams onto GPU_MAX_HW_QUEUES
+    # hardware queues (four by default); more busy streams than that share queues,
+    # whose time-slicing adds milliseconds to the served tail.  The serving run
+    # uses six server streams besides torch's, so it asks for at least eight.
+    # Read when the process first touches the GPU, so it is set before torch is
+    # imported; a larger value already in the environment is kept.
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+        os.environ["GPU_MAX_HW_QUEUES"] = "8"
     import torch
     from paper_2511_19204_amd import flops, mppi, synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
