@@ -129,8 +129,8 @@ def test_autotune_picks_a_valid_lane_count_without_changing_results():
 # streams; several streams: no side streams, and in iteration mode each robot type
 # owns a stream (with four streams and at most three types, at least one stream
 # is owned by none and takes ticks of one type at a time)
-SERVER_CASES = [("batched", 1), ("batched", 2), ("plain", 2), ("iteration", 1), ("iteration", 3),
-                ("iteration", 4)]
+SERVER_CASES = [("batched", 1), ("batched", 2), ("plain", 2), ("plain", 6), ("iteration", 1), ("iteration", 3),
+                ("iteration", 4), ("iteration", 6)]
 
 
 @pytest.mark.parametrize("mode,n_streams", SERVER_CASES)
