@@ -2757,9 +2757,9 @@ __device__ __forceinline__ float block_sum(float x, float* buf) {
 
 // Sums over one index range of a row-major [*, E] array, V consecutive floats
 // (V = 4 or 1) per element block.  The workgroup covers up to T element blocks
-// at a time; the G = T / (blocks in the chunk) thread groups take the rows in
-// turn (group g: rows g, g + G, ...), each in index
-// order, and their sums are added in group order.
+// at a time; G = T / min(T, blocks) thread groups take the rows in turn (group
+// g: rows g, g + G, ...), each in index order, and their sums are added in
+// group order.
 template <int V>
 struct VecT;
 template <>
