@@ -5,7 +5,10 @@ whole tree folded by lane moves): a hexapod (19 bodies, 32 lanes per rollout)
 and the quadruped with a second contact point on every shank (two contacts on a
 body, so not the four-by-three kernel).  The body schedule must equal the chain
 schedule bit for bit, and the step must meet the oracle step by step along the
-GPU's own trajectories (the bars of the forced-parity tests)."""
+GPU's own trajectories (the bars of the forced-parity tests).  The hexapod's
+knot count first showed the update's two sample forms (drawn again, stored)
+summing in different orders past one chunk of element blocks; the last test
+pins them equal at such sizes."""
 import numpy as np
 import pytest
 
@@ -137,3 +140,25 @@ def test_batches_that_widen_the_kernel_equal_plain_steps(persistent):
     torch.cuda.synchronize()
     for i in range(len(made)):
         assert np.array_equal(kout[i].cpu().numpy(), plain[i]["knots"]), i
+
+
+@pytest.mark.parametrize("n_samples,n_knots", [(2048, 48), (600, 40), (4096, 8)])
+def test_update_drawn_again_equals_update_of_stored_samples(n_samples, n_knots):
+    """The fused step draws every sample's knots again in the update; the traced
+    iterations store them and update from the stored rows.  The two must agree bit
+    for bit whatever the element count: 12 joints x 48 knots is 288 element blocks
+    for 256 update threads, 40 knots 240 blocks for 64 threads (a chunk of blocks
+    beyond the first), 8 knots the throughput shape."""
+    m = synth.quadruped_model(0)
+    p = synth.params(m, n_samples, 20, 0.005, n_knots, 2, ("exp", 0.4, 1.0, 1.0), "walking")
+    s = 4200 + n_knots
+    model = mppi.Model(m)
+    c = mppi.Controller(model, p, s)
+    kn = synth.nominal_knots(m, p["n_knots"])
+    x0 = np.asarray(m["x0"], np.float64)
+    its = traced_iterations(c, m, p, 1, x0, kn, [np.arange(2)] * p["n_iters"])
+    fused = fused_step(c, m, p, 1, x0, kn)
+    for it, d in enumerate(its):
+        assert np.array_equal(d["costs"], fused["costs"][it]), it
+    assert np.array_equal(its[-1]["next"], fused["knots"])
+    assert np.all(np.isfinite(fused["knots"]))
