@@ -687,13 +687,24 @@ static bool legged_4x3(const DevModel& M) {
   return true;
 }
 
+// A fixed-base serial chain: body b's parent is body b - 1, the first body's the
+// world.
+static bool serial_chain(const DevModel& M) {
+  if (M.fb || M.nb < 1 || M.parent[0] != -1) return false;
+  for (int b = 1; b < M.nb; ++b)
+    if (M.parent[b] != b - 1) return false;
+  return true;
+}
+
 struct Dims {
   int E = 0, nb = 0, nc = 0, nch = 0, natt = 0, ns = 0, depth = 0;
-  bool leg = true, quad = true;  // every instance added is a legged tree / of four chains of three
+  // every instance added is a legged tree / of four chains of three / a serial chain
+  bool leg = true, quad = true, serial = true;
   void add(const mppi_ctx* c) {
     const DevModel& M = c->m->host;
     leg = leg && legged(M);
     quad = quad && legged_4x3(M);
+    serial = serial && serial_chain(M);
     E = std::max(E, c->E);
     nb = std::max(nb, M.nb);
     nc = std::max(nc, M.nc);
@@ -756,6 +767,13 @@ static hipError_t launch_rollout_G(int blocks, const DevInst* insts, const int2*
   if constexpr (G >= 8 && G <= 32) {
     if (depth <= 3 && dm.leg) {
       hipLaunchKernelGGL((rollout_kernel<G, 3, 1>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride,
+                         sh.table, x0_in, nominal_in);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (G == 4 || G == 8) {
+    if (depth <= 3 && dm.serial) {
+      hipLaunchKernelGGL((rollout_kernel<G, 3, 3>), dim3(blocks), dim3(64), sh.lds, s, insts, work, sh.stride,
                          sh.table, x0_in, nominal_in);
       return hipGetLastError();
     }
@@ -836,6 +854,8 @@ static hipError_t launch_persistent_body(int n_items, const LaunchShape& sh, con
     if (dm.depth <= 3 && dm.quad) return launch_persistent_k(rollout_persistent_kernel<16, 3, 2>, P_ARGS);
   if constexpr (G >= 8 && G <= 32)
     if (dm.depth <= 3 && dm.leg) return launch_persistent_k(rollout_persistent_kernel<G, 3, 1>, P_ARGS);
+  if constexpr (G == 4 || G == 8)
+    if (dm.depth <= 3 && dm.serial) return launch_persistent_k(rollout_persistent_kernel<G, 3, 3>, P_ARGS);
   if (dm.depth <= 3) return launch_persistent_k(rollout_persistent_kernel<G, 3, 0>, P_ARGS);
   if (dm.depth <= 6) return launch_persistent_k(rollout_persistent_kernel<G, 6, 0>, P_ARGS);
   return launch_persistent_k(rollout_persistent_kernel<G, 0, 0>, P_ARGS);
@@ -1570,6 +1590,13 @@ static hipError_t launch_trace_G(const DevInst* inst, int N, const LaunchShape& 
   if constexpr (G >= 8 && G <= 32) {
     if (depth <= 3 && dm.leg) {
       hipLaunchKernelGGL((rollout_trace_kernel<G, 3, 1>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr,
+                         sh.stride, sh.table);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (G == 4 || G == 8) {
+    if (depth <= 3 && dm.serial) {
+      hipLaunchKernelGGL((rollout_trace_kernel<G, 3, 3>), dim3(blocks), dim3(64), sh.lds, s, inst, nullptr,
                          sh.stride, sh.table);
       return hipGetLastError();
     }

@@ -875,8 +875,10 @@ template <int D> constexpr int kLevelUnrollRoot = D > 0 ? D + 1 : 1;
 // except the base's, which gathers the chains through LDS.  LEG = 2: such a
 // tree with four chains of three bodies in groups of 16 lanes (the chains'
 // first bodies at lanes 1, 4, 7 and 10), whose base gathers the chains by row
-// shifts instead.  The same arithmetic as the general form (children added in
-// the same order), with its LDS paths and their branches compiled out.
+// shifts instead.  LEG = 3: a fixed-base serial chain (body b's parent is body
+// b - 1, the first body's the world), so every hand-over is a neighbour's and
+// nothing goes through LDS.  The same arithmetic as the general form (children
+// added in the same order), with its LDS paths and their branches compiled out.
 template <int G, int D = 0, int LEG = 0>
 __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const float* tab, float* __restrict__ gs,
                              int b, bool body_lane, StepIO& io, BodyKin& kin_kept, bool want_cost,
@@ -887,7 +889,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
   float Pt[28];
   load_rotation_constants(bc.P, Pt);
   float* slots = gs;
-  const int fb = LEG != 0 ? 1 : sc.fb;  // legged trees have a floating base
+  const int fb = LEG == 3 ? 0 : (LEG != 0 ? 1 : sc.fb);  // legged trees have a floating base, serial chains not
   const bool is_base = body_lane && fb && b == 0;
   const bool is_joint = body_lane && !is_base;
 
@@ -949,14 +951,14 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
         fk_base_child(io.bv, C, bc.p_tree, bc.axis_p, io.v, R, p, e, ax, v, c, beta);
       } else {
         float Rl[9], pl[3], vl[6], bl[6];
-        if (LEG != 0 || (bc.flags & kAdjParent)) {
+        if (LEG == 3 ? d > 1 : (LEG != 0 || (bc.flags & kAdjParent))) {
 #pragma unroll
           for (int k = 0; k < 9; ++k) Rl[k] = sR[k];
 #pragma unroll
           for (int k = 0; k < 3; ++k) pl[k] = sp[k];
 #pragma unroll
           for (int k = 0; k < 6; ++k) { vl[k] = sv[k]; bl[k] = sb[k]; }
-        } else if (lam >= 0) {
+        } else if (LEG != 3 && lam >= 0) {
           get_frame(slots + lam * kSlot, Rl, pl, vl, bl);
         } else {
 #pragma unroll
@@ -1061,7 +1063,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
     }
     if (body_lane && depth == d) {
       const int nch = bc.n_child;
-      if (LEG != 2 && (LEG == 0 || d == 0) && nch > 0) {
+      if (LEG != 2 && LEG != 3 && (LEG == 0 || d == 0) && nch > 0) {
         // children reached through LDS: the first kFold records are read together
         // (a missing child reads this lane's own slot and is not added), then
         // added in child order; more children follow one by one
@@ -1089,7 +1091,7 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
       }
       if (is_joint) {
         backward_joint(IA, pA, ax, c, e, tau, bc.arm, gain, U, invD, u, Ip, pp);
-        if (LEG != 2 && (LEG == 0 || d == 1) && (bc.flags & kArtOut)) put_art(slots + b * kSlot, Ip, pp);
+        if (LEG != 2 && LEG != 3 && (LEG == 0 || d == 1) && (bc.flags & kArtOut)) put_art(slots + b * kSlot, Ip, pp);
       }
     }
     wave_sync();
@@ -1143,10 +1145,10 @@ __device__ void physics_step(const StepConst& sc, const BodyConst& bc, const flo
       if (fb && d == 1) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) al[k] = a0[k];
-      } else if (LEG != 0 || (bc.flags & kAdjParent)) {
+      } else if (LEG == 3 ? d > 1 : (LEG != 0 || (bc.flags & kAdjParent))) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) al[k] = sa[k];
-      } else if (lam >= 0) {
+      } else if (LEG != 3 && lam >= 0) {
         get_acc(slots + lam * kSlot, al);
       } else {
         // fixed world: a' = -a_g = (0, 0, 0, 0, 0, g); its angular part is zero, so no shift term
@@ -1446,7 +1448,7 @@ __device__ __attribute__((always_inline)) void rollout_item(const DevInst& I, in
   wave_sync();
 
   const StepConst sc = load_step_const(M, &I, 0.f);
-  const int fb = LEG != 0 ? 1 : sc.fb, nb = M.nb, nq = fb ? 7 + M.nu : M.nu;
+  const int fb = LEG == 3 ? 0 : (LEG != 0 ? 1 : sc.fb), nb = M.nb, nq = fb ? 7 + M.nu : M.nu;
   const bool body_lane = l < nb;
   const int b = l;
   const bool is_joint = body_lane && !(fb && b == 0);
@@ -3284,6 +3286,16 @@ MPPI_LEG_INST(8)
 MPPI_LEG_INST(16)
 MPPI_LEG_INST(32)
 #undef MPPI_LEG_INST
+// fixed-base serial chains up to 3 bodies
+#define MPPI_SERIAL_INST(G)                                                                            \
+  template __global__ void rollout_kernel<G, 3, 3>(const DevInst*, const int2*, int, int, const float*,   \
+                                                      const float*);                                      \
+  template __global__ void rollout_trace_kernel<G, 3, 3>(const DevInst*, const int2*, int, int);                \
+  template __global__ void rollout_persistent_kernel<G, 3, 3>(const DevInst*, const int2*, int, unsigned int*, int,  \
+                                                             int);
+MPPI_SERIAL_INST(4)
+MPPI_SERIAL_INST(8)
+#undef MPPI_SERIAL_INST
 // four chains of three bodies on 16 lanes (the quadruped's shape)
 template __global__ void rollout_kernel<16, 3, 2>(const DevInst*, const int2*, int, int, const float*, const float*);
 template __global__ void rollout_trace_kernel<16, 3, 2>(const DevInst*, const int2*, int, int);
