@@ -300,9 +300,13 @@ def test_full_step_quadruped():
     assert g["n_nonfinite"] == 0
 
 
-@pytest.mark.parametrize("lanes", [16, 32, 64])
-def test_lane_count_does_not_change_results(lanes):
-    m, p, seed, model, c = _ctrl("quadruped", n_samples=40)
+@pytest.mark.parametrize("name,lanes", [("quadruped", 16), ("quadruped", 32), ("quadruped", 64),
+                                        ("chain", 8), ("chain", 16)])
+def test_lane_count_does_not_change_results(name, lanes):
+    """The same step at another lane count (another kernel specialisation: the
+    quadruped-shaped, legged-tree and general kernels; the serial-chain kernel at
+    4 and 8 lanes and the general one at 16) gives the same bits."""
+    m, p, seed, model, c = _ctrl(name, n_samples=40)
     kn = synth.nominal_knots(m, p["n_knots"])
     c.tick = 2
     a = _run_step(c, m, p, kn)
