@@ -12,8 +12,9 @@ Also reported:
   batched_vs_plain 64 robots drawn from the serving mix (chain / quadruped /
                    humanoid, K in 32..1024, H in 50..200, 3 iterations): one
                    plain mppi_step per robot in sequence vs one fused
-                   mppi_step_batch vs its captured hipGraph, rollout-steps/s and
-                   per-robot tick latency;
+                   mppi_step_batch (launch per item, and persistent) vs its
+                   captured hipGraph (both forms), rollout-steps/s and per-robot
+                   tick latency;
   serving          the same robots ticking as Poisson processes at 50 Hz for a few
                    seconds, served with request-level batches ("batched"),
                    iteration-level rounds ("iteration") and plain per-instance
@@ -258,18 +259,24 @@ def batched_vs_plain(args, torch, mppi, synth):
             mppi.set_batch_options(persistent=False)
 
     graph = mppi.Graph(ctrls, states, kins, kouts)
+    # the same round as one persistent fused launch per lane count, captured
+    mppi.set_batch_options(persistent=True)
+    try:
+        graph_p = mppi.Graph(ctrls, states, kins, kouts)
+    finally:
+        mppi.set_batch_options(persistent=False)
 
-    def graph_round():
+    def replay(g):
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
         start.record(stream)
-        graph.launch()
+        g.launch()
         end.record(stream)
         return start, [end] * len(made)
 
     out = {}
     for name, fn in (("plain", plain_round), ("batched", batched_round), ("batched_persistent", persistent_round),
-                     ("graph", graph_round)):
+                     ("graph", lambda: replay(graph)), ("graph_persistent", lambda: replay(graph_p))):
         fn()  # warm-up (builds the batched launch plan once)
         torch.cuda.synchronize()
         lat = []
@@ -282,6 +289,7 @@ def batched_vs_plain(args, torch, mppi, synth):
         out[name] = {"rollout_steps_per_s": work * rounds / wall, "ms_per_round": 1e3 * wall / rounds,
                      "tick_latency_p50_ms": _pct(lat, 50), "tick_latency_p99_ms": _pct(lat, 99)}
     graph.close()
+    graph_p.close()
     out["robots"] = len(made)
     out["rollout_steps_per_round"] = work
     out["speedup"] = out["batched"]["rollout_steps_per_s"] / out["plain"]["rollout_steps_per_s"]
